@@ -1,0 +1,279 @@
+/*
+ * pdmrg.h -- C ABI of the MI355X (gfx950) hot path of real-space parallel
+ * DMRG (E. M. Stoudenmire and S. R. White, "Real-Space Parallel Density
+ * Matrix Renormalization Group").
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Status: every function returns int.  0 = OK; > 0 = warning
+ * (PDMRG_WARN_NOT_CONVERGED, PDMRG_WARN_V_FLOORED); < 0 = error (see the
+ * PDMRG_E* codes).  pdmrg_last_error() returns a thread-local message for the
+ * last non-zero status.  No C++ exception crosses the ABI.
+ *
+ * Charges: integers q = 2 S^z.  Bond charges are left-accumulated: a bond
+ * state's charge is the total charge of the sites to its left, so every MPS
+ * tensor satisfies q_left + q_phys = q_right; bond 0 is {q = 0, dim 1} and bond
+ * N is {q = target, dim 1}.  A bond is a list of sectors with strictly
+ * ascending charge and positive dimension; within a sector, states are ordered
+ * as produced by the SVD (descending singular value).
+ *
+ * Memory: pointers named *_dev are device pointers (HIP device memory of the
+ * context's device, e.g. torch tensors); every other pointer is host memory.
+ * The library never frees caller memory.  Device data is FP64 unless an
+ * argument says otherwise; layouts are row-major.
+ *
+ * Layouts (block-sparse, U(1) allowed blocks only), all blocks concatenated in
+ * ascending order of their leading sector:
+ *  PDMRG_SITE     A[a, s, b] on bonds (bl, br): for each left sector q_a, a
+ *                 row-major block of dim(q_a) rows and sum_s dim_br(q_a + q_s)
+ *                 columns, the column segments ordered by s ascending (absent
+ *                 right sectors skipped).
+ *  PDMRG_TWO_SITE Psi[a, s1, s2, b] on (bl, br): as SITE with the column
+ *                 segments ordered by (s1, s2) lexicographically (Eq. eqn:wf).
+ *  PDMRG_ENV_L    left environment L[a, w, a'] on a bond (a = bra, a' = ket):
+ *                 for each ket sector q', a row-major block whose rows run over
+ *                 the MPO channels w ascending and, within w, the bra states of
+ *                 sector q' + delta_w; columns are the ket states of q'.
+ *  PDMRG_ENV_R    right environment R[b, w, b'] (b = bra): for each bra sector
+ *                 q, a row-major block whose rows run over w ascending and,
+ *                 within w, the ket states of sector q - delta_w; columns are
+ *                 the bra states of q.  (R is stored with its ket index on the
+ *                 rows.)
+ * pdmrg_layout_blocks() lists every block with its offset, shape and leading
+ * dimension, so callers can move data in and out.
+ *
+ * MPO tensors W_i[wl, s, s', wr] (<s|O|s'> for channel wl -> wr) are host
+ * arrays; channel charges delta_w satisfy delta_wl + q_s - q_s' = delta_wr.
+ * The environment of bond 0 is L = [[1]] on MPO channel 0 and that of bond N
+ * is R = [[1]] on the last bond's single channel.
+ */
+#ifndef PDMRG_H
+#define PDMRG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------ status */
+#define PDMRG_OK 0
+#define PDMRG_WARN_NOT_CONVERGED 1
+#define PDMRG_WARN_V_FLOORED 2
+#define PDMRG_EINVAL (-1)     /* bad argument                              */
+#define PDMRG_ESHAPE (-2)     /* sector / charge structure mismatch         */
+#define PDMRG_ENOMEM (-3)     /* device or host allocation failed           */
+#define PDMRG_EHIP (-4)       /* HIP runtime error                          */
+#define PDMRG_ENUMERIC (-5)   /* NaN / Inf detected                         */
+
+/* --------------------------------------------------------------- precision */
+#define PDMRG_F64 0           /* FP64 MFMA, FP64 storage                     */
+#define PDMRG_F32 1           /* FP32 MFMA, FP32 storage, FP32 accumulation  */
+#define PDMRG_BF16X3 2        /* split-BF16 x3 MFMA (hi*hi + hi*lo + lo*hi),
+                                 FP32 storage and accumulation              */
+
+/* ----------------------------------------------------------------- layouts */
+#define PDMRG_SITE 0
+#define PDMRG_TWO_SITE 1
+#define PDMRG_ENV_L 2
+#define PDMRG_ENV_R 3
+
+typedef struct {
+    int32_t nsec;             /* number of sectors                          */
+    const int32_t *q;         /* [nsec] charges, strictly ascending         */
+    const int32_t *dim;       /* [nsec] dimensions, > 0                     */
+} pdmrg_bond;
+
+typedef struct {
+    int32_t d;                /* local dimension                            */
+    const int32_t *q;         /* [d] charges of the local states            */
+} pdmrg_phys;
+
+typedef struct {
+    int32_t Dl, Dr, d;
+    const double *W;          /* [Dl][d][d][Dr], row-major                   */
+    const int32_t *dl;        /* [Dl] channel charges of the left MPO bond   */
+    const int32_t *dr;        /* [Dr] channel charges of the right MPO bond  */
+} pdmrg_mpo_site;
+
+typedef struct pdmrg_ctx pdmrg_ctx;
+typedef struct pdmrg_mpo pdmrg_mpo;
+typedef struct pdmrg_heff pdmrg_heff;
+typedef struct pdmrg_svd pdmrg_svd;
+typedef struct pdmrg_mps pdmrg_mps;
+
+const char *pdmrg_last_error(void);
+const char *pdmrg_version(void);
+
+/* Context on one device.  stream: a hipStream_t (NULL = default stream) on
+ * which every kernel of this context is launched, in order.  Not thread-safe:
+ * one context per host thread. */
+int pdmrg_ctx_create(int device, void *stream, pdmrg_ctx **out);
+int pdmrg_ctx_destroy(pdmrg_ctx *ctx);
+/* Average duration (ms) of the last heff_apply stage kernels, measured with
+ * HIP events on the context's stream when timing is enabled. */
+int pdmrg_ctx_set_timing(pdmrg_ctx *ctx, int enable);
+int pdmrg_ctx_timing(pdmrg_ctx *ctx, double *ms_stage /*[4]: L.psi, W, .R, total*/,
+                     int64_t *n_calls);
+
+/* Host-only layout bookkeeping (no device needed).  kind = PDMRG_SITE /
+ * TWO_SITE use (b1 = left bond, b2 = right bond, phys); ENV_L / ENV_R use
+ * (b1 = the bond, deltas[ndelta] = MPO channel charges of that bond).
+ * pdmrg_layout_size gives the element count and block count; blocks lists
+ * per block: key[3] (SITE: q_left, s, -; TWO_SITE: q_left, s1, s2; ENV: q_bra, w, -),
+ * offset, rows, cols, ld.  For ENV_R the stored block is the transpose of
+ * R[b, w, b'] restricted to the sectors (rows = ket b', cols = bra b). */
+int pdmrg_layout_size(int kind, const pdmrg_bond *b1, const pdmrg_bond *b2,
+                      const pdmrg_phys *phys, const int32_t *deltas, int32_t ndelta,
+                      int64_t *n_elems, int32_t *n_blocks);
+int pdmrg_layout_blocks(int kind, const pdmrg_bond *b1, const pdmrg_bond *b2,
+                        const pdmrg_phys *phys, const int32_t *deltas, int32_t ndelta,
+                        int32_t *keys /*[nb][3]*/, int64_t *offsets, int32_t *rows,
+                        int32_t *cols, int32_t *ld);
+
+/* ------------------------------------------------------------------- MPO
+ * mpo_build: MPO of a lattice Hamiltonian (Sec. III models) from a finite
+ * state machine over term prefixes (channels 'start', shared operator
+ * prefixes, 'done'; the coupling sits on each term's last operator).
+ * Host-only.  lattice: 0 = open chain (Lx sites), 1 = square cylinder
+ * Lx x Ly (open x, periodic y, snake order), 2 = triangular cylinder,
+ * 3 = J-Q2 square cylinder, 4 = transverse-field Ising chain (no symmetry:
+ * all charges 0).  couplings[]: chain/square/triangular {J, Delta};
+ * J-Q2 {J, Q}; TFIM {J, h}. */
+int mpo_build(int lattice, int Lx, int Ly, const double *couplings, int ncouplings,
+              pdmrg_mpo **out);
+/* MPO from caller tensors (copied). */
+int mpo_from_sites(int nsites, const pdmrg_mpo_site *sites, pdmrg_mpo **out);
+int mpo_info(const pdmrg_mpo *mpo, int32_t *nsites, int32_t *d, int32_t *phys_q /*[d]*/,
+             int32_t *D /*[nsites+1]*/);
+int mpo_get_site(const pdmrg_mpo *mpo, int site, double *W /*[Dl*d*d*Dr]*/,
+                 int32_t *dl, int32_t *dr);
+void mpo_free(pdmrg_mpo *mpo);
+
+/* ------------------------------------------------------------------ H_eff
+ * Two-site effective Hamiltonian of Sec. II: y = (L x W1 W2 x R) x,
+ * y[a,s1,s2,b] = sum L[a,w,a'] W1[w,s1,t1,c] W2[c,s2,t2,w2] R[b,w2,b'] x[a',t1,t2,b'].
+ * heff_create builds the contraction plan for the bonds (bl, br) and copies
+ * L (ENV_L on bl with W1's left channels) and R (ENV_R on br with W2's right
+ * channels) into the precision `prec` (the caller may free L, R afterwards).
+ * heff_apply: x_dev, y_dev in TWO_SITE layout, FP64. */
+int heff_create(pdmrg_ctx *ctx, const pdmrg_bond *bl, const pdmrg_bond *br,
+                const pdmrg_phys *phys, const pdmrg_mpo_site *W1, const pdmrg_mpo_site *W2,
+                const double *L_dev, const double *R_dev, int prec, pdmrg_heff **out);
+int heff_apply(pdmrg_ctx *ctx, pdmrg_heff *op, const double *x_dev, double *y_dev);
+/* Algorithmic flop count of one heff_apply (U(1)-allowed blocks, nonzero MPO
+ * entries only, 2 flops per multiply-add) and element counts. */
+int heff_info(const pdmrg_heff *op, double *flops_Lpsi, double *flops_W, double *flops_R,
+              int64_t *n_psi, int64_t *n_L, int64_t *n_R, int64_t *n_T1, int64_t *n_T2);
+/* diag(H_eff) into diag_dev (TWO_SITE layout, FP64). */
+int heff_diag(pdmrg_ctx *ctx, pdmrg_heff *op, double *diag_dev);
+void heff_free(pdmrg_heff *op);
+
+/* ------------------------------------------------------------- environments
+ * dir = +1: L_out (ENV_L on br) from L_in (ENV_L on bl) and the site tensor
+ *           A (SITE on (bl, br)): L'[b,w',b'] = sum A[a,s,b] L[a,w,a'] W[w,s,s',w'] A[a',s',b'].
+ * dir = -1: R_out (ENV_R on bl) from R_in (ENV_R on br) and B:
+ *           R'[a,w,a'] = sum B[a,s,b] W[w,s,s',w'] R[b,w',b'] B[a',s',b'].
+ * (Sec. II, transformation of the projected operators while sweeping.) */
+int env_update(pdmrg_ctx *ctx, int dir, const pdmrg_bond *bl, const pdmrg_bond *br,
+               const pdmrg_phys *phys, const pdmrg_mpo_site *W, const double *env_in_dev,
+               const double *site_dev, double *env_out_dev, int prec);
+
+/* ---------------------------------------------------------------- Davidson
+ * Lowest eigenpair of H_eff by Davidson (Rayleigh-Ritz on an orthonormal
+ * basis, FP64 classical Gram-Schmidt twice, diagonal preconditioner, restart
+ * to the Ritz vector at max_sub vectors; Sec. II "a few Davidson steps").
+ * psi_dev: initial guess in, normalised eigenvector out.  If `op` is not FP64,
+ * op64 (FP64 operator of the same bond, may be NULL for no refinement) is
+ * used for outer FP64 refinement: each restart recomputes H x in FP64, so the
+ * low-precision error enters only through the correction directions. */
+typedef struct {
+    int32_t max_matvec;       /* total matvec budget (low + high precision) */
+    int32_t max_sub;          /* basis size before restart                  */
+    double tol;               /* stop when ||H x - E x|| <= tol (FP64 residual) */
+} pdmrg_dav_params;
+int davidson_step(pdmrg_ctx *ctx, pdmrg_heff *op, pdmrg_heff *op64, double *psi_dev,
+                  const pdmrg_dav_params *p, double *energy, double *resid, int32_t *n_matvec);
+
+/* -------------------------------------------------------------------- SVD
+ * Truncated SVD of the two-site Psi (Eq. eqn:svd) as the (m d) x (d m) matrix,
+ * block-diagonal in the middle charge; per block a one-sided block-Jacobi SVD
+ * followed by the Appendix recursion on singular values below eps * lambda_1
+ * of that block.  Keeps the max_m largest singular values over all blocks
+ * (ties: larger lambda, then smaller charge, then smaller index), dropping
+ * lambda < cutoff * lambda_max, renormalised to sum lambda^2 = 1.
+ * mode 0 = ABSORB_RIGHT (A kept, centre Lambda B), 1 = ABSORB_LEFT (B kept,
+ * centre A Lambda), 2 = SPLIT (A Lambda and Lambda B, plus V = 1/Lambda
+ * floored at 1/(1e-12 lambda_max); Eqs. eqn:inverse, eqn:isvd).
+ * Returns a result handle; read the new bond with svd_result_bond, then copy
+ * tensors into caller buffers with svd_result_copy (SITE layouts on
+ * (bl, new) and (new, br); lam / V in bond order). */
+#define PDMRG_ABSORB_RIGHT 0
+#define PDMRG_ABSORB_LEFT 1
+#define PDMRG_SPLIT 2
+int svd_truncate(pdmrg_ctx *ctx, const pdmrg_bond *bl, const pdmrg_bond *br,
+                 const pdmrg_phys *phys, const double *psi_dev, int32_t max_m, double cutoff,
+                 double eps, int mode, pdmrg_svd **out);
+int svd_result_bond(const pdmrg_svd *res, int32_t *nsec, int32_t *q /*cap nsec_max*/,
+                    int32_t *dim, int32_t nsec_max, double *discarded, int32_t *n_floored);
+/* Any device pointer may be NULL.  left_dev: A (ABSORB_RIGHT) or A Lambda
+ * (ABSORB_LEFT, SPLIT); right_dev: Lambda B (ABSORB_RIGHT, SPLIT) or B
+ * (ABSORB_LEFT); A_dev / B_dev: the orthonormal factors. */
+int svd_result_copy(pdmrg_ctx *ctx, const pdmrg_svd *res, double *A_dev, double *B_dev,
+                    double *left_dev, double *right_dev, double *lam_host, double *V_host);
+void svd_free(pdmrg_svd *res);
+
+/* -------------------------------------------------------------------- merge
+ * Psi'[a,s3,s4,b] = sum_alpha psiL[a,s3,alpha] V[alpha] psiR[alpha,s4,b]
+ * (Eq. eqn:merge).  psiL: SITE on (bl, bm); psiR: SITE on (bm, br);
+ * V_dev: FP64 of length total(bm) in bond order; out: TWO_SITE on (bl, br). */
+int merge_regions(pdmrg_ctx *ctx, const pdmrg_bond *bl, const pdmrg_bond *bm,
+                  const pdmrg_bond *br, const pdmrg_phys *phys, const double *psiL_dev,
+                  const double *V_dev, const double *psiR_dev, double *psi2_dev);
+
+/* ---------------------------------------------------------------- MPS, sweep
+ * mps_alloc: MPS of nsites sites with the given bond sector tables
+ * (nsites+1 bonds); site data (SITE layouts, FP64, host) via mps_set_site.
+ * sweep: one full sweep.  The first call brings the MPS to right-canonical
+ * form with its centre on site 0 and builds the environments.  With
+ * n_regions = 1 it is the standard two-site sweep (right, then back).  With
+ * n_regions > 1 the first such call splits the chain into n contiguous
+ * regions (V = Lambda^{-1} on every shared bond, odd regions centred at their
+ * left end, even ones at their right end) and every call runs the staggered
+ * pattern of Fig. 4: half-sweep A (odd regions right, even left), merge and
+ * re-split at shared bonds 1|2, 3|4, ...; half-sweep B, merges at 2|3, ...
+ * Regions of one half-sweep advance in lockstep and their matvecs share
+ * launches.  energy: <Psi|H|Psi>/<Psi|Psi> of the whole MPS after the sweep. */
+typedef struct {
+    int32_t max_m;
+    int32_t n_regions;
+    int32_t prec;                     /* precision of bulk H_eff contractions */
+    int32_t refine;                   /* 1: FP64 refinement when prec != F64  */
+    pdmrg_dav_params dav;             /* interior bonds                       */
+    pdmrg_dav_params dav_shared;      /* shared (merge) bonds                 */
+    double cutoff, eps;
+} pdmrg_sweep_params;
+typedef struct {
+    double energy;                    /* full <H> after the sweep             */
+    double max_trunc;                 /* largest discarded weight             */
+    double seconds;                   /* wall time of the sweep               */
+    double seconds_heff;              /* time inside H_eff matvecs            */
+    int64_t n_matvec;
+    int32_t n_floored;
+    int32_t max_bond;
+} pdmrg_sweep_report;
+int mps_alloc(pdmrg_ctx *ctx, int nsites, const pdmrg_phys *phys, int32_t q_target,
+              const pdmrg_bond *bonds, pdmrg_mps **out);
+int mps_set_site(pdmrg_mps *mps, int site, const double *host_data, int64_t n);
+int mps_bond(const pdmrg_mps *mps, int b, int32_t *nsec, int32_t *q, int32_t *dim, int32_t cap);
+int mps_get_site(pdmrg_mps *mps, int site, double *host_data, int64_t cap);
+int sweep(pdmrg_ctx *ctx, pdmrg_mps *mps, const pdmrg_mpo *mpo, const pdmrg_sweep_params *p,
+          pdmrg_sweep_report *rep);
+int mps_energy(pdmrg_ctx *ctx, pdmrg_mps *mps, const pdmrg_mpo *mpo, double *energy);
+void mps_free(pdmrg_mps *mps);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PDMRG_H */

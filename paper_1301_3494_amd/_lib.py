@@ -1,0 +1,291 @@
+"""ctypes binding of libpdmrg.so (include/pdmrg.h): argument marshalling only.
+
+Every computation happens inside the HIP library; this module converts Python
+bond / MPO descriptions into the C structs and device tensors into pointers.
+It raises immediately if the library has not been built.
+"""
+import ctypes
+import os
+from ctypes import POINTER, Structure, byref, c_char_p, c_double, c_int, c_int32, c_int64, c_void_p
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpdmrg.so")
+
+F64, F32, BF16X3 = 0, 1, 2
+SITE, TWO_SITE, ENV_L, ENV_R = 0, 1, 2, 3
+ABSORB_RIGHT, ABSORB_LEFT, SPLIT = 0, 1, 2
+WARN_NOT_CONVERGED, WARN_V_FLOORED = 1, 2
+PREC_NAMES = {"f64": F64, "f32": F32, "bf16x3": BF16X3}
+
+
+class CBond(Structure):
+    _fields_ = [("nsec", c_int32), ("q", POINTER(c_int32)), ("dim", POINTER(c_int32))]
+
+
+class CPhys(Structure):
+    _fields_ = [("d", c_int32), ("q", POINTER(c_int32))]
+
+
+class CMpoSite(Structure):
+    _fields_ = [("Dl", c_int32), ("Dr", c_int32), ("d", c_int32), ("W", POINTER(c_double)),
+                ("dl", POINTER(c_int32)), ("dr", POINTER(c_int32))]
+
+
+class CDavParams(Structure):
+    _fields_ = [("max_matvec", c_int32), ("max_sub", c_int32), ("tol", c_double)]
+
+
+class CSweepParams(Structure):
+    _fields_ = [("max_m", c_int32), ("n_regions", c_int32), ("prec", c_int32), ("refine", c_int32),
+                ("dav", CDavParams), ("dav_shared", CDavParams), ("cutoff", c_double), ("eps", c_double)]
+
+
+class CSweepReport(Structure):
+    _fields_ = [("energy", c_double), ("max_trunc", c_double), ("seconds", c_double),
+                ("seconds_heff", c_double), ("n_matvec", c_int64), ("n_floored", c_int32),
+                ("max_bond", c_int32)]
+
+
+class PdmrgError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("pdmrg error %d: %s" % (code, msg))
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """Load libpdmrg.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libpdmrg.so not built: run paper_1301_3494_amd/build.py (or __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        _declare(L)
+        _lib = L
+    return _lib
+
+
+EXPORTS = [
+    "pdmrg_last_error", "pdmrg_version", "pdmrg_ctx_create", "pdmrg_ctx_destroy", "pdmrg_ctx_set_timing",
+    "pdmrg_ctx_timing", "pdmrg_layout_size", "pdmrg_layout_blocks", "mpo_build", "mpo_from_sites",
+    "mpo_info", "mpo_get_site", "mpo_free", "heff_create", "heff_apply", "heff_info", "heff_diag",
+    "heff_free", "env_update", "davidson_step", "svd_truncate", "svd_result_bond", "svd_result_copy",
+    "svd_free", "merge_regions", "mps_alloc", "mps_set_site", "mps_bond", "mps_get_site", "sweep",
+    "mps_energy", "mps_free",
+]
+
+
+def _declare(L):
+    P = c_void_p
+    pb, pp, pm = POINTER(CBond), POINTER(CPhys), POINTER(CMpoSite)
+    pi32, pi64, pd = POINTER(c_int32), POINTER(c_int64), POINTER(c_double)
+    sig = {
+        "pdmrg_last_error": (c_char_p, []),
+        "pdmrg_version": (c_char_p, []),
+        "pdmrg_ctx_create": (c_int, [c_int, P, POINTER(P)]),
+        "pdmrg_ctx_destroy": (c_int, [P]),
+        "pdmrg_ctx_set_timing": (c_int, [P, c_int]),
+        "pdmrg_ctx_timing": (c_int, [P, pd, pi64]),
+        "pdmrg_layout_size": (c_int, [c_int, pb, pb, pp, pi32, c_int32, pi64, pi32]),
+        "pdmrg_layout_blocks": (c_int, [c_int, pb, pb, pp, pi32, c_int32, pi32, pi64, pi32, pi32, pi32]),
+        "mpo_build": (c_int, [c_int, c_int, c_int, pd, c_int, POINTER(P)]),
+        "mpo_from_sites": (c_int, [c_int, pm, POINTER(P)]),
+        "mpo_info": (c_int, [P, pi32, pi32, pi32, pi32]),
+        "mpo_get_site": (c_int, [P, c_int, pd, pi32, pi32]),
+        "mpo_free": (None, [P]),
+        "heff_create": (c_int, [P, pb, pb, pp, pm, pm, P, P, c_int, POINTER(P)]),
+        "heff_apply": (c_int, [P, P, P, P]),
+        "heff_info": (c_int, [P, pd, pd, pd, pi64, pi64, pi64, pi64, pi64]),
+        "heff_diag": (c_int, [P, P, P]),
+        "heff_free": (None, [P]),
+        "env_update": (c_int, [P, c_int, pb, pb, pp, pm, P, P, P, c_int]),
+        "davidson_step": (c_int, [P, P, P, P, POINTER(CDavParams), pd, pd, pi32]),
+        "svd_truncate": (c_int, [P, pb, pb, pp, P, c_int32, c_double, c_double, c_int, POINTER(P)]),
+        "svd_result_bond": (c_int, [P, pi32, pi32, pi32, c_int32, pd, pi32]),
+        "svd_result_copy": (c_int, [P, P, P, P, P, P, pd, pd]),
+        "svd_free": (None, [P]),
+        "merge_regions": (c_int, [P, pb, pb, pb, pp, P, P, P, P]),
+        "mps_alloc": (c_int, [P, c_int, pp, c_int32, pb, POINTER(P)]),
+        "mps_set_site": (c_int, [P, c_int, pd, c_int64]),
+        "mps_bond": (c_int, [P, c_int, pi32, pi32, pi32, c_int32]),
+        "mps_get_site": (c_int, [P, c_int, pd, c_int64]),
+        "sweep": (c_int, [P, P, P, POINTER(CSweepParams), POINTER(CSweepReport)]),
+        "mps_energy": (c_int, [P, P, P, pd]),
+        "mps_free": (None, [P]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+
+
+def check(code, allow_warn=False):
+    if code < 0 or (code > 0 and not allow_warn):
+        msg = lib().pdmrg_last_error()
+        raise PdmrgError(code, msg.decode() if msg else "")
+    return code
+
+
+# ---------------------------------------------------------------- marshalling
+class Bond:
+    """Host bond descriptor {charge: dim}; keeps the arrays alive."""
+
+    def __init__(self, sectors):
+        items = sorted((int(q), int(n)) for q, n in dict(sectors).items() if int(n) > 0)
+        self.sectors = dict(items)
+        self.q = np.array([q for q, _ in items], dtype=np.int32)
+        self.dim = np.array([n for _, n in items], dtype=np.int32)
+        self.c = CBond(len(items), self.q.ctypes.data_as(POINTER(c_int32)),
+                       self.dim.ctypes.data_as(POINTER(c_int32)))
+
+    @property
+    def ref(self):
+        return byref(self.c)
+
+
+class Phys:
+    def __init__(self, qs):
+        self.q = np.array(qs, dtype=np.int32)
+        self.c = CPhys(len(qs), self.q.ctypes.data_as(POINTER(c_int32)))
+
+    @property
+    def ref(self):
+        return byref(self.c)
+
+
+class MpoSite:
+    def __init__(self, W, dl, dr):
+        self.W = np.ascontiguousarray(W, dtype=np.float64)
+        self.dl = np.ascontiguousarray(dl, dtype=np.int32)
+        self.dr = np.ascontiguousarray(dr, dtype=np.int32)
+        Dl, d, _, Dr = self.W.shape
+        self.c = CMpoSite(Dl, Dr, d, self.W.ctypes.data_as(POINTER(c_double)),
+                          self.dl.ctypes.data_as(POINTER(c_int32)), self.dr.ctypes.data_as(POINTER(c_int32)))
+
+    @property
+    def ref(self):
+        return byref(self.c)
+
+
+def layout(kind, b1, b2=None, phys=None, deltas=None):
+    """Block table of a layout: list of (key tuple, offset, rows, cols, ld) and
+    the total element count."""
+    L = lib()
+    dl = None if deltas is None else np.ascontiguousarray(deltas, dtype=np.int32)
+    dptr = None if dl is None else dl.ctypes.data_as(POINTER(c_int32))
+    nd = 0 if dl is None else len(dl)
+    b2r = None if b2 is None else b2.ref
+    pr = None if phys is None else phys.ref
+    n, nb = c_int64(), c_int32()
+    check(L.pdmrg_layout_size(kind, b1.ref, b2r, pr, dptr, nd, byref(n), byref(nb)))
+    k = np.zeros((max(nb.value, 1), 3), np.int32)
+    off = np.zeros(max(nb.value, 1), np.int64)
+    r = np.zeros(max(nb.value, 1), np.int32)
+    c = np.zeros(max(nb.value, 1), np.int32)
+    ld = np.zeros(max(nb.value, 1), np.int32)
+    check(L.pdmrg_layout_blocks(kind, b1.ref, b2r, pr, dptr, nd,
+                                k.ctypes.data_as(POINTER(c_int32)), off.ctypes.data_as(POINTER(c_int64)),
+                                r.ctypes.data_as(POINTER(c_int32)), c.ctypes.data_as(POINTER(c_int32)),
+                                ld.ctypes.data_as(POINTER(c_int32))))
+    blocks = [(tuple(int(v) for v in k[i]), int(off[i]), int(r[i]), int(c[i]), int(ld[i]))
+              for i in range(nb.value)]
+    return blocks, n.value
+
+
+def ptr(t):
+    """Device pointer of a torch tensor (or None)."""
+    return None if t is None else c_void_p(t.data_ptr())
+
+
+class Context:
+    """pdmrg context bound to a torch CUDA (HIP) device and stream."""
+
+    def __init__(self, device=0, stream=None):
+        import torch
+        self.device = device
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        h = c_void_p()
+        check(lib().pdmrg_ctx_create(device, c_void_p(self.stream.cuda_stream), byref(h)))
+        self.h = h
+
+    def close(self):
+        if self.h:
+            lib().pdmrg_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------- operations
+class Heff:
+    """heff_create / heff_apply / heff_info / heff_diag / heff_free."""
+
+    def __init__(self, ctx, bl, br, phys, W1, W2, L, R, prec=F64):
+        self.ctx = ctx
+        self._keep = (bl, br, phys, W1, W2)
+        h = c_void_p()
+        check(lib().heff_create(ctx.h, bl.ref, br.ref, phys.ref, W1.ref, W2.ref, ptr(L), ptr(R), int(prec),
+                                byref(h)))
+        self.h = h
+
+    def apply(self, x, y):
+        check(lib().heff_apply(self.ctx.h, self.h, ptr(x), ptr(y)))
+
+    def info(self):
+        f = [c_double() for _ in range(3)]
+        n = [c_int64() for _ in range(5)]
+        check(lib().heff_info(self.h, *[byref(v) for v in f], *[byref(v) for v in n]))
+        keys = ["n_psi", "n_L", "n_R", "n_T1", "n_T2"]
+        out = dict(flops_Lpsi=f[0].value, flops_W=f[1].value, flops_R=f[2].value)
+        out.update({k: v.value for k, v in zip(keys, n)})
+        out["flops"] = out["flops_Lpsi"] + out["flops_W"] + out["flops_R"]
+        return out
+
+    def diag(self, out):
+        check(lib().heff_diag(self.ctx.h, self.h, ptr(out)))
+
+    def free(self):
+        if self.h:
+            lib().heff_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def env_update(ctx, direction, bl, br, phys, W, env_in, site, env_out, prec=F64):
+    check(lib().env_update(ctx.h, int(direction), bl.ref, br.ref, phys.ref, W.ref, ptr(env_in), ptr(site),
+                           ptr(env_out), int(prec)))
+
+
+def davidson_step(ctx, op, psi, max_matvec=20, max_sub=8, tol=1e-10, op64=None):
+    p = CDavParams(int(max_matvec), int(max_sub), float(tol))
+    E, r, n = c_double(), c_double(), c_int32()
+    code = check(lib().davidson_step(ctx.h, op.h, None if op64 is None else op64.h, ptr(psi), byref(p),
+                                     byref(E), byref(r), byref(n)), allow_warn=True)
+    return E.value, r.value, n.value, code
+
+
+def merge_regions(ctx, bl, bm, br, phys, psiL, V, psiR, out):
+    check(lib().merge_regions(ctx.h, bl.ref, bm.ref, br.ref, phys.ref, ptr(psiL), ptr(V), ptr(psiR), ptr(out)))
+
+
+def timing(ctx, enable=None):
+    if enable is not None:
+        check(lib().pdmrg_ctx_set_timing(ctx.h, int(bool(enable))))
+        return None
+    ms = (c_double * 4)()
+    n = c_int64()
+    check(lib().pdmrg_ctx_timing(ctx.h, ms, byref(n)))
+    return list(ms), n.value

@@ -1,0 +1,325 @@
+// Bandwidth-bound kernels of the pdmrg library: the MPO (W) stage as a scaled
+// sum of strided blocks, diag(H_eff), precision conversions, the FP64 vector
+// kernels of the Davidson solver and its small projected eigenproblem.
+// Reductions are two-pass with a fixed summation order (no floating-point
+// atomics), so results are bitwise reproducible.
+#include "kernels.hpp"
+
+namespace pdmrg {
+
+constexpr int LC_TR = 16, LC_TC = 128;
+
+// ------------------------------------------------------------ W stage
+template <typename T>
+__global__ __launch_bounds__(256) void lincomb_kernel(Slots slots, const LcTask *__restrict__ tasks,
+                                                      const LcSrc *__restrict__ srcs,
+                                                      const LcTile *__restrict__ tiles) {
+    const LcTile tl = tiles[blockIdx.x];
+    const LcTask tk = tasks[tl.task];
+    T *dst = static_cast<T *>(const_cast<void *>(slots.p[tk.dst_slot])) + tk.dst_off;
+    const int c = tl.c0 + (threadIdx.x % LC_TC);
+    if (c >= tk.cols) return;
+    const int rmax = min(tk.rows, tl.r0 + LC_TR);
+    for (int r = tl.r0 + (int)(threadIdx.x / LC_TC); r < rmax; r += 256 / LC_TC) {
+        T acc = 0;
+        for (int j = 0; j < tk.nsrc; ++j) {
+            const LcSrc sj = srcs[tk.src0 + j];
+            const T *src = static_cast<const T *>(slots.p[sj.slot]) + sj.off;
+            acc += (T)sj.coef * src[(int64_t)r * sj.ld + c];
+        }
+        dst[(int64_t)r * tk.ld + c] = acc;
+    }
+}
+
+void launch_lincomb(bool f64, const Slots &slots, const LcTask *tasks, const LcSrc *srcs,
+                    const LcTile *tiles, int ntiles, hipStream_t s) {
+    if (ntiles <= 0) return;
+    if (f64) hipLaunchKernelGGL(lincomb_kernel<double>, dim3(ntiles), dim3(256), 0, s, slots, tasks, srcs, tiles);
+    else hipLaunchKernelGGL(lincomb_kernel<float>, dim3(ntiles), dim3(256), 0, s, slots, tasks, srcs, tiles);
+}
+
+// ------------------------------------------------------------ diag(H_eff)
+__global__ __launch_bounds__(256) void diag_kernel(Slots slots, const DiagTerm *__restrict__ terms,
+                                                   const int32_t *__restrict__ groups) {
+    const int g = blockIdx.x;
+    const int t0 = groups[g], t1 = groups[g + 1];
+    if (t0 == t1) return;
+    const DiagTerm head = terms[t0];
+    double *out = static_cast<double *>(const_cast<void *>(slots.p[0])) + head.out_off;
+    const int r = blockIdx.y;
+    if (r >= head.rows) return;
+    for (int c = threadIdx.x; c < head.cols; c += 256) {
+        double acc = 0.0;
+        for (int t = t0; t < t1; ++t) {
+            const DiagTerm tm = terms[t];
+            const double *L = static_cast<const double *>(slots.p[1]) + tm.l_off;
+            const double *R = static_cast<const double *>(slots.p[2]) + tm.r_off;
+            acc += tm.coef * L[(int64_t)r * tm.lstride] * R[(int64_t)c * tm.rstride];
+        }
+        out[(int64_t)r * head.ld + c] = acc;
+    }
+}
+
+void launch_diag_terms(const Slots &slots, const DiagTerm *terms, const int32_t *groups, int ngroups,
+                       int max_rows, hipStream_t s) {
+    if (ngroups <= 0 || max_rows <= 0) return;
+    hipLaunchKernelGGL(diag_kernel, dim3(ngroups, max_rows), dim3(256), 0, s, slots, terms, groups);
+}
+
+// ------------------------------------------------------------ elementwise
+__global__ void cvt_d2f(const double *x, float *y, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = (float)x[i];
+}
+__global__ void cvt_f2d(const float *x, double *y, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = (double)x[i];
+}
+__global__ void fill_kernel(double *x, double v, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        x[i] = v;
+}
+
+static dim3 grid_for(int64_t n) {
+    int64_t b = (n + 255) / 256;
+    if (b > 8192) b = 8192;
+    if (b < 1) b = 1;
+    return dim3((unsigned)b);
+}
+
+void launch_convert_f64_f32(const double *x, float *y, int64_t n, hipStream_t s) {
+    if (n > 0) hipLaunchKernelGGL(cvt_d2f, grid_for(n), dim3(256), 0, s, x, y, n);
+}
+void launch_convert_f32_f64(const float *x, double *y, int64_t n, hipStream_t s) {
+    if (n > 0) hipLaunchKernelGGL(cvt_f2d, grid_for(n), dim3(256), 0, s, x, y, n);
+}
+void launch_fill(double *x, double v, int64_t n, hipStream_t s) {
+    if (n > 0) hipLaunchKernelGGL(fill_kernel, grid_for(n), dim3(256), 0, s, x, v, n);
+}
+
+__global__ void row_scale_kernel(const double *x, double *y, const int64_t *base, const int32_t *rows,
+                                 const int32_t *cols, const int64_t *vbase, const double *scale) {
+    const int k = blockIdx.y;
+    const int64_t n = (int64_t)rows[k] * cols[k];
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        const int r = (int)(e / cols[k]);
+        y[base[k] + e] = x[base[k] + e] * scale[vbase[k] + r];
+    }
+}
+
+void launch_row_scale(const double *x, double *y, const int64_t *base, const int32_t *rows,
+                      const int32_t *cols, const int64_t *vbase, int nblk, int max_elems,
+                      const double *scale, hipStream_t s) {
+    if (nblk <= 0 || max_elems <= 0) return;
+    dim3 g(std::min(1024, (max_elems + 255) / 256), nblk);
+    hipLaunchKernelGGL(row_scale_kernel, g, dim3(256), 0, s, x, y, base, rows, cols, vbase, scale);
+}
+
+// ------------------------------------------------------------ Davidson vectors
+__device__ __forceinline__ double block_sum(double v, double *sh) {
+    // fixed-order tree reduction over 256 threads
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    const double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+__global__ __launch_bounds__(256) void multidot_kernel(const double *V, int64_t ldv, int nvec, const double *w,
+                                                       int64_t n, double *partial) {
+    __shared__ double sh[256];
+    const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
+    const int64_t i0 = blockIdx.x * chunk, i1 = min(n, i0 + chunk);
+    for (int v = 0; v < nvec; ++v) {
+        double acc = 0.0;
+        for (int64_t i = i0 + threadIdx.x; i < i1; i += 256) acc += V[v * ldv + i] * w[i];
+        acc = block_sum(acc, sh);
+        if (threadIdx.x == 0) partial[blockIdx.x * nvec + v] = acc;
+    }
+}
+
+void launch_multidot(const double *V, int64_t ldv, int nvec, const double *w, int64_t n, double *partial,
+                     int nblk, hipStream_t s) {
+    if (nvec <= 0) return;
+    hipLaunchKernelGGL(multidot_kernel, dim3(nblk), dim3(256), 0, s, V, ldv, nvec, w, n, partial);
+}
+
+__global__ void reduce_partials_kernel(const double *partial, int nblk, int nvec, double *out, int stride) {
+    for (int v = threadIdx.x; v < nvec; v += blockDim.x) {
+        double acc = 0.0;
+        for (int b = 0; b < nblk; ++b) acc += partial[b * nvec + v];
+        out[(int64_t)v * stride] = acc;
+    }
+}
+
+void launch_reduce_partials(const double *partial, int nblk, int nvec, double *out, int stride,
+                            hipStream_t s) {
+    if (nvec <= 0) return;
+    hipLaunchKernelGGL(reduce_partials_kernel, dim3(1), dim3(64), 0, s, partial, nblk, nvec, out, stride);
+}
+
+__global__ void combine_kernel(const double *V, int64_t ldv, int nvec, const double *c, double *y, int64_t n,
+                               double beta, double sign) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        double acc = 0.0;
+        for (int v = 0; v < nvec; ++v) acc += c[v] * V[v * ldv + i];
+        y[i] = beta * y[i] + sign * acc;
+    }
+}
+
+void launch_combine(const double *V, int64_t ldv, int nvec, const double *c, double *y, int64_t n, double beta,
+                    hipStream_t s) {
+    hipLaunchKernelGGL(combine_kernel, grid_for(n), dim3(256), 0, s, V, ldv, nvec, c, y, n, beta, 1.0);
+}
+void launch_subtract_combine(const double *V, int64_t ldv, int nvec, const double *c, double *y, int64_t n,
+                             hipStream_t s) {
+    hipLaunchKernelGGL(combine_kernel, grid_for(n), dim3(256), 0, s, V, ldv, nvec, c, y, n, 1.0, -1.0);
+}
+
+__global__ void residual_kernel(const double *hx, const double *x, const double *theta, double *r, int64_t n) {
+    const double th = *theta;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        r[i] = hx[i] - th * x[i];
+}
+void launch_residual(const double *hx, const double *x, const double *theta, double *r, int64_t n,
+                     hipStream_t s) {
+    hipLaunchKernelGGL(residual_kernel, grid_for(n), dim3(256), 0, s, hx, x, theta, r, n);
+}
+
+__global__ void precond_kernel(const double *r, const double *diag, const double *theta, double *t, int64_t n) {
+    const double th = *theta;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        double den = diag[i] - th;
+        if (fabs(den) < 1e-8) den = copysign(1e-8, den);
+        t[i] = r[i] / den;
+    }
+}
+void launch_precond(const double *r, const double *diag, const double *theta, double *t, int64_t n,
+                    hipStream_t s) {
+    hipLaunchKernelGGL(precond_kernel, grid_for(n), dim3(256), 0, s, r, diag, theta, t, n);
+}
+
+__global__ void scale_inv_sqrt_kernel(const double *x, const double *nrm2, double *y, int64_t n) {
+    const double f = 1.0 / sqrt(*nrm2);
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = x[i] * f;
+}
+void launch_scale_by_inv_sqrt(const double *x, const double *nrm2, double *y, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(scale_inv_sqrt_kernel, grid_for(n), dim3(256), 0, s, x, nrm2, y, n);
+}
+
+// ------------------------------------------------------------ projected eigenproblem
+// Cyclic Jacobi with the round-robin (circle) ordering: each round rotates
+// n/2 disjoint index pairs, first their columns (A J, V J), then their rows
+// (J^T A).  One wave64; k <= 64.
+constexpr int SE_MAX = 64;
+
+__global__ __launch_bounds__(64) void small_eig_kernel(const double *G, int k, int ld, double *theta_out,
+                                                       double *c_out) {
+    __shared__ double A[SE_MAX][SE_MAX + 1];
+    __shared__ double V[SE_MAX][SE_MAX + 1];
+    __shared__ double rc[SE_MAX / 2], rs[SE_MAX / 2];
+    __shared__ int rp[SE_MAX / 2], rq[SE_MAX / 2];
+    __shared__ double red[64];
+    const int l = threadIdx.x;
+    for (int i = 0; i < k; ++i)
+        for (int j = l; j < k; j += 64) {
+            A[i][j] = 0.5 * (G[i * ld + j] + G[j * ld + i]);
+            V[i][j] = (i == j) ? 1.0 : 0.0;
+        }
+    __syncthreads();
+    const int n = (k % 2) ? k + 1 : k;   // players, one dummy if k is odd
+    for (int sweep = 0; sweep < 60; ++sweep) {
+        double off = 0.0, dia = 0.0;
+        for (int i = 0; i < k; ++i)
+            for (int j = l; j < k; j += 64) {
+                if (i != j) off += A[i][j] * A[i][j];
+                else dia += A[i][j] * A[i][j];
+            }
+        red[l] = off;
+        __syncthreads();
+        if (l == 0) {
+            double so = 0.0;
+            for (int i = 0; i < 64; ++i) so += red[i];
+            red[0] = so;
+        }
+        __syncthreads();
+        const double soff = red[0];
+        __syncthreads();
+        red[l] = dia;
+        __syncthreads();
+        if (l == 0) {
+            double sd = 0.0;
+            for (int i = 0; i < 64; ++i) sd += red[i];
+            red[0] = sd;
+        }
+        __syncthreads();
+        const double sdia = red[0];
+        __syncthreads();
+        if (soff <= 1e-30 * sdia || soff == 0.0) break;
+        for (int r = 0; r < n - 1; ++r) {
+            if (l < n / 2) {
+                int p = (l == 0) ? n - 1 : (r + l) % (n - 1);
+                int q = (r - l + (n - 1)) % (n - 1);
+                if (p > q) { const int t = p; p = q; q = t; }
+                double c = 1.0, s = 0.0;
+                if (q < k && p < k && A[p][q] != 0.0) {
+                    const double tau = (A[q][q] - A[p][p]) / (2.0 * A[p][q]);
+                    const double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                    c = 1.0 / sqrt(1.0 + t * t);
+                    s = t * c;
+                }
+                rp[l] = p; rq[l] = q; rc[l] = c; rs[l] = s;
+            }
+            __syncthreads();
+            // columns: A J and V J
+            for (int e = l; e < (n / 2) * k; e += 64) {
+                const int pr = e / k, i = e % k;
+                const int p = rp[pr], q = rq[pr];
+                if (q >= k) continue;
+                const double c = rc[pr], s = rs[pr];
+                const double ap = A[i][p], aq = A[i][q];
+                A[i][p] = c * ap - s * aq;
+                A[i][q] = s * ap + c * aq;
+                const double vp = V[i][p], vq = V[i][q];
+                V[i][p] = c * vp - s * vq;
+                V[i][q] = s * vp + c * vq;
+            }
+            __syncthreads();
+            // rows: J^T A
+            for (int e = l; e < (n / 2) * k; e += 64) {
+                const int pr = e / k, j = e % k;
+                const int p = rp[pr], q = rq[pr];
+                if (q >= k) continue;
+                const double c = rc[pr], s = rs[pr];
+                const double ap = A[p][j], aq = A[q][j];
+                A[p][j] = c * ap - s * aq;
+                A[q][j] = s * ap + c * aq;
+            }
+            __syncthreads();
+        }
+    }
+    if (l == 0) {
+        int best = 0;
+        for (int i = 1; i < k; ++i)
+            if (A[i][i] < A[best][best]) best = i;
+        red[0] = A[best][best];
+        red[1] = (V[0][best] < 0.0) ? -1.0 : 1.0;
+        rp[0] = best;
+    }
+    __syncthreads();
+    const int best = rp[0];
+    const double sg = red[1];
+    for (int i = l; i < k; i += 64) c_out[i] = sg * V[i][best];
+    if (l == 0) theta_out[0] = red[0];
+}
+
+void launch_small_eig(const double *G, int k, int ld, double *theta_out, double *c_out, hipStream_t s) {
+    hipLaunchKernelGGL(small_eig_kernel, dim3(1), dim3(64), 0, s, G, k, ld, theta_out, c_out);
+}
+
+}  // namespace pdmrg

@@ -1,0 +1,135 @@
+// Shared host-side definitions of the pdmrg library: errors, bonds, layouts
+// of the block-sparse tensors (see include/pdmrg.h) and device buffers.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/pdmrg.h"
+
+namespace pdmrg {
+
+struct Error : std::runtime_error {
+    int code;
+    Error(int c, const std::string &m) : std::runtime_error(m), code(c) {}
+};
+
+#define PD_REQUIRE(cond, code, msg)                                              \
+    do {                                                                         \
+        if (!(cond)) throw ::pdmrg::Error((code), std::string(msg));             \
+    } while (0)
+
+#define HIP_OK(expr)                                                             \
+    do {                                                                         \
+        hipError_t e_ = (expr);                                                  \
+        if (e_ != hipSuccess)                                                    \
+            throw ::pdmrg::Error(PDMRG_EHIP, std::string(#expr) + ": " +        \
+                                                 hipGetErrorString(e_));          \
+    } while (0)
+
+void set_last_error(const std::string &msg);
+
+// ---------------------------------------------------------------- bonds
+struct Bond {
+    std::vector<int> q, dim;
+    std::vector<int64_t> off;   // first state of each sector in bond order
+    int total = 0;
+
+    Bond() = default;
+    Bond(const std::vector<int> &qs, const std::vector<int> &dims);
+    static Bond from(const pdmrg_bond *b);
+    int find(int charge) const;   // sector index or -1
+    int dim_of(int charge) const { int k = find(charge); return k < 0 ? 0 : dim[k]; }
+    int nsec() const { return (int)q.size(); }
+    bool operator==(const Bond &o) const { return q == o.q && dim == o.dim; }
+};
+
+struct Phys {
+    std::vector<int> q;
+    int d() const { return (int)q.size(); }
+    static Phys from(const pdmrg_phys *p);
+};
+
+// ---------------------------------------------------------------- layouts
+// SITE / TWO_SITE: one row-major block per left sector.
+struct SiteLayout {
+    int nphys = 0;                   // d (SITE) or d*d (TWO_SITE)
+    std::vector<int64_t> base;       // per left sector
+    std::vector<int> rows, cols;     // per left sector
+    std::vector<int> colo;           // [nsec_left * nphys]: column offset or -1
+    std::vector<int> width;          // [nsec_left * nphys]: segment width (0 if absent)
+    int64_t size = 0;
+};
+SiteLayout site_layout(const Bond &bl, const Bond &br, const Phys &p);
+SiteLayout two_site_layout(const Bond &bl, const Bond &br, const Phys &p);
+
+// ENV_L / ENV_R: one row-major block per ket (L) or bra (R) sector; rows grouped
+// by channel.
+struct EnvLayout {
+    int D = 0;
+    std::vector<int64_t> base;       // per sector
+    std::vector<int> rows, cols;     // per sector (cols = dim of the sector)
+    std::vector<int> rowo;           // [nsec * D]: row offset of channel w or -1
+    int64_t size = 0;
+};
+EnvLayout env_l_layout(const Bond &b, const std::vector<int> &deltas);
+EnvLayout env_r_layout(const Bond &b, const std::vector<int> &deltas);
+
+// ---------------------------------------------------------------- MPO site
+struct MpoSite {
+    int Dl = 0, Dr = 0, d = 0;
+    std::vector<double> W;           // [Dl][d][d][Dr]
+    std::vector<int> dl, dr;
+    double at(int wl, int s, int t, int wr) const {
+        return W[(((size_t)wl * d + s) * d + t) * Dr + wr];
+    }
+    static MpoSite from(const pdmrg_mpo_site *s);
+};
+
+// ---------------------------------------------------------------- device memory
+struct DevBuf {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    explicit DevBuf(size_t n) { alloc(n); }
+    ~DevBuf() { release(); }
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    DevBuf(DevBuf &&o) noexcept : ptr(o.ptr), bytes(o.bytes) { o.ptr = nullptr; o.bytes = 0; }
+    DevBuf &operator=(DevBuf &&o) noexcept {
+        if (this != &o) { release(); ptr = o.ptr; bytes = o.bytes; o.ptr = nullptr; o.bytes = 0; }
+        return *this;
+    }
+    void alloc(size_t n);
+    void ensure(size_t n) { if (n > bytes) { release(); alloc(n); } }
+    void release();
+    template <class T> T *as() const { return static_cast<T *>(ptr); }
+};
+
+template <class T>
+void upload(DevBuf &buf, const std::vector<T> &v, hipStream_t s) {
+    buf.ensure(std::max<size_t>(v.size() * sizeof(T), 16));
+    if (!v.empty()) HIP_OK(hipMemcpyAsync(buf.ptr, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+}
+
+}  // namespace pdmrg
+
+struct pdmrg_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool timing = false;
+    double stage_ms[4] = {0, 0, 0, 0};
+    int64_t n_timed = 0;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    pdmrg::DevBuf ws_dav;           // Davidson basis and scalars
+    pdmrg::DevBuf ws_env;           // environment-update intermediates
+    pdmrg::DevBuf ws_merge;         // merge: V-scaled right tensor
+    pdmrg::DevBuf ws_svd;           // SVD work space
+};

@@ -1,0 +1,53 @@
+// Internal objects behind the opaque handles of include/pdmrg.h.
+#pragma once
+#include "plans.hpp"
+
+struct pdmrg_heff {
+    pdmrg::HeffPlan plan;
+    int prec = PDMRG_F64;
+    pdmrg::DevBuf L, R;            // environments in the operator's precision
+    pdmrg::DevBuf T1, T2, xs;      // intermediates, low-precision copy of x
+    pdmrg::DevBuf diag;            // diag(H_eff), FP64
+    pdmrg::DevBuf diag_terms, diag_groups;
+    int64_t nX = 0, nL = 0, nR = 0;
+};
+
+struct pdmrg_mpo {
+    int N = 0, d = 0;
+    std::vector<int> phys_q;
+    std::vector<pdmrg::MpoSite> W;   // W[i]: Dl = D(i), Dr = D(i+1)
+};
+
+namespace pdmrg {
+
+GemmPrec gemm_prec(int prec);
+void heff_build(pdmrg_ctx *ctx, pdmrg_heff *op, const Bond &bl, const Bond &br, const Phys &p,
+                const MpoSite &W1, const MpoSite &W2, const double *L, const double *R, int prec);
+void heff_run(pdmrg_ctx *ctx, pdmrg_heff *op, const double *x, double *y);
+
+struct DavResult {
+    double energy = 0, resid = 0;
+    int nmv = 0;
+    bool converged = false;
+};
+DavResult davidson_run(pdmrg_ctx *ctx, pdmrg_heff *op, pdmrg_heff *op64, double *psi,
+                       const pdmrg_dav_params &p);
+
+// Truncated SVD of a two-site tensor (svd.cpp).
+struct SvdOut {
+    Bond bl, br, bnew;
+    Phys p;
+    int mode = 0;
+    DevBuf A, B, left, right;      // SITE layouts: A, left on (bl, bnew); B, right on (bnew, br)
+    std::vector<double> lam, V;    // in new-bond order
+    double discarded = 0;
+    int n_floored = 0;
+};
+void svd_truncate_run(pdmrg_ctx *ctx, const Bond &bl, const Bond &br, const Phys &p, const double *psi,
+                      int max_m, double cutoff, double eps, int mode, SvdOut &out);
+
+}  // namespace pdmrg
+
+struct pdmrg_svd {
+    pdmrg::SvdOut r;
+};

@@ -1,0 +1,112 @@
+// Work-list records and kernel launchers of the pdmrg library.
+//
+// Every operand of a grouped launch is addressed as (slot, element offset):
+// the launch passes up to kMaxSlots base pointers, so a work list built once
+// for a bond stays valid for any input / output buffer of that bond.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace pdmrg {
+
+constexpr int kMaxSlots = 8;
+
+struct Slots {
+    const void *p[kMaxSlots];
+};
+
+// One GEMM segment: C += op(A) (M x K) * op(B) (K x N); segments of an item
+// share C, M, N.
+struct GemmSeg {
+    int64_t a_off, b_off;
+    int32_t a_slot, b_slot;
+    int32_t K, lda, ldb;
+    int32_t pad_;
+};
+
+struct GemmItem {
+    int64_t c_off;
+    int32_t c_slot, M, N, ldc;
+    int32_t seg0, nseg;
+};
+
+struct GemmTile {
+    int32_t item, m0, n0, pad_;
+};
+
+// Scaled sum of same-shaped strided blocks: dst = sum_j coef_j * src_j.
+struct LcTask {
+    int64_t dst_off;
+    int32_t dst_slot, rows, cols, ld;
+    int32_t src0, nsrc;
+};
+
+struct LcSrc {
+    int64_t off;
+    int32_t slot, ld;
+    double coef;
+};
+
+struct LcTile {
+    int32_t task, r0, c0, pad_;
+};
+
+// Rank-1 diagonal contributions of diag(H_eff): for a block of rows x cols
+// (leading dim ld), out[a][b] += coef * L[a * lstride] * R[b * rstride].
+struct DiagTerm {
+    int64_t out_off, l_off, r_off;
+    int32_t rows, cols, ld, lstride, rstride;
+    int32_t pad_;
+    double coef;
+};
+
+enum class GemmPrec { F64, F32, BF16X3 };
+
+// Launchers (defined in gemm.hip / blas.hip).  All asynchronous on `s`.
+// c_is_f64: C written as double (F32 / BF16X3 inputs are float).
+void launch_gemm(GemmPrec prec, bool ta, bool tb, bool c_is_f64, const Slots &slots,
+                 const GemmItem *items, const GemmSeg *segs, const GemmTile *tiles,
+                 int ntiles, hipStream_t s);
+void launch_lincomb(bool f64, const Slots &slots, const LcTask *tasks, const LcSrc *srcs,
+                    const LcTile *tiles, int ntiles, hipStream_t s);
+// groups[g]..groups[g+1]: the terms of output block g (all share out_off, rows,
+// cols, ld); each output block is written once (zero if it has no terms).
+void launch_diag_terms(const Slots &slots, const DiagTerm *terms, const int32_t *groups, int ngroups,
+                       int max_rows, hipStream_t s);
+void launch_convert_f64_f32(const double *x, float *y, int64_t n, hipStream_t s);
+void launch_convert_f32_f64(const float *x, double *y, int64_t n, hipStream_t s);
+void launch_fill(double *x, double v, int64_t n, hipStream_t s);
+// Row scaling of row-major blocks: block k (base[k], rows[k] x cols[k]) gets
+// y[r][c] = x[r][c] * scale[vbase[k] + r].
+void launch_row_scale(const double *x, double *y, const int64_t *base, const int32_t *rows,
+                      const int32_t *cols, const int64_t *vbase, int nblk, int max_elems,
+                      const double *scale, hipStream_t s);
+
+// Davidson helpers (FP64).
+// partial[b * nvec + v] = sum over block b's range of V[v][i] * w[i]
+void launch_multidot(const double *V, int64_t ldv, int nvec, const double *w, int64_t n,
+                     double *partial, int nblk, hipStream_t s);
+// out[v * stride] = sum_b partial[b * nvec + v] (fixed order)
+void launch_reduce_partials(const double *partial, int nblk, int nvec, double *out, int stride,
+                            hipStream_t s);
+// y = sum_v c[v] * V[v] (+ beta * y)
+void launch_combine(const double *V, int64_t ldv, int nvec, const double *c, double *y, int64_t n,
+                    double beta, hipStream_t s);
+// y -= sum_v c[v] * V[v]
+void launch_subtract_combine(const double *V, int64_t ldv, int nvec, const double *c, double *y,
+                             int64_t n, hipStream_t s);
+// r = hx - theta x ; theta from dev scalar
+void launch_residual(const double *hx, const double *x, const double *theta, double *r, int64_t n,
+                     hipStream_t s);
+// t = r / (diag - theta) with |den| >= 1e-8
+void launch_precond(const double *r, const double *diag, const double *theta, double *t, int64_t n,
+                    hipStream_t s);
+// y = x / sqrt(*nrm2)
+void launch_scale_by_inv_sqrt(const double *x, const double *nrm2, double *y, int64_t n, hipStream_t s);
+// Lowest eigenpair of the k x k symmetric matrix G (row-major, ld) by cyclic
+// Jacobi in one workgroup: theta_out[0] = eigenvalue, c_out[0..k) eigenvector
+// with c[0] >= 0.
+void launch_small_eig(const double *G, int k, int ld, double *theta_out, double *c_out, hipStream_t s);
+
+}  // namespace pdmrg

@@ -1,0 +1,531 @@
+// Builders of the contraction work lists (host bookkeeping).
+#include "plans.hpp"
+
+namespace pdmrg {
+
+int GemmList::add_item(int c_slot, int64_t c_off, int M, int N, int ldc) {
+    GemmItem it{};
+    it.c_off = c_off;
+    it.c_slot = c_slot;
+    it.M = M;
+    it.N = N;
+    it.ldc = ldc;
+    it.seg0 = (int32_t)segs.size();
+    it.nseg = 0;
+    items.push_back(it);
+    return (int)items.size() - 1;
+}
+
+void GemmList::add_seg(int a_slot, int64_t a_off, int lda, int b_slot, int64_t b_off, int ldb, int K) {
+    PD_REQUIRE(!items.empty(), PDMRG_EINVAL, "gemm list: segment without item");
+    GemmSeg sg{};
+    sg.a_off = a_off;
+    sg.b_off = b_off;
+    sg.a_slot = a_slot;
+    sg.b_slot = b_slot;
+    sg.K = K;
+    sg.lda = lda;
+    sg.ldb = ldb;
+    segs.push_back(sg);
+    GemmItem &it = items.back();
+    it.nseg += 1;
+    flops += 2.0 * it.M * (double)it.N * K;
+}
+
+void GemmList::finish(hipStream_t s) {
+    tiles.clear();
+    for (size_t i = 0; i < items.size(); ++i) {
+        const GemmItem &it = items[i];
+        for (int m0 = 0; m0 < it.M; m0 += kTile)
+            for (int n0 = 0; n0 < it.N; n0 += kTile) tiles.push_back(GemmTile{(int32_t)i, m0, n0, 0});
+    }
+    upload(d_items, items, s);
+    upload(d_segs, segs, s);
+    upload(d_tiles, tiles, s);
+}
+
+static void check_span(const std::vector<int64_t> &slot_elems, int slot, int64_t off, int rows, int cols,
+                       int64_t ld, const char *what) {
+    if (rows <= 0 || cols <= 0) return;
+    PD_REQUIRE(slot >= 0 && slot < (int)slot_elems.size(), PDMRG_ESHAPE, std::string(what) + ": bad slot");
+    PD_REQUIRE(ld >= cols, PDMRG_ESHAPE, std::string(what) + ": leading dimension below width");
+    const int64_t last = off + (int64_t)(rows - 1) * ld + (cols - 1);
+    PD_REQUIRE(off >= 0 && last < slot_elems[slot], PDMRG_ESHAPE,
+               std::string(what) + ": work list reaches outside its buffer");
+}
+
+void GemmList::validate(const std::vector<int64_t> &slot_elems) const {
+    for (const GemmItem &it : items) {
+        check_span(slot_elems, it.c_slot, it.c_off, it.M, it.N, it.ldc, "gemm C");
+        for (int k = 0; k < it.nseg; ++k) {
+            const GemmSeg &sg = segs[it.seg0 + k];
+            if (ta) check_span(slot_elems, sg.a_slot, sg.a_off, sg.K, it.M, sg.lda, "gemm A^T");
+            else check_span(slot_elems, sg.a_slot, sg.a_off, it.M, sg.K, sg.lda, "gemm A");
+            if (tb) check_span(slot_elems, sg.b_slot, sg.b_off, it.N, sg.K, sg.ldb, "gemm B^T");
+            else check_span(slot_elems, sg.b_slot, sg.b_off, sg.K, it.N, sg.ldb, "gemm B");
+        }
+    }
+}
+
+void LcList::validate(const std::vector<int64_t> &slot_elems) const {
+    for (const LcTask &t : tasks) {
+        check_span(slot_elems, t.dst_slot, t.dst_off, t.rows, t.cols, t.ld, "W stage dst");
+        for (int j = 0; j < t.nsrc; ++j) {
+            const LcSrc &sj = srcs[t.src0 + j];
+            check_span(slot_elems, sj.slot, sj.off, t.rows, t.cols, sj.ld, "W stage src");
+        }
+    }
+}
+
+void GemmList::launch(GemmPrec prec, bool c_is_f64, const Slots &sl, hipStream_t s) const {
+    launch_gemm(prec, ta, tb, c_is_f64, sl, d_items.as<GemmItem>(), d_segs.as<GemmSeg>(),
+                d_tiles.as<GemmTile>(), (int)tiles.size(), s);
+}
+
+int LcList::add_task(int dst_slot, int64_t dst_off, int rows, int cols, int ld) {
+    LcTask t{};
+    t.dst_off = dst_off;
+    t.dst_slot = dst_slot;
+    t.rows = rows;
+    t.cols = cols;
+    t.ld = ld;
+    t.src0 = (int32_t)srcs.size();
+    t.nsrc = 0;
+    tasks.push_back(t);
+    elems_out += (int64_t)rows * cols;
+    return (int)tasks.size() - 1;
+}
+
+void LcList::add_src(int slot, int64_t off, int ld, double coef) {
+    LcSrc sj{};
+    sj.off = off;
+    sj.slot = slot;
+    sj.ld = ld;
+    sj.coef = coef;
+    srcs.push_back(sj);
+    LcTask &t = tasks.back();
+    t.nsrc += 1;
+    flops += 2.0 * t.rows * (double)t.cols;
+    elems_in += (int64_t)t.rows * t.cols;
+}
+
+void LcList::finish(hipStream_t s) {
+    tiles.clear();
+    for (size_t i = 0; i < tasks.size(); ++i) {
+        const LcTask &t = tasks[i];
+        for (int r0 = 0; r0 < t.rows; r0 += kLcRows)
+            for (int c0 = 0; c0 < t.cols; c0 += kLcCols) tiles.push_back(LcTile{(int32_t)i, r0, c0, 0});
+    }
+    upload(d_tasks, tasks, s);
+    upload(d_srcs, srcs, s);
+    upload(d_tiles, tiles, s);
+}
+
+void LcList::launch(bool f64, const Slots &sl, hipStream_t s) const {
+    launch_lincomb(f64, sl, d_tasks.as<LcTask>(), d_srcs.as<LcSrc>(), d_tiles.as<LcTile>(), (int)tiles.size(), s);
+}
+
+std::vector<double> two_site_mpo(const MpoSite &W1, const MpoSite &W2) {
+    // W12[w][s1][t1][s2][t2][w2] = sum_c W1[w][s1][t1][c] W2[c][s2][t2][w2]
+    PD_REQUIRE(W1.Dr == W2.Dl && W1.d == W2.d, PDMRG_ESHAPE, "two-site MPO: inner channel mismatch");
+    const int d = W1.d, Dl = W1.Dl, Dm = W1.Dr, Dr = W2.Dr;
+    std::vector<double> W12((size_t)Dl * d * d * d * d * Dr, 0.0);
+    for (int w = 0; w < Dl; ++w)
+        for (int s1 = 0; s1 < d; ++s1)
+            for (int t1 = 0; t1 < d; ++t1)
+                for (int c = 0; c < Dm; ++c) {
+                    const double a = W1.at(w, s1, t1, c);
+                    if (a == 0.0) continue;
+                    for (int s2 = 0; s2 < d; ++s2)
+                        for (int t2 = 0; t2 < d; ++t2)
+                            for (int w2 = 0; w2 < Dr; ++w2) {
+                                const double b = W2.at(c, s2, t2, w2);
+                                if (b == 0.0) continue;
+                                W12[((((((size_t)w * d + s1) * d + t1) * d + s2) * d + t2) * Dr) + w2] += a * b;
+                            }
+                }
+    return W12;
+}
+
+// ---------------------------------------------------------------- H_eff
+void HeffPlan::build(const Bond &bl_, const Bond &br_, const Phys &p_, const MpoSite &W1, const MpoSite &W2,
+                     hipStream_t s) {
+    bl = bl_;
+    br = br_;
+    p = p_;
+    const int d = p.d(), d2 = d * d;
+    PD_REQUIRE(W1.d == d && W2.d == d, PDMRG_ESHAPE, "heff: MPO local dimension mismatch");
+    PD_REQUIRE(W1.Dr == W2.Dl, PDMRG_ESHAPE, "heff: W1/W2 channel mismatch");
+    const int Dl = W1.Dl, Dr = W2.Dr;
+    X = two_site_layout(bl, br, p);
+    Lt = env_l_layout(bl, W1.dl);
+    Rt = env_r_layout(br, W2.dr);
+    const std::vector<double> W12 = two_site_mpo(W1, W2);
+    auto w12 = [&](int w, int s1, int t1, int s2, int t2, int w2) {
+        return W12[((((((size_t)w * d + s1) * d + t1) * d + s2) * d + t2) * Dr) + w2];
+    };
+    const int nl = bl.nsec();
+
+    // stage 1: T1[j] = Lket[j] (rows (w, a)) x X[j] (rows a', cols (t1 t2 b'))
+    std::vector<int64_t> t1base(nl, -1);
+    nT1 = 0;
+    g1 = GemmList();
+    for (int j = 0; j < nl; ++j) {
+        const int M = Lt.rows[j], N = X.cols[j], K = bl.dim[j];
+        if (M == 0 || N == 0) continue;
+        t1base[j] = nT1;
+        g1.add_item(4, nT1, M, N, N);
+        g1.add_seg(2, Lt.base[j], K, 0, X.base[j], N, K);
+        nT1 += (int64_t)M * N;
+    }
+
+    // T2 blocks: one per output block (i, s1 s2) -> [dim(q_i) x Rt.rows[k]]
+    std::vector<int64_t> t2base((size_t)nl * d2, -1);
+    nT2 = 0;
+    for (int i = 0; i < nl; ++i)
+        for (int sg = 0; sg < d2; ++sg) {
+            if (X.colo[(size_t)i * d2 + sg] < 0) continue;
+            const int k = br.find(bl.q[i] + p.q[sg / d] + p.q[sg % d]);
+            t2base[(size_t)i * d2 + sg] = nT2;
+            nT2 += (int64_t)bl.dim[i] * Rt.rows[k];
+        }
+
+    // stage 2: W stage
+    w = LcList();
+    for (int i = 0; i < nl; ++i)
+        for (int sg = 0; sg < d2; ++sg) {
+            const int64_t tb = t2base[(size_t)i * d2 + sg];
+            if (tb < 0) continue;
+            const int s1 = sg / d, s2 = sg % d;
+            const int qb = bl.q[i] + p.q[s1] + p.q[s2];
+            const int k = br.find(qb);
+            for (int w2 = 0; w2 < Dr; ++w2) {
+                const int ro = Rt.rowo[(size_t)k * Dr + w2];
+                if (ro < 0) continue;
+                const int cols = br.dim_of(qb - W2.dr[w2]);
+                w.add_task(5, tb + ro, bl.dim[i], cols, Rt.rows[k]);
+                for (int ww = 0; ww < Dl; ++ww) {
+                    const int j = bl.find(bl.q[i] - W1.dl[ww]);
+                    if (j < 0 || t1base[j] < 0) continue;
+                    const int lro = Lt.rowo[(size_t)j * Dl + ww];
+                    if (lro < 0) continue;
+                    for (int t1 = 0; t1 < d; ++t1)
+                        for (int t2 = 0; t2 < d; ++t2) {
+                            const double c = w12(ww, s1, t1, s2, t2, w2);
+                            if (c == 0.0) continue;
+                            const int co = X.colo[(size_t)j * d2 + t1 * d + t2];
+                            if (co < 0) continue;
+                            PD_REQUIRE(X.width[(size_t)j * d2 + t1 * d + t2] == cols, PDMRG_ESHAPE,
+                                       "heff: MPO entry violates charge conservation");
+                            w.add_src(4, t1base[j] + (int64_t)lro * X.cols[j] + co, X.cols[j], c);
+                        }
+                }
+            }
+        }
+
+    // stage 3: y[i, s1 s2] = T2[i, s1 s2] x Rbra[k]
+    g3 = GemmList();
+    for (int i = 0; i < nl; ++i)
+        for (int sg = 0; sg < d2; ++sg) {
+            const int64_t tb = t2base[(size_t)i * d2 + sg];
+            if (tb < 0) continue;
+            const int k = br.find(bl.q[i] + p.q[sg / d] + p.q[sg % d]);
+            g3.add_item(1, X.base[i] + X.colo[(size_t)i * d2 + sg], bl.dim[i], br.dim[k], X.cols[i]);
+            if (Rt.rows[k] > 0) g3.add_seg(5, tb, Rt.rows[k], 3, Rt.base[k], br.dim[k], Rt.rows[k]);
+        }
+
+    // diag(H_eff): sum over channels with delta = 0 of L[a,w,a] W12 R[b,w2,b]
+    diag_terms.clear();
+    diag_groups.assign(1, 0);
+    diag_max_rows = 0;
+    for (int i = 0; i < nl; ++i)
+        for (int sg = 0; sg < d2; ++sg) {
+            if (X.colo[(size_t)i * d2 + sg] < 0) continue;
+            const int s1 = sg / d, s2 = sg % d;
+            const int k = br.find(bl.q[i] + p.q[s1] + p.q[s2]);
+            DiagTerm base{};
+            base.out_off = X.base[i] + X.colo[(size_t)i * d2 + sg];
+            base.rows = bl.dim[i];
+            base.cols = br.dim[k];
+            base.ld = X.cols[i];
+            diag_max_rows = std::max(diag_max_rows, base.rows);
+            bool any = false;
+            for (int ww = 0; ww < Dl; ++ww) {
+                if (W1.dl[ww] != 0) continue;
+                const int lro = Lt.rowo[(size_t)i * Dl + ww];
+                if (lro < 0) continue;
+                for (int w2 = 0; w2 < Dr; ++w2) {
+                    if (W2.dr[w2] != 0) continue;
+                    const double c = w12(ww, s1, s1, s2, s2, w2);
+                    if (c == 0.0) continue;
+                    const int rro = Rt.rowo[(size_t)k * Dr + w2];
+                    if (rro < 0) continue;
+                    DiagTerm t = base;
+                    t.coef = c;
+                    t.l_off = Lt.base[i] + (int64_t)lro * Lt.cols[i];
+                    t.lstride = Lt.cols[i] + 1;
+                    t.r_off = Rt.base[k] + (int64_t)rro * Rt.cols[k];
+                    t.rstride = Rt.cols[k] + 1;
+                    diag_terms.push_back(t);
+                    any = true;
+                }
+            }
+            if (!any) {   // still write zeros
+                DiagTerm t = base;
+                t.coef = 0.0;
+                t.l_off = 0;
+                t.r_off = 0;
+                t.lstride = 0;
+                t.rstride = 0;
+                diag_terms.push_back(t);
+            }
+            diag_groups.push_back((int32_t)diag_terms.size());
+        }
+
+    const std::vector<int64_t> sz = {X.size, X.size, Lt.size, Rt.size, nT1, nT2};
+    g1.validate(sz);
+    w.validate(sz);
+    g3.validate(sz);
+    g1.finish(s);
+    w.finish(s);
+    g3.finish(s);
+}
+
+// ---------------------------------------------------------------- environments
+void EnvPlan::build(int dir_, const Bond &bl_, const Bond &br_, const Phys &p_, const MpoSite &W, hipStream_t s) {
+    dir = dir_;
+    bl = bl_;
+    br = br_;
+    p = p_;
+    const int d = p.d();
+    PD_REQUIRE(W.d == d, PDMRG_ESHAPE, "env: MPO local dimension mismatch");
+    const int Dl = W.Dl, Dr = W.Dr;
+    S = site_layout(bl, br, p);
+    const int nl = bl.nsec(), nr = br.nsec();
+    g1 = GemmList();
+    g3 = GemmList();
+    w = LcList();
+    if (dir > 0) {
+        Ein = env_l_layout(bl, W.dl);
+        Eout = env_l_layout(br, W.dr);
+        Aux = env_r_layout(br, W.dr);     // column structure of U2 blocks
+        // E1: U1[j] = Lket[j] x A[j]
+        std::vector<int64_t> u1base(nl, -1);
+        nU1 = 0;
+        for (int j = 0; j < nl; ++j) {
+            const int M = Ein.rows[j], N = S.cols[j], K = bl.dim[j];
+            if (M == 0 || N == 0) continue;
+            u1base[j] = nU1;
+            g1.add_item(3, nU1, M, N, N);
+            g1.add_seg(0, Ein.base[j], K, 1, S.base[j], N, K);
+            nU1 += (int64_t)M * N;
+        }
+        // U2 blocks (i, s): [dim(q_i) x Aux.rows[k]]
+        std::vector<int64_t> u2base((size_t)nl * d, -1);
+        nU2 = 0;
+        for (int i = 0; i < nl; ++i)
+            for (int sp = 0; sp < d; ++sp) {
+                if (S.colo[(size_t)i * d + sp] < 0) continue;
+                const int k = br.find(bl.q[i] + p.q[sp]);
+                u2base[(size_t)i * d + sp] = nU2;
+                nU2 += (int64_t)bl.dim[i] * Aux.rows[k];
+            }
+        // E2: U2[(i,s)][a, (w', b')] = sum W[w,s,t,w'] U1[q_i - dl_w][(w,a), (t,b')]
+        for (int i = 0; i < nl; ++i)
+            for (int sp = 0; sp < d; ++sp) {
+                const int64_t ub = u2base[(size_t)i * d + sp];
+                if (ub < 0) continue;
+                const int qb = bl.q[i] + p.q[sp];
+                const int k = br.find(qb);
+                for (int w2 = 0; w2 < Dr; ++w2) {
+                    const int ro = Aux.rowo[(size_t)k * Dr + w2];
+                    if (ro < 0) continue;
+                    const int cols = br.dim_of(qb - W.dr[w2]);
+                    w.add_task(4, ub + ro, bl.dim[i], cols, Aux.rows[k]);
+                    for (int ww = 0; ww < Dl; ++ww) {
+                        const int j = bl.find(bl.q[i] - W.dl[ww]);
+                        if (j < 0 || u1base[j] < 0) continue;
+                        const int lro = Ein.rowo[(size_t)j * Dl + ww];
+                        if (lro < 0) continue;
+                        for (int t = 0; t < d; ++t) {
+                            const double c = W.at(ww, sp, t, w2);
+                            if (c == 0.0) continue;
+                            const int co = S.colo[(size_t)j * d + t];
+                            if (co < 0) continue;
+                            PD_REQUIRE(S.width[(size_t)j * d + t] == cols, PDMRG_ESHAPE,
+                                       "env: MPO entry violates charge conservation");
+                            w.add_src(3, u1base[j] + (int64_t)lro * S.cols[j] + co, S.cols[j], c);
+                        }
+                    }
+                }
+            }
+        // E3: Lout[j'] rows (w', b) = sum_s A[(i,s)]^T U2[(i,s)][:, w' segment]
+        g3.ta = true;
+        for (int jp = 0; jp < nr; ++jp)
+            for (int w2 = 0; w2 < Dr; ++w2) {
+                const int ro = Eout.rowo[(size_t)jp * Dr + w2];
+                if (ro < 0) continue;
+                const int k = br.find(br.q[jp] + W.dr[w2]);
+                g3.add_item(2, Eout.base[jp] + (int64_t)ro * br.dim[jp], br.dim[k], br.dim[jp], br.dim[jp]);
+                for (int sp = 0; sp < d; ++sp) {
+                    const int i = bl.find(br.q[k] - p.q[sp]);
+                    if (i < 0) continue;
+                    const int64_t ub = u2base[(size_t)i * d + sp];
+                    if (ub < 0) continue;
+                    const int aro = Aux.rowo[(size_t)k * Dr + w2];
+                    g3.add_seg(1, S.base[i] + S.colo[(size_t)i * d + sp], S.cols[i], 4, ub + aro, Aux.rows[k],
+                               bl.dim[i]);
+                }
+            }
+    } else {
+        Ein = env_r_layout(br, W.dr);
+        Eout = env_r_layout(bl, W.dl);
+        // F1: Z1[(k,s)] = Rbra[k] x B[(i,s)]^T, i = q_k - q_s
+        std::vector<int64_t> z1base((size_t)nr * d, -1);
+        nU1 = 0;
+        g1.tb = true;
+        for (int k = 0; k < nr; ++k)
+            for (int sp = 0; sp < d; ++sp) {
+                const int i = bl.find(br.q[k] - p.q[sp]);
+                if (i < 0 || Ein.rows[k] == 0) continue;
+                z1base[(size_t)k * d + sp] = nU1;
+                g1.add_item(3, nU1, Ein.rows[k], bl.dim[i], bl.dim[i]);
+                g1.add_seg(0, Ein.base[k], br.dim[k], 1, S.base[i] + S.colo[(size_t)i * d + sp], S.cols[i],
+                           br.dim[k]);
+                nU1 += (int64_t)Ein.rows[k] * bl.dim[i];
+            }
+        // Z2 blocks (i, w): [S.cols[i'] x dim(q_i)], i' = q_i - dl_w
+        std::vector<int64_t> z2base((size_t)nl * Dl, -1);
+        nU2 = 0;
+        for (int i = 0; i < nl; ++i)
+            for (int ww = 0; ww < Dl; ++ww) {
+                const int ip = bl.find(bl.q[i] - W.dl[ww]);
+                if (ip < 0 || S.cols[ip] == 0) continue;
+                z2base[(size_t)i * Dl + ww] = nU2;
+                nU2 += (int64_t)S.cols[ip] * bl.dim[i];
+            }
+        // F2: Z2[(i,w)][(s', b'), a] = sum W[w,s,s',w2] Z1[(k,s)][(w2,b'), a]
+        for (int i = 0; i < nl; ++i)
+            for (int ww = 0; ww < Dl; ++ww) {
+                const int64_t zb = z2base[(size_t)i * Dl + ww];
+                if (zb < 0) continue;
+                const int ip = bl.find(bl.q[i] - W.dl[ww]);
+                for (int spp = 0; spp < d; ++spp) {
+                    const int co = S.colo[(size_t)ip * d + spp];
+                    if (co < 0) continue;
+                    const int rows = S.width[(size_t)ip * d + spp];
+                    w.add_task(4, zb + (int64_t)co * bl.dim[i], rows, bl.dim[i], bl.dim[i]);
+                    for (int sp = 0; sp < d; ++sp) {
+                        const int k = br.find(bl.q[i] + p.q[sp]);
+                        if (k < 0) continue;
+                        const int64_t z1 = z1base[(size_t)k * d + sp];
+                        if (z1 < 0) continue;
+                        for (int w2 = 0; w2 < Dr; ++w2) {
+                            const double c = W.at(ww, sp, spp, w2);
+                            if (c == 0.0) continue;
+                            const int ro = Ein.rowo[(size_t)k * Dr + w2];
+                            if (ro < 0) continue;
+                            PD_REQUIRE(br.dim_of(br.q[k] - W.dr[w2]) == rows, PDMRG_ESHAPE,
+                                       "env: MPO entry violates charge conservation");
+                            w.add_src(3, z1 + (int64_t)ro * bl.dim[i], bl.dim[i], c);
+                        }
+                    }
+                }
+            }
+        // F3: Rout[i] rows (w, a') = B[i'] x Z2[(i,w)]
+        for (int i = 0; i < nl; ++i)
+            for (int ww = 0; ww < Dl; ++ww) {
+                const int ro = Eout.rowo[(size_t)i * Dl + ww];
+                if (ro < 0) continue;
+                const int ip = bl.find(bl.q[i] - W.dl[ww]);
+                g3.add_item(2, Eout.base[i] + (int64_t)ro * bl.dim[i], bl.dim[ip], bl.dim[i], bl.dim[i]);
+                const int64_t zb = z2base[(size_t)i * Dl + ww];
+                if (zb >= 0) g3.add_seg(1, S.base[ip], S.cols[ip], 4, zb, bl.dim[i], S.cols[ip]);
+            }
+    }
+    const std::vector<int64_t> sz = {Ein.size, S.size, Eout.size, nU1, nU2};
+    g1.validate(sz);
+    w.validate(sz);
+    g3.validate(sz);
+    g1.finish(s);
+    w.finish(s);
+    g3.finish(s);
+}
+
+void EnvPlan::run(GemmPrec prec, const void *env_in, const void *site, void *env_out, void *U1, void *U2,
+                  hipStream_t s) const {
+    Slots sl{};
+    sl.p[0] = env_in;
+    sl.p[1] = site;
+    sl.p[2] = env_out;
+    sl.p[3] = U1;
+    sl.p[4] = U2;
+    const bool f64 = prec == GemmPrec::F64;
+    g1.launch(prec, f64, sl, s);
+    w.launch(f64, sl, s);
+    g3.launch(prec, f64, sl, s);
+}
+
+// ---------------------------------------------------------------- merge
+void MergePlan::build(const Bond &bl_, const Bond &bm_, const Bond &br_, const Phys &p_, hipStream_t s) {
+    bl = bl_;
+    bm = bm_;
+    br = br_;
+    p = p_;
+    const int d = p.d(), d2 = d * d;
+    SL = site_layout(bl, bm, p);
+    SR = site_layout(bm, br, p);
+    X = two_site_layout(bl, br, p);
+    rs_base.clear();
+    rs_vbase.clear();
+    rs_rows.clear();
+    rs_cols.clear();
+    rs_max = 0;
+    for (int k = 0; k < bm.nsec(); ++k) {
+        if (SR.cols[k] == 0) continue;
+        rs_base.push_back(SR.base[k]);
+        rs_vbase.push_back(bm.off[k]);
+        rs_rows.push_back(bm.dim[k]);
+        rs_cols.push_back(SR.cols[k]);
+        rs_max = std::max<int64_t>(rs_max, (int64_t)bm.dim[k] * SR.cols[k]);
+    }
+    g = GemmList();
+    for (int i = 0; i < bl.nsec(); ++i)
+        for (int s3 = 0; s3 < d; ++s3) {
+            const int lco = SL.colo[(size_t)i * d + s3];
+            if (lco < 0) continue;
+            const int k = bm.find(bl.q[i] + p.q[s3]);
+            if (SR.cols[k] == 0) continue;
+            int col0 = -1;
+            for (int s4 = 0; s4 < d; ++s4) {
+                const int xc = X.colo[(size_t)i * d2 + s3 * d + s4];
+                const int rc = SR.colo[(size_t)k * d + s4];
+                PD_REQUIRE((xc < 0) == (rc < 0), PDMRG_ESHAPE, "merge: sector mismatch");
+                if (xc < 0) continue;
+                if (col0 < 0) col0 = xc - rc;
+                PD_REQUIRE(xc - rc == col0, PDMRG_ESHAPE, "merge: column layout mismatch");
+            }
+            g.add_item(2, X.base[i] + col0, bl.dim[i], SR.cols[k], X.cols[i]);
+            g.add_seg(0, SL.base[i] + lco, SL.cols[i], 1, SR.base[k], SR.cols[k], bm.dim[k]);
+        }
+    g.validate({SL.size, SR.size, X.size});
+    g.finish(s);
+    upload(d_rs_base, rs_base, s);
+    upload(d_rs_vbase, rs_vbase, s);
+    upload(d_rs_rows, rs_rows, s);
+    upload(d_rs_cols, rs_cols, s);
+}
+
+void MergePlan::run(const double *psiL, const double *V, const double *psiR, double *out, double *scaled,
+                    hipStream_t s) const {
+    launch_row_scale(psiR, scaled, d_rs_base.as<int64_t>(), d_rs_rows.as<int32_t>(), d_rs_cols.as<int32_t>(),
+                     d_rs_vbase.as<int64_t>(), (int)rs_base.size(), rs_max, V, s);
+    launch_fill(out, 0.0, X.size, s);
+    Slots sl{};
+    sl.p[0] = psiL;
+    sl.p[1] = scaled;
+    sl.p[2] = out;
+    g.launch(GemmPrec::F64, true, sl, s);
+}
+
+}  // namespace pdmrg

@@ -1,0 +1,96 @@
+// Contraction plans: host-built work lists of the grouped GEMM and W-stage
+// launches for H_eff, environment updates and the merge.
+#pragma once
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace pdmrg {
+
+constexpr int kTile = 64;      // GEMM output tile edge
+constexpr int kLcRows = 16;    // W-stage tile rows
+constexpr int kLcCols = 128;   // W-stage tile columns
+
+struct GemmList {
+    bool ta = false, tb = false;
+    std::vector<GemmItem> items;
+    std::vector<GemmSeg> segs;
+    std::vector<GemmTile> tiles;
+    double flops = 0.0;
+    DevBuf d_items, d_segs, d_tiles;
+
+    int add_item(int c_slot, int64_t c_off, int M, int N, int ldc);
+    void add_seg(int a_slot, int64_t a_off, int lda, int b_slot, int64_t b_off, int ldb, int K);
+    void finish(hipStream_t s);   // build tiles, upload
+    void launch(GemmPrec prec, bool c_is_f64, const Slots &sl, hipStream_t s) const;
+    // Throws unless every element an item touches lies inside its slot's
+    // buffer (sizes in elements, per slot).
+    void validate(const std::vector<int64_t> &slot_elems) const;
+};
+
+struct LcList {
+    std::vector<LcTask> tasks;
+    std::vector<LcSrc> srcs;
+    std::vector<LcTile> tiles;
+    double flops = 0.0;
+    int64_t elems_out = 0, elems_in = 0;
+    DevBuf d_tasks, d_srcs, d_tiles;
+
+    int add_task(int dst_slot, int64_t dst_off, int rows, int cols, int ld);
+    void add_src(int slot, int64_t off, int ld, double coef);
+    void finish(hipStream_t s);
+    void launch(bool f64, const Slots &sl, hipStream_t s) const;
+    void validate(const std::vector<int64_t> &slot_elems) const;
+};
+
+// y = H_eff x on bonds (bl, br) -- stage 1: T1 = L x (per ket sector, the
+// MPO channels stacked on M); stage 2: T2 = (W1 W2) T1 (W stage); stage 3:
+// y = T2 R (per output block, the (channel, ket) pairs stacked on K).
+struct HeffPlan {
+    Bond bl, br;
+    Phys p;
+    SiteLayout X;
+    EnvLayout Lt, Rt;
+    int64_t nT1 = 0, nT2 = 0;
+    GemmList g1, g3;
+    LcList w;
+    std::vector<DiagTerm> diag_terms;
+    std::vector<int32_t> diag_groups;
+    int diag_max_rows = 0;
+    void build(const Bond &bl_, const Bond &br_, const Phys &p_, const MpoSite &W1, const MpoSite &W2,
+               hipStream_t s);
+};
+
+// Environment updates (dir +1: L on bl -> L on br; dir -1: R on br -> R on bl).
+struct EnvPlan {
+    int dir = 1;
+    Bond bl, br;
+    Phys p;
+    SiteLayout S;
+    EnvLayout Ein, Eout, Aux;
+    int64_t nU1 = 0, nU2 = 0;
+    GemmList g1, g3;
+    LcList w;
+    void build(int dir_, const Bond &bl_, const Bond &br_, const Phys &p_, const MpoSite &W, hipStream_t s);
+    // slots: 0 env_in, 1 site, 2 env_out, 3 U1, 4 U2
+    void run(GemmPrec prec, const void *env_in, const void *site, void *env_out, void *U1, void *U2,
+             hipStream_t s) const;
+};
+
+// Psi' = psiL V psiR (Eq. eqn:merge).
+struct MergePlan {
+    Bond bl, bm, br;
+    Phys p;
+    SiteLayout SL, SR, X;
+    GemmList g;
+    std::vector<int64_t> rs_base, rs_vbase;
+    std::vector<int32_t> rs_rows, rs_cols;
+    DevBuf d_rs_base, d_rs_vbase, d_rs_rows, d_rs_cols;
+    int rs_max = 0;
+    void build(const Bond &bl_, const Bond &bm_, const Bond &br_, const Phys &p_, hipStream_t s);
+    void run(const double *psiL, const double *V, const double *psiR, double *out, double *scaled,
+             hipStream_t s) const;
+};
+
+std::vector<double> two_site_mpo(const MpoSite &W1, const MpoSite &W2);
+
+}  // namespace pdmrg

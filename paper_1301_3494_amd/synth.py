@@ -81,6 +81,41 @@ def random_mps(N, m, seed, phys_q=SPIN_HALF_Q, q_target=0):
     return bonds, sites
 
 
+def isometric_scale(sites, bonds, phys_q, center):
+    """Haar-random isometries in place of the Gaussian blocks, so that
+    environments built from them stay O(1): a site left of `center` maps each
+    right sector onto orthonormal columns (the Q factor of its Gaussian
+    (a, s) x b stack), a site right of center + 1 has orthonormal rows per
+    left sector.  Sampling only; returns new dicts."""
+    out = []
+    for i, s in enumerate(sites):
+        new = dict(s)
+        if i < center:
+            for qb in sorted({qa + phys_q[k] for (qa, k) in s}):
+                parts = [(qa, k) for (qa, k) in sorted(s) if qa + phys_q[k] == qb]
+                G = np.vstack([s[p] for p in parts])
+                if G.shape[0] >= G.shape[1]:
+                    Q, _ = np.linalg.qr(G)
+                    r0 = 0
+                    for p in parts:
+                        n = s[p].shape[0]
+                        new[p] = Q[r0:r0 + n].copy()
+                        r0 += n
+        elif i > center + 1:
+            for qa in sorted({qa for (qa, k) in s}):
+                parts = [(q, k) for (q, k) in sorted(s, key=lambda t: t[1]) if q == qa]
+                G = np.hstack([s[p] for p in parts])
+                if G.shape[1] >= G.shape[0]:
+                    Q, _ = np.linalg.qr(G.T)
+                    c0 = 0
+                    for p in parts:
+                        n = s[p].shape[1]
+                        new[p] = Q[c0:c0 + n].T.copy()
+                        c0 += n
+        out.append(new)
+    return out
+
+
 def random_two_site_blocks(bl, br, phys_q, rng):
     out = {}
     for qa in sorted(bl):
