@@ -1,0 +1,191 @@
+#!/usr/bin/env python3
+"""Benchmark of the real-space parallel DMRG hot path on one MI355X.
+
+Workload (the metric's microbenchmark configuration): spin-1/2 Heisenberg
+model on an 8 x 4 cylinder (periodic in y, snake ordering, MPO bond
+dimension 14), bond dimension m = 1024, U(1) S^z blocks; the two-site
+effective Hamiltonian at the centre (sites 15, 16, 0-based) with left and
+right environments built on the GPU from a seeded random MPS.
+
+One step = one two-site H_eff matvec y = (L W W R) x in the headline
+precision (FP32 MFMA with FP32 accumulation; FP64 and split-BF16x3 are
+measured beside it).  value = algorithmic block-sparse TFLOP/s of the step
+(U(1)-allowed blocks and nonzero MPO entries only, 2 flops per multiply-add).
+The timed region holds exactly K matvecs between two device synchronisations
+with all inputs resident in HBM.
+
+Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16x3": 2500.0}   # dense MFMA peaks of MI355X
+HBM_PEAK_GBS = 8000.0
+
+
+def build_workload(ctx, pl, synth, np, torch):
+    PQ = (-1, 1)
+    Lx, Ly, m, seed, center = 8, 4, 1024, 2, 15
+    N = Lx * Ly
+    mpo = pl.Mpo("square", Lx, Ly, (1.0, 1.0))
+    bonds, sites = synth.random_mps(N, m, seed)
+    sites = synth.isometric_scale(sites, bonds, PQ, center)
+    P = pl.Phys(PQ)
+
+    def flat_site(i):
+        table, n = pl.layout(pl.SITE, pl.Bond(bonds[i]), pl.Bond(bonds[i + 1]), P)
+        out = np.zeros(n)
+        for key, off, rows, cols, ld in table:
+            b = sites[i][key[:2]]
+            for r in range(rows):
+                out[off + r * ld: off + r * ld + cols] = b[r]
+        return torch.from_numpy(out).cuda()
+
+    L = torch.ones(1, dtype=torch.float64, device="cuda")
+    for i in range(center):
+        _, n = pl.layout(pl.ENV_L, pl.Bond(bonds[i + 1]), deltas=mpo.deltas[i + 1])
+        out = torch.empty(n, dtype=torch.float64, device="cuda")
+        pl.env_update(ctx, 1, pl.Bond(bonds[i]), pl.Bond(bonds[i + 1]), P, mpo.site(i), L, flat_site(i), out)
+        L = out
+    R = torch.ones(1, dtype=torch.float64, device="cuda")
+    for i in range(N - 1, center + 1, -1):
+        _, n = pl.layout(pl.ENV_R, pl.Bond(bonds[i]), deltas=mpo.deltas[i])
+        out = torch.empty(n, dtype=torch.float64, device="cuda")
+        pl.env_update(ctx, -1, pl.Bond(bonds[i]), pl.Bond(bonds[i + 1]), P, mpo.site(i), R, flat_site(i), out)
+        R = out
+    B1, B2 = pl.Bond(bonds[center]), pl.Bond(bonds[center + 2])
+    _, nx = pl.layout(pl.TWO_SITE, B1, B2, P)
+    g = torch.Generator(device="cpu").manual_seed(seed)
+    x = torch.randn(nx, dtype=torch.float64, generator=g)
+    x = (x / x.norm()).cuda()
+    return dict(mpo=mpo, bonds=bonds, center=center, L=L, R=R, x=x, B1=B1, B2=B2, P=P, N=N, m=m)
+
+
+def time_matvecs(ctx, pl, torch, op, x, y, steps, warmup):
+    for _ in range(warmup):
+        op.apply(x, y)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        op.apply(x, y)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    # per-stage durations with HIP events on the library's stream
+    pl.timing(ctx, True)
+    for _ in range(steps):
+        op.apply(x, y)
+    ms, n = pl.timing(ctx)
+    pl.timing(ctx, False)
+    torch.cuda.synchronize()
+    return wall, ms
+
+
+def cpu_baseline(wl, flops, budget_s=12.0):
+    """The oracle's H_eff on the host cores, same block shapes (random blocks)."""
+    import numpy as np
+    from paper_1301_3494_amd import synth
+    from oracle import dmrg
+    from oracle.blocks import Bond
+    c = wl["center"]
+    bonds, mpo = wl["bonds"], wl["mpo"]
+    rng = np.random.default_rng(7)
+    L = synth.random_env_blocks(bonds[c], mpo.deltas[c], rng)
+    R = synth.random_env_blocks(bonds[c + 2], mpo.deltas[c + 2], rng)
+    psi = synth.random_two_site_blocks(bonds[c], bonds[c + 2], (-1, 1), rng)
+    args = (L, R, mpo.W[c], mpo.W[c + 1])
+    bl, br = Bond(bonds[c]), Bond(bonds[c + 2])
+    dmrg.heff_apply(*args, psi, bl, br, (-1, 1), mpo.deltas[c], mpo.deltas[c + 2])   # warm-up
+    n, t0 = 0, time.perf_counter()
+    while time.perf_counter() - t0 < budget_s:
+        dmrg.heff_apply(*args, psi, bl, br, (-1, 1), mpo.deltas[c], mpo.deltas[c + 2])
+        n += 1
+    dt = (time.perf_counter() - t0) / n
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.environ.get("OPENBLAS_NUM_THREADS", os.cpu_count() or 1)))
+    return {"value": round(flops / dt / 1e12, 6), "unit": "TFLOP/s", "cores": threads, "kind": "oracle",
+            "sample": "%d oracle H_eff matvecs (numpy/BLAS FP64) on the same 8x4 m=1024 block shapes, "
+                      "%.3f s each" % (n, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--prec", default="f32", choices=["f64", "f32", "bf16x3"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU only (the regions of one sweep share a device); "
+              "--gpus %d is not supported" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1301_3494_amd import _lib as pl, synth
+
+    ctx = pl.Context(0)
+    wl = build_workload(ctx, pl, synth, np, torch)
+    c = wl["center"]
+    W1, W2 = wl["mpo"].site(c), wl["mpo"].site(c + 1)
+    results = {}
+    y64 = None
+    for name in ("f64", "f32", "bf16x3"):
+        op = pl.Heff(ctx, wl["B1"], wl["B2"], wl["P"], W1, W2, wl["L"], wl["R"], pl.PREC_NAMES[name])
+        info = op.info()
+        y = torch.empty_like(wl["x"])
+        steps = args.steps if name == args.prec else max(10, args.steps // 4)
+        wall, ms = time_matvecs(ctx, pl, torch, op, wl["x"], y, steps, args.warmup)
+        if name == "f64":
+            y64 = y.clone()
+        err = float((y - y64).norm() / y64.norm())
+        results[name] = dict(op=op, info=info, wall=wall, steps=steps, ms=ms, err=err,
+                             tflops=info["flops"] / (wall / steps) / 1e12)
+    r = results[args.prec]
+    info = r["info"]
+    ms_step = r["wall"] / r["steps"] * 1e3
+    # dominant kernel: the slower of the two MFMA stages
+    st = 0 if r["ms"][0] >= r["ms"][2] else 2
+    stage_flops = info["flops_Lpsi"] if st == 0 else info["flops_R"]
+    achieved = stage_flops / (r["ms"][st] * 1e-3) / 1e12
+    peak = PEAK_TFLOPS[args.prec]
+    out = {
+        "metric": "H_eff matvec TFLOP/s (% MFMA peak); sweep s, mixed vs FP64 at 1e-9 rel E",
+        "value": round(r["tflops"], 4),
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": r["steps"],
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.prec,
+        "data": "synthetic (seeded random MPS, environments built on the GPU)",
+        "config": {"workload": "heisenberg_cyl8x4_m1024_centre_heff", "lattice": "8x4 cylinder, snake order",
+                   "m": wl["m"], "mpo_D": int(W1.W.shape[0]), "psi_elems": info["n_psi"],
+                   "flops_per_matvec": info["flops"], "dense_equiv_flops": 4.0 * 14 * 4 * 1024 ** 3},
+        "roofline": {"bound": "mfma", "kernel": "gemm stage %d (%s)" % (st + 1, "L.psi" if st == 0 else "T2.R"),
+                     "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+                     "frac": round(achieved / peak, 4), "traffic": None},
+        "stage_ms": {k: [round(v, 5) for v in results[k]["ms"]] for k in results},
+        "precisions": {k: {"tflops": round(v["tflops"], 3), "ms_per_matvec": round(v["wall"] / v["steps"] * 1e3, 5),
+                           "rel_err_vs_f64": v["err"], "pct_peak": round(100 * v["tflops"] / PEAK_TFLOPS[k], 2)}
+                       for k, v in results.items()},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wl, info["flops"])
+    for v in results.values():
+        v["op"].free()
+    ctx.close()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -111,8 +111,11 @@ const char *pdmrg_version(void);
  * one context per host thread. */
 int pdmrg_ctx_create(int device, void *stream, pdmrg_ctx **out);
 int pdmrg_ctx_destroy(pdmrg_ctx *ctx);
-/* Average duration (ms) of the last heff_apply stage kernels, measured with
- * HIP events on the context's stream when timing is enabled. */
+/* H_eff stage timing: while enabled, every heff_apply records HIP events on
+ * the context's stream around its three stages (no synchronisation);
+ * pdmrg_ctx_timing waits for the last one and returns the average duration
+ * (ms) of stage 1 (L psi), 2 (W), 3 (. R) and their sum over the calls since
+ * timing was enabled. */
 int pdmrg_ctx_set_timing(pdmrg_ctx *ctx, int enable);
 int pdmrg_ctx_timing(pdmrg_ctx *ctx, double *ms_stage /*[4]: L.psi, W, .R, total*/,
                      int64_t *n_calls);

@@ -289,3 +289,87 @@ def timing(ctx, enable=None):
     n = c_int64()
     check(lib().pdmrg_ctx_timing(ctx.h, ms, byref(n)))
     return list(ms), n.value
+
+
+LATTICES = {"chain": 0, "square": 1, "triangular": 2, "jq2": 3, "tfim": 4}
+
+
+class Mpo:
+    """mpo_build (or mpo_from_sites) handle with its site tensors exported."""
+
+    def __init__(self, lattice=None, Lx=None, Ly=1, couplings=(1.0, 1.0), sites=None):
+        L = lib()
+        h = c_void_p()
+        if sites is not None:
+            arr = (CMpoSite * len(sites))(*[s.c for s in sites])
+            self._keep = sites
+            check(L.mpo_from_sites(len(sites), arr, byref(h)))
+        else:
+            cc = (c_double * len(couplings))(*couplings)
+            check(L.mpo_build(LATTICES.get(lattice, lattice), int(Lx), int(Ly), cc, len(couplings), byref(h)))
+        self.h = h
+        n, d = c_int32(), c_int32()
+        check(L.mpo_info(h, byref(n), byref(d), None, None))
+        self.N, self.d = n.value, d.value
+        D = np.zeros(self.N + 1, np.int32)
+        pq = np.zeros(self.d, np.int32)
+        check(L.mpo_info(h, None, None, pq.ctypes.data_as(POINTER(c_int32)), D.ctypes.data_as(POINTER(c_int32))))
+        self.D, self.phys_q = D, tuple(int(v) for v in pq)
+        self.W, self.deltas = [], []
+        for i in range(self.N):
+            W = np.zeros((D[i], self.d, self.d, D[i + 1]))
+            dl = np.zeros(D[i], np.int32)
+            dr = np.zeros(D[i + 1], np.int32)
+            check(L.mpo_get_site(h, i, W.ctypes.data_as(POINTER(c_double)), dl.ctypes.data_as(POINTER(c_int32)),
+                                 dr.ctypes.data_as(POINTER(c_int32))))
+            self.W.append(W)
+            self.deltas.append(dl)
+        self.deltas.append(dr)
+
+    def site(self, i):
+        return MpoSite(self.W[i], self.deltas[i], self.deltas[i + 1])
+
+    def free(self):
+        if self.h:
+            lib().mpo_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class SvdResult:
+    """svd_truncate handle: new bond, discarded weight, and output tensors."""
+
+    def __init__(self, ctx, bl, br, phys, psi, max_m, cutoff=1e-12, eps=1e-4, mode=ABSORB_RIGHT):
+        import torch
+        self.ctx = ctx
+        h = c_void_p()
+        self.code = check(lib().svd_truncate(ctx.h, bl.ref, br.ref, phys.ref, ptr(psi), int(max_m), float(cutoff),
+                                             float(eps), int(mode), byref(h)), allow_warn=True)
+        self.h = h
+        n = c_int32()
+        disc, nf = c_double(), c_int32()
+        check(lib().svd_result_bond(h, byref(n), None, None, 0, byref(disc), byref(nf)))
+        q = np.zeros(max(n.value, 1), np.int32)
+        d = np.zeros(max(n.value, 1), np.int32)
+        check(lib().svd_result_bond(h, None, q.ctypes.data_as(POINTER(c_int32)), d.ctypes.data_as(POINTER(c_int32)),
+                                    n.value, None, None))
+        self.bond = {int(a): int(b) for a, b in zip(q[:n.value], d[:n.value])}
+        self.discarded, self.n_floored = disc.value, nf.value
+        B = Bond(self.bond)
+        _, na = layout(SITE, bl, B, phys)
+        _, nb = layout(SITE, B, br, phys)
+        mk = lambda k: torch.empty(max(k, 1), dtype=torch.float64, device="cuda")
+        self.A, self.B, self.left, self.right = mk(na), mk(nb), mk(na), mk(nb)
+        m = sum(self.bond.values())
+        self.lam = np.zeros(max(m, 1))
+        self.V = np.zeros(max(m, 1))
+        check(lib().svd_result_copy(ctx.h, h, ptr(self.A), ptr(self.B), ptr(self.left), ptr(self.right),
+                                    self.lam.ctypes.data_as(POINTER(c_double)), self.V.ctypes.data_as(POINTER(c_double))))
+        self.lam, self.V = self.lam[:m], self.V[:m]
+        lib().svd_free(h)
+        self.h = None

@@ -42,7 +42,6 @@ int pdmrg_ctx_create(int device, void *stream, pdmrg_ctx **out) {
     auto *c = new pdmrg_ctx();
     c->device = device;
     c->stream = static_cast<hipStream_t>(stream);
-    for (auto &e : c->ev) HIP_OK(hipEventCreate(&e));
     *out = c;
     API_END
 }
@@ -51,8 +50,7 @@ int pdmrg_ctx_destroy(pdmrg_ctx *ctx) {
     API_BEGIN
     if (!ctx) return PDMRG_OK;
     (void)hipStreamSynchronize(ctx->stream);
-    for (auto &e : ctx->ev)
-        if (e) (void)hipEventDestroy(e);
+    for (auto &e : ctx->ev_pool) (void)hipEventDestroy(e);
     delete ctx;
     API_END
 }
@@ -61,7 +59,6 @@ int pdmrg_ctx_set_timing(pdmrg_ctx *ctx, int enable) {
     API_BEGIN
     PD_REQUIRE(ctx, PDMRG_EINVAL, "null ctx");
     ctx->timing = enable != 0;
-    for (double &v : ctx->stage_ms) v = 0.0;
     ctx->n_timed = 0;
     API_END
 }
@@ -69,8 +66,21 @@ int pdmrg_ctx_set_timing(pdmrg_ctx *ctx, int enable) {
 int pdmrg_ctx_timing(pdmrg_ctx *ctx, double *ms_stage, int64_t *n_calls) {
     API_BEGIN
     PD_REQUIRE(ctx && ms_stage && n_calls, PDMRG_EINVAL, "null argument");
+    double acc[4] = {0, 0, 0, 0};
+    if (ctx->n_timed > 0) {
+        HIP_OK(hipEventSynchronize(ctx->ev_pool[(size_t)ctx->n_timed * 4 - 1]));
+        for (int64_t c = 0; c < ctx->n_timed; ++c) {
+            hipEvent_t *e = &ctx->ev_pool[(size_t)c * 4];
+            for (int k = 0; k < 3; ++k) {
+                float ms = 0.f;
+                HIP_OK(hipEventElapsedTime(&ms, e[k], e[k + 1]));
+                acc[k] += ms;
+                acc[3] += ms;
+            }
+        }
+    }
     *n_calls = ctx->n_timed;
-    for (int i = 0; i < 4; ++i) ms_stage[i] = ctx->n_timed ? ctx->stage_ms[i] / ctx->n_timed : 0.0;
+    for (int i = 0; i < 4; ++i) ms_stage[i] = ctx->n_timed ? acc[i] / ctx->n_timed : 0.0;
     API_END
 }
 
@@ -304,5 +314,65 @@ int merge_regions(pdmrg_ctx *ctx, const pdmrg_bond *bl, const pdmrg_bond *bm, co
     HIP_OK(hipStreamSynchronize(ctx->stream));
     API_END
 }
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ SVD
+extern "C" {
+
+int svd_truncate(pdmrg_ctx *ctx, const pdmrg_bond *bl, const pdmrg_bond *br, const pdmrg_phys *phys,
+                 const double *psi_dev, int32_t max_m, double cutoff, double eps, int mode, pdmrg_svd **out) {
+    API_BEGIN
+    PD_REQUIRE(ctx && psi_dev && out, PDMRG_EINVAL, "svd_truncate: null argument");
+    PD_REQUIRE(cutoff >= 0.0 && eps >= 0.0 && eps < 1.0, PDMRG_EINVAL, "svd_truncate: bad cutoff / eps");
+    auto r = std::make_unique<pdmrg_svd>();
+    svd_truncate_run(ctx, Bond::from(bl), Bond::from(br), Phys::from(phys), psi_dev, max_m, cutoff, eps, mode, r->r);
+    const bool floored = mode == PDMRG_SPLIT && r->r.n_floored > 0;
+    *out = r.release();
+    if (floored) {
+        pdmrg::set_last_error("svd_truncate: some V entries were floored");
+        return PDMRG_WARN_V_FLOORED;
+    }
+    API_END
+}
+
+int svd_result_bond(const pdmrg_svd *res, int32_t *nsec, int32_t *q, int32_t *dim, int32_t nsec_max,
+                    double *discarded, int32_t *n_floored) {
+    API_BEGIN
+    PD_REQUIRE(res, PDMRG_EINVAL, "svd_result_bond: null result");
+    const Bond &b = res->r.bnew;
+    if (nsec) *nsec = b.nsec();
+    if (q || dim) {
+        PD_REQUIRE(nsec_max >= b.nsec(), PDMRG_EINVAL, "svd_result_bond: capacity too small");
+        for (int k = 0; k < b.nsec(); ++k) {
+            if (q) q[k] = b.q[k];
+            if (dim) dim[k] = b.dim[k];
+        }
+    }
+    if (discarded) *discarded = res->r.discarded;
+    if (n_floored) *n_floored = res->r.n_floored;
+    API_END
+}
+
+int svd_result_copy(pdmrg_ctx *ctx, const pdmrg_svd *res, double *A_dev, double *B_dev, double *left_dev,
+                    double *right_dev, double *lam_host, double *V_host) {
+    API_BEGIN
+    PD_REQUIRE(ctx && res, PDMRG_EINVAL, "svd_result_copy: null argument");
+    const SvdOut &r = res->r;
+    const int64_t na = site_layout(r.bl, r.bnew, r.p).size, nb = site_layout(r.bnew, r.br, r.p).size;
+    auto cp = [&](double *dst, const DevBuf &src, int64_t n) {
+        if (dst && n) HIP_OK(hipMemcpyAsync(dst, src.ptr, n * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+    };
+    cp(A_dev, r.A, na);
+    cp(B_dev, r.B, nb);
+    cp(left_dev, r.mode == PDMRG_ABSORB_RIGHT ? r.A : r.left, na);
+    cp(right_dev, r.mode == PDMRG_ABSORB_LEFT ? r.B : r.right, nb);
+    if (lam_host) std::copy(r.lam.begin(), r.lam.end(), lam_host);
+    if (V_host) std::copy(r.V.begin(), r.V.end(), V_host);
+    HIP_OK(hipStreamSynchronize(ctx->stream));
+    API_END
+}
+
+void svd_free(pdmrg_svd *res) { delete res; }
 
 }  // extern "C"

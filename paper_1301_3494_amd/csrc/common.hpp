@@ -124,10 +124,12 @@ void upload(DevBuf &buf, const std::vector<T> &v, hipStream_t s) {
 struct pdmrg_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
+    // H_eff stage timing: 4 events per heff_apply (before stage 1, 2, 3, after),
+    // recorded without synchronisation and summed when queried.
     bool timing = false;
-    double stage_ms[4] = {0, 0, 0, 0};
+    std::vector<hipEvent_t> ev_pool;
     int64_t n_timed = 0;
-    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    double stage_ms[4] = {0, 0, 0, 0};
     pdmrg::DevBuf ws_dav;           // Davidson basis and scalars
     pdmrg::DevBuf ws_env;           // environment-update intermediates
     pdmrg::DevBuf ws_merge;         // merge: V-scaled right tensor

@@ -10,9 +10,11 @@
 //
 // Mixed precision (operator in FP32 / BF16x3 with an FP64 operator op64):
 // the first basis vector's product H x is always taken in FP64 and every
-// restart recomputes it, so the low-precision error enters only through the
-// correction directions, whose weight shrinks as the iteration converges.
-// Convergence is declared on the FP64 residual of the restarted vector.
+// restart recomputes it; the coupling of x to the correction directions
+// t_k is taken from that exact product (t_k . H x), so the low-precision
+// error enters only through the t_k . H~ t_j block, whose weight in the Ritz
+// vector shrinks quadratically with the correction.  Convergence is declared
+// on the FP64 residual of the restarted vector.
 #include "internal.hpp"
 
 #include <cmath>
@@ -80,6 +82,11 @@ DavResult davidson_run(pdmrg_ctx *ctx, pdmrg_heff *op, pdmrg_heff *op64, double 
     auto extend_G = [&](int k) {
         dot_into(w.V, k + 1, w.HV + (size_t)k * n, w.G + k, ks);          // column k
         if (k > 0) dot_into(w.HV, k, w.V + (size_t)k * n, w.G + (size_t)k * ks);   // row k
+        // Mixed precision: G[0][k] = x . H~ t_k carries the low-precision error
+        // ~eps |H| whatever the size of the correction, while G[k][0] = t_k . H x
+        // uses the exact FP64 product; take the exact one for both.
+        if (refine && k > 0)
+            HIP_OK(hipMemcpyAsync(w.G + k, w.G + (size_t)k * ks, sizeof(double), hipMemcpyDeviceToDevice, s));
     };
 
     // V0 = psi / |psi|

@@ -67,25 +67,24 @@ void heff_run(pdmrg_ctx *ctx, pdmrg_heff *op, const double *x, double *y) {
     sl.p[3] = op->R.ptr;
     sl.p[4] = op->T1.ptr;
     sl.p[5] = op->T2.ptr;
-    if (ctx->timing) HIP_OK(hipEventRecord(ctx->ev[0], s));
-    pl.g1.launch(gp, f64, sl, s);
-    if (ctx->timing) HIP_OK(hipEventRecord(ctx->ev[1], s));
-    pl.w.launch(f64, sl, s);
-    if (ctx->timing) HIP_OK(hipEventRecord(ctx->ev[2], s));
-    pl.g3.launch(gp, true, sl, s);
+    hipEvent_t *ev = nullptr;
     if (ctx->timing) {
-        HIP_OK(hipEventRecord(ctx->ev[3], s));
-        HIP_OK(hipEventSynchronize(ctx->ev[3]));
-        float a = 0, b = 0, c = 0;
-        HIP_OK(hipEventElapsedTime(&a, ctx->ev[0], ctx->ev[1]));
-        HIP_OK(hipEventElapsedTime(&b, ctx->ev[1], ctx->ev[2]));
-        HIP_OK(hipEventElapsedTime(&c, ctx->ev[2], ctx->ev[3]));
-        ctx->stage_ms[0] += a;
-        ctx->stage_ms[1] += b;
-        ctx->stage_ms[2] += c;
-        ctx->stage_ms[3] += a + b + c;
+        const size_t need = (size_t)(ctx->n_timed + 1) * 4;
+        while (ctx->ev_pool.size() < need) {
+            hipEvent_t e;
+            HIP_OK(hipEventCreate(&e));
+            ctx->ev_pool.push_back(e);
+        }
+        ev = &ctx->ev_pool[(size_t)ctx->n_timed * 4];
         ctx->n_timed += 1;
+        HIP_OK(hipEventRecord(ev[0], s));
     }
+    pl.g1.launch(gp, f64, sl, s);
+    if (ev) HIP_OK(hipEventRecord(ev[1], s));
+    pl.w.launch(f64, sl, s);
+    if (ev) HIP_OK(hipEventRecord(ev[2], s));
+    pl.g3.launch(gp, true, sl, s);
+    if (ev) HIP_OK(hipEventRecord(ev[3], s));
 }
 
 }  // namespace pdmrg

@@ -10,15 +10,6 @@ static int not_built(const char *name) {
 }
 
 extern "C" {
-int svd_truncate(pdmrg_ctx *, const pdmrg_bond *, const pdmrg_bond *, const pdmrg_phys *, const double *, int32_t,
-                 double, double, int, pdmrg_svd **) { return not_built("svd_truncate"); }
-int svd_result_bond(const pdmrg_svd *, int32_t *, int32_t *, int32_t *, int32_t, double *, int32_t *) {
-    return not_built("svd_result_bond");
-}
-int svd_result_copy(pdmrg_ctx *, const pdmrg_svd *, double *, double *, double *, double *, double *, double *) {
-    return not_built("svd_result_copy");
-}
-void svd_free(pdmrg_svd *) {}
 int mps_alloc(pdmrg_ctx *, int, const pdmrg_phys *, int32_t, const pdmrg_bond *, pdmrg_mps **) {
     return not_built("mps_alloc");
 }

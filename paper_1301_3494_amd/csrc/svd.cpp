@@ -1,0 +1,515 @@
+// Truncated SVD of the two-site wavefunction (Eq. eqn:svd) with the accurate
+// recursive SVD of the Appendix, on the device.
+//
+// Psi viewed as the (m d) x (d m) matrix is block-diagonal in the middle
+// charge; each block M (rows (s1, a), columns (s2, b)) is gathered densely and
+// decomposed M = U Lambda Vt by one-sided block Jacobi (svd.hip).  Appendix
+// recursion: for the singular values of a block below eps * lambda_1 (indices
+// p..k-1), X = Ut[p:] M Vt[p:]^T is formed with FP64 GEMMs and decomposed the
+// same way (recursively), then Ut[p:] <- Ut~ Ut[p:], Vt[p:] <- Vt~ Vt[p:],
+// lambda[p:] <- lambda~ and the block is re-sorted.  Truncation keeps the
+// max_m largest values over all blocks (ties: larger value, smaller charge,
+// smaller index), drops lambda < cutoff * lambda_max, renormalises.
+#include "internal.hpp"
+#include "svd.hpp"
+
+#include <cmath>
+#include <numeric>
+#include <tuple>
+
+namespace pdmrg {
+
+namespace {
+
+constexpr int kJacBlock = 8;
+constexpr int kMaxSweeps = 40;
+constexpr int kMaxDepth = 8;
+
+struct Arena {
+    std::shared_ptr<DevBuf> buf = std::make_shared<DevBuf>();
+    size_t cap = 0, used = 0;
+    void reserve(size_t ndoubles) {
+        buf->ensure(std::max<size_t>(ndoubles, 32) * sizeof(double));
+        cap = buf->bytes / sizeof(double);
+        used = 0;
+    }
+    double *take(size_t n) {
+        n = (n + 31) & ~size_t(31);
+        PD_REQUIRE(used + n <= cap, PDMRG_ENOMEM, "svd: arena overflow");
+        double *p = buf->as<double>() + used;
+        used += n;
+        return p;
+    }
+    double *base() const { return buf->as<double>(); }
+};
+
+struct Mat {
+    const double *M;   // device, row-major, ld = nc
+    int nr, nc;
+};
+
+struct SvdRes {
+    double *Ut = nullptr, *Vt = nullptr;   // k x nr, k x nc (device)
+    std::vector<double> lam;               // k, descending
+    int k = 0, nr = 0, nc = 0;
+};
+
+size_t round32(size_t n) { return (n + 31) & ~size_t(31); }
+
+void run_copies(const std::vector<CopyTask> &tasks, hipStream_t s) {
+    if (tasks.empty()) return;
+    DevBuf d;
+    upload(d, tasks, s);
+    int64_t mx = 0;
+    for (auto &t : tasks) mx = std::max<int64_t>(mx, (int64_t)t.rows * t.cols);
+    launch_copies(d.as<CopyTask>(), (int)tasks.size(), mx, s);
+    HIP_OK(hipStreamSynchronize(s));   // d is freed on return
+}
+
+// One-sided block Jacobi on every matrix; returns sorted factors in `arena`.
+void svd_batch(pdmrg_ctx *ctx, const std::vector<Mat> &mats, std::vector<SvdRes> &out, double eps, int depth,
+               std::vector<Arena> &keep) {
+    hipStream_t s = ctx->stream;
+    const int nm = (int)mats.size();
+    out.assign(nm, SvdRes());
+    if (nm == 0) return;
+    Arena ar;
+    size_t need = 64;
+    for (const Mat &m : mats) {
+        const size_t nv = std::min(m.nr, m.nc), len = std::max(m.nr, m.nc);
+        need += round32(nv * len) + round32(nv * nv) + round32(nv * m.nr) + round32(nv * m.nc) + round32(nv) + 96;
+    }
+    ar.reserve(need);
+    std::vector<JacItem> items(nm);
+    std::vector<CopyTask> cp;
+    for (int i = 0; i < nm; ++i) {
+        const Mat &m = mats[i];
+        const bool wide = m.nr <= m.nc;
+        const int nv = std::min(m.nr, m.nc), len = std::max(m.nr, m.nc);
+        items[i].nv = nv;
+        items[i].len = len;
+        items[i].W = ar.take((size_t)nv * len);
+        items[i].Z = ar.take((size_t)nv * nv);
+        out[i].nr = m.nr;
+        out[i].nc = m.nc;
+        out[i].k = nv;
+        out[i].Ut = ar.take((size_t)nv * m.nr);
+        out[i].Vt = ar.take((size_t)nv * m.nc);
+        CopyTask t{};
+        t.src = m.M;
+        t.dst = items[i].W;
+        t.rows = nv;
+        t.cols = len;
+        t.sld = m.nc;
+        t.dld = len;
+        t.trans = wide ? 0 : 1;   // tall: W = M^T
+        cp.push_back(t);
+    }
+    run_copies(cp, s);
+    DevBuf d_items;
+    upload(d_items, items, s);
+    int max_nv = 0;
+    for (auto &it : items) max_nv = std::max(max_nv, it.nv);
+    launch_identity(d_items.as<JacItem>(), nm, max_nv, s);
+
+    // circle schedule over blocks of 8 rows
+    std::vector<int> nblk(nm);
+    int rmax = 0;
+    for (int i = 0; i < nm; ++i) {
+        int nb = std::max(2, (items[i].nv + kJacBlock - 1) / kJacBlock);
+        if (nb % 2) ++nb;
+        nblk[i] = nb;
+        rmax = std::max(rmax, nb - 1);
+    }
+    std::vector<std::vector<JacPair>> rounds(rmax);
+    for (int i = 0; i < nm; ++i) {
+        const int nb = nblk[i], real = (items[i].nv + kJacBlock - 1) / kJacBlock;
+        for (int r = 0; r < nb - 1; ++r)
+            for (int l = 0; l < nb / 2; ++l) {
+                const int p = (l == 0) ? nb - 1 : (r + l) % (nb - 1);
+                const int q = (r - l + (nb - 1)) % (nb - 1);
+                if (p >= real && q >= real) continue;
+                rounds[r].push_back(JacPair{i, std::min(p, q), std::max(p, q), 0});
+            }
+    }
+    std::vector<JacPair> flat;
+    std::vector<int> roff(rmax + 1, 0);
+    for (int r = 0; r < rmax; ++r) {
+        roff[r] = (int)flat.size();
+        flat.insert(flat.end(), rounds[r].begin(), rounds[r].end());
+    }
+    roff[rmax] = (int)flat.size();
+    DevBuf d_pairs, d_active, d_off;
+    upload(d_pairs, flat, s);
+    std::vector<int32_t> active(nm, 1);
+    d_off.ensure(std::max(nm, 1) * sizeof(unsigned long long));
+    std::vector<double> tol(nm);
+    for (int i = 0; i < nm; ++i) tol[i] = std::max(1e-14, 8.0 * 2.220446049250313e-16 * std::sqrt((double)items[i].len));
+    double tol_all = *std::max_element(tol.begin(), tol.end());
+    for (int sweep = 0; sweep < kMaxSweeps; ++sweep) {
+        upload(d_active, active, s);
+        launch_fill(d_off.as<double>(), 0.0, nm, s);
+        for (int r = 0; r < rmax; ++r)
+            launch_jac_round(d_items.as<JacItem>(), d_pairs.as<JacPair>() + roff[r], roff[r + 1] - roff[r],
+                             d_active.as<int32_t>(), d_off.as<unsigned long long>(), tol_all, s);
+        std::vector<double> off(nm);
+        HIP_OK(hipMemcpyAsync(off.data(), d_off.ptr, nm * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_OK(hipStreamSynchronize(s));
+        bool any = false;
+        for (int i = 0; i < nm; ++i) {
+            if (active[i] && off[i] <= tol_all) active[i] = 0;
+            any = any || active[i];
+        }
+        if (!any) break;
+    }
+
+    // singular values = row norms
+    std::vector<RowRef> refs;
+    std::vector<int> first(nm + 1, 0);
+    for (int i = 0; i < nm; ++i) {
+        first[i] = (int)refs.size();
+        for (int r = 0; r < items[i].nv; ++r) refs.push_back(RowRef{items[i].W + (size_t)r * items[i].len, items[i].len, 0});
+    }
+    first[nm] = (int)refs.size();
+    DevBuf d_refs, d_norm;
+    upload(d_refs, refs, s);
+    d_norm.ensure(std::max<size_t>(refs.size(), 1) * sizeof(double));
+    launch_row_norms(d_refs.as<RowRef>(), (int)refs.size(), d_norm.as<double>(), s);
+    std::vector<double> norms(refs.size());
+    if (!refs.empty())
+        HIP_OK(hipMemcpyAsync(norms.data(), d_norm.ptr, refs.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+
+    // sorted factors: wide Ut = Z rows, Vt = W rows / lambda; tall the reverse
+    std::vector<double> scales;
+    std::vector<CopyTask> gt;
+    std::vector<std::tuple<const double *, double *, int, int>> rowjobs;   // src, dst, len, scale index
+    for (int i = 0; i < nm; ++i) {
+        const int nv = items[i].nv;
+        std::vector<int> perm(nv);
+        std::iota(perm.begin(), perm.end(), 0);
+        std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) { return norms[first[i] + a] > norms[first[i] + b]; });
+        const bool wide = mats[i].nr <= mats[i].nc;
+        out[i].lam.resize(nv);
+        for (int j = 0; j < nv; ++j) {
+            const double l = norms[first[i] + perm[j]];
+            out[i].lam[j] = l;
+            const double *wrow = items[i].W + (size_t)perm[j] * items[i].len;
+            const double *zrow = items[i].Z + (size_t)perm[j] * nv;
+            const double inv = l > 0.0 ? 1.0 / l : 0.0;
+            if (wide) {
+                rowjobs.emplace_back(zrow, out[i].Ut + (size_t)j * mats[i].nr, nv, (int)scales.size());
+                scales.push_back(1.0);
+                rowjobs.emplace_back(wrow, out[i].Vt + (size_t)j * mats[i].nc, items[i].len, (int)scales.size());
+                scales.push_back(inv);
+            } else {
+                rowjobs.emplace_back(wrow, out[i].Ut + (size_t)j * mats[i].nr, items[i].len, (int)scales.size());
+                scales.push_back(inv);
+                rowjobs.emplace_back(zrow, out[i].Vt + (size_t)j * mats[i].nc, nv, (int)scales.size());
+                scales.push_back(1.0);
+            }
+        }
+    }
+    DevBuf d_scales;
+    upload(d_scales, scales, s);
+    for (auto &[src, dst, len, si] : rowjobs) {
+        CopyTask t{};
+        t.src = src;
+        t.dst = dst;
+        t.rows = 1;
+        t.cols = len;
+        t.sld = len;
+        t.dld = len;
+        t.rscale = d_scales.as<double>() + si;
+        gt.push_back(t);
+    }
+    run_copies(gt, s);
+
+    // Appendix recursion on the trailing singular values
+    if (depth < kMaxDepth) {
+        std::vector<int> who, pstart;
+        for (int i = 0; i < nm; ++i) {
+            const auto &l = out[i].lam;
+            if (l.empty() || !(l[0] > 0.0)) continue;
+            int p = -1;
+            for (int j = 0; j < (int)l.size(); ++j)
+                if (l[j] < eps * l[0]) { p = j; break; }
+            if (p < 0) continue;
+            who.push_back(i);
+            pstart.push_back(p);
+        }
+        if (!who.empty()) {
+            Arena sub;
+            size_t need2 = 64;
+            for (size_t w = 0; w < who.size(); ++w) {
+                const SvdRes &o = out[who[w]];
+                const size_t t = o.k - pstart[w];
+                need2 += round32(t * o.nc) + round32(t * t) + round32(t * std::max(o.nr, o.nc)) + 64;
+            }
+            sub.reserve(need2);
+            // slots: 0 current arena (Ut, Vt, M lives elsewhere -> slot 2), 1 sub arena
+            GemmList gy, gx;
+            gx.tb = true;
+            std::vector<Mat> subs;
+            std::vector<double *> Y(who.size()), X(who.size()), T(who.size());
+            const double *Mbase = mats[0].M;
+            for (const Mat &m : mats) Mbase = std::min(Mbase, m.M);
+            for (size_t w = 0; w < who.size(); ++w) {
+                const SvdRes &o = out[who[w]];
+                const int p = pstart[w], t = o.k - p;
+                Y[w] = sub.take((size_t)t * o.nc);
+                X[w] = sub.take((size_t)t * t);
+                T[w] = sub.take((size_t)t * std::max(o.nr, o.nc));
+                // Y = Ut[p:] (t x nr) M (nr x nc)
+                gy.add_item(1, Y[w] - sub.base(), t, o.nc, o.nc);
+                gy.add_seg(0, (o.Ut + (size_t)p * o.nr) - ar.base(), o.nr, 2, mats[who[w]].M - Mbase, o.nc, o.nr);
+                // X = Y Vt[p:]^T (t x t)
+                gx.add_item(1, X[w] - sub.base(), t, t, t);
+                gx.add_seg(1, Y[w] - sub.base(), o.nc, 0, (o.Vt + (size_t)p * o.nc) - ar.base(), o.nc, o.nc);
+                subs.push_back(Mat{X[w], t, t});
+            }
+            Slots sl{};
+            sl.p[0] = ar.base();
+            sl.p[1] = sub.base();
+            sl.p[2] = Mbase;
+            gy.finish(s);
+            gy.launch(GemmPrec::F64, true, sl, s);
+            gx.finish(s);
+            gx.launch(GemmPrec::F64, true, sl, s);
+            HIP_OK(hipStreamSynchronize(s));
+            std::vector<SvdRes> so;
+            svd_batch(ctx, subs, so, eps, depth + 1, keep);
+            // Ut[p:] <- Ut~ Ut[p:] ; Vt[p:] <- Vt~ Vt[p:]  (via T, then copy back)
+            const double *SB = so[0].Ut;
+            for (auto &r : so) SB = std::min<const double *>(SB, std::min(r.Ut, r.Vt));
+            std::vector<CopyTask> back;
+            for (int pass = 0; pass < 2; ++pass) {
+                GemmList gu;
+                for (size_t w = 0; w < who.size(); ++w) {
+                    SvdRes &o = out[who[w]];
+                    const int p = pstart[w], t = o.k - p;
+                    const int len = pass == 0 ? o.nr : o.nc;
+                    double *base = pass == 0 ? o.Ut : o.Vt;
+                    const double *small = pass == 0 ? so[w].Ut : so[w].Vt;
+                    gu.add_item(1, T[w] - sub.base(), t, len, len);
+                    gu.add_seg(3, small - SB, t, 0, (base + (size_t)p * len) - ar.base(), len, t);
+                    CopyTask c{};
+                    c.src = T[w];
+                    c.dst = base + (size_t)p * len;
+                    c.rows = t;
+                    c.cols = len;
+                    c.sld = len;
+                    c.dld = len;
+                    back.push_back(c);
+                }
+                Slots s2{};
+                s2.p[0] = ar.base();
+                s2.p[1] = sub.base();
+                s2.p[3] = SB;
+                gu.finish(s);
+                gu.launch(GemmPrec::F64, true, s2, s);
+                run_copies(back, s);
+                back.clear();
+            }
+            // new trailing values; re-sort each block
+            std::vector<CopyTask> perm_tasks, perm_back;
+            for (size_t w = 0; w < who.size(); ++w) {
+                SvdRes &o = out[who[w]];
+                const int p = pstart[w];
+                for (int j = p; j < o.k; ++j) o.lam[j] = so[w].lam[j - p];
+                std::vector<int> perm(o.k);
+                std::iota(perm.begin(), perm.end(), 0);
+                std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) { return o.lam[a] > o.lam[b]; });
+                bool same = true;
+                for (int j = 0; j < o.k; ++j) same = same && perm[j] == j;
+                if (same) continue;
+                std::vector<double> nl(o.k);
+                for (int j = 0; j < o.k; ++j) nl[j] = o.lam[perm[j]];
+                o.lam = nl;
+                // stage into T-sized scratch: reuse a fresh buffer
+                auto tmp = std::make_shared<DevBuf>((size_t)o.k * (o.nr + o.nc) * sizeof(double));
+                keep.push_back(Arena{tmp, 0, 0});
+                double *tu = tmp->as<double>(), *tv = tu + (size_t)o.k * o.nr;
+                for (int j = 0; j < o.k; ++j) {
+                    perm_tasks.push_back(CopyTask{o.Ut + (size_t)perm[j] * o.nr, tu + (size_t)j * o.nr, nullptr, nullptr,
+                                                  1, o.nr, o.nr, o.nr, 0, 0});
+                    perm_tasks.push_back(CopyTask{o.Vt + (size_t)perm[j] * o.nc, tv + (size_t)j * o.nc, nullptr, nullptr,
+                                                  1, o.nc, o.nc, o.nc, 0, 0});
+                }
+                perm_back.push_back(CopyTask{tu, o.Ut, nullptr, nullptr, o.k, o.nr, o.nr, o.nr, 0, 0});
+                perm_back.push_back(CopyTask{tv, o.Vt, nullptr, nullptr, o.k, o.nc, o.nc, o.nc, 0, 0});
+            }
+            run_copies(perm_tasks, s);
+            run_copies(perm_back, s);
+            keep.push_back(sub);
+        }
+    }
+    keep.push_back(ar);
+}
+
+}  // namespace
+
+void svd_truncate_run(pdmrg_ctx *ctx, const Bond &bl, const Bond &br, const Phys &p, const double *psi, int max_m,
+                      double cutoff, double eps, int mode, SvdOut &out) {
+    hipStream_t s = ctx->stream;
+    PD_REQUIRE(mode >= 0 && mode <= 2, PDMRG_EINVAL, "svd_truncate: bad mode");
+    PD_REQUIRE(max_m >= 1, PDMRG_EINVAL, "svd_truncate: max_m must be >= 1");
+    const int d = p.d();
+    const SiteLayout X = two_site_layout(bl, br, p);
+    // middle-charge blocks
+    std::vector<int> mids;
+    for (int i = 0; i < bl.nsec(); ++i)
+        for (int s1 = 0; s1 < d; ++s1) mids.push_back(bl.q[i] + p.q[s1]);
+    std::sort(mids.begin(), mids.end());
+    mids.erase(std::unique(mids.begin(), mids.end()), mids.end());
+    struct Sec {
+        int qm, nr = 0, nc = 0;
+        std::vector<std::pair<int, int>> rows;   // (s1, i)
+        std::vector<std::pair<int, int>> cols;   // (s2, k)
+        const double *M = nullptr;
+    };
+    std::vector<Sec> secs;
+    for (int qm : mids) {
+        Sec sc;
+        sc.qm = qm;
+        for (int s2 = 0; s2 < d; ++s2) {
+            const int k = br.find(qm + p.q[s2]);
+            if (k >= 0) { sc.cols.push_back({s2, k}); sc.nc += br.dim[k]; }
+        }
+        for (int s1 = 0; s1 < d; ++s1) {
+            const int i = bl.find(qm - p.q[s1]);
+            if (i >= 0 && sc.nc > 0) { sc.rows.push_back({s1, i}); sc.nr += bl.dim[i]; }
+        }
+        if (sc.nr > 0 && sc.nc > 0) secs.push_back(sc);
+    }
+    size_t need = 64;
+    for (auto &sc : secs) need += round32((size_t)sc.nr * sc.nc);
+    ctx->ws_svd.ensure(need * sizeof(double));
+    double *mbase = ctx->ws_svd.as<double>();
+    size_t off = 0;
+    std::vector<CopyTask> gather;
+    std::vector<Mat> mats;
+    for (auto &sc : secs) {
+        double *M = mbase + off;
+        off += round32((size_t)sc.nr * sc.nc);
+        sc.M = M;
+        int r0 = 0;
+        for (auto [s1, i] : sc.rows) {
+            int col0 = -1;
+            for (auto [s2, k] : sc.cols) {
+                const int co = X.colo[(size_t)i * d * d + s1 * d + s2];
+                PD_REQUIRE(co >= 0, PDMRG_ESHAPE, "svd_truncate: missing block");
+                if (col0 < 0) col0 = co;
+            }
+            CopyTask t{};
+            t.src = psi + X.base[i] + col0;
+            t.dst = M + (size_t)r0 * sc.nc;
+            t.rows = bl.dim[i];
+            t.cols = sc.nc;
+            t.sld = X.cols[i];
+            t.dld = sc.nc;
+            gather.push_back(t);
+            r0 += bl.dim[i];
+        }
+        mats.push_back(Mat{M, sc.nr, sc.nc});
+    }
+    run_copies(gather, s);
+    std::vector<SvdRes> res;
+    std::vector<Arena> keep;
+    svd_batch(ctx, mats, res, eps, 0, keep);
+
+    // global truncation
+    struct Cand { double l; int q, idx, sec; };
+    std::vector<Cand> cand;
+    double total = 0.0;
+    for (size_t k = 0; k < secs.size(); ++k)
+        for (int j = 0; j < res[k].k; ++j) {
+            cand.push_back(Cand{res[k].lam[j], secs[k].qm, j, (int)k});
+            total += res[k].lam[j] * res[k].lam[j];
+        }
+    std::sort(cand.begin(), cand.end(), [](const Cand &a, const Cand &b) {
+        if (a.l != b.l) return a.l > b.l;
+        if (a.q != b.q) return a.q < b.q;
+        return a.idx < b.idx;
+    });
+    PD_REQUIRE(!cand.empty() && cand[0].l > 0.0, PDMRG_ENUMERIC, "svd_truncate: zero wavefunction");
+    const double lmax = cand[0].l;
+    std::vector<int> kept(secs.size(), 0);
+    for (size_t c = 0; c < cand.size() && (int)c < max_m; ++c)
+        if (cand[c].l >= cutoff * lmax && cand[c].l > 0.0) kept[cand[c].sec] += 1;
+    double kept_w = 0.0;
+    std::vector<int> nq, nd;
+    std::vector<int> secidx;
+    for (size_t k = 0; k < secs.size(); ++k) {
+        if (kept[k] == 0) continue;
+        for (int j = 0; j < kept[k]; ++j) kept_w += res[k].lam[j] * res[k].lam[j];
+        nq.push_back(secs[k].qm);
+        nd.push_back(kept[k]);
+        secidx.push_back((int)k);
+    }
+    const double scale = 1.0 / std::sqrt(kept_w);
+    out.bl = bl;
+    out.br = br;
+    out.p = p;
+    out.mode = mode;
+    out.bnew = Bond(nq, nd);
+    out.discarded = std::max(0.0, 1.0 - kept_w / total);
+    out.lam.clear();
+    out.V.clear();
+    out.n_floored = 0;
+    for (size_t t = 0; t < secidx.size(); ++t)
+        for (int j = 0; j < nd[t]; ++j) out.lam.push_back(res[secidx[t]].lam[j] * scale);
+    const double lm = *std::max_element(out.lam.begin(), out.lam.end());
+    for (double l : out.lam) {
+        const double fl = std::max(l, 1e-12 * lm);
+        if (l < 1e-12 * lm) out.n_floored += 1;
+        out.V.push_back(1.0 / fl);
+    }
+    DevBuf d_lam;
+    upload(d_lam, out.lam, s);
+    const SiteLayout SA = site_layout(bl, out.bnew, p), SB = site_layout(out.bnew, br, p);
+    out.A.ensure(std::max<int64_t>(SA.size, 1) * sizeof(double));
+    out.B.ensure(std::max<int64_t>(SB.size, 1) * sizeof(double));
+    out.left.ensure(std::max<int64_t>(SA.size, 1) * sizeof(double));
+    out.right.ensure(std::max<int64_t>(SB.size, 1) * sizeof(double));
+    std::vector<CopyTask> ct;
+    for (size_t t = 0; t < secidx.size(); ++t) {
+        const Sec &sc = secs[secidx[t]];
+        const SvdRes &r = res[secidx[t]];
+        const int kq = nd[t];
+        const double *lam_q = d_lam.as<double>() + out.bnew.off[t];
+        int r0 = 0;
+        for (auto [s1, i] : sc.rows) {
+            const int co = SA.colo[(size_t)i * d + s1];
+            PD_REQUIRE(co >= 0, PDMRG_ESHAPE, "svd_truncate: output layout mismatch");
+            for (int pass = 0; pass < 2; ++pass) {
+                CopyTask c{};
+                c.src = r.Ut + r0;           // element (a, alpha) = Ut[alpha][r0 + a]
+                c.sld = r.nr;
+                c.trans = 1;
+                c.dst = (pass == 0 ? out.A.as<double>() : out.left.as<double>()) + SA.base[i] + co;
+                c.dld = SA.cols[i];
+                c.rows = bl.dim[i];
+                c.cols = kq;
+                c.cscale = pass == 0 ? nullptr : lam_q;
+                ct.push_back(c);
+            }
+            r0 += bl.dim[i];
+        }
+        PD_REQUIRE(SB.cols[t] == sc.nc, PDMRG_ESHAPE, "svd_truncate: right layout mismatch");
+        for (int pass = 0; pass < 2; ++pass) {
+            CopyTask c{};
+            c.src = r.Vt;
+            c.sld = r.nc;
+            c.dst = (pass == 0 ? out.B.as<double>() : out.right.as<double>()) + SB.base[t];
+            c.dld = SB.cols[t];
+            c.rows = kq;
+            c.cols = sc.nc;
+            c.rscale = pass == 0 ? nullptr : lam_q;
+            ct.push_back(c);
+        }
+    }
+    run_copies(ct, s);
+}
+
+}  // namespace pdmrg

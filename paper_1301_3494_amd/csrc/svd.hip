@@ -20,26 +20,28 @@ __device__ void sym_eig16(double (*A)[J2 + 1], double (*Q)[J2 + 1], double *red,
     const int tid = threadIdx.x;
     for (int e = tid; e < J2 * J2; e += blockDim.x) Q[e / J2][e % J2] = (e / J2 == e % J2) ? 1.0 : 0.0;
     __syncthreads();
+    // Relative stopping / skipping rule |a_pq| <= tol sqrt(|a_pp a_qq|), so that
+    // small eigenvalues of a graded Gram matrix are resolved to high relative
+    // accuracy (a norm-wide criterion would stop before they are).
     for (int sweep = 0; sweep < 40; ++sweep) {
-        double off = 0.0, dia = 0.0;
+        double off = 0.0;
         for (int e = tid; e < J2 * J2; e += blockDim.x) {
-            const double v = A[e / J2][e % J2];
-            if (e / J2 != e % J2) off += v * v;
-            else dia += v * v;
+            const int i = e / J2, j = e % J2;
+            if (i >= j) continue;
+            const double v = fabs(A[i][j]);
+            if (v == 0.0) continue;
+            const double dd = sqrt(fabs(A[i][i] * A[j][j]));
+            off = fmax(off, dd > 0.0 ? v / dd : 1.0);
         }
         red[tid] = off;
-        red[256 + tid] = dia;
         __syncthreads();
         for (int w = 128; w > 0; w >>= 1) {
-            if (tid < w) {
-                red[tid] += red[tid + w];
-                red[256 + tid] += red[256 + tid + w];
-            }
+            if (tid < w) red[tid] = fmax(red[tid], red[tid + w]);
             __syncthreads();
         }
-        const double soff = red[0], sdia = red[256];
+        const double roff = red[0];
         __syncthreads();
-        if (soff == 0.0 || soff <= 1e-32 * sdia) break;
+        if (roff <= 1e-15) break;
         for (int r = 0; r < J2 - 1; ++r) {
             if (tid < J2 / 2) {
                 int p = (tid == 0) ? J2 - 1 : (r + tid) % (J2 - 1);
@@ -47,7 +49,7 @@ __device__ void sym_eig16(double (*A)[J2 + 1], double (*Q)[J2 + 1], double *red,
                 if (p > q) { const int t = p; p = q; q = t; }
                 double c = 1.0, s = 0.0;
                 const double apq = A[p][q];
-                if (apq != 0.0) {
+                if (apq != 0.0 && fabs(apq) > 1e-17 * sqrt(fabs(A[p][p] * A[q][q]))) {
                     const double tau = (A[q][q] - A[p][p]) / (2.0 * apq);
                     const double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
                     c = 1.0 / sqrt(1.0 + t * t);
