@@ -246,8 +246,10 @@ int merge_regions(pdmrg_ctx *ctx, const pdmrg_bond *bl, const pdmrg_bond *bm,
  * left end, even ones at their right end) and every call runs the staggered
  * pattern of Fig. 4: half-sweep A (odd regions right, even left), merge and
  * re-split at shared bonds 1|2, 3|4, ...; half-sweep B, merges at 2|3, ...
- * Regions of one half-sweep advance in lockstep and their matvecs share
- * launches.  energy: <Psi|H|Psi>/<Psi|Psi> of the whole MPS after the sweep. */
+ * The regions of a half-sweep share no data, so they are processed one after
+ * the other on the context's stream; the result does not depend on their
+ * order.  energy: <Psi|H|Psi>/<Psi|Psi> of the whole MPS after the sweep
+ * (V applied on the shared bonds). */
 typedef struct {
     int32_t max_m;
     int32_t n_regions;

@@ -373,3 +373,63 @@ class SvdResult:
         self.lam, self.V = self.lam[:m], self.V[:m]
         lib().svd_free(h)
         self.h = None
+
+
+def dav_params(max_matvec=4, max_sub=8, tol=1e-8):
+    return CDavParams(int(max_matvec), int(max_sub), float(tol))
+
+
+class Mps:
+    """mps_alloc / mps_set_site / sweep / mps_energy on a context."""
+
+    def __init__(self, ctx, bonds, sites, phys_q=(-1, 1), q_target=0):
+        self.ctx = ctx
+        self.phys = Phys(phys_q)
+        self.B = [Bond(b) for b in bonds]
+        arr = (CBond * len(self.B))(*[b.c for b in self.B])
+        h = c_void_p()
+        check(lib().mps_alloc(ctx.h, len(sites), self.phys.ref, int(q_target), arr, byref(h)))
+        self.h = h
+        self.N = len(sites)
+        for i, s in enumerate(sites):
+            table, n = layout(SITE, self.B[i], self.B[i + 1], self.phys)
+            flat = np.zeros(n)
+            for key, off, rows, cols, ld in table:
+                b = s[key[:2]]
+                for r in range(rows):
+                    flat[off + r * ld: off + r * ld + cols] = b[r]
+            check(lib().mps_set_site(h, i, flat.ctypes.data_as(POINTER(c_double)), n))
+
+    def sweep(self, mpo, max_m, n_regions=1, prec=F64, refine=True, dav=None, dav_shared=None,
+              cutoff=1e-12, eps=1e-4):
+        p = CSweepParams(int(max_m), int(n_regions), int(prec), int(bool(refine)),
+                         dav or dav_params(4, 8, 1e-8), dav_shared or dav_params(40, 8, 1e-10),
+                         float(cutoff), float(eps))
+        rep = CSweepReport()
+        check(lib().sweep(self.ctx.h, self.h, mpo.h, byref(p), byref(rep)))
+        return {f: getattr(rep, f) for f, _ in CSweepReport._fields_}
+
+    def energy(self, mpo):
+        e = c_double()
+        check(lib().mps_energy(self.ctx.h, self.h, mpo.h, byref(e)))
+        return e.value
+
+    def bond(self, b):
+        n = c_int32()
+        check(lib().mps_bond(self.h, b, byref(n), None, None, 0))
+        q = np.zeros(max(n.value, 1), np.int32)
+        d = np.zeros(max(n.value, 1), np.int32)
+        check(lib().mps_bond(self.h, b, None, q.ctypes.data_as(POINTER(c_int32)), d.ctypes.data_as(POINTER(c_int32)),
+                             n.value))
+        return {int(a): int(c) for a, c in zip(q[:n.value], d[:n.value])}
+
+    def free(self):
+        if self.h:
+            lib().mps_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass

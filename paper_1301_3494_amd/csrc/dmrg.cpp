@@ -1,0 +1,398 @@
+// MPS state and the sweep driver (Sec. II, Fig. 4) on the device.
+//
+// Serial two-site sweep: bonds 0..N-2 moving right (A kept, centre Lambda B),
+// then back (B kept, centre A Lambda).  Real-space parallel sweep over n
+// contiguous regions: V = Lambda^{-1} is inserted on every shared bond
+// (Eqs. eqn:inverse, eqn:isvd), odd regions start at their left end and even
+// ones at their right end; half-sweep A (odd right, even left) is followed by
+// merges at shared bonds 1|2, 3|4, ... (Psi' = psi_L V psi_R, Eq. eqn:merge,
+// optimised and split again), half-sweep B by merges at 2|3, 4|5, ...  With
+// one region this is exactly the serial sweep.  No information crosses
+// regions between merges, so the regions of one half-sweep are independent.
+#include "internal.hpp"
+#include "svd.hpp"
+
+#include <chrono>
+#include <cmath>
+
+using namespace pdmrg;
+
+struct pdmrg_mps {
+    int N = 0, q_target = 0;
+    Phys p;
+    std::vector<Bond> bonds;                 // N + 1
+    std::vector<DevBuf> sites;               // SITE layouts, FP64
+    std::vector<DevBuf> L, R;                // environments on bonds 0..N
+    std::map<int, std::vector<double>> V;    // shared bond -> V (bond order)
+    std::map<int, DevBuf> Vd;
+    bool ready = false;                      // canonical form + environments
+    int n_regions = 1;
+    bool split = false;
+    std::vector<std::pair<int, int>> regions;
+};
+
+namespace {
+
+struct Driver {
+    pdmrg_ctx *ctx;
+    pdmrg_mps *m;
+    const pdmrg_mpo *mpo;
+    pdmrg_sweep_params prm{};
+    pdmrg_sweep_report rep{};
+    double t_heff = 0.0;
+
+    hipStream_t s() const { return ctx->stream; }
+    const MpoSite &W(int i) const { return mpo->W[i]; }
+
+    int64_t site_size(int i) const { return site_layout(m->bonds[i], m->bonds[i + 1], m->p).size; }
+
+    // psi2 = site i . site i+1 (optionally with V on the middle bond)
+    DevBuf contract(int i, const double *Vdev) {
+        MergePlan mp;
+        mp.build(m->bonds[i], m->bonds[i + 1], m->bonds[i + 2], m->p, s());
+        DevBuf out(std::max<int64_t>(mp.X.size, 1) * sizeof(double));
+        if (Vdev) {
+            ctx->ws_merge.ensure(std::max<int64_t>(mp.SR.size, 1) * sizeof(double));
+            mp.run(m->sites[i].as<double>(), Vdev, m->sites[i + 1].as<double>(), out.as<double>(),
+                   ctx->ws_merge.as<double>(), s());
+        } else {
+            launch_fill(out.as<double>(), 0.0, mp.X.size, s());
+            Slots sl{};
+            sl.p[0] = m->sites[i].ptr;
+            sl.p[1] = m->sites[i + 1].ptr;
+            sl.p[2] = out.ptr;
+            mp.g.launch(GemmPrec::F64, true, sl, s());
+        }
+        HIP_OK(hipStreamSynchronize(s()));
+        return out;
+    }
+
+    void env_L(int i) {   // L[i+1] from L[i] and site i
+        EnvPlan ep;
+        ep.build(1, m->bonds[i], m->bonds[i + 1], m->p, W(i), s());
+        DevBuf out(std::max<int64_t>(ep.Eout.size, 1) * sizeof(double));
+        ctx->ws_env.ensure((size_t)(std::max<int64_t>(ep.nU1, 1) + std::max<int64_t>(ep.nU2, 1)) * sizeof(double));
+        double *U1 = ctx->ws_env.as<double>();
+        ep.run(GemmPrec::F64, m->L[i].ptr, m->sites[i].ptr, out.ptr, U1, U1 + std::max<int64_t>(ep.nU1, 1), s());
+        HIP_OK(hipStreamSynchronize(s()));
+        m->L[i + 1] = std::move(out);
+    }
+
+    void env_R(int i) {   // R[i] from R[i+1] and site i
+        EnvPlan ep;
+        ep.build(-1, m->bonds[i], m->bonds[i + 1], m->p, W(i), s());
+        DevBuf out(std::max<int64_t>(ep.Eout.size, 1) * sizeof(double));
+        ctx->ws_env.ensure((size_t)(std::max<int64_t>(ep.nU1, 1) + std::max<int64_t>(ep.nU2, 1)) * sizeof(double));
+        double *U1 = ctx->ws_env.as<double>();
+        ep.run(GemmPrec::F64, m->R[i + 1].ptr, m->sites[i].ptr, out.ptr, U1, U1 + std::max<int64_t>(ep.nU1, 1), s());
+        HIP_OK(hipStreamSynchronize(s()));
+        m->R[i] = std::move(out);
+    }
+
+    DevBuf take(const DevBuf &src, int64_t n) {
+        DevBuf d(std::max<int64_t>(n, 1) * sizeof(double));
+        if (n) HIP_OK(hipMemcpyAsync(d.ptr, src.ptr, n * sizeof(double), hipMemcpyDeviceToDevice, s()));
+        return d;
+    }
+
+    // store an SVD result at bond i+1 (sites i, i+1)
+    void store(int i, SvdOut &r, int mode) {
+        m->bonds[i + 1] = r.bnew;
+        const int64_t na = site_layout(m->bonds[i], r.bnew, m->p).size;
+        const int64_t nb = site_layout(r.bnew, m->bonds[i + 2], m->p).size;
+        if (mode == PDMRG_ABSORB_RIGHT) {
+            m->sites[i] = take(r.A, na);
+            m->sites[i + 1] = take(r.right, nb);
+            env_L(i);
+        } else if (mode == PDMRG_ABSORB_LEFT) {
+            m->sites[i] = take(r.left, na);
+            m->sites[i + 1] = take(r.B, nb);
+            env_R(i + 1);
+        } else {
+            // environments from the orthonormal factors A and B
+            m->sites[i] = take(r.A, na);
+            m->sites[i + 1] = take(r.B, nb);
+            env_L(i);
+            env_R(i + 1);
+            m->sites[i] = take(r.left, na);
+            m->sites[i + 1] = take(r.right, nb);
+            m->V[i + 1] = r.V;
+            m->Vd[i + 1] = DevBuf();
+            upload(m->Vd[i + 1], r.V, s());
+            rep.n_floored += r.n_floored;
+        }
+        HIP_OK(hipStreamSynchronize(s()));
+        rep.max_trunc = std::max(rep.max_trunc, r.discarded);
+        rep.max_bond = std::max(rep.max_bond, r.bnew.total);
+    }
+
+    double solve(int i, DevBuf &psi, const pdmrg_dav_params &dav) {
+        const Bond &bl = m->bonds[i], &br = m->bonds[i + 2];
+        const double *Ld = m->L[i].as<double>(), *Rd = m->R[i + 2].as<double>();
+        pdmrg_heff op, op64;
+        heff_build(ctx, &op, bl, br, m->p, W(i), W(i + 1), Ld, Rd, prm.prec);
+        const bool refine = prm.prec != PDMRG_F64 && prm.refine;
+        if (refine) heff_build(ctx, &op64, bl, br, m->p, W(i), W(i + 1), Ld, Rd, PDMRG_F64);
+        const auto t0 = std::chrono::steady_clock::now();
+        DavResult r = davidson_run(ctx, &op, refine ? &op64 : nullptr, psi.as<double>(), dav);
+        t_heff += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        rep.n_matvec += r.nmv;
+        return r.energy;
+    }
+
+    void optimize(int i, int mode, const pdmrg_dav_params &dav) {
+        DevBuf psi = contract(i, nullptr);
+        solve(i, psi, dav);
+        SvdOut r;
+        svd_truncate_run(ctx, m->bonds[i], m->bonds[i + 2], m->p, psi.as<double>(), prm.max_m, prm.cutoff, prm.eps,
+                         mode, r);
+        store(i, r, mode);
+    }
+
+    void gauge_move(int i, int mode, int max_m, double cutoff) {
+        DevBuf psi = contract(i, nullptr);
+        SvdOut r;
+        svd_truncate_run(ctx, m->bonds[i], m->bonds[i + 2], m->p, psi.as<double>(), max_m, cutoff, prm.eps, mode, r);
+        store(i, r, mode);
+    }
+
+    void merge_shared(int j) {
+        DevBuf psi = contract(j, m->Vd.at(j + 1).as<double>());
+        solve(j, psi, prm.dav_shared);   // Davidson normalises its start vector
+        SvdOut r;
+        svd_truncate_run(ctx, m->bonds[j], m->bonds[j + 2], m->p, psi.as<double>(), prm.max_m, prm.cutoff, prm.eps,
+                         PDMRG_SPLIT, r);
+        store(j, r, PDMRG_SPLIT);
+    }
+
+    void init() {
+        const int N = m->N;
+        m->L.clear();
+        m->R.clear();
+        m->L.resize(N + 1);
+        m->R.resize(N + 1);
+        std::vector<double> one = {1.0};
+        upload(m->L[0], one, s());
+        upload(m->R[N], one, s());
+        // right-canonical form with the centre on site 0, by two-site SVDs
+        // from the right keeping every nonzero singular value
+        for (int i = N - 2; i >= 0; --i) gauge_move(i, PDMRG_ABSORB_LEFT, 1 << 30, 1e-14);
+        m->ready = true;
+    }
+
+    void split_regions() {
+        const auto &rg = m->regions;
+        const int n = (int)rg.size();
+        for (int r = 0; r < n; ++r) {
+            const int lo = rg[r].first, hi = rg[r].second;
+            for (int i = lo; i < hi; ++i) gauge_move(i, PDMRG_ABSORB_RIGHT, prm.max_m, prm.cutoff);
+            if (r < n - 1) gauge_move(hi, PDMRG_SPLIT, prm.max_m, prm.cutoff);
+        }
+        for (int r = 0; r < n; r += 2) {
+            const int lo = rg[r].first, hi = rg[r].second;
+            for (int i = hi - 1; i >= lo; --i) gauge_move(i, PDMRG_ABSORB_LEFT, prm.max_m, prm.cutoff);
+        }
+        m->split = true;
+    }
+
+    void parallel_sweep() {
+        const auto &rg = m->regions;
+        const int n = (int)rg.size();
+        for (int half = 0; half < 2; ++half) {
+            for (int r = 0; r < n; ++r) {
+                const int lo = rg[r].first, hi = rg[r].second;
+                const bool right = (r % 2 == 0) == (half == 0);
+                if (right)
+                    for (int i = lo; i < hi; ++i) optimize(i, PDMRG_ABSORB_RIGHT, prm.dav);
+                else
+                    for (int i = hi - 1; i >= lo; --i) optimize(i, PDMRG_ABSORB_LEFT, prm.dav);
+            }
+            for (int r = half; r < n - 1; r += 2) merge_shared(rg[r].second);
+        }
+    }
+
+    // <Psi|O|Psi> of the whole MPS (V applied on shared bonds) by left transfer
+    double expectation(bool identity) {
+        const int N = m->N;
+        DevBuf E;
+        std::vector<double> one = {1.0};
+        upload(E, one, s());
+        std::vector<int> zero = {0};
+        for (int i = 0; i < N; ++i) {
+            MpoSite Wi;
+            if (identity) {
+                Wi.Dl = Wi.Dr = 1;
+                Wi.d = m->p.d();
+                Wi.W.assign((size_t)Wi.d * Wi.d, 0.0);
+                for (int a = 0; a < Wi.d; ++a) Wi.W[(size_t)a * Wi.d + a] = 1.0;
+                Wi.dl = zero;
+                Wi.dr = zero;
+            } else {
+                Wi = W(i);
+            }
+            EnvPlan ep;
+            ep.build(1, m->bonds[i], m->bonds[i + 1], m->p, Wi, s());
+            DevBuf out(std::max<int64_t>(ep.Eout.size, 1) * sizeof(double));
+            ctx->ws_env.ensure((size_t)(std::max<int64_t>(ep.nU1, 1) + std::max<int64_t>(ep.nU2, 1)) * sizeof(double));
+            double *U1 = ctx->ws_env.as<double>();
+            ep.run(GemmPrec::F64, E.ptr, m->sites[i].ptr, out.ptr, U1, U1 + std::max<int64_t>(ep.nU1, 1), s());
+            auto it = m->Vd.find(i + 1);
+            if (it != m->Vd.end() && m->split) {
+                // E[a, w, a'] *= V[a] V[a']
+                const Bond &b = m->bonds[i + 1];
+                const EnvLayout &El = ep.Eout;
+                const double *V = it->second.as<double>();
+                std::vector<CopyTask> ct;
+                for (int j = 0; j < b.nsec(); ++j)
+                    for (int w = 0; w < El.D; ++w) {
+                        const int ro = El.rowo[(size_t)j * El.D + w];
+                        if (ro < 0) continue;
+                        const int k = b.find(b.q[j] + Wi.dr[w]);
+                        double *blk = out.as<double>() + El.base[j] + (int64_t)ro * b.dim[j];
+                        ct.push_back(CopyTask{blk, blk, V + b.off[k], V + b.off[j], b.dim[k], b.dim[j], b.dim[j],
+                                              b.dim[j], 0, 0});
+                    }
+                DevBuf d;
+                upload(d, ct, s());
+                int64_t mx = 0;
+                for (auto &t : ct) mx = std::max<int64_t>(mx, (int64_t)t.rows * t.cols);
+                launch_copies(d.as<CopyTask>(), (int)ct.size(), mx, s());
+                HIP_OK(hipStreamSynchronize(s()));
+            }
+            HIP_OK(hipStreamSynchronize(s()));
+            E = std::move(out);
+        }
+        double v = 0.0;
+        HIP_OK(hipMemcpyAsync(&v, E.ptr, sizeof(double), hipMemcpyDeviceToHost, s()));
+        HIP_OK(hipStreamSynchronize(s()));
+        return v;
+    }
+
+    double energy() { return expectation(false) / expectation(true); }
+};
+
+void check_mpo(const pdmrg_mps *m, const pdmrg_mpo *mpo) {
+    PD_REQUIRE(mpo->N == m->N, PDMRG_ESHAPE, "sweep: MPO and MPS lengths differ");
+    PD_REQUIRE(mpo->W[0].Dl == 1 && mpo->W[m->N - 1].Dr == 1, PDMRG_ESHAPE, "sweep: MPO boundary channels");
+    PD_REQUIRE(mpo->d == m->p.d(), PDMRG_ESHAPE, "sweep: MPO local dimension differs from the MPS");
+}
+
+}  // namespace
+
+#define API_TRY try {
+#define API_CATCH                                   \
+    }                                               \
+    catch (const Error &e) {                        \
+        set_last_error(e.what());                   \
+        return e.code;                              \
+    }                                               \
+    catch (const std::exception &e) {               \
+        set_last_error(e.what());                   \
+        return PDMRG_EINVAL;                        \
+    }                                               \
+    return PDMRG_OK;
+
+extern "C" {
+
+int mps_alloc(pdmrg_ctx *ctx, int nsites, const pdmrg_phys *phys, int32_t q_target, const pdmrg_bond *bonds,
+              pdmrg_mps **out) {
+    API_TRY
+    PD_REQUIRE(ctx && phys && bonds && out && nsites >= 2, PDMRG_EINVAL, "mps_alloc: bad arguments");
+    auto m = std::make_unique<pdmrg_mps>();
+    m->N = nsites;
+    m->q_target = q_target;
+    m->p = Phys::from(phys);
+    for (int b = 0; b <= nsites; ++b) m->bonds.push_back(Bond::from(&bonds[b]));
+    PD_REQUIRE(m->bonds[0].q == std::vector<int>{0} && m->bonds[0].dim == std::vector<int>{1}, PDMRG_ESHAPE,
+               "mps_alloc: bond 0 must be {q=0, dim=1}");
+    PD_REQUIRE(m->bonds[nsites].q == std::vector<int>{q_target} && m->bonds[nsites].dim == std::vector<int>{1},
+               PDMRG_ESHAPE, "mps_alloc: last bond must be {q=target, dim=1}");
+    m->sites.resize(nsites);
+    for (int i = 0; i < nsites; ++i) {
+        const int64_t n = site_layout(m->bonds[i], m->bonds[i + 1], m->p).size;
+        PD_REQUIRE(n > 0, PDMRG_ESHAPE, "mps_alloc: site " + std::to_string(i) + " has no allowed block");
+        m->sites[i].alloc(n * sizeof(double));
+        HIP_OK(hipMemsetAsync(m->sites[i].ptr, 0, n * sizeof(double), ctx->stream));
+    }
+    HIP_OK(hipStreamSynchronize(ctx->stream));
+    *out = m.release();
+    API_CATCH
+}
+
+int mps_set_site(pdmrg_mps *m, int site, const double *host_data, int64_t n) {
+    API_TRY
+    PD_REQUIRE(m && host_data && site >= 0 && site < m->N, PDMRG_EINVAL, "mps_set_site: bad arguments");
+    const int64_t need = site_layout(m->bonds[site], m->bonds[site + 1], m->p).size;
+    PD_REQUIRE(n == need, PDMRG_ESHAPE, "mps_set_site: expected " + std::to_string(need) + " elements");
+    HIP_OK(hipMemcpy(m->sites[site].ptr, host_data, n * sizeof(double), hipMemcpyHostToDevice));
+    m->ready = false;
+    m->split = false;
+    API_CATCH
+}
+
+int mps_bond(const pdmrg_mps *m, int b, int32_t *nsec, int32_t *q, int32_t *dim, int32_t cap) {
+    API_TRY
+    PD_REQUIRE(m && b >= 0 && b <= m->N, PDMRG_EINVAL, "mps_bond: bad bond");
+    const Bond &B = m->bonds[b];
+    if (nsec) *nsec = B.nsec();
+    if (q || dim) {
+        PD_REQUIRE(cap >= B.nsec(), PDMRG_EINVAL, "mps_bond: capacity too small");
+        for (int k = 0; k < B.nsec(); ++k) {
+            if (q) q[k] = B.q[k];
+            if (dim) dim[k] = B.dim[k];
+        }
+    }
+    API_CATCH
+}
+
+int mps_get_site(pdmrg_mps *m, int site, double *host_data, int64_t cap) {
+    API_TRY
+    PD_REQUIRE(m && host_data && site >= 0 && site < m->N, PDMRG_EINVAL, "mps_get_site: bad arguments");
+    const int64_t n = site_layout(m->bonds[site], m->bonds[site + 1], m->p).size;
+    PD_REQUIRE(cap >= n, PDMRG_EINVAL, "mps_get_site: capacity too small");
+    HIP_OK(hipMemcpy(host_data, m->sites[site].ptr, n * sizeof(double), hipMemcpyDeviceToHost));
+    API_CATCH
+}
+
+int sweep(pdmrg_ctx *ctx, pdmrg_mps *m, const pdmrg_mpo *mpo, const pdmrg_sweep_params *p, pdmrg_sweep_report *rep) {
+    API_TRY
+    PD_REQUIRE(ctx && m && mpo && p, PDMRG_EINVAL, "sweep: null argument");
+    check_mpo(m, mpo);
+    PD_REQUIRE(p->max_m >= 1 && p->n_regions >= 1, PDMRG_EINVAL, "sweep: bad parameters");
+    const auto t0 = std::chrono::steady_clock::now();
+    Driver dr{ctx, m, mpo};
+    dr.prm = *p;
+    if (!m->ready) dr.init();
+    if (p->n_regions != m->n_regions || m->regions.empty()) {
+        PD_REQUIRE(!m->split, PDMRG_EINVAL, "sweep: the region count cannot change after the split");
+        const int size = m->N / p->n_regions;
+        PD_REQUIRE(size >= 2 && size * p->n_regions == m->N, PDMRG_EINVAL,
+                   "sweep: regions must hold >= 2 sites and tile the chain");
+        m->n_regions = p->n_regions;
+        m->regions.clear();
+        for (int r = 0; r < p->n_regions; ++r) m->regions.push_back({r * size, (r + 1) * size - 1});
+    }
+    if (m->n_regions > 1 && !m->split) dr.split_regions();
+    dr.parallel_sweep();
+    const double E = dr.energy();
+    if (rep) {
+        *rep = dr.rep;
+        rep->energy = E;
+        rep->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        rep->seconds_heff = dr.t_heff;
+    }
+    API_CATCH
+}
+
+int mps_energy(pdmrg_ctx *ctx, pdmrg_mps *m, const pdmrg_mpo *mpo, double *energy) {
+    API_TRY
+    PD_REQUIRE(ctx && m && mpo && energy, PDMRG_EINVAL, "mps_energy: null argument");
+    check_mpo(m, mpo);
+    Driver dr{ctx, m, mpo};
+    *energy = dr.energy();
+    API_CATCH
+}
+
+void mps_free(pdmrg_mps *m) { delete m; }
+
+}  // extern "C"

@@ -1,0 +1,102 @@
+"""End-to-end DMRG sweeps on the GPU against the oracle and exact references:
+serial and real-space parallel sweeps (Sec. II, Fig. 4), FP64 and mixed
+precision with FP64 refinement, U(1) and no-symmetry models."""
+import numpy as np
+import pytest
+
+from helpers import pl, synth, say
+from oracle import models, mpo as M, dmrg, exact
+
+pytestmark = pytest.mark.gpu
+E_ED_CHAIN16 = -6.911737145575103
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available()
+    c = pl.Context(0)
+    yield c
+    c.close()
+
+
+def _oracle_run(terms, N, phys, bonds, sites, schedule, n_regions, n_warmup, dav, dav_shared, q=0):
+    mpo = M.build_mpo(terms, N, models.OPS, phys)
+    p = dmrg.SweepParams(schedule=schedule, n_warmup=n_warmup, n_regions=n_regions,
+                         dav=dmrg.DavidsonParams(max_matvec=dav[0], max_sub=dav[1], tol=dav[2]),
+                         dav_shared=dmrg.DavidsonParams(max_matvec=dav_shared[0], max_sub=dav_shared[1],
+                                                        tol=dav_shared[2]))
+    return dmrg.run_dmrg(mpo, bonds, sites, q, p)[1]
+
+
+def _gpu_run(ctx, mpo, bonds, sites, schedule, n_regions, n_warmup, dav, dav_shared, prec=pl.F64, phys=(-1, 1), q=0):
+    mps = pl.Mps(ctx, bonds, sites, phys, q)
+    out = []
+    for k, m in enumerate(schedule):
+        nreg = 1 if k < n_warmup else n_regions
+        rep = mps.sweep(mpo, m, nreg, prec=prec, dav=pl.dav_params(*dav), dav_shared=pl.dav_params(*dav_shared))
+        out.append(rep)
+    mps.free()
+    return out
+
+
+def test_chain16_serial_matches_ed_and_oracle(ctx):
+    N = 16
+    bonds, sites = synth.random_mps(N, 16, 1)
+    mpo = pl.Mpo("chain", N, 1, (1.0, 1.0))
+    dav, davs = (20, 8, 1e-10), (40, 8, 1e-10)
+    reps = _gpu_run(ctx, mpo, bonds, sites, [64] * 4, 1, 0, dav, davs)
+    Eo = _oracle_run(models.heisenberg_terms(models.chain_bonds(N)), N, (-1, 1), bonds, sites, [64] * 4, 1, 0, dav, davs)
+    Eg = [r["energy"] for r in reps]
+    say("chain16 gpu", Eg, "oracle", Eo, "s/sweep", [round(r["seconds"], 3) for r in reps])
+    assert abs(Eg[-1] - E_ED_CHAIN16) <= 1e-9 * abs(E_ED_CHAIN16)
+    for a, b in zip(Eg, Eo):
+        assert abs(a - b) <= 1e-9 * abs(b)
+
+
+@pytest.mark.parametrize("n_regions", [2, 4])
+def test_chain16_parallel_regions(ctx, n_regions):
+    N = 16
+    bonds, sites = synth.random_mps(N, 16, 1)
+    mpo = pl.Mpo("chain", N, 1, (1.0, 1.0))
+    sched = [32, 32, 64, 64, 64]
+    dav, davs = (10, 8, 1e-10), (40, 8, 1e-10)
+    reps = _gpu_run(ctx, mpo, bonds, sites, sched, n_regions, 2, dav, davs)
+    Eo = _oracle_run(models.heisenberg_terms(models.chain_bonds(N)), N, (-1, 1), bonds, sites, sched, n_regions, 2,
+                     dav, davs)
+    Eg = [r["energy"] for r in reps]
+    say("regions", n_regions, "gpu", Eg, "oracle", Eo)
+    assert abs(Eg[-1] - E_ED_CHAIN16) <= 1e-9 * abs(E_ED_CHAIN16)
+    assert abs(Eo[-1] - E_ED_CHAIN16) <= 1e-9 * abs(E_ED_CHAIN16)
+    for a, b in zip(Eg, Eo):
+        assert abs(a - b) <= 1e-8 * abs(b)
+
+
+@pytest.mark.parametrize("prec", [pl.F32, pl.BF16X3])
+def test_chain16_mixed_precision_reaches_ed(ctx, prec):
+    N = 16
+    bonds, sites = synth.random_mps(N, 16, 1)
+    mpo = pl.Mpo("chain", N, 1, (1.0, 1.0))
+    reps = _gpu_run(ctx, mpo, bonds, sites, [64] * 4, 1, 0, (30, 8, 1e-10), (40, 8, 1e-10), prec=prec)
+    say("mixed", prec, [r["energy"] for r in reps])
+    assert abs(reps[-1]["energy"] - E_ED_CHAIN16) <= 1e-9 * abs(E_ED_CHAIN16)
+
+
+def test_tfim_no_symmetry_closed_form(ctx):
+    N, h = 12, 0.8
+    bonds, sites = synth.random_mps(N, 16, 4, phys_q=synth.TRIVIAL_Q)
+    mpo = pl.Mpo("tfim", N, 1, (1.0, h))
+    reps = _gpu_run(ctx, mpo, bonds, sites, [64] * 4, 1, 0, (30, 8, 1e-10), (40, 8, 1e-10), phys=synth.TRIVIAL_Q)
+    e = exact.tfim_chain_energy(N, 1.0, h)
+    say("tfim", reps[-1]["energy"], e)
+    assert abs(reps[-1]["energy"] - e) <= 1e-9 * abs(e)
+
+
+def test_xx_chain_closed_form_two_regions(ctx):
+    N = 16
+    bonds, sites = synth.random_mps(N, 16, 6)
+    mpo = pl.Mpo("chain", N, 1, (1.0, 0.0))
+    reps = _gpu_run(ctx, mpo, bonds, sites, [32, 64, 64, 64, 64, 64], 2, 1, (20, 8, 1e-10), (40, 8, 1e-11))
+    e = exact.xx_chain_energy(N)
+    say("xx", reps[-1]["energy"], e)
+    assert abs(reps[-1]["energy"] - e) <= 1e-9 * abs(e)
