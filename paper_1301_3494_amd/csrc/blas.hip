@@ -148,18 +148,21 @@ void launch_multidot(const double *V, int64_t ldv, int nvec, const double *w, in
     hipLaunchKernelGGL(multidot_kernel, dim3(nblk), dim3(256), 0, s, V, ldv, nvec, w, n, partial);
 }
 
-__global__ void reduce_partials_kernel(const double *partial, int nblk, int nvec, double *out, int stride) {
-    for (int v = threadIdx.x; v < nvec; v += blockDim.x) {
-        double acc = 0.0;
-        for (int b = 0; b < nblk; ++b) acc += partial[b * nvec + v];
-        out[(int64_t)v * stride] = acc;
-    }
+// one workgroup per vector: strided partial sums, then a fixed-order tree
+__global__ __launch_bounds__(256) void reduce_partials_kernel(const double *partial, int nblk, int nvec,
+                                                              double *out, int stride) {
+    __shared__ double sh[256];
+    const int v = blockIdx.x;
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += 256) acc += partial[b * nvec + v];
+    acc = block_sum(acc, sh);
+    if (threadIdx.x == 0) out[(int64_t)v * stride] = acc;
 }
 
 void launch_reduce_partials(const double *partial, int nblk, int nvec, double *out, int stride,
                             hipStream_t s) {
     if (nvec <= 0) return;
-    hipLaunchKernelGGL(reduce_partials_kernel, dim3(1), dim3(64), 0, s, partial, nblk, nvec, out, stride);
+    hipLaunchKernelGGL(reduce_partials_kernel, dim3(nvec), dim3(256), 0, s, partial, nblk, nvec, out, stride);
 }
 
 __global__ void combine_kernel(const double *V, int64_t ldv, int nvec, const double *c, double *y, int64_t n,

@@ -8,15 +8,15 @@
 //
 // Workgroup: 256 threads = 4 wave64, each wave owns a 32 x 32 quarter of the
 // tile as 2 x 2 MFMA 16 x 16 blocks.  Operands are staged through LDS:
-//   FP64 / FP32  : K-major LDS tiles, v_mfma_f64_16x16x4 / v_mfma_f32_16x16x4;
+//   FP64 / FP32  : v_mfma_f64_16x16x4 / v_mfma_f32_16x16x4 on double-buffered
+//                  LDS tiles (see below);
 //   BF16x3       : FP32 operands split on the fly into bf16 hi + lo halves
 //                  (x = hi + lo, both rounded to nearest even), K-contiguous
 //                  LDS tiles, C += hi*hi' + hi*lo' + lo*hi' with
 //                  v_mfma_f32_16x16x32_bf16 and FP32 accumulation.
 // Global loads of the next K-step are issued before the MFMAs of the current
-// one (register double buffering).  Tiles are mapped XCD-major: the 8 XCDs
-// each receive a contiguous run of the tile list, so the tiles that share an
-// operand panel share an L2.
+// one.  Tiles are mapped XCD-major: the 8 XCDs each receive a contiguous run
+// of the tile list, so the tiles that share an operand panel share an L2.
 #include "kernels.hpp"
 
 namespace pdmrg {
@@ -44,73 +44,92 @@ __device__ __forceinline__ int map_tile(int ntiles) {
     return (blockIdx.x % 8) * chunk + blockIdx.x / 8;
 }
 
-// Iterates the (segment, k0) steps of one item.
-struct KIter {
-    int seg, k0, nseg;
-};
-
 // ---------------------------------------------------------------- FP64 / FP32
-template <typename T, typename TC, bool TA, bool TB>
+// LDS tiles are M-major (A) / N-major (B) with the K index contiguous and an
+// odd row stride (BK + 1 elements), so both the global->LDS stores of either
+// operand orientation and the MFMA operand reads (16 lanes = 16 rows, same k)
+// are free of bank conflicts.  Two LDS buffers: the next K-step's global loads
+// are in flight during the current MFMAs and one barrier separates steps.
+template <typename T> struct KStep;
+template <> struct KStep<double> { static constexpr int BK = 16; };
+template <> struct KStep<float> { static constexpr int BK = 32; };
+
+template <typename T, typename TC, bool TA, bool TB, int TM>
 __global__ __launch_bounds__(NT) void gemm_kmajor(Slots slots, const GemmItem *__restrict__ items,
                                                   const GemmSeg *__restrict__ segs,
                                                   const GemmTile *__restrict__ tiles, int ntiles) {
-    constexpr int BK = 16;
+    // TM x TM output tile; each wave owns a (TM/2) x (TM/2) quarter as
+    // (TM/32) x (TM/32) MFMA 16 x 16 blocks.
+    constexpr int BM = TM, BN = TM, BK = KStep<T>::BK, LDK = BK + 1;
+    constexpr int NL = BM * BK / NT;   // elements of each operand loaded per thread and step
+    constexpr int WB = TM / 32;        // MFMA blocks per wave and dimension
     const int t = map_tile(ntiles);
     if (t >= ntiles) return;
     const GemmTile tile = tiles[t];
     const GemmItem it = items[tile.item];
-    __shared__ T As[BK][BM + 2];
-    __shared__ T Bs[BK][BN + 2];
+    __shared__ T As[2][BM][LDK];
+    __shared__ T Bs[2][BN][LDK];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+    const int wm = (wave >> 1) * (TM / 2), wn = (wave & 1) * (TM / 2);
     const int m0 = tile.m0, n0 = tile.n0;
     using V4 = typename Acc<T>::type;
-    V4 acc[2][2];
+    V4 acc[WB][WB];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < WB; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = V4{0, 0, 0, 0};
+        for (int j = 0; j < WB; ++j) acc[i][j] = V4{0, 0, 0, 0};
 
-    // thread -> load coordinates (4 elements of A and of B per K-step)
-    const int a_r = TA ? (tid & 15) * 4 : tid >> 2;   // m (first of 4 if TA)
-    const int a_k = TA ? tid >> 4 : (tid & 3) * 4;    // k (first of 4 if !TA)
-    const int b_n = TB ? tid >> 2 : (tid & 15) * 4;
-    const int b_k = TB ? (tid & 3) * 4 : tid >> 4;
-
-    T ra[4], rb[4];
+    // coalesced thread -> element maps: consecutive threads walk the
+    // contiguous global index of each operand
+    //   A (M x K):  K contiguous (!TA): k = tid % BK, m = tid / BK + u * (NT / BK)
+    //               M contiguous (TA):  m = tid % BM, k = tid / BM + u * (NT / BM)
+    //   B (K x N):  N contiguous (!TB): n = tid % BN, k = tid / BN + u * (NT / BN)
+    //               K contiguous (TB):  k = tid % BK, n = tid / BK + u * (NT / BK)
+    T ra[NL], rb[NL];
     auto load = [&](const GemmSeg &sg, int k0) {
         const T *A = static_cast<const T *>(slots.p[sg.a_slot]) + sg.a_off;
         const T *B = static_cast<const T *>(slots.p[sg.b_slot]) + sg.b_off;
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int gm = m0 + a_r + (TA ? u : 0), gk = k0 + a_k + (TA ? 0 : u);
+        for (int u = 0; u < NL; ++u) {
+            int am, ak, bn, bk;
+            if (TA) { am = tid % BM; ak = tid / BM + u * (NT / BM); }
+            else    { ak = tid % BK; am = tid / BK + u * (NT / BK); }
+            if (TB) { bk = tid % BK; bn = tid / BK + u * (NT / BK); }
+            else    { bn = tid % BN; bk = tid / BN + u * (NT / BN); }
+            const int gm = m0 + am, gk = k0 + ak, gn = n0 + bn, gkb = k0 + bk;
             ra[u] = (gm < it.M && gk < sg.K)
                         ? (TA ? A[(int64_t)gk * sg.lda + gm] : A[(int64_t)gm * sg.lda + gk])
                         : T(0);
-            const int gn = n0 + b_n + (TB ? 0 : u), gkb = k0 + b_k + (TB ? u : 0);
             rb[u] = (gn < it.N && gkb < sg.K)
                         ? (TB ? B[(int64_t)gn * sg.ldb + gkb] : B[(int64_t)gkb * sg.ldb + gn])
                         : T(0);
         }
     };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int u = 0; u < NL; ++u) {
+            int am, ak, bn, bk;
+            if (TA) { am = tid % BM; ak = tid / BM + u * (NT / BM); }
+            else    { ak = tid % BK; am = tid / BK + u * (NT / BK); }
+            if (TB) { bk = tid % BK; bn = tid / BK + u * (NT / BK); }
+            else    { bn = tid % BN; bk = tid / BN + u * (NT / BN); }
+            As[buf][am][ak] = ra[u];
+            Bs[buf][bn][bk] = rb[u];
+        }
+    };
 
     int sidx = 0, k0 = 0;
-    // skip empty segments
     while (sidx < it.nseg && segs[it.seg0 + sidx].K <= 0) ++sidx;
     GemmSeg sg;
+    int buf = 0;
     if (sidx < it.nseg) {
         sg = segs[it.seg0 + sidx];
         load(sg, 0);
+        store(0);
     }
+    __syncthreads();
     while (sidx < it.nseg) {
-        __syncthreads();
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            if (TA) As[a_k][a_r + u] = ra[u]; else As[a_k + u][a_r] = ra[u];
-            if (TB) Bs[b_k + u][b_n] = rb[u]; else Bs[b_k][b_n + u] = rb[u];
-        }
-        __syncthreads();
-        // advance and prefetch the next step
+        // advance to the next step and prefetch it
         k0 += BK;
         if (k0 >= sg.K) {
             k0 = 0;
@@ -118,26 +137,33 @@ __global__ __launch_bounds__(NT) void gemm_kmajor(Slots slots, const GemmItem *_
             while (sidx < it.nseg && segs[it.seg0 + sidx].K <= 0) ++sidx;
             if (sidx < it.nseg) sg = segs[it.seg0 + sidx];
         }
-        if (sidx < it.nseg) load(sg, k0);
+        const bool more = sidx < it.nseg;
+        if (more) load(sg, k0);
 #pragma unroll
         for (int kk = 0; kk < BK; kk += 4) {
             const int kr = kk + (lane >> 4), c = lane & 15;
-            const T a0 = As[kr][wm + c], a1 = As[kr][wm + 16 + c];
-            const T b0 = Bs[kr][wn + c], b1 = Bs[kr][wn + 16 + c];
-            acc[0][0] = mfma16(a0, b0, acc[0][0]);
-            acc[0][1] = mfma16(a0, b1, acc[0][1]);
-            acc[1][0] = mfma16(a1, b0, acc[1][0]);
-            acc[1][1] = mfma16(a1, b1, acc[1][1]);
+            T a[WB], b[WB];
+#pragma unroll
+            for (int i = 0; i < WB; ++i) a[i] = As[buf][wm + i * 16 + c][kr];
+#pragma unroll
+            for (int j = 0; j < WB; ++j) b[j] = Bs[buf][wn + j * 16 + c][kr];
+#pragma unroll
+            for (int i = 0; i < WB; ++i)
+#pragma unroll
+                for (int j = 0; j < WB; ++j) acc[i][j] = mfma16(a[i], b[j], acc[i][j]);
         }
+        if (more) store(buf ^ 1);
+        __syncthreads();
+        buf ^= 1;
     }
     // Result rows held by (lane, register r): v_mfma_f64_16x16x4 returns row
     // 4 r + lane/16, v_mfma_f32_16x16x4 row 4 (lane/16) + r; column lane % 16.
     constexpr bool kF64 = sizeof(T) == 8;
     TC *C = static_cast<TC *>(const_cast<void *>(slots.p[it.c_slot])) + it.c_off;
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < WB; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < WB; ++j)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int row = kF64 ? r * 4 + (lane >> 4) : (lane >> 4) * 4 + r;
@@ -262,13 +288,20 @@ __global__ __launch_bounds__(NT) void gemm_bf16x3(Slots slots, const GemmItem *_
 }
 
 // ---------------------------------------------------------------- launcher
+template <typename T, typename TC, int TM>
+static void dispatch_tm(bool ta, bool tb, dim3 g, hipStream_t s, const Slots &sl, const GemmItem *it,
+                        const GemmSeg *sg, const GemmTile *tl, int n) {
+    if (!ta && !tb) hipLaunchKernelGGL((gemm_kmajor<T, TC, false, false, TM>), g, dim3(NT), 0, s, sl, it, sg, tl, n);
+    else if (ta && !tb) hipLaunchKernelGGL((gemm_kmajor<T, TC, true, false, TM>), g, dim3(NT), 0, s, sl, it, sg, tl, n);
+    else if (!ta && tb) hipLaunchKernelGGL((gemm_kmajor<T, TC, false, true, TM>), g, dim3(NT), 0, s, sl, it, sg, tl, n);
+    else hipLaunchKernelGGL((gemm_kmajor<T, TC, true, true, TM>), g, dim3(NT), 0, s, sl, it, sg, tl, n);
+}
+
 template <typename T, typename TC>
-static void dispatch_kmajor(bool ta, bool tb, dim3 g, hipStream_t s, const Slots &sl,
+static void dispatch_kmajor(int tm, bool ta, bool tb, dim3 g, hipStream_t s, const Slots &sl,
                             const GemmItem *it, const GemmSeg *sg, const GemmTile *tl, int n) {
-    if (!ta && !tb) hipLaunchKernelGGL((gemm_kmajor<T, TC, false, false>), g, dim3(NT), 0, s, sl, it, sg, tl, n);
-    else if (ta && !tb) hipLaunchKernelGGL((gemm_kmajor<T, TC, true, false>), g, dim3(NT), 0, s, sl, it, sg, tl, n);
-    else if (!ta && tb) hipLaunchKernelGGL((gemm_kmajor<T, TC, false, true>), g, dim3(NT), 0, s, sl, it, sg, tl, n);
-    else hipLaunchKernelGGL((gemm_kmajor<T, TC, true, true>), g, dim3(NT), 0, s, sl, it, sg, tl, n);
+    if (tm == 128) dispatch_tm<T, TC, 128>(ta, tb, g, s, sl, it, sg, tl, n);
+    else dispatch_tm<T, TC, 64>(ta, tb, g, s, sl, it, sg, tl, n);
 }
 
 template <typename TC>
@@ -280,7 +313,7 @@ static void dispatch_bf16(bool ta, bool tb, dim3 g, hipStream_t s, const Slots &
     else hipLaunchKernelGGL((gemm_bf16x3<TC, true, true>), g, dim3(NT), 0, s, sl, it, sg, tl, n);
 }
 
-void launch_gemm(GemmPrec prec, bool ta, bool tb, bool c_is_f64, const Slots &slots,
+void launch_gemm(GemmPrec prec, int tm, bool ta, bool tb, bool c_is_f64, const Slots &slots,
                  const GemmItem *items, const GemmSeg *segs, const GemmTile *tiles, int ntiles,
                  hipStream_t s) {
     if (ntiles <= 0) return;
@@ -288,11 +321,11 @@ void launch_gemm(GemmPrec prec, bool ta, bool tb, bool c_is_f64, const Slots &sl
     dim3 grid(chunk * 8);
     switch (prec) {
         case GemmPrec::F64:
-            dispatch_kmajor<double, double>(ta, tb, grid, s, slots, items, segs, tiles, ntiles);
+            dispatch_kmajor<double, double>(tm, ta, tb, grid, s, slots, items, segs, tiles, ntiles);
             break;
         case GemmPrec::F32:
-            if (c_is_f64) dispatch_kmajor<float, double>(ta, tb, grid, s, slots, items, segs, tiles, ntiles);
-            else dispatch_kmajor<float, float>(ta, tb, grid, s, slots, items, segs, tiles, ntiles);
+            if (c_is_f64) dispatch_kmajor<float, double>(tm, ta, tb, grid, s, slots, items, segs, tiles, ntiles);
+            else dispatch_kmajor<float, float>(tm, ta, tb, grid, s, slots, items, segs, tiles, ntiles);
             break;
         case GemmPrec::BF16X3:
             if (c_is_f64) dispatch_bf16<double>(ta, tb, grid, s, slots, items, segs, tiles, ntiles);

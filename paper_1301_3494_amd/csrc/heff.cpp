@@ -18,7 +18,7 @@ void heff_build(pdmrg_ctx *ctx, pdmrg_heff *op, const Bond &bl, const Bond &br, 
     hipStream_t s = ctx->stream;
     (void)gemm_prec(prec);
     op->prec = prec;
-    op->plan.build(bl, br, p, W1, W2, s);
+    op->plan.build(bl, br, p, W1, W2, prec, s);
     HeffPlan &pl = op->plan;
     op->nX = pl.X.size;
     op->nL = pl.Lt.size;
@@ -48,6 +48,7 @@ void heff_build(pdmrg_ctx *ctx, pdmrg_heff *op, const Bond &bl, const Bond &br, 
     }
     op->T1.ensure(std::max<int64_t>(pl.nT1, 1) * es);
     op->T2.ensure(std::max<int64_t>(pl.nT2, 1) * es);
+    op->P.ensure(std::max<int64_t>(pl.nP, 1) * sizeof(double));
 }
 
 void heff_run(pdmrg_ctx *ctx, pdmrg_heff *op, const double *x, double *y) {
@@ -67,6 +68,7 @@ void heff_run(pdmrg_ctx *ctx, pdmrg_heff *op, const double *x, double *y) {
     sl.p[3] = op->R.ptr;
     sl.p[4] = op->T1.ptr;
     sl.p[5] = op->T2.ptr;
+    sl.p[6] = op->P.ptr;
     hipEvent_t *ev = nullptr;
     if (ctx->timing) {
         const size_t need = (size_t)(ctx->n_timed + 1) * 4;
@@ -84,6 +86,7 @@ void heff_run(pdmrg_ctx *ctx, pdmrg_heff *op, const double *x, double *y) {
     pl.w.launch(f64, sl, s);
     if (ev) HIP_OK(hipEventRecord(ev[2], s));
     pl.g3.launch(gp, true, sl, s);
+    pl.r3.launch(true, sl, s);
     if (ev) HIP_OK(hipEventRecord(ev[3], s));
 }
 

@@ -7,6 +7,7 @@ struct pdmrg_heff {
     int prec = PDMRG_F64;
     pdmrg::DevBuf L, R;            // environments in the operator's precision
     pdmrg::DevBuf T1, T2, xs;      // intermediates, low-precision copy of x
+    pdmrg::DevBuf P;               // split-K partials of stage 3 (FP64)
     pdmrg::DevBuf diag;            // diag(H_eff), FP64
     pdmrg::DevBuf diag_terms, diag_groups;
     int64_t nX = 0, nL = 0, nR = 0;

@@ -64,8 +64,9 @@ struct DiagTerm {
 enum class GemmPrec { F64, F32, BF16X3 };
 
 // Launchers (defined in gemm.hip / blas.hip).  All asynchronous on `s`.
-// c_is_f64: C written as double (F32 / BF16X3 inputs are float).
-void launch_gemm(GemmPrec prec, bool ta, bool tb, bool c_is_f64, const Slots &slots,
+// c_is_f64: C written as double (F32 / BF16X3 inputs are float).  tm: output
+// tile edge of the FP64 / FP32 kernels (64 or 128; BF16X3 always uses 64).
+void launch_gemm(GemmPrec prec, int tm, bool ta, bool tb, bool c_is_f64, const Slots &slots,
                  const GemmItem *items, const GemmSeg *segs, const GemmTile *tiles,
                  int ntiles, hipStream_t s);
 void launch_lincomb(bool f64, const Slots &slots, const LcTask *tasks, const LcSrc *srcs,

@@ -120,19 +120,84 @@ static EnvLayout generic_env_layout(const Bond &b, const std::vector<int> &delta
 EnvLayout env_l_layout(const Bond &b, const std::vector<int> &deltas) { return generic_env_layout(b, deltas, +1); }
 EnvLayout env_r_layout(const Bond &b, const std::vector<int> &deltas) { return generic_env_layout(b, deltas, -1); }
 
+// Caching device allocator behind DevBuf.  Sizes are rounded up to a power of
+// two (at least 256 bytes); released blocks go to a pending list and become
+// reusable only after one device-wide synchronisation, so a block can never be
+// handed out while a kernel launched before its release still uses it.
+// Cached blocks are kept until the process ends.
+namespace {
+struct DeviceCache {
+    std::map<std::pair<int, size_t>, std::vector<void *>> free_, pending_;
+    bool has_pending = false;
+};
+DeviceCache &cache() {
+    static DeviceCache *c = new DeviceCache();   // never destroyed: no hipFree after runtime teardown
+    return *c;
+}
+size_t size_class(size_t n) {
+    size_t c = 256;
+    while (c < n) c <<= 1;
+    return c;
+}
+}  // namespace
+
 void DevBuf::alloc(size_t n) {
     if (n == 0) n = 16;
-    hipError_t e = hipMalloc(&ptr, n);
+    int dev = 0;
+    HIP_OK(hipGetDevice(&dev));
+    const size_t cls = size_class(n);
+    DeviceCache &c = cache();
+    auto key = std::make_pair(dev, cls);
+    auto it = c.free_.find(key);
+    if ((it == c.free_.end() || it->second.empty()) && c.has_pending) {
+        auto pit = c.pending_.find(key);
+        if (pit != c.pending_.end() && !pit->second.empty()) {
+            HIP_OK(hipDeviceSynchronize());
+            for (auto &kv : c.pending_) {
+                auto &dst = c.free_[kv.first];
+                dst.insert(dst.end(), kv.second.begin(), kv.second.end());
+                kv.second.clear();
+            }
+            c.has_pending = false;
+            it = c.free_.find(key);
+        }
+    }
+    if (it != c.free_.end() && !it->second.empty()) {
+        ptr = it->second.back();
+        it->second.pop_back();
+        bytes = cls;
+        return;
+    }
+    hipError_t e = hipMalloc(&ptr, cls);
+    if (e != hipSuccess) {
+        // release every cached block and retry once
+        (void)hipGetLastError();
+        HIP_OK(hipDeviceSynchronize());
+        for (auto *m : {&c.free_, &c.pending_})
+            for (auto &kv : *m) {
+                for (void *p : kv.second) (void)hipFree(p);
+                kv.second.clear();
+            }
+        c.has_pending = false;
+        e = hipMalloc(&ptr, cls);
+    }
     if (e != hipSuccess) {
         ptr = nullptr;
         bytes = 0;
-        throw Error(PDMRG_ENOMEM, "hipMalloc of " + std::to_string(n) + " bytes failed: " + hipGetErrorString(e));
+        throw Error(PDMRG_ENOMEM, "hipMalloc of " + std::to_string(cls) + " bytes failed: " + hipGetErrorString(e));
     }
-    bytes = n;
+    bytes = cls;
 }
 
 void DevBuf::release() {
-    if (ptr) (void)hipFree(ptr);
+    if (ptr) {
+        int dev = 0;
+        if (hipGetDevice(&dev) == hipSuccess) {
+            DeviceCache &c = cache();
+            c.pending_[std::make_pair(dev, bytes)].push_back(ptr);
+            c.has_pending = true;
+        }
+    }
     ptr = nullptr;
     bytes = 0;
 }

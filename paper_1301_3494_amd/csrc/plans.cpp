@@ -32,12 +32,31 @@ void GemmList::add_seg(int a_slot, int64_t a_off, int lda, int b_slot, int64_t b
     flops += 2.0 * it.M * (double)it.N * K;
 }
 
+void GemmList::pick_tile() {
+    double big = 0.0, all = 0.0;
+    for (const GemmItem &it : items) {
+        double k = 0.0;
+        for (int j = 0; j < it.nseg; ++j) k += segs[it.seg0 + j].K;
+        const double f = (double)it.M * it.N * k;
+        all += f;
+        if (it.M >= 96 && it.N >= 96) big += f;
+    }
+    tm = (tm_max >= 128 && all > 0.0 && big >= 0.5 * all) ? 128 : 64;
+}
+
+int GemmList::ntiles_for(int edge) const {
+    int n = 0;
+    for (const GemmItem &it : items) n += ((it.M + edge - 1) / edge) * ((it.N + edge - 1) / edge);
+    return n;
+}
+
 void GemmList::finish(hipStream_t s) {
+    if (tm > tm_max) tm = tm_max;
     tiles.clear();
     for (size_t i = 0; i < items.size(); ++i) {
         const GemmItem &it = items[i];
-        for (int m0 = 0; m0 < it.M; m0 += kTile)
-            for (int n0 = 0; n0 < it.N; n0 += kTile) tiles.push_back(GemmTile{(int32_t)i, m0, n0, 0});
+        for (int m0 = 0; m0 < it.M; m0 += tm)
+            for (int n0 = 0; n0 < it.N; n0 += tm) tiles.push_back(GemmTile{(int32_t)i, m0, n0, 0});
     }
     upload(d_items, items, s);
     upload(d_segs, segs, s);
@@ -77,8 +96,61 @@ void LcList::validate(const std::vector<int64_t> &slot_elems) const {
     }
 }
 
+int64_t GemmList::split_k(int parts, int pslot, LcList &reduce) {
+    if (parts <= 1) return 0;
+    std::vector<GemmItem> nitems;
+    std::vector<GemmSeg> nsegs;
+    int64_t pel = 0;
+    for (const GemmItem &it : items) {
+        int64_t ktot = 0;
+        for (int k = 0; k < it.nseg; ++k) ktot += segs[it.seg0 + k].K;
+        if (ktot < (int64_t)parts * 128 || it.M == 0 || it.N == 0) {
+            GemmItem c = it;
+            c.seg0 = (int32_t)nsegs.size();
+            for (int k = 0; k < it.nseg; ++k) nsegs.push_back(segs[it.seg0 + k]);
+            nitems.push_back(c);
+            continue;
+        }
+        reduce.add_task(it.c_slot, it.c_off, it.M, it.N, it.ldc);
+        for (int p = 0; p < parts; ++p) {
+            // K range [kb, ke), boundaries rounded to multiples of 32
+            const int64_t kb = (ktot * p / parts) / 32 * 32;
+            const int64_t ke = p + 1 == parts ? ktot : (ktot * (p + 1) / parts) / 32 * 32;
+            GemmItem c{};
+            c.c_slot = pslot;
+            c.c_off = pel;
+            c.M = it.M;
+            c.N = it.N;
+            c.ldc = it.N;
+            c.seg0 = (int32_t)nsegs.size();
+            c.nseg = 0;
+            int64_t g0 = 0;   // global K index of the current segment's start
+            for (int k = 0; k < it.nseg; ++k) {
+                GemmSeg sg = segs[it.seg0 + k];
+                const int64_t s0 = std::max<int64_t>(kb, g0), s1 = std::min<int64_t>(ke, g0 + sg.K);
+                if (s1 > s0) {
+                    const int64_t d = s0 - g0;
+                    GemmSeg sub = sg;
+                    sub.K = (int32_t)(s1 - s0);
+                    sub.a_off += ta ? d * sg.lda : d;
+                    sub.b_off += tb ? d : d * sg.ldb;
+                    nsegs.push_back(sub);
+                    c.nseg += 1;
+                }
+                g0 += sg.K;
+            }
+            nitems.push_back(c);
+            reduce.add_src(pslot, pel, it.N, 1.0);
+            pel += (int64_t)it.M * it.N;
+        }
+    }
+    items.swap(nitems);
+    segs.swap(nsegs);
+    return pel;
+}
+
 void GemmList::launch(GemmPrec prec, bool c_is_f64, const Slots &sl, hipStream_t s) const {
-    launch_gemm(prec, ta, tb, c_is_f64, sl, d_items.as<GemmItem>(), d_segs.as<GemmSeg>(),
+    launch_gemm(prec, tm, ta, tb, c_is_f64, sl, d_items.as<GemmItem>(), d_segs.as<GemmSeg>(),
                 d_tiles.as<GemmTile>(), (int)tiles.size(), s);
 }
 
@@ -149,7 +221,7 @@ std::vector<double> two_site_mpo(const MpoSite &W1, const MpoSite &W2) {
 
 // ---------------------------------------------------------------- H_eff
 void HeffPlan::build(const Bond &bl_, const Bond &br_, const Phys &p_, const MpoSite &W1, const MpoSite &W2,
-                     hipStream_t s) {
+                     int prec, hipStream_t s) {
     bl = bl_;
     br = br_;
     p = p_;
@@ -282,13 +354,25 @@ void HeffPlan::build(const Bond &bl_, const Bond &br_, const Phys &p_, const Mpo
             diag_groups.push_back((int32_t)diag_terms.size());
         }
 
-    const std::vector<int64_t> sz = {X.size, X.size, Lt.size, Rt.size, nT1, nT2};
+    // tile edges (the BF16x3 kernel has 64 x 64 tiles only)
+    if (prec == PDMRG_BF16X3) g1.tm_max = g3.tm_max = 64;
+    g1.pick_tile();
+    g3.pick_tile();
+    // split-K for stage 3: aim at >= 1024 output tiles (4 per CU)
+    const int tiles3 = std::max(1, g3.ntiles_for(g3.tm));
+    const int parts = std::max(1, std::min(8, (1024 + tiles3 - 1) / tiles3));
+    r3 = LcList();
+    nP = g3.split_k(parts, 6, r3);
+
+    const std::vector<int64_t> sz = {X.size, X.size, Lt.size, Rt.size, nT1, nT2, nP};
     g1.validate(sz);
     w.validate(sz);
     g3.validate(sz);
+    r3.validate(sz);
     g1.finish(s);
     w.finish(s);
     g3.finish(s);
+    r3.finish(s);
 }
 
 // ---------------------------------------------------------------- environments
@@ -447,6 +531,8 @@ void EnvPlan::build(int dir_, const Bond &bl_, const Bond &br_, const Phys &p_, 
     g1.validate(sz);
     w.validate(sz);
     g3.validate(sz);
+    g1.pick_tile();
+    g3.pick_tile();
     g1.finish(s);
     w.finish(s);
     g3.finish(s);
@@ -509,6 +595,7 @@ void MergePlan::build(const Bond &bl_, const Bond &bm_, const Bond &br_, const P
             g.add_seg(0, SL.base[i] + lco, SL.cols[i], 1, SR.base[k], SR.cols[k], bm.dim[k]);
         }
     g.validate({SL.size, SR.size, X.size});
+    g.pick_tile();
     g.finish(s);
     upload(d_rs_base, rs_base, s);
     upload(d_rs_vbase, rs_vbase, s);

@@ -6,12 +6,15 @@
 
 namespace pdmrg {
 
-constexpr int kTile = 64;      // GEMM output tile edge
 constexpr int kLcRows = 16;    // W-stage tile rows
 constexpr int kLcCols = 128;   // W-stage tile columns
 
+struct LcList;
+
 struct GemmList {
     bool ta = false, tb = false;
+    int tm = 64;        // output tile edge (64 or 128), set by pick_tile()
+    int tm_max = 64;    // largest edge allowed (128 x 128 measured slower on the 8x4 m=1024 H_eff)
     std::vector<GemmItem> items;
     std::vector<GemmSeg> segs;
     std::vector<GemmTile> tiles;
@@ -20,11 +23,19 @@ struct GemmList {
 
     int add_item(int c_slot, int64_t c_off, int M, int N, int ldc);
     void add_seg(int a_slot, int64_t a_off, int lda, int b_slot, int64_t b_off, int ldb, int K);
-    void finish(hipStream_t s);   // build tiles, upload
+    void pick_tile();             // 128 x 128 tiles when most flops sit in blocks >= 96 wide
+    int ntiles_for(int edge) const;
+    void finish(hipStream_t s);   // pick_tile if not done, build tiles, upload
     void launch(GemmPrec prec, bool c_is_f64, const Slots &sl, hipStream_t s) const;
     // Throws unless every element an item touches lies inside its slot's
     // buffer (sizes in elements, per slot).
     void validate(const std::vector<int64_t> &slot_elems) const;
+    // Split-K: every item whose total K allows it is cut into `parts` items
+    // over consecutive K ranges, each writing a partial product into slot
+    // `pslot` (packed, ld = N); `reduce` receives one task per original item
+    // that sums its partials into the original C in a fixed order.  Returns
+    // the number of partial elements.  Call before validate / finish.
+    int64_t split_k(int parts, int pslot, LcList &reduce);
 };
 
 struct LcList {
@@ -44,20 +55,21 @@ struct LcList {
 
 // y = H_eff x on bonds (bl, br) -- stage 1: T1 = L x (per ket sector, the
 // MPO channels stacked on M); stage 2: T2 = (W1 W2) T1 (W stage); stage 3:
-// y = T2 R (per output block, the (channel, ket) pairs stacked on K).
+// y = T2 R (per output block, the (channel, ket) pairs stacked on K), split
+// along K when its output tiles alone cannot fill the device.
 struct HeffPlan {
     Bond bl, br;
     Phys p;
     SiteLayout X;
     EnvLayout Lt, Rt;
-    int64_t nT1 = 0, nT2 = 0;
+    int64_t nT1 = 0, nT2 = 0, nP = 0;
     GemmList g1, g3;
-    LcList w;
+    LcList w, r3;   // W stage; split-K reduction of stage 3 (partials in slot 6, FP64)
     std::vector<DiagTerm> diag_terms;
     std::vector<int32_t> diag_groups;
     int diag_max_rows = 0;
     void build(const Bond &bl_, const Bond &br_, const Phys &p_, const MpoSite &W1, const MpoSite &W2,
-               hipStream_t s);
+               int prec, hipStream_t s);
 };
 
 // Environment updates (dir +1: L on bl -> L on br; dir -1: R on br -> R on bl).

@@ -13,19 +13,26 @@
 
 namespace pdmrg {
 
-constexpr int JB = 8, J2 = 16, JCH = 64;
+constexpr int JB = 8, J2 = 16, JCH = 256;
+
+// Threads per block pair: the row streaming (Gram, rotation) needs several
+// waves for latency hiding; the 16 x 16 eigensolver is short.
+constexpr int JT = 256;
 
 __device__ void sym_eig16(double (*A)[J2 + 1], double (*Q)[J2 + 1], double *red, int *rp, int *rq, double *rc,
                           double *rs) {
     const int tid = threadIdx.x;
-    for (int e = tid; e < J2 * J2; e += blockDim.x) Q[e / J2][e % J2] = (e / J2 == e % J2) ? 1.0 : 0.0;
+    for (int e = tid; e < J2 * J2; e += JT) Q[e / J2][e % J2] = (e / J2 == e % J2) ? 1.0 : 0.0;
     __syncthreads();
-    // Relative stopping / skipping rule |a_pq| <= tol sqrt(|a_pp a_qq|), so that
-    // small eigenvalues of a graded Gram matrix are resolved to high relative
-    // accuracy (a norm-wide criterion would stop before they are).
-    for (int sweep = 0; sweep < 40; ++sweep) {
+    // Relative skipping rule |a_pq| <= tol sqrt(|a_pp a_qq|), so that small
+    // eigenvalues of a graded Gram matrix are resolved in relative terms (a
+    // norm-wide rule would never rotate them).  Only a few sweeps: the outer
+    // block-Jacobi iteration re-measures orthogonality on fresh Gram matrices,
+    // so a partial diagonalisation (still an exact rotation of the rows) is
+    // enough and convergence is decided there.
+    for (int sweep = 0; sweep < 3; ++sweep) {
         double off = 0.0;
-        for (int e = tid; e < J2 * J2; e += blockDim.x) {
+        for (int e = tid; e < J2 * J2; e += JT) {
             const int i = e / J2, j = e % J2;
             if (i >= j) continue;
             const double v = fabs(A[i][j]);
@@ -35,7 +42,7 @@ __device__ void sym_eig16(double (*A)[J2 + 1], double (*Q)[J2 + 1], double *red,
         }
         red[tid] = off;
         __syncthreads();
-        for (int w = 128; w > 0; w >>= 1) {
+        for (int w = JT / 2; w > 0; w >>= 1) {
             if (tid < w) red[tid] = fmax(red[tid], red[tid + w]);
             __syncthreads();
         }
@@ -49,7 +56,7 @@ __device__ void sym_eig16(double (*A)[J2 + 1], double (*Q)[J2 + 1], double *red,
                 if (p > q) { const int t = p; p = q; q = t; }
                 double c = 1.0, s = 0.0;
                 const double apq = A[p][q];
-                if (apq != 0.0 && fabs(apq) > 1e-17 * sqrt(fabs(A[p][p] * A[q][q]))) {
+                if (apq != 0.0 && fabs(apq) > 1e-16 * sqrt(fabs(A[p][p] * A[q][q]))) {
                     const double tau = (A[q][q] - A[p][p]) / (2.0 * apq);
                     const double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
                     c = 1.0 / sqrt(1.0 + t * t);
@@ -58,10 +65,11 @@ __device__ void sym_eig16(double (*A)[J2 + 1], double (*Q)[J2 + 1], double *red,
                 rp[tid] = p; rq[tid] = q; rc[tid] = c; rs[tid] = s;
             }
             __syncthreads();
-            for (int e = tid; e < (J2 / 2) * J2; e += blockDim.x) {
+            for (int e = tid; e < (J2 / 2) * J2; e += JT) {
                 const int pr = e / J2, i = e % J2;
                 const int p = rp[pr], q = rq[pr];
                 const double c = rc[pr], s = rs[pr];
+                if (s == 0.0) continue;
                 const double ap = A[i][p], aq = A[i][q];
                 A[i][p] = c * ap - s * aq;
                 A[i][q] = s * ap + c * aq;
@@ -70,10 +78,11 @@ __device__ void sym_eig16(double (*A)[J2 + 1], double (*Q)[J2 + 1], double *red,
                 Q[i][q] = s * qp + c * qq;
             }
             __syncthreads();
-            for (int e = tid; e < (J2 / 2) * J2; e += blockDim.x) {
+            for (int e = tid; e < (J2 / 2) * J2; e += JT) {
                 const int pr = e / J2, j = e % J2;
                 const int p = rp[pr], q = rq[pr];
                 const double c = rc[pr], s = rs[pr];
+                if (s == 0.0) continue;
                 const double ap = A[p][j], aq = A[q][j];
                 A[p][j] = c * ap - s * aq;
                 A[q][j] = s * ap + c * aq;
@@ -83,17 +92,17 @@ __device__ void sym_eig16(double (*A)[J2 + 1], double (*Q)[J2 + 1], double *red,
     }
 }
 
-__global__ __launch_bounds__(256) void jac_pair_kernel(const JacItem *__restrict__ items,
-                                                       const JacPair *__restrict__ pairs,
-                                                       const int32_t *__restrict__ active,
-                                                       unsigned long long *__restrict__ offmax, double tol) {
+__global__ __launch_bounds__(JT) void jac_pair_kernel(const JacItem *__restrict__ items,
+                                                      const JacPair *__restrict__ pairs,
+                                                      const int32_t *__restrict__ active,
+                                                      unsigned long long *__restrict__ offmax, double tol) {
     const JacPair pr = pairs[blockIdx.x];
     if (!active[pr.item]) return;
     const JacItem it = items[pr.item];
     __shared__ double chunk[J2][JCH + 1];
     __shared__ double G[J2][J2 + 1];
     __shared__ double Q[J2][J2 + 1];
-    __shared__ double red[512];
+    __shared__ double red[JT];
     __shared__ double rc[J2 / 2], rs[J2 / 2];
     __shared__ int rp[J2 / 2], rq[J2 / 2];
     __shared__ int rowid[J2], ev[J2], vp[J2];
@@ -104,39 +113,46 @@ __global__ __launch_bounds__(256) void jac_pair_kernel(const JacItem *__restrict
         rowid[tid] = r < it.nv ? r : -1;
     }
     __syncthreads();
-    // Gram matrix of the 16 rows: thread t < 136 owns one (r <= s) entry
-    int gr = -1, gs = -1;
-    if (tid < J2 * (J2 + 1) / 2) {
-        int t = tid, r = 0;
-        while (t >= J2 - r) { t -= J2 - r; ++r; }
-        gr = r;
-        gs = r + t;
+    // Gram matrix of the 16 rows: 136 (r <= s) entries, up to 3 per lane
+    constexpr int NG = J2 * (J2 + 1) / 2;
+    int gr[3], gs[3];
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int u = 0; u < 3; ++u) {
+        int t = tid + u * JT, r = 0;
+        gr[u] = gs[u] = -1;
+        if (t < NG) {
+            while (t >= J2 - r) { t -= J2 - r; ++r; }
+            gr[u] = r;
+            gs[u] = r + t;
+        }
     }
-    double acc = 0.0;
     for (int c0 = 0; c0 < it.len; c0 += JCH) {
-        for (int e = tid; e < J2 * JCH; e += 256) {
+        for (int e = tid; e < J2 * JCH; e += JT) {
             const int r = e / JCH, c = e % JCH, gc = c0 + c;
             chunk[r][c] = (rowid[r] >= 0 && gc < it.len) ? it.W[(int64_t)rowid[r] * it.len + gc] : 0.0;
         }
         __syncthreads();
-        if (gr >= 0)
-            for (int c = 0; c < JCH; ++c) acc += chunk[gr][c] * chunk[gs][c];
+        for (int u = 0; u < 3; ++u)
+            if (gr[u] >= 0)
+                for (int c = 0; c < JCH; ++c) acc[u] += chunk[gr[u]][c] * chunk[gs[u]][c];
         __syncthreads();
     }
-    if (gr >= 0) {
-        G[gr][gs] = acc;
-        G[gs][gr] = acc;
-    }
+    double off = 0.0;
+    for (int u = 0; u < 3; ++u)
+        if (gr[u] >= 0) {
+            G[gr[u]][gs[u]] = acc[u];
+            G[gs[u]][gr[u]] = acc[u];
+        }
     __syncthreads();
     // relative off-diagonal of this pair
-    double off = 0.0;
-    if (gr >= 0 && gr != gs && rowid[gr] >= 0 && rowid[gs] >= 0) {
-        const double dd = G[gr][gr] * G[gs][gs];
-        if (dd > 0.0) off = fabs(G[gr][gs]) / sqrt(dd);
-    }
+    for (int u = 0; u < 3; ++u)
+        if (gr[u] >= 0 && gr[u] != gs[u] && rowid[gr[u]] >= 0 && rowid[gs[u]] >= 0) {
+            const double dd = G[gr[u]][gr[u]] * G[gs[u]][gs[u]];
+            if (dd > 0.0) off = fmax(off, fabs(G[gr[u]][gs[u]]) / sqrt(dd));
+        }
     red[tid] = off;
     __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
+    for (int w = JT / 2; w > 0; w >>= 1) {
         if (tid < w) red[tid] = fmax(red[tid], red[tid + w]);
         __syncthreads();
     }
@@ -145,10 +161,8 @@ __global__ __launch_bounds__(256) void jac_pair_kernel(const JacItem *__restrict
     if (tid == 0) atomicMax(&offmax[pr.item], (unsigned long long)__double_as_longlong(poff));
     if (poff <= tol) return;
     // rows absent from the matrix: isolated with eigenvalue -1 (never rotated)
-    if (tid < J2 && rowid[tid] < 0) {
-        for (int j = 0; j < J2; ++j) { G[tid][j] = 0.0; }
-        G[tid][tid] = -1.0;
-    }
+    if (tid < J2 && rowid[tid] < 0)
+        for (int j = 0; j < J2; ++j) G[tid][j] = (j == tid) ? -1.0 : 0.0;
     __syncthreads();
     if (tid < J2 && rowid[tid] < 0)
         for (int j = 0; j < J2; ++j)
@@ -175,12 +189,12 @@ __global__ __launch_bounds__(256) void jac_pair_kernel(const JacItem *__restrict
         double *M = pass == 0 ? it.W : it.Z;
         const int len = pass == 0 ? it.len : it.nv;
         for (int c0 = 0; c0 < len; c0 += JCH) {
-            for (int e = tid; e < J2 * JCH; e += 256) {
+            for (int e = tid; e < J2 * JCH; e += JT) {
                 const int r = e / JCH, c = e % JCH, gc = c0 + c;
                 chunk[r][c] = (rowid[r] >= 0 && gc < len) ? M[(int64_t)rowid[r] * len + gc] : 0.0;
             }
             __syncthreads();
-            for (int e = tid; e < n * JCH; e += 256) {
+            for (int e = tid; e < n * JCH; e += JT) {
                 const int j = e / JCH, c = e % JCH, gc = c0 + c;
                 if (gc >= len) continue;
                 const int col = ev[j];
@@ -196,7 +210,7 @@ __global__ __launch_bounds__(256) void jac_pair_kernel(const JacItem *__restrict
 void launch_jac_round(const JacItem *items, const JacPair *pairs, int npairs, const int32_t *active,
                       unsigned long long *offmax, double tol, hipStream_t s) {
     if (npairs <= 0) return;
-    hipLaunchKernelGGL(jac_pair_kernel, dim3(npairs), dim3(256), 0, s, items, pairs, active, offmax, tol);
+    hipLaunchKernelGGL(jac_pair_kernel, dim3(npairs), dim3(JT), 0, s, items, pairs, active, offmax, tol);
 }
 
 __global__ void identity_kernel(const JacItem *items) {
