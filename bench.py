@@ -120,6 +120,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--prec", default="f32", choices=["f64", "f32", "bf16x3"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--autotune", type=int, default=1, choices=[0, 1, 2],
+                    help="tile-shape selection: 0 cost model, 1 timed at operator creation, 2 = 1 + log")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only (the regions of one sweep share a device); "
@@ -132,6 +134,7 @@ def main():
 
     ctx = pl.Context(0)
     wl = build_workload(ctx, pl, synth, np, torch)
+    pl.set_autotune(ctx, args.autotune)
     c = wl["center"]
     W1, W2 = wl["mpo"].site(c), wl["mpo"].site(c + 1)
     results = {}
@@ -169,6 +172,7 @@ def main():
         "dtype": args.prec,
         "data": "synthetic (seeded random MPS, environments built on the GPU)",
         "config": {"workload": "heisenberg_cyl8x4_m1024_centre_heff", "lattice": "8x4 cylinder, snake order",
+                   "autotune": args.autotune,
                    "m": wl["m"], "mpo_D": int(W1.W.shape[0]), "psi_elems": info["n_psi"],
                    "flops_per_matvec": info["flops"], "dense_equiv_flops": 4.0 * 14 * 4 * 1024 ** 3},
         "roofline": {"bound": "mfma", "kernel": "gemm stage %d (%s)" % (st + 1, "L.psi" if st == 0 else "T2.R"),

@@ -117,6 +117,18 @@ int pdmrg_ctx_destroy(pdmrg_ctx *ctx);
  * (ms) of stage 1 (L psi), 2 (W), 3 (. R) and their sum over the calls since
  * timing was enabled. */
 int pdmrg_ctx_set_timing(pdmrg_ctx *ctx, int enable);
+/* Tile-shape selection of the grouped GEMMs of every H_eff built afterwards
+ * on this context (the contraction order of Sec. II is unchanged):
+ *   0  (default) a cost model of padded MFMA work and device fill;
+ *   1  each allowed shape of stage 1 and stage 3 is timed on the operator's
+ *      own buffers when it is created (a few ms), and the fastest is kept in a
+ *      process-wide cache keyed by device, precision, bond sectors and MPO
+ *      widths, so later operators of the same shape are not re-timed;
+ *   2  as 1, with one line per tuned signature on stderr.
+ * Results are identical for every shape in FP64; in FP32 / BF16x3 they can
+ * differ in the last bits (the split-K partition follows the tile count).
+ * Returns PDMRG_EINVAL for another level. */
+int pdmrg_ctx_set_autotune(pdmrg_ctx *ctx, int level);
 int pdmrg_ctx_timing(pdmrg_ctx *ctx, double *ms_stage /*[4]: L.psi, W, .R, total*/,
                      int64_t *n_calls);
 

@@ -63,6 +63,14 @@ int pdmrg_ctx_set_timing(pdmrg_ctx *ctx, int enable) {
     API_END
 }
 
+int pdmrg_ctx_set_autotune(pdmrg_ctx *ctx, int level) {
+    API_BEGIN
+    PD_REQUIRE(ctx, PDMRG_EINVAL, "null ctx");
+    PD_REQUIRE(level >= 0 && level <= 2, PDMRG_EINVAL, "autotune level must be 0, 1 or 2");
+    ctx->autotune = level;
+    API_END
+}
+
 int pdmrg_ctx_timing(pdmrg_ctx *ctx, double *ms_stage, int64_t *n_calls) {
     API_BEGIN
     PD_REQUIRE(ctx && ms_stage && n_calls, PDMRG_EINVAL, "null argument");

@@ -7,28 +7,49 @@
 
 namespace pdmrg {
 
-constexpr int LC_TR = 16, LC_TC = 128;
-
 // ------------------------------------------------------------ W stage
+// One workgroup per tile = a run of kLcChunk consecutive elements of a task's
+// rows x cols block in row-major order, so narrow sector blocks keep every
+// thread busy.  Each thread owns kLcChunk / 256 elements and keeps their loads
+// of one source in flight together; sources are summed in list order.
 template <typename T>
 __global__ __launch_bounds__(256) void lincomb_kernel(Slots slots, const LcTask *__restrict__ tasks,
                                                       const LcSrc *__restrict__ srcs,
                                                       const LcTile *__restrict__ tiles) {
+    constexpr int U = kLcChunk / 256;
     const LcTile tl = tiles[blockIdx.x];
     const LcTask tk = tasks[tl.task];
-    T *dst = static_cast<T *>(const_cast<void *>(slots.p[tk.dst_slot])) + tk.dst_off;
-    const int c = tl.c0 + (threadIdx.x % LC_TC);
-    if (c >= tk.cols) return;
-    const int rmax = min(tk.rows, tl.r0 + LC_TR);
-    for (int r = tl.r0 + (int)(threadIdx.x / LC_TC); r < rmax; r += 256 / LC_TC) {
-        T acc = 0;
-        for (int j = 0; j < tk.nsrc; ++j) {
-            const LcSrc sj = srcs[tk.src0 + j];
-            const T *src = static_cast<const T *>(slots.p[sj.slot]) + sj.off;
-            acc += (T)sj.coef * src[(int64_t)r * sj.ld + c];
-        }
-        dst[(int64_t)r * tk.ld + c] = acc;
+    // rows * cols < 2^31 (checked when the list is built)
+    const unsigned n = (unsigned)tk.rows * (unsigned)tk.cols;
+    const unsigned e0 = (unsigned)tl.r0 * kLcChunk;
+    int64_t roff[U];
+    int cc[U];
+    bool ok[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const unsigned e = e0 + threadIdx.x + 256 * u;
+        ok[u] = e < n;
+        const unsigned r = ok[u] ? e / (unsigned)tk.cols : 0u;
+        cc[u] = ok[u] ? (int)(e - r * (unsigned)tk.cols) : 0;
+        roff[u] = r;
     }
+    T acc[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc[u] = 0;
+    for (int j = 0; j < tk.nsrc; ++j) {
+        const LcSrc sj = srcs[tk.src0 + j];
+        const T *src = static_cast<const T *>(slots.p[sj.slot]) + sj.off;
+        const T cf = (T)sj.coef;
+        T v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = ok[u] ? src[roff[u] * sj.ld + cc[u]] : T(0);
+#pragma unroll
+        for (int u = 0; u < U; ++u) acc[u] += cf * v[u];
+    }
+    T *dst = static_cast<T *>(const_cast<void *>(slots.p[tk.dst_slot])) + tk.dst_off;
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+        if (ok[u]) dst[roff[u] * tk.ld + cc[u]] = acc[u];
 }
 
 void launch_lincomb(bool f64, const Slots &slots, const LcTask *tasks, const LcSrc *srcs,

@@ -1,22 +1,27 @@
 // Grouped block-sparse GEMM on CDNA4 matrix cores (gfx950).
 //
-// One launch runs a list of 64 x 64 output tiles drawn from many GEMM items
-// (the U(1) sector blocks of one contraction, possibly of several bonds).
-// Each item is C (M x N) = sum over its K-segments of op(A) op(B); the
-// segments let one output block accumulate products whose operands live in
-// different places (e.g. the physical-index sum of an environment update).
+// One launch runs a list of output tiles drawn from many GEMM items (the U(1)
+// sector blocks of one contraction, possibly of several bonds).  Each item is
+// C (M x N) = sum over its K-segments of op(A) op(B); the segments let one
+// output block accumulate products whose operands live in different places
+// (e.g. the physical-index sum of an environment update).  An item may stack
+// blocks with different output leading dimensions along M through a row
+// offset table.
 //
-// Workgroup: 256 threads = 4 wave64, each wave owns a 32 x 32 quarter of the
-// tile as 2 x 2 MFMA 16 x 16 blocks.  Operands are staged through LDS:
-//   FP64 / FP32  : v_mfma_f64_16x16x4 / v_mfma_f32_16x16x4 on double-buffered
-//                  LDS tiles (see below);
-//   BF16x3       : FP32 operands split on the fly into bf16 hi + lo halves
-//                  (x = hi + lo, both rounded to nearest even), K-contiguous
-//                  LDS tiles, C += hi*hi' + hi*lo' + lo*hi' with
-//                  v_mfma_f32_16x16x32_bf16 and FP32 accumulation.
-// Global loads of the next K-step are issued before the MFMAs of the current
-// one.  Tiles are mapped XCD-major: the 8 XCDs each receive a contiguous run
-// of the tile list, so the tiles that share an operand panel share an L2.
+// Workgroup: 256 threads = 4 wave64.  FP64 / FP32 tiles are BM x BN with the
+// waves on a WGM x WGN grid, each wave owning an (BM/WGM) x (BN/WGN) sub-tile
+// of 16 x 16 MFMA blocks (v_mfma_f64_16x16x4 / v_mfma_f32_16x16x4).  The
+// BF16x3 kernel (64 x 64 tiles) splits FP32 operands on the fly into bf16
+// hi + lo halves (x = hi + lo, both rounded to nearest even) in K-contiguous
+// LDS tiles and accumulates hi*hi' + hi*lo' + lo*hi' with
+// v_mfma_f32_16x16x32_bf16 in FP32.
+//
+// Operands are read with buffer loads: the descriptor of each segment spans
+// its operand and an offset outside it returns zero, so ragged tile edges need
+// no branches.  Global loads of the next K-step are issued before the MFMAs of
+// the current one.  Tiles are mapped XCD-major: the 8 XCDs each receive a
+// contiguous run of the tile list, so the tiles that share an operand panel
+// share an L2.
 #include "kernels.hpp"
 
 namespace pdmrg {
@@ -26,7 +31,7 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef unsigned short us8 __attribute__((ext_vector_type(8)));
 
-constexpr int BM = 64, BN = 64, NT = 256;
+constexpr int NT = 256;
 
 __device__ __forceinline__ d4 mfma16(double a, double b, d4 c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -44,40 +49,69 @@ __device__ __forceinline__ int map_tile(int ntiles) {
     return (blockIdx.x % 8) * chunk + blockIdx.x / 8;
 }
 
+// A pointer that is the same in every lane, held in scalar registers.
+__device__ __forceinline__ void *uniform_ptr(const void *p) {
+    const uint64_t v = reinterpret_cast<uint64_t>(p);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return reinterpret_cast<void *>(((uint64_t)hi << 32) | lo);
+}
+
+// Raw buffer descriptor over [p, p + 2 GiB): an offset at or beyond kOutOfRange
+// reads as zero.
+constexpr unsigned kOutOfRange = 0x80000000u;
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t operand_rsrc(const void *p) {
+    return __builtin_amdgcn_make_buffer_rsrc(uniform_ptr(p), 0, 0x7fffffff, 0x00020000);
+}
+__device__ __forceinline__ double buf_load(__amdgpu_buffer_rsrc_t r, unsigned off, double) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+__device__ __forceinline__ float buf_load(__amdgpu_buffer_rsrc_t r, unsigned off, float) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+
+// Element offset of row r of an item's C.
+__device__ __forceinline__ int64_t c_row(const GemmItem &it, const int64_t *__restrict__ rowoff, int r) {
+    return it.rmap >= 0 ? rowoff[it.rmap + r] : (int64_t)r * it.ldc;
+}
+
 // ---------------------------------------------------------------- FP64 / FP32
 // LDS tiles are M-major (A) / N-major (B) with the K index contiguous and an
-// odd row stride (BK + 1 elements), so both the global->LDS stores of either
+// odd row stride (BK + 1 elements), so the global->LDS stores of either
 // operand orientation and the MFMA operand reads (16 lanes = 16 rows, same k)
-// are free of bank conflicts.  Two LDS buffers: the next K-step's global loads
-// are in flight during the current MFMAs and one barrier separates steps.
+// spread over the banks.  Two LDS buffers: the next K-step's global loads are
+// in flight during the current MFMAs and one barrier separates steps.
 template <typename T> struct KStep;
 template <> struct KStep<double> { static constexpr int BK = 16; };
 template <> struct KStep<float> { static constexpr int BK = 32; };
 
-template <typename T, typename TC, bool TA, bool TB, int TM>
+template <typename T, typename TC, bool TA, bool TB, int BM, int BN, int WGM>
 __global__ __launch_bounds__(NT) void gemm_kmajor(Slots slots, const GemmItem *__restrict__ items,
                                                   const GemmSeg *__restrict__ segs,
-                                                  const GemmTile *__restrict__ tiles, int ntiles) {
-    // TM x TM output tile; each wave owns a (TM/2) x (TM/2) quarter as
-    // (TM/32) x (TM/32) MFMA 16 x 16 blocks.
-    constexpr int BM = TM, BN = TM, BK = KStep<T>::BK, LDK = BK + 1;
-    constexpr int NL = BM * BK / NT;   // elements of each operand loaded per thread and step
-    constexpr int WB = TM / 32;        // MFMA blocks per wave and dimension
+                                                  const GemmTile *__restrict__ tiles,
+                                                  const int64_t *__restrict__ rowoff, int ntiles) {
+    constexpr int WGN = 4 / WGM;
+    constexpr int BK = KStep<T>::BK, LDK = BK + 1;
+    constexpr int NLA = BM * BK / NT, NLB = BN * BK / NT;   // elements per thread and step
+    constexpr int SM = BM / WGM, SN = BN / WGN;              // wave sub-tile
+    constexpr int WBM = SM / 16, WBN = SN / 16;              // MFMA blocks per wave
+    static_assert(NT % BK == 0 && NT % BM == 0 && NT % BN == 0 && WBM >= 1 && WBN >= 1, "tile shape");
     const int t = map_tile(ntiles);
     if (t >= ntiles) return;
     const GemmTile tile = tiles[t];
     const GemmItem it = items[tile.item];
     __shared__ T As[2][BM][LDK];
     __shared__ T Bs[2][BN][LDK];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = (wave >> 1) * (TM / 2), wn = (wave & 1) * (TM / 2);
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wm = (wave / WGN) * SM, wn = (wave % WGN) * SN;
     const int m0 = tile.m0, n0 = tile.n0;
     using V4 = typename Acc<T>::type;
-    V4 acc[WB][WB];
+    V4 acc[WBM][WBN];
 #pragma unroll
-    for (int i = 0; i < WB; ++i)
+    for (int i = 0; i < WBM; ++i)
 #pragma unroll
-        for (int j = 0; j < WB; ++j) acc[i][j] = V4{0, 0, 0, 0};
+        for (int j = 0; j < WBN; ++j) acc[i][j] = V4{0, 0, 0, 0};
 
     // coalesced thread -> element maps: consecutive threads walk the
     // contiguous global index of each operand
@@ -85,72 +119,89 @@ __global__ __launch_bounds__(NT) void gemm_kmajor(Slots slots, const GemmItem *_
     //               M contiguous (TA):  m = tid % BM, k = tid / BM + u * (NT / BM)
     //   B (K x N):  N contiguous (!TB): n = tid % BN, k = tid / BN + u * (NT / BN)
     //               K contiguous (TB):  k = tid % BK, n = tid / BK + u * (NT / BK)
-    T ra[NL], rb[NL];
-    auto load = [&](const GemmSeg &sg, int k0) {
-        const T *A = static_cast<const T *>(slots.p[sg.a_slot]) + sg.a_off;
-        const T *B = static_cast<const T *>(slots.p[sg.b_slot]) + sg.b_off;
+    auto a_idx = [&](int u, int &m, int &k) {
+        if (TA) { m = tid % BM; k = tid / BM + u * (NT / BM); }
+        else    { k = tid % BK; m = tid / BK + u * (NT / BK); }
+    };
+    auto b_idx = [&](int u, int &n, int &k) {
+        if (TB) { k = tid % BK; n = tid / BK + u * (NT / BK); }
+        else    { n = tid % BN; k = tid / BN + u * (NT / BN); }
+    };
+    T ra[NLA], rb[NLB];
+    int K = 0, lda = 0, ldb = 0;
+    __amdgpu_buffer_rsrc_t rA, rB;
+    auto set_seg = [&](const GemmSeg &sg) {
+        K = __builtin_amdgcn_readfirstlane(sg.K);
+        lda = __builtin_amdgcn_readfirstlane(sg.lda);
+        ldb = __builtin_amdgcn_readfirstlane(sg.ldb);
+        rA = operand_rsrc(static_cast<const T *>(slots.p[sg.a_slot]) + sg.a_off);
+        rB = operand_rsrc(static_cast<const T *>(slots.p[sg.b_slot]) + sg.b_off);
+    };
+    auto load = [&](int k0) {
 #pragma unroll
-        for (int u = 0; u < NL; ++u) {
-            int am, ak, bn, bk;
-            if (TA) { am = tid % BM; ak = tid / BM + u * (NT / BM); }
-            else    { ak = tid % BK; am = tid / BK + u * (NT / BK); }
-            if (TB) { bk = tid % BK; bn = tid / BK + u * (NT / BK); }
-            else    { bn = tid % BN; bk = tid / BN + u * (NT / BN); }
-            const int gm = m0 + am, gk = k0 + ak, gn = n0 + bn, gkb = k0 + bk;
-            ra[u] = (gm < it.M && gk < sg.K)
-                        ? (TA ? A[(int64_t)gk * sg.lda + gm] : A[(int64_t)gm * sg.lda + gk])
-                        : T(0);
-            rb[u] = (gn < it.N && gkb < sg.K)
-                        ? (TB ? B[(int64_t)gn * sg.ldb + gkb] : B[(int64_t)gkb * sg.ldb + gn])
-                        : T(0);
+        for (int u = 0; u < NLA; ++u) {
+            int m, k;
+            a_idx(u, m, k);
+            const int gm = m0 + m, gk = k0 + k;
+            const unsigned off = TA ? (unsigned)(gk * lda + gm) : (unsigned)(gm * lda + gk);
+            ra[u] = buf_load(rA, (gm < it.M && gk < K) ? off * (unsigned)sizeof(T) : kOutOfRange, T());
+        }
+#pragma unroll
+        for (int u = 0; u < NLB; ++u) {
+            int n, k;
+            b_idx(u, n, k);
+            const int gn = n0 + n, gk = k0 + k;
+            const unsigned off = TB ? (unsigned)(gn * ldb + gk) : (unsigned)(gk * ldb + gn);
+            rb[u] = buf_load(rB, (gn < it.N && gk < K) ? off * (unsigned)sizeof(T) : kOutOfRange, T());
         }
     };
     auto store = [&](int buf) {
 #pragma unroll
-        for (int u = 0; u < NL; ++u) {
-            int am, ak, bn, bk;
-            if (TA) { am = tid % BM; ak = tid / BM + u * (NT / BM); }
-            else    { ak = tid % BK; am = tid / BK + u * (NT / BK); }
-            if (TB) { bk = tid % BK; bn = tid / BK + u * (NT / BK); }
-            else    { bn = tid % BN; bk = tid / BN + u * (NT / BN); }
-            As[buf][am][ak] = ra[u];
-            Bs[buf][bn][bk] = rb[u];
+        for (int u = 0; u < NLA; ++u) {
+            int m, k;
+            a_idx(u, m, k);
+            As[buf][m][k] = ra[u];
+        }
+#pragma unroll
+        for (int u = 0; u < NLB; ++u) {
+            int n, k;
+            b_idx(u, n, k);
+            Bs[buf][n][k] = rb[u];
         }
     };
 
     int sidx = 0, k0 = 0;
     while (sidx < it.nseg && segs[it.seg0 + sidx].K <= 0) ++sidx;
-    GemmSeg sg;
     int buf = 0;
     if (sidx < it.nseg) {
-        sg = segs[it.seg0 + sidx];
-        load(sg, 0);
+        set_seg(segs[it.seg0 + sidx]);
+        load(0);
         store(0);
     }
     __syncthreads();
     while (sidx < it.nseg) {
         // advance to the next step and prefetch it
         k0 += BK;
-        if (k0 >= sg.K) {
+        if (k0 >= K) {
             k0 = 0;
             ++sidx;
             while (sidx < it.nseg && segs[it.seg0 + sidx].K <= 0) ++sidx;
-            if (sidx < it.nseg) sg = segs[it.seg0 + sidx];
+            if (sidx < it.nseg) set_seg(segs[it.seg0 + sidx]);
         }
         const bool more = sidx < it.nseg;
-        if (more) load(sg, k0);
+        if (more) load(k0);
 #pragma unroll
         for (int kk = 0; kk < BK; kk += 4) {
             const int kr = kk + (lane >> 4), c = lane & 15;
-            T a[WB], b[WB];
+            T a[WBM], b[WBN];
 #pragma unroll
-            for (int i = 0; i < WB; ++i) a[i] = As[buf][wm + i * 16 + c][kr];
+            for (int i = 0; i < WBM; ++i) a[i] = As[buf][wm + i * 16 + c][kr];
 #pragma unroll
-            for (int j = 0; j < WB; ++j) b[j] = Bs[buf][wn + j * 16 + c][kr];
+            for (int j = 0; j < WBN; ++j) b[j] = Bs[buf][wn + j * 16 + c][kr];
 #pragma unroll
-            for (int i = 0; i < WB; ++i)
+            for (int i = 0; i < WBM; ++i)
 #pragma unroll
-                for (int j = 0; j < WB; ++j) acc[i][j] = mfma16(a[i], b[j], acc[i][j]);
+                for (int j = 0; j < WBN; ++j) acc[i][j] = mfma16(a[i], b[j], acc[i][j]);
         }
         if (more) store(buf ^ 1);
         __syncthreads();
@@ -161,16 +212,19 @@ __global__ __launch_bounds__(NT) void gemm_kmajor(Slots slots, const GemmItem *_
     constexpr bool kF64 = sizeof(T) == 8;
     TC *C = static_cast<TC *>(const_cast<void *>(slots.p[it.c_slot])) + it.c_off;
 #pragma unroll
-    for (int i = 0; i < WB; ++i)
+    for (int i = 0; i < WBM; ++i)
 #pragma unroll
-        for (int j = 0; j < WB; ++j)
+        for (int r = 0; r < 4; ++r) {
+            const int row = kF64 ? r * 4 + (lane >> 4) : (lane >> 4) * 4 + r;
+            const int gm = m0 + wm + i * 16 + row;
+            if (gm >= it.M) continue;
+            TC *Cr = C + c_row(it, rowoff, gm);
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int row = kF64 ? r * 4 + (lane >> 4) : (lane >> 4) * 4 + r;
-                const int gm = m0 + wm + i * 16 + row;
+            for (int j = 0; j < WBN; ++j) {
                 const int gn = n0 + wn + j * 16 + (lane & 15);
-                if (gm < it.M && gn < it.N) C[(int64_t)gm * it.ldc + gn] = (TC)acc[i][j][r];
+                if (gn < it.N) Cr[gn] = (TC)acc[i][j][r];
             }
+        }
 }
 
 // ---------------------------------------------------------------- BF16 x3
@@ -187,7 +241,9 @@ __device__ __forceinline__ float bf16_to_f32(unsigned short h) {
 template <typename TC, bool TA, bool TB>
 __global__ __launch_bounds__(NT) void gemm_bf16x3(Slots slots, const GemmItem *__restrict__ items,
                                                   const GemmSeg *__restrict__ segs,
-                                                  const GemmTile *__restrict__ tiles, int ntiles) {
+                                                  const GemmTile *__restrict__ tiles,
+                                                  const int64_t *__restrict__ rowoff, int ntiles) {
+    constexpr int BM = 64, BN = 64;
     constexpr int BK = 32, LD = BK + 8;   // 80-byte LDS rows keep 16-byte alignment
     const int t = map_tile(ntiles);
     if (t >= ntiles) return;
@@ -278,58 +334,76 @@ __global__ __launch_bounds__(NT) void gemm_bf16x3(Slots slots, const GemmItem *_
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int r = 0; r < 4; ++r) {
+            const int gm = m0 + wm + i * 16 + (lane >> 4) * 4 + r;
+            if (gm >= it.M) continue;
+            TC *Cr = C + c_row(it, rowoff, gm);
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int gm = m0 + wm + i * 16 + (lane >> 4) * 4 + r;
+            for (int j = 0; j < 2; ++j) {
                 const int gn = n0 + wn + j * 16 + (lane & 15);
-                if (gm < it.M && gn < it.N) C[(int64_t)gm * it.ldc + gn] = (TC)acc[i][j][r];
+                if (gn < it.N) Cr[gn] = (TC)acc[i][j][r];
             }
+        }
 }
 
 // ---------------------------------------------------------------- launcher
-template <typename T, typename TC, int TM>
-static void dispatch_tm(bool ta, bool tb, dim3 g, hipStream_t s, const Slots &sl, const GemmItem *it,
-                        const GemmSeg *sg, const GemmTile *tl, int n) {
-    if (!ta && !tb) hipLaunchKernelGGL((gemm_kmajor<T, TC, false, false, TM>), g, dim3(NT), 0, s, sl, it, sg, tl, n);
-    else if (ta && !tb) hipLaunchKernelGGL((gemm_kmajor<T, TC, true, false, TM>), g, dim3(NT), 0, s, sl, it, sg, tl, n);
-    else if (!ta && tb) hipLaunchKernelGGL((gemm_kmajor<T, TC, false, true, TM>), g, dim3(NT), 0, s, sl, it, sg, tl, n);
-    else hipLaunchKernelGGL((gemm_kmajor<T, TC, true, true, TM>), g, dim3(NT), 0, s, sl, it, sg, tl, n);
+struct GemmArgs {
+    Slots sl;
+    const GemmItem *it;
+    const GemmSeg *sg;
+    const GemmTile *tl;
+    const int64_t *ro;
+    int n;
+};
+
+template <typename T, typename TC, int BM, int BN, int WGM>
+static void dispatch_shape(bool ta, bool tb, dim3 g, hipStream_t s, const GemmArgs &a) {
+    if (!ta && !tb)
+        hipLaunchKernelGGL((gemm_kmajor<T, TC, false, false, BM, BN, WGM>), g, dim3(NT), 0, s, a.sl, a.it, a.sg, a.tl, a.ro, a.n);
+    else if (ta && !tb)
+        hipLaunchKernelGGL((gemm_kmajor<T, TC, true, false, BM, BN, WGM>), g, dim3(NT), 0, s, a.sl, a.it, a.sg, a.tl, a.ro, a.n);
+    else if (!ta && tb)
+        hipLaunchKernelGGL((gemm_kmajor<T, TC, false, true, BM, BN, WGM>), g, dim3(NT), 0, s, a.sl, a.it, a.sg, a.tl, a.ro, a.n);
+    else
+        hipLaunchKernelGGL((gemm_kmajor<T, TC, true, true, BM, BN, WGM>), g, dim3(NT), 0, s, a.sl, a.it, a.sg, a.tl, a.ro, a.n);
 }
 
 template <typename T, typename TC>
-static void dispatch_kmajor(int tm, bool ta, bool tb, dim3 g, hipStream_t s, const Slots &sl,
-                            const GemmItem *it, const GemmSeg *sg, const GemmTile *tl, int n) {
-    if (tm == 128) dispatch_tm<T, TC, 128>(ta, tb, g, s, sl, it, sg, tl, n);
-    else dispatch_tm<T, TC, 64>(ta, tb, g, s, sl, it, sg, tl, n);
+static void dispatch_kmajor(TileShape shape, bool ta, bool tb, dim3 g, hipStream_t s, const GemmArgs &a) {
+    switch (shape) {
+        case TileShape::T64x64: dispatch_shape<T, TC, 64, 64, 2>(ta, tb, g, s, a); break;
+        case TileShape::T128x32: dispatch_shape<T, TC, 128, 32, 4>(ta, tb, g, s, a); break;
+        case TileShape::T32x128: dispatch_shape<T, TC, 32, 128, 1>(ta, tb, g, s, a); break;
+        case TileShape::T128x128: dispatch_shape<T, TC, 128, 128, 2>(ta, tb, g, s, a); break;
+    }
 }
 
 template <typename TC>
-static void dispatch_bf16(bool ta, bool tb, dim3 g, hipStream_t s, const Slots &sl,
-                          const GemmItem *it, const GemmSeg *sg, const GemmTile *tl, int n) {
-    if (!ta && !tb) hipLaunchKernelGGL((gemm_bf16x3<TC, false, false>), g, dim3(NT), 0, s, sl, it, sg, tl, n);
-    else if (ta && !tb) hipLaunchKernelGGL((gemm_bf16x3<TC, true, false>), g, dim3(NT), 0, s, sl, it, sg, tl, n);
-    else if (!ta && tb) hipLaunchKernelGGL((gemm_bf16x3<TC, false, true>), g, dim3(NT), 0, s, sl, it, sg, tl, n);
-    else hipLaunchKernelGGL((gemm_bf16x3<TC, true, true>), g, dim3(NT), 0, s, sl, it, sg, tl, n);
+static void dispatch_bf16(bool ta, bool tb, dim3 g, hipStream_t s, const GemmArgs &a) {
+    if (!ta && !tb) hipLaunchKernelGGL((gemm_bf16x3<TC, false, false>), g, dim3(NT), 0, s, a.sl, a.it, a.sg, a.tl, a.ro, a.n);
+    else if (ta && !tb) hipLaunchKernelGGL((gemm_bf16x3<TC, true, false>), g, dim3(NT), 0, s, a.sl, a.it, a.sg, a.tl, a.ro, a.n);
+    else if (!ta && tb) hipLaunchKernelGGL((gemm_bf16x3<TC, false, true>), g, dim3(NT), 0, s, a.sl, a.it, a.sg, a.tl, a.ro, a.n);
+    else hipLaunchKernelGGL((gemm_bf16x3<TC, true, true>), g, dim3(NT), 0, s, a.sl, a.it, a.sg, a.tl, a.ro, a.n);
 }
 
-void launch_gemm(GemmPrec prec, int tm, bool ta, bool tb, bool c_is_f64, const Slots &slots,
-                 const GemmItem *items, const GemmSeg *segs, const GemmTile *tiles, int ntiles,
-                 hipStream_t s) {
+void launch_gemm(GemmPrec prec, TileShape shape, bool ta, bool tb, bool c_is_f64, const Slots &slots,
+                 const GemmItem *items, const GemmSeg *segs, const GemmTile *tiles, const int64_t *rowoff,
+                 int ntiles, hipStream_t s) {
     if (ntiles <= 0) return;
     const int chunk = (ntiles + 7) / 8;
     dim3 grid(chunk * 8);
+    const GemmArgs a{slots, items, segs, tiles, rowoff, ntiles};
     switch (prec) {
         case GemmPrec::F64:
-            dispatch_kmajor<double, double>(tm, ta, tb, grid, s, slots, items, segs, tiles, ntiles);
+            dispatch_kmajor<double, double>(shape, ta, tb, grid, s, a);
             break;
         case GemmPrec::F32:
-            if (c_is_f64) dispatch_kmajor<float, double>(tm, ta, tb, grid, s, slots, items, segs, tiles, ntiles);
-            else dispatch_kmajor<float, float>(tm, ta, tb, grid, s, slots, items, segs, tiles, ntiles);
+            if (c_is_f64) dispatch_kmajor<float, double>(shape, ta, tb, grid, s, a);
+            else dispatch_kmajor<float, float>(shape, ta, tb, grid, s, a);
             break;
         case GemmPrec::BF16X3:
-            if (c_is_f64) dispatch_bf16<double>(ta, tb, grid, s, slots, items, segs, tiles, ntiles);
-            else dispatch_bf16<float>(ta, tb, grid, s, slots, items, segs, tiles, ntiles);
+            if (c_is_f64) dispatch_bf16<double>(ta, tb, grid, s, a);
+            else dispatch_bf16<float>(ta, tb, grid, s, a);
             break;
     }
 }

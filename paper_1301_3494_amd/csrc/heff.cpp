@@ -1,8 +1,107 @@
 // Two-site effective Hamiltonian operator (Sec. II): plan + environments in
 // the compute precision + intermediates.
+#include <cstdio>
+#include <map>
+#include <mutex>
+#include <sstream>
+
 #include "internal.hpp"
 
 namespace pdmrg {
+
+namespace {
+std::mutex g_tune_mu;
+std::map<std::string, std::pair<int, int>> &tune_cache() {
+    static auto *m = new std::map<std::string, std::pair<int, int>>();
+    return *m;
+}
+
+std::string tune_key(int device, int prec, const Bond &bl, const Bond &br, const MpoSite &W1, const MpoSite &W2) {
+    std::ostringstream o;
+    o << device << '|' << prec << '|';
+    for (int k = 0; k < bl.nsec(); ++k) o << bl.q[k] << ':' << bl.dim[k] << ',';
+    o << '|';
+    for (int k = 0; k < br.nsec(); ++k) o << br.q[k] << ':' << br.dim[k] << ',';
+    o << '|' << W1.Dl << ',' << W1.Dr << ',' << W2.Dr << ',' << W1.d;
+    for (int w : W1.dl) o << ',' << w;
+    for (int w : W2.dr) o << ',' << w;
+    return o.str();
+}
+
+// Average time (ms) of `reps` runs of fn on stream s after one warm-up run.
+template <class F>
+double time_ms(hipStream_t s, int reps, F &&fn) {
+    hipEvent_t e0, e1;
+    HIP_OK(hipEventCreate(&e0));
+    HIP_OK(hipEventCreate(&e1));
+    fn();
+    HIP_OK(hipEventRecord(e0, s));
+    for (int r = 0; r < reps; ++r) fn();
+    HIP_OK(hipEventRecord(e1, s));
+    HIP_OK(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIP_OK(hipEventElapsedTime(&ms, e0, e1));
+    HIP_OK(hipEventDestroy(e0));
+    HIP_OK(hipEventDestroy(e1));
+    return ms / reps;
+}
+
+const char *shape_name(int t) {
+    static const char *n[kNumShapes] = {"64x64", "128x32", "32x128", "128x128"};
+    return n[t];
+}
+
+// Times every allowed tile shape of stage 1 and of stage 3 (with its split-K
+// reduction) on the operator's buffers and keeps the fastest of each.
+void tune_heff(pdmrg_ctx *ctx, pdmrg_heff *op, const std::string &key) {
+    hipStream_t s = ctx->stream;
+    HeffPlan &pl = op->plan;
+    const GemmPrec gp = gemm_prec(op->prec);
+    const bool f64 = op->prec == PDMRG_F64;
+    const size_t es = f64 ? sizeof(double) : sizeof(float);
+    DevBuf xin(std::max<int64_t>(op->nX, 1) * es), yout(std::max<int64_t>(op->nX, 1) * sizeof(double));
+    HIP_OK(hipMemsetAsync(xin.ptr, 0, xin.bytes, s));
+    Slots sl{};
+    sl.p[0] = xin.ptr;
+    sl.p[1] = yout.ptr;
+    sl.p[2] = op->L.ptr;
+    sl.p[3] = op->R.ptr;
+    sl.p[4] = op->T1.ptr;
+    sl.p[5] = op->T2.ptr;
+    const int reps = 3;
+    int best1 = (int)pl.g1.shape, best3 = (int)pl.g3.shape;
+    double t1best = 1e30, t3best = 1e30;
+    std::ostringstream log;
+    for (int t = 0; t < kNumShapes; ++t) {
+        if (!(pl.g1.shapes_allowed & (1u << t))) continue;
+        pl.set_g1_shape((TileShape)t, s);
+        const double ms = time_ms(s, reps, [&] { pl.g1.launch(gp, f64, sl, s); });
+        log << " g1 " << shape_name(t) << ' ' << ms;
+        if (ms < t1best) { t1best = ms; best1 = t; }
+    }
+    for (int t = 0; t < kNumShapes; ++t) {
+        if (!(pl.g3.shapes_allowed & (1u << t))) continue;
+        pl.set_g3_shape((TileShape)t, s);
+        op->P.ensure(std::max<int64_t>(pl.nP, 1) * sizeof(double));
+        sl.p[6] = op->P.ptr;
+        const double ms = time_ms(s, reps, [&] {
+            pl.g3.launch(gp, true, sl, s);
+            pl.r3.launch(true, sl, s);
+        });
+        log << " g3 " << shape_name(t) << ' ' << ms;
+        if (ms < t3best) { t3best = ms; best3 = t; }
+    }
+    pl.set_g1_shape((TileShape)best1, s);
+    pl.set_g3_shape((TileShape)best3, s);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        tune_cache()[key] = {best1, best3};
+    }
+    if (ctx->autotune >= 2)
+        std::fprintf(stderr, "pdmrg autotune: g1 %s g3 %s  (ms:%s)\n", shape_name(best1), shape_name(best3),
+                     log.str().c_str());
+}
+}  // namespace
 
 GemmPrec gemm_prec(int prec) {
     switch (prec) {
@@ -48,6 +147,21 @@ void heff_build(pdmrg_ctx *ctx, pdmrg_heff *op, const Bond &bl, const Bond &br, 
     }
     op->T1.ensure(std::max<int64_t>(pl.nT1, 1) * es);
     op->T2.ensure(std::max<int64_t>(pl.nT2, 1) * es);
+    if (ctx->autotune > 0) {
+        const std::string key = tune_key(ctx->device, prec, bl, br, W1, W2);
+        std::pair<int, int> hit{-1, -1};
+        {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            auto it = tune_cache().find(key);
+            if (it != tune_cache().end()) hit = it->second;
+        }
+        if (hit.first >= 0) {
+            if (hit.first != (int)pl.g1.shape) pl.set_g1_shape((TileShape)hit.first, s);
+            if (hit.second != (int)pl.g3.shape) pl.set_g3_shape((TileShape)hit.second, s);
+        } else {
+            tune_heff(ctx, op, key);
+        }
+    }
     op->P.ensure(std::max<int64_t>(pl.nP, 1) * sizeof(double));
 }
 

@@ -25,10 +25,14 @@ struct GemmSeg {
     int32_t pad_;
 };
 
+// C row r of an item lies at c_off + r * ldc, or, when rmap >= 0, at
+// c_off + rowoff[rmap + r] (items that stack blocks of different leading
+// dimensions along M).
 struct GemmItem {
     int64_t c_off;
     int32_t c_slot, M, N, ldc;
     int32_t seg0, nseg;
+    int32_t rmap, pad_;
 };
 
 struct GemmTile {
@@ -48,6 +52,9 @@ struct LcSrc {
     double coef;
 };
 
+// Tile of a W-stage launch: elements [r0 * kLcChunk, (r0 + 1) * kLcChunk) of
+// task `task` (row-major over its rows x cols block).
+constexpr int kLcChunk = 2048;
 struct LcTile {
     int32_t task, r0, c0, pad_;
 };
@@ -63,11 +70,18 @@ struct DiagTerm {
 
 enum class GemmPrec { F64, F32, BF16X3 };
 
+// Output tile shapes of the FP64 / FP32 kernels (4 waves, each a 32 x 32 or
+// 64 x 64 sub-tile of 16 x 16 MFMA blocks).  BF16X3 runs T64x64 only.
+enum class TileShape { T64x64 = 0, T128x32 = 1, T32x128 = 2, T128x128 = 3 };
+constexpr int kNumShapes = 4;
+inline int tile_bm(TileShape t) { return t == TileShape::T64x64 ? 64 : t == TileShape::T32x128 ? 32 : 128; }
+inline int tile_bn(TileShape t) { return t == TileShape::T64x64 ? 64 : t == TileShape::T128x32 ? 32 : 128; }
+
 // Launchers (defined in gemm.hip / blas.hip).  All asynchronous on `s`.
-// c_is_f64: C written as double (F32 / BF16X3 inputs are float).  tm: output
-// tile edge of the FP64 / FP32 kernels (64 or 128; BF16X3 always uses 64).
-void launch_gemm(GemmPrec prec, int tm, bool ta, bool tb, bool c_is_f64, const Slots &slots,
-                 const GemmItem *items, const GemmSeg *segs, const GemmTile *tiles,
+// c_is_f64: C written as double (F32 / BF16X3 inputs are float).  rowoff:
+// row-offset table of the items with rmap >= 0 (may be null otherwise).
+void launch_gemm(GemmPrec prec, TileShape shape, bool ta, bool tb, bool c_is_f64, const Slots &slots,
+                 const GemmItem *items, const GemmSeg *segs, const GemmTile *tiles, const int64_t *rowoff,
                  int ntiles, hipStream_t s);
 void launch_lincomb(bool f64, const Slots &slots, const LcTask *tasks, const LcSrc *srcs,
                     const LcTile *tiles, int ntiles, hipStream_t s);

@@ -12,6 +12,33 @@ int GemmList::add_item(int c_slot, int64_t c_off, int M, int N, int ldc) {
     it.ldc = ldc;
     it.seg0 = (int32_t)segs.size();
     it.nseg = 0;
+    it.rmap = -1;
+    items.push_back(it);
+    blk0.push_back(-1);
+    return (int)items.size() - 1;
+}
+
+int GemmList::add_stacked_item(int c_slot, int N, const std::vector<RowBlock> &blks) {
+    PD_REQUIRE(!blks.empty(), PDMRG_EINVAL, "gemm list: stacked item without blocks");
+    GemmItem it{};
+    it.c_off = 0;
+    it.c_slot = c_slot;
+    it.N = N;
+    it.ldc = N;
+    it.seg0 = (int32_t)segs.size();
+    it.nseg = 0;
+    it.rmap = (int32_t)rowoff.size();
+    blk0.push_back((int32_t)blocks.size());
+    int M = 0;
+    for (RowBlock b : blks) {
+        PD_REQUIRE(b.rows > 0 && b.ldc >= N, PDMRG_EINVAL, "gemm list: bad stacked block");
+        b.r0 = M;
+        for (int r = 0; r < b.rows; ++r) rowoff.push_back(b.c_off + (int64_t)r * b.ldc);
+        blocks.push_back(b);
+        M += b.rows;
+    }
+    blocks.push_back(RowBlock{0, M, 0, 0});   // terminator: r0 = M
+    it.M = M;
     items.push_back(it);
     return (int)items.size() - 1;
 }
@@ -32,35 +59,82 @@ void GemmList::add_seg(int a_slot, int64_t a_off, int lda, int b_slot, int64_t b
     flops += 2.0 * it.M * (double)it.N * K;
 }
 
-void GemmList::pick_tile() {
-    double big = 0.0, all = 0.0;
-    for (const GemmItem &it : items) {
-        double k = 0.0;
-        for (int j = 0; j < it.nseg; ++j) k += segs[it.seg0 + j].K;
-        const double f = (double)it.M * it.N * k;
-        all += f;
-        if (it.M >= 96 && it.N >= 96) big += f;
-    }
-    tm = (tm_max >= 128 && all > 0.0 && big >= 0.5 * all) ? 128 : 64;
+static int64_t item_k(const GemmList &g, const GemmItem &it) {
+    int64_t k = 0;
+    for (int j = 0; j < it.nseg; ++j) k += g.segs[it.seg0 + j].K;
+    return k;
 }
 
-int GemmList::ntiles_for(int edge) const {
+int GemmList::ntiles_for(TileShape t) const {
+    const int bm = tile_bm(t), bn = tile_bn(t);
     int n = 0;
-    for (const GemmItem &it : items) n += ((it.M + edge - 1) / edge) * ((it.N + edge - 1) / edge);
+    for (const GemmItem &it : items) n += ((it.M + bm - 1) / bm) * ((it.N + bn - 1) / bn);
     return n;
 }
 
+double GemmList::padded_flops(TileShape t) const {
+    const int bm = tile_bm(t), bn = tile_bn(t);
+    double f = 0.0;
+    for (const GemmItem &it : items)
+        f += 2.0 * ((it.M + bm - 1) / bm * bm) * (double)((it.N + bn - 1) / bn * bn) * (double)item_k(*this, it);
+    return f;
+}
+
+void GemmList::pick_tile() {
+    // Relative MFMA throughput per padded flop, measured on uniform 64-deep
+    // K loops: 128 x 128 tiles (64 x 64 per wave) reuse each LDS operand
+    // twice as often as the 32 x 32-per-wave shapes.
+    static const double kRate[kNumShapes] = {1.0, 0.85, 0.85, 1.25};
+    double best = 0.0;
+    bool have = false;
+    for (int t = 0; t < kNumShapes; ++t) {
+        if (!(shapes_allowed & (1u << t))) continue;
+        const TileShape ts = (TileShape)t;
+        double cap = 0.0;   // tiles after the split-K the long items allow
+        const int bm = tile_bm(ts), bn = tile_bn(ts);
+        for (const GemmItem &it : items) {
+            const double nt = ((it.M + bm - 1) / bm) * (double)((it.N + bn - 1) / bn);
+            cap += nt * std::max<int64_t>(1, std::min<int64_t>(8, item_k(*this, it) / 256));
+        }
+        const double fill = std::min(1.0, cap / 1024.0);
+        const double cost = padded_flops(ts) / (kRate[t] * std::max(fill, 1e-3));
+        if (!have || cost < best * 0.999) {
+            best = cost;
+            shape = ts;
+            have = true;
+        }
+    }
+}
+
+GemmList GemmList::host_copy() const {
+    GemmList g;
+    g.ta = ta;
+    g.tb = tb;
+    g.shape = shape;
+    g.shapes_allowed = shapes_allowed;
+    g.items = items;
+    g.segs = segs;
+    g.rowoff = rowoff;
+    g.blk0 = blk0;
+    g.blocks = blocks;
+    g.flops = flops;
+    return g;
+}
+
 void GemmList::finish(hipStream_t s) {
-    if (tm > tm_max) tm = tm_max;
+    if (!(shapes_allowed & (1u << (int)shape))) shape = TileShape::T64x64;
+    const int bm = tile_bm(shape), bn = tile_bn(shape);
     tiles.clear();
     for (size_t i = 0; i < items.size(); ++i) {
         const GemmItem &it = items[i];
-        for (int m0 = 0; m0 < it.M; m0 += tm)
-            for (int n0 = 0; n0 < it.N; n0 += tm) tiles.push_back(GemmTile{(int32_t)i, m0, n0, 0});
+        for (int m0 = 0; m0 < it.M; m0 += bm)
+            for (int n0 = 0; n0 < it.N; n0 += bn) tiles.push_back(GemmTile{(int32_t)i, m0, n0, 0});
     }
     upload(d_items, items, s);
     upload(d_segs, segs, s);
     upload(d_tiles, tiles, s);
+    if (rowoff.empty()) d_rowoff.release();
+    else upload(d_rowoff, rowoff, s);
 }
 
 static void check_span(const std::vector<int64_t> &slot_elems, int slot, int64_t off, int rows, int cols,
@@ -75,7 +149,21 @@ static void check_span(const std::vector<int64_t> &slot_elems, int slot, int64_t
 
 void GemmList::validate(const std::vector<int64_t> &slot_elems) const {
     for (const GemmItem &it : items) {
-        check_span(slot_elems, it.c_slot, it.c_off, it.M, it.N, it.ldc, "gemm C");
+        if (it.rmap >= 0) {
+            PD_REQUIRE(it.rmap + (int64_t)it.M <= (int64_t)rowoff.size(), PDMRG_ESHAPE, "gemm C: row map too short");
+            for (int r = 0; r < it.M; ++r)
+                check_span(slot_elems, it.c_slot, it.c_off + rowoff[it.rmap + r], 1, it.N, it.N, "gemm C row");
+        } else {
+            check_span(slot_elems, it.c_slot, it.c_off, it.M, it.N, it.ldc, "gemm C");
+        }
+        // buffer-load descriptors address one segment operand with 32-bit byte offsets
+        for (int k = 0; k < it.nseg; ++k) {
+            const GemmSeg &sg = segs[it.seg0 + k];
+            const int64_t span_a = ta ? (int64_t)sg.K * sg.lda : (int64_t)it.M * sg.lda;
+            const int64_t span_b = tb ? (int64_t)it.N * sg.ldb : (int64_t)sg.K * sg.ldb;
+            PD_REQUIRE(span_a * 8 < ((int64_t)1 << 31) && span_b * 8 < ((int64_t)1 << 31), PDMRG_ESHAPE,
+                       "gemm: operand block exceeds 2 GiB");
+        }
         for (int k = 0; k < it.nseg; ++k) {
             const GemmSeg &sg = segs[it.seg0 + k];
             if (ta) check_span(slot_elems, sg.a_slot, sg.a_off, sg.K, it.M, sg.lda, "gemm A^T");
@@ -88,6 +176,7 @@ void GemmList::validate(const std::vector<int64_t> &slot_elems) const {
 
 void LcList::validate(const std::vector<int64_t> &slot_elems) const {
     for (const LcTask &t : tasks) {
+        PD_REQUIRE((int64_t)t.rows * t.cols < ((int64_t)1 << 31), PDMRG_ESHAPE, "W stage: block too large");
         check_span(slot_elems, t.dst_slot, t.dst_off, t.rows, t.cols, t.ld, "W stage dst");
         for (int j = 0; j < t.nsrc; ++j) {
             const LcSrc &sj = srcs[t.src0 + j];
@@ -100,18 +189,36 @@ int64_t GemmList::split_k(int parts, int pslot, LcList &reduce) {
     if (parts <= 1) return 0;
     std::vector<GemmItem> nitems;
     std::vector<GemmSeg> nsegs;
+    std::vector<int32_t> nblk0;
+    std::vector<RowBlock> nblocks;
     int64_t pel = 0;
-    for (const GemmItem &it : items) {
-        int64_t ktot = 0;
-        for (int k = 0; k < it.nseg; ++k) ktot += segs[it.seg0 + k].K;
+    for (size_t ii = 0; ii < items.size(); ++ii) {
+        const GemmItem &it = items[ii];
+        const int64_t ktot = item_k(*this, it);
         if (ktot < (int64_t)parts * 128 || it.M == 0 || it.N == 0) {
             GemmItem c = it;
             c.seg0 = (int32_t)nsegs.size();
             for (int k = 0; k < it.nseg; ++k) nsegs.push_back(segs[it.seg0 + k]);
+            if (blk0[ii] >= 0) {
+                nblk0.push_back((int32_t)nblocks.size());
+                for (int b = blk0[ii];; ++b) {
+                    nblocks.push_back(blocks[b]);
+                    if (blocks[b].r0 == it.M && blocks[b].rows == 0) break;
+                }
+            } else {
+                nblk0.push_back(-1);
+            }
             nitems.push_back(c);
             continue;
         }
-        reduce.add_task(it.c_slot, it.c_off, it.M, it.N, it.ldc);
+        // the output blocks this item writes: one plain block, or its stacked blocks
+        std::vector<RowBlock> outb;
+        if (blk0[ii] >= 0) {
+            for (int b = blk0[ii]; blocks[b].rows > 0; ++b) outb.push_back(blocks[b]);
+        } else {
+            outb.push_back(RowBlock{it.c_off, 0, it.M, it.ldc});
+        }
+        const int64_t pbase = pel;
         for (int p = 0; p < parts; ++p) {
             // K range [kb, ke), boundaries rounded to multiples of 32
             const int64_t kb = (ktot * p / parts) / 32 * 32;
@@ -122,6 +229,7 @@ int64_t GemmList::split_k(int parts, int pslot, LcList &reduce) {
             c.M = it.M;
             c.N = it.N;
             c.ldc = it.N;
+            c.rmap = -1;
             c.seg0 = (int32_t)nsegs.size();
             c.nseg = 0;
             int64_t g0 = 0;   // global K index of the current segment's start
@@ -140,18 +248,26 @@ int64_t GemmList::split_k(int parts, int pslot, LcList &reduce) {
                 g0 += sg.K;
             }
             nitems.push_back(c);
-            reduce.add_src(pslot, pel, it.N, 1.0);
+            nblk0.push_back(-1);
             pel += (int64_t)it.M * it.N;
+        }
+        // fixed-order reduction of the parts into each output block
+        for (const RowBlock &ob : outb) {
+            reduce.add_task(it.c_slot, ob.c_off, ob.rows, it.N, ob.ldc);
+            for (int p = 0; p < parts; ++p)
+                reduce.add_src(pslot, pbase + (int64_t)p * it.M * it.N + (int64_t)ob.r0 * it.N, it.N, 1.0);
         }
     }
     items.swap(nitems);
     segs.swap(nsegs);
+    blk0.swap(nblk0);
+    blocks.swap(nblocks);
     return pel;
 }
 
 void GemmList::launch(GemmPrec prec, bool c_is_f64, const Slots &sl, hipStream_t s) const {
-    launch_gemm(prec, tm, ta, tb, c_is_f64, sl, d_items.as<GemmItem>(), d_segs.as<GemmSeg>(),
-                d_tiles.as<GemmTile>(), (int)tiles.size(), s);
+    launch_gemm(prec, shape, ta, tb, c_is_f64, sl, d_items.as<GemmItem>(), d_segs.as<GemmSeg>(),
+                d_tiles.as<GemmTile>(), d_rowoff.as<int64_t>(), (int)tiles.size(), s);
 }
 
 int LcList::add_task(int dst_slot, int64_t dst_off, int rows, int cols, int ld) {
@@ -185,8 +301,8 @@ void LcList::finish(hipStream_t s) {
     tiles.clear();
     for (size_t i = 0; i < tasks.size(); ++i) {
         const LcTask &t = tasks[i];
-        for (int r0 = 0; r0 < t.rows; r0 += kLcRows)
-            for (int c0 = 0; c0 < t.cols; c0 += kLcCols) tiles.push_back(LcTile{(int32_t)i, r0, c0, 0});
+        const int64_t n = (int64_t)t.rows * t.cols;
+        for (int64_t c = 0; c * kLcChunk < n; ++c) tiles.push_back(LcTile{(int32_t)i, (int32_t)c, 0, 0});
     }
     upload(d_tasks, tasks, s);
     upload(d_srcs, srcs, s);
@@ -251,13 +367,19 @@ void HeffPlan::build(const Bond &bl_, const Bond &br_, const Phys &p_, const Mpo
         nT1 += (int64_t)M * N;
     }
 
-    // T2 blocks: one per output block (i, s1 s2) -> [dim(q_i) x Rt.rows[k]]
+    // T2 blocks: one per output block (i, s1 s2) -> [dim(q_i) x Rt.rows[k]],
+    // grouped by the bra sector k they multiply, so that the blocks sharing
+    // R[k] form one contiguous (sum of dims) x Rt.rows[k] matrix.
     std::vector<int64_t> t2base((size_t)nl * d2, -1);
-    nT2 = 0;
+    std::vector<std::vector<std::pair<int, int>>> by_k(br.nsec());
     for (int i = 0; i < nl; ++i)
         for (int sg = 0; sg < d2; ++sg) {
             if (X.colo[(size_t)i * d2 + sg] < 0) continue;
-            const int k = br.find(bl.q[i] + p.q[sg / d] + p.q[sg % d]);
+            by_k[br.find(bl.q[i] + p.q[sg / d] + p.q[sg % d])].push_back({i, sg});
+        }
+    nT2 = 0;
+    for (int k = 0; k < br.nsec(); ++k)
+        for (auto [i, sg] : by_k[k]) {
             t2base[(size_t)i * d2 + sg] = nT2;
             nT2 += (int64_t)bl.dim[i] * Rt.rows[k];
         }
@@ -295,16 +417,17 @@ void HeffPlan::build(const Bond &bl_, const Bond &br_, const Phys &p_, const Mpo
             }
         }
 
-    // stage 3: y[i, s1 s2] = T2[i, s1 s2] x Rbra[k]
+    // stage 3: y[i, s1 s2] = T2[i, s1 s2] x Rbra[k], one stacked item per k
     g3 = GemmList();
-    for (int i = 0; i < nl; ++i)
-        for (int sg = 0; sg < d2; ++sg) {
-            const int64_t tb = t2base[(size_t)i * d2 + sg];
-            if (tb < 0) continue;
-            const int k = br.find(bl.q[i] + p.q[sg / d] + p.q[sg % d]);
-            g3.add_item(1, X.base[i] + X.colo[(size_t)i * d2 + sg], bl.dim[i], br.dim[k], X.cols[i]);
-            if (Rt.rows[k] > 0) g3.add_seg(5, tb, Rt.rows[k], 3, Rt.base[k], br.dim[k], Rt.rows[k]);
-        }
+    for (int k = 0; k < br.nsec(); ++k) {
+        if (by_k[k].empty()) continue;
+        std::vector<RowBlock> blks;
+        for (auto [i, sg] : by_k[k])
+            blks.push_back(RowBlock{X.base[i] + X.colo[(size_t)i * d2 + sg], 0, bl.dim[i], X.cols[i]});
+        g3.add_stacked_item(1, br.dim[k], blks);
+        const auto [i0, sg0] = by_k[k][0];
+        if (Rt.rows[k] > 0) g3.add_seg(5, t2base[(size_t)i0 * d2 + sg0], Rt.rows[k], 3, Rt.base[k], br.dim[k], Rt.rows[k]);
+    }
 
     // diag(H_eff): sum over channels with delta = 0 of L[a,w,a] W12 R[b,w2,b]
     diag_terms.clear();
@@ -354,23 +477,35 @@ void HeffPlan::build(const Bond &bl_, const Bond &br_, const Phys &p_, const Mpo
             diag_groups.push_back((int32_t)diag_terms.size());
         }
 
-    // tile edges (the BF16x3 kernel has 64 x 64 tiles only)
-    if (prec == PDMRG_BF16X3) g1.tm_max = g3.tm_max = 64;
+    // tile shapes (the BF16x3 kernel has 64 x 64 tiles only)
+    if (prec == PDMRG_BF16X3) g1.shapes_allowed = g3.shapes_allowed = 1u << (int)TileShape::T64x64;
     g1.pick_tile();
     g3.pick_tile();
+    const std::vector<int64_t> sz = {X.size, X.size, Lt.size, Rt.size, nT1, nT2, 0};
+    g1.validate(sz);
+    w.validate(sz);
+    g1.finish(s);
+    w.finish(s);
+    g3_base = g3.host_copy();
+    set_g3_shape(g3.shape, s);
+}
+
+void HeffPlan::set_g1_shape(TileShape t, hipStream_t s) {
+    g1.shape = t;
+    g1.finish(s);
+}
+
+void HeffPlan::set_g3_shape(TileShape t, hipStream_t s) {
+    g3 = g3_base.host_copy();
+    g3.shape = t;
     // split-K for stage 3: aim at >= 1024 output tiles (4 per CU)
-    const int tiles3 = std::max(1, g3.ntiles_for(g3.tm));
+    const int tiles3 = std::max(1, g3.ntiles_for(g3.shape));
     const int parts = std::max(1, std::min(8, (1024 + tiles3 - 1) / tiles3));
     r3 = LcList();
     nP = g3.split_k(parts, 6, r3);
-
     const std::vector<int64_t> sz = {X.size, X.size, Lt.size, Rt.size, nT1, nT2, nP};
-    g1.validate(sz);
-    w.validate(sz);
     g3.validate(sz);
     r3.validate(sz);
-    g1.finish(s);
-    w.finish(s);
     g3.finish(s);
     r3.finish(s);
 }

@@ -6,27 +6,40 @@
 
 namespace pdmrg {
 
-constexpr int kLcRows = 16;    // W-stage tile rows
-constexpr int kLcCols = 128;   // W-stage tile columns
-
 struct LcList;
+
+// Rows [r0, r0 + rows) of a stacked item: C row r0 + r lies at c_off + r * ldc.
+struct RowBlock {
+    int64_t c_off;
+    int32_t r0, rows, ldc;
+};
 
 struct GemmList {
     bool ta = false, tb = false;
-    int tm = 64;        // output tile edge (64 or 128), set by pick_tile()
-    int tm_max = 64;    // largest edge allowed (128 x 128 measured slower on the 8x4 m=1024 H_eff)
+    TileShape shape = TileShape::T64x64;   // set by pick_tile()
+    unsigned shapes_allowed = (1u << kNumShapes) - 1;
     std::vector<GemmItem> items;
     std::vector<GemmSeg> segs;
     std::vector<GemmTile> tiles;
+    std::vector<int64_t> rowoff;           // row offsets of stacked items
+    std::vector<int32_t> blk0;             // per item: first RowBlock, -1 for a plain item
+    std::vector<RowBlock> blocks;
     double flops = 0.0;
-    DevBuf d_items, d_segs, d_tiles;
+    DevBuf d_items, d_segs, d_tiles, d_rowoff;
 
     int add_item(int c_slot, int64_t c_off, int M, int N, int ldc);
+    // An item whose M rows stack the given output blocks (each N wide).
+    int add_stacked_item(int c_slot, int N, const std::vector<RowBlock> &blks);
     void add_seg(int a_slot, int64_t a_off, int lda, int b_slot, int64_t b_off, int ldb, int K);
-    void pick_tile();             // 128 x 128 tiles when most flops sit in blocks >= 96 wide
-    int ntiles_for(int edge) const;
-    void finish(hipStream_t s);   // pick_tile if not done, build tiles, upload
+    // Tile shape of least estimated time: padded MFMA work over the fraction of
+    // the device that the tiles (times the split-K factor they allow) can fill.
+    void pick_tile();
+    int ntiles_for(TileShape t) const;
+    double padded_flops(TileShape t) const;
+    void finish(hipStream_t s);   // build tiles, upload
     void launch(GemmPrec prec, bool c_is_f64, const Slots &sl, hipStream_t s) const;
+    // Copy of the host-side lists (no device buffers).
+    GemmList host_copy() const;
     // Throws unless every element an item touches lies inside its slot's
     // buffer (sizes in elements, per slot).
     void validate(const std::vector<int64_t> &slot_elems) const;
@@ -64,7 +77,11 @@ struct HeffPlan {
     EnvLayout Lt, Rt;
     int64_t nT1 = 0, nT2 = 0, nP = 0;
     GemmList g1, g3;
+    GemmList g3_base;   // stage 3 before split-K
     LcList w, r3;   // W stage; split-K reduction of stage 3 (partials in slot 6, FP64)
+    // Re-tile stage 1 / stage 3 (stage 3 is re-split for the new tile count).
+    void set_g1_shape(TileShape t, hipStream_t s);
+    void set_g3_shape(TileShape t, hipStream_t s);
     std::vector<DiagTerm> diag_terms;
     std::vector<int32_t> diag_groups;
     int diag_max_rows = 0;
