@@ -185,6 +185,20 @@ int heff_info(const pdmrg_heff *op, double *flops_Lpsi, double *flops_W, double 
 int heff_diag(pdmrg_ctx *ctx, pdmrg_heff *op, double *diag_dev);
 void heff_free(pdmrg_heff *op);
 
+/* ------------------------------------------------------------- gradient
+ * Hellmann-Feynman derivative of <psi|H|psi> with respect to one MPO tensor
+ * at fixed state (not part of the paper; its Sec. III motivates scans over
+ * large coupling spaces).  For a single-site centre psi (SITE layout on
+ * (bl, br), FP64, device) between L (ENV_L on bl, deltas W->dl) and R (ENV_R
+ * on br, deltas W->dr):
+ *   G[w, s, t, w'] = sum L[a,w,a'] psi[a,s,b] psi[a',t,b'] R[b,w',b'],
+ * written to G_dev (device, W->Dl * d * d * W->Dr doubles, row-major, every
+ * entry overwritten).  Not normalised by <psi|psi>.  Deterministic (fixed
+ * summation order).  Synchronises the context stream. */
+int grad_site(pdmrg_ctx *ctx, const pdmrg_bond *bl, const pdmrg_bond *br, const pdmrg_phys *phys,
+              const pdmrg_mpo_site *W, const double *L_dev, const double *psi_dev, const double *R_dev,
+              double *G_dev);
+
 /* ------------------------------------------------------------- environments
  * dir = +1: L_out (ENV_L on br) from L_in (ENV_L on bl) and the site tensor
  *           A (SITE on (bl, br)): L'[b,w',b'] = sum A[a,s,b] L[a,w,a'] W[w,s,s',w'] A[a',s',b'].
@@ -288,6 +302,18 @@ int mps_get_site(pdmrg_mps *mps, int site, double *host_data, int64_t cap);
 int sweep(pdmrg_ctx *ctx, pdmrg_mps *mps, const pdmrg_mpo *mpo, const pdmrg_sweep_params *p,
           pdmrg_sweep_report *rep);
 int mps_energy(pdmrg_ctx *ctx, pdmrg_mps *mps, const pdmrg_mpo *mpo, double *energy);
+/* Measurement sweep for dE/dW of E = <Psi|H|Psi>/<Psi|Psi> at fixed Psi:
+ * G_dev (device, n_G doubles) receives G_0, ..., G_{N-1} concatenated, G_i
+ * of shape [Dl_i][d][d][Dr_i] (mpo_get_site sizes), each the grad_site value
+ * at centre i divided by <Psi|Psi>.  For couplings theta entering W affinely,
+ * dE/dtheta = sum_i <G_i, dW_i/dtheta> (= <Psi| dH/dtheta |Psi>).  The MPS is
+ * left unsplit (V folded into the left neighbour of each shared bond; the
+ * re-canonicalisation drops only singular values below 1e-14 of the
+ * largest) with the centre on the last site; the next sweep re-canonicalises
+ * and re-splits it.  *energy (optional) receives E
+ * before the gauge changes.  PDMRG_ESHAPE if n_G is not the total size. */
+int grad_mpo(pdmrg_ctx *ctx, pdmrg_mps *mps, const pdmrg_mpo *mpo, double *G_dev, int64_t n_G, double *energy);
+
 void mps_free(pdmrg_mps *mps);
 
 #ifdef __cplusplus

@@ -75,7 +75,7 @@ EXPORTS = [
     "mpo_info", "mpo_get_site", "mpo_free", "heff_create", "heff_apply", "heff_info", "heff_diag",
     "heff_free", "env_update", "davidson_step", "svd_truncate", "svd_result_bond", "svd_result_copy",
     "svd_free", "merge_regions", "mps_alloc", "mps_set_site", "mps_bond", "mps_get_site", "sweep",
-    "mps_energy", "mps_free",
+    "mps_energy", "mps_free", "grad_site", "grad_mpo",
 ]
 
 
@@ -117,6 +117,8 @@ def _declare(L):
         "sweep": (c_int, [P, P, P, POINTER(CSweepParams), POINTER(CSweepReport)]),
         "mps_energy": (c_int, [P, P, P, pd]),
         "mps_free": (None, [P]),
+        "grad_site": (c_int, [P, pb, pb, pp, pm, P, P, P, P]),
+        "grad_mpo": (c_int, [P, P, P, P, c_int64, pd]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -421,6 +423,22 @@ class Mps:
         check(lib().mps_energy(self.ctx.h, self.h, mpo.h, byref(e)))
         return e.value
 
+    def gradients(self, mpo):
+        """grad_mpo: (E, [G_i]) with G_i = dE/dW_i at fixed state, torch
+        tensors [Dl, d, d, Dr] on the device.  Leaves the MPS unsplit."""
+        import torch
+        shapes = [w.shape for w in mpo.W]
+        n = sum(int(np.prod(sh)) for sh in shapes)
+        G = torch.empty(max(n, 1), dtype=torch.float64, device="cuda")
+        e = c_double()
+        check(lib().grad_mpo(self.ctx.h, self.h, mpo.h, ptr(G), n, byref(e)))
+        out, o = [], 0
+        for sh in shapes:
+            k = int(np.prod(sh))
+            out.append(G[o:o + k].view(*sh))
+            o += k
+        return e.value, out
+
     def bond(self, b):
         n = c_int32()
         check(lib().mps_bond(self.h, b, byref(n), None, None, 0))
@@ -440,3 +458,67 @@ class Mps:
             self.free()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------- gradients
+def grad_site(ctx, bl, br, phys, W, L, psi, R):
+    """grad_site: G[w, s, t, w'] (torch, device) for a single-site centre."""
+    import torch
+    G = torch.empty(W.W.size, dtype=torch.float64, device="cuda")
+    check(lib().grad_site(ctx.h, bl.ref, br.ref, phys.ref, W.ref, ptr(L), ptr(psi), ptr(R), ptr(G)))
+    return G.view(*W.W.shape)
+
+
+def _energy_function():
+    import torch
+
+    class MpoEnergy(torch.autograd.Function):
+        """E(W_0..W_{N-1}) = <Psi|H(W)|Psi>/<Psi|Psi> at a fixed MPS; the
+        backward pass is the grad_mpo measurement sweep (G_i = dE/dW_i)."""
+
+        @staticmethod
+        def forward(fctx, mps, deltas, *W):
+            sites = [MpoSite(w.detach().cpu().numpy(), deltas[i], deltas[i + 1]) for i, w in enumerate(W)]
+            mpo = Mpo(sites=sites)
+            fctx.mps, fctx.mpo = mps, mpo
+            fctx.devices = [w.device for w in W]
+            return torch.tensor(mps.energy(mpo), dtype=torch.float64)
+
+        @staticmethod
+        def backward(fctx, gE):
+            _, G = fctx.mps.gradients(fctx.mpo)
+            fctx.mpo.free()
+            return (None, None) + tuple((gE.to(g.device) * g).to(dev) for g, dev in zip(G, fctx.devices))
+
+    return MpoEnergy
+
+
+def mpo_energy(mps, deltas, W):
+    """Differentiable E(W) at fixed state (torch.autograd); W: list of
+    [Dl, d, d, Dr] tensors, deltas: channel charges of bonds 0..N."""
+    return _energy_function().apply(mps, deltas, *W)
+
+
+def coupling_derivatives(lattice, Lx, Ly, couplings):
+    """dW_i/dtheta_k for each coupling k, exact for the built-in models (every
+    coefficient is affine in each coupling): W(theta + e_k) - W(theta)."""
+    base = Mpo(lattice, Lx, Ly, couplings)
+    out = []
+    for k in range(len(couplings)):
+        c = list(couplings)
+        c[k] += 1.0
+        up = Mpo(lattice, Lx, Ly, c)
+        if any(a.shape != b.shape for a, b in zip(up.W, base.W)):
+            raise ValueError("MPO structure changes with coupling %d; derivative undefined here" % k)
+        out.append([a - b for a, b in zip(up.W, base.W)])
+        up.free()
+    base.free()
+    return out
+
+
+def dE_dcouplings(mps, mpo, lattice, Lx, Ly, couplings):
+    """(E, [dE/dtheta_k]) by one grad_mpo measurement sweep."""
+    E, G = mps.gradients(mpo)
+    Gh = [g.cpu().numpy() for g in G]
+    return E, [float(sum(np.sum(g * dw) for g, dw in zip(Gh, dW)))
+               for dW in coupling_derivatives(lattice, Lx, Ly, couplings)]

@@ -293,6 +293,20 @@ int env_update(pdmrg_ctx *ctx, int dir, const pdmrg_bond *bl, const pdmrg_bond *
     API_END
 }
 
+// ------------------------------------------------------------------ gradient
+
+int grad_site(pdmrg_ctx *ctx, const pdmrg_bond *bl, const pdmrg_bond *br, const pdmrg_phys *phys,
+              const pdmrg_mpo_site *W, const double *L_dev, const double *psi_dev, const double *R_dev,
+              double *G_dev) {
+    API_BEGIN
+    PD_REQUIRE(ctx && L_dev && psi_dev && R_dev && G_dev, PDMRG_EINVAL, "grad_site: null argument");
+    GradPlan plan;
+    plan.build(Bond::from(bl), Bond::from(br), Phys::from(phys), MpoSite::from(W), ctx->stream);
+    grad_site_run(ctx, plan, L_dev, psi_dev, R_dev, G_dev);
+    HIP_OK(hipStreamSynchronize(ctx->stream));
+    API_END
+}
+
 // ------------------------------------------------------------------ Davidson
 int davidson_step(pdmrg_ctx *ctx, pdmrg_heff *op, pdmrg_heff *op64, double *psi_dev, const pdmrg_dav_params *p,
                   double *energy, double *resid, int32_t *n_matvec) {

@@ -59,6 +59,60 @@ void launch_lincomb(bool f64, const Slots &slots, const LcTask *tasks, const LcS
     else hipLaunchKernelGGL(lincomb_kernel<float>, dim3(ntiles), dim3(256), 0, s, slots, tasks, srcs, tiles);
 }
 
+// ------------------------------------------------------------ block dot products
+__global__ __launch_bounds__(256) void dot_partial_kernel(Slots slots, int a_slot, int b_slot,
+                                                          const DotTask *__restrict__ tasks,
+                                                          const DotTile *__restrict__ tiles,
+                                                          double *__restrict__ partial) {
+    constexpr int U = kDotChunk / 256;
+    __shared__ double red[256];
+    const DotTile tl = tiles[blockIdx.x];
+    const DotTask tk = tasks[tl.task];
+    const double *a = static_cast<const double *>(slots.p[a_slot]) + tk.a_off;
+    const double *b = static_cast<const double *>(slots.p[b_slot]) + tk.b_off;
+    const int e0 = tl.chunk * kDotChunk + (int)threadIdx.x;
+    double va[U], vb[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int e = e0 + 256 * u;
+        va[u] = e < tk.n ? a[e] : 0.0;
+        vb[u] = e < tk.n ? b[e] : 0.0;
+    }
+    double acc = 0.0;
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc += va[u] * vb[u];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ void dot_reduce_kernel(const double *__restrict__ partial, const int32_t *__restrict__ t0,
+                                  const int32_t *__restrict__ g_of, int ngroups, double *__restrict__ out) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= ngroups) return;
+    double acc = 0.0;
+    for (int t = t0[k]; t < t0[k + 1]; ++t) acc += partial[t];
+    out[g_of[k]] = acc;
+}
+
+void launch_dot_partials(const Slots &slots, int a_slot, int b_slot, const DotTask *tasks, const DotTile *tiles,
+                         int ntiles, double *partial, hipStream_t s) {
+    if (ntiles <= 0) return;
+    hipLaunchKernelGGL(dot_partial_kernel, dim3(ntiles), dim3(256), 0, s, slots, a_slot, b_slot, tasks, tiles,
+                       partial);
+}
+
+void launch_dot_reduce(const double *partial, const int32_t *t0, const int32_t *g_of, int ngroups, double *out,
+                       hipStream_t s) {
+    if (ngroups <= 0) return;
+    hipLaunchKernelGGL(dot_reduce_kernel, dim3((ngroups + 255) / 256), dim3(256), 0, s, partial, t0, g_of, ngroups,
+                       out);
+}
+
 // ------------------------------------------------------------ diag(H_eff)
 __global__ __launch_bounds__(256) void diag_kernel(Slots slots, const DiagTerm *__restrict__ terms,
                                                    const int32_t *__restrict__ groups) {

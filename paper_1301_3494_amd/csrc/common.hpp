@@ -134,6 +134,7 @@ struct pdmrg_ctx {
     pdmrg::DevBuf ws_env;           // environment-update intermediates
     pdmrg::DevBuf ws_merge;         // merge: V-scaled right tensor
     pdmrg::DevBuf ws_svd;           // SVD work space
+    pdmrg::DevBuf ws_grad;          // gradient intermediates
     // Tile-shape autotuning of H_eff plans: 0 cost model, 1 measured and
     // cached per block signature, 2 = 1 plus a log line per tuned plan.
     int autotune = 0;

@@ -269,6 +269,61 @@ struct Driver {
     }
 
     double energy() { return expectation(false) / expectation(true); }
+
+    // Undo the region split: fold V into the left neighbour of every shared
+    // bond (psi' = psi_L V psi_R re-split, dropping only singular values
+    // below 1e-14 of the largest).
+    void unsplit() {
+        if (!m->split) return;
+        for (auto &kv : m->Vd) {
+            const int j = kv.first - 1;
+            DevBuf psi = contract(j, kv.second.as<double>());
+            SvdOut r;
+            svd_truncate_run(ctx, m->bonds[j], m->bonds[j + 2], m->p, psi.as<double>(), 1 << 30, 1e-14, prm.eps,
+                             PDMRG_ABSORB_LEFT, r);
+            m->bonds[j + 1] = r.bnew;
+            m->sites[j] = take(r.left, site_layout(m->bonds[j], r.bnew, m->p).size);
+            m->sites[j + 1] = take(r.B, site_layout(r.bnew, m->bonds[j + 2], m->p).size);
+        }
+        HIP_OK(hipStreamSynchronize(s()));
+        m->V.clear();
+        m->Vd.clear();
+        m->split = false;
+        m->regions.clear();
+        m->n_regions = 1;
+    }
+
+    // Measurement sweep: right-canonical form with the centre on site 0, then
+    // G_i at each centre i, moving the centre right by two-site SVDs that drop
+    // only singular values below 1e-14 of the largest.  G_i is divided by
+    // <Psi|Psi> (the centre's squared norm).
+    void gradients(double *G, const std::vector<int64_t> &goff) {
+        unsplit();
+        init();
+        for (int i = 0; i < m->N; ++i) {
+            GradPlan gp;
+            gp.build(m->bonds[i], m->bonds[i + 1], m->p, W(i), s());
+            grad_site_run(ctx, gp, m->L[i].as<double>(), m->sites[i].as<double>(), m->R[i + 1].as<double>(),
+                          G + goff[i]);
+            // norm^2 of the centre
+            const int64_t n = site_layout(m->bonds[i], m->bonds[i + 1], m->p).size;
+            std::vector<double> h(n);
+            HIP_OK(hipMemcpyAsync(h.data(), m->sites[i].ptr, n * sizeof(double), hipMemcpyDeviceToHost, s()));
+            HIP_OK(hipStreamSynchronize(s()));
+            double nrm2 = 0.0;
+            for (double v : h) nrm2 += v * v;
+            PD_REQUIRE(nrm2 > 0.0, PDMRG_ENUMERIC, "grad_mpo: zero state");
+            const int64_t gn = goff[i + 1] - goff[i];
+            std::vector<double> g(gn);
+            HIP_OK(hipMemcpyAsync(g.data(), G + goff[i], gn * sizeof(double), hipMemcpyDeviceToHost, s()));
+            HIP_OK(hipStreamSynchronize(s()));
+            for (double &v : g) v /= nrm2;
+            HIP_OK(hipMemcpyAsync(G + goff[i], g.data(), gn * sizeof(double), hipMemcpyHostToDevice, s()));
+            HIP_OK(hipStreamSynchronize(s()));
+            if (i + 1 < m->N) gauge_move(i, PDMRG_ABSORB_RIGHT, 1 << 30, 1e-14);
+        }
+        m->ready = false;   // centre now on the last site: the next sweep re-canonicalises
+    }
 };
 
 void check_mpo(const pdmrg_mps *m, const pdmrg_mpo *mpo) {
@@ -390,6 +445,23 @@ int mps_energy(pdmrg_ctx *ctx, pdmrg_mps *m, const pdmrg_mpo *mpo, double *energ
     check_mpo(m, mpo);
     Driver dr{ctx, m, mpo};
     *energy = dr.energy();
+    API_CATCH
+}
+
+int grad_mpo(pdmrg_ctx *ctx, pdmrg_mps *m, const pdmrg_mpo *mpo, double *G_dev, int64_t n_G, double *energy) {
+    API_TRY
+    PD_REQUIRE(ctx && m && mpo && G_dev, PDMRG_EINVAL, "grad_mpo: null argument");
+    check_mpo(m, mpo);
+    std::vector<int64_t> goff(m->N + 1, 0);
+    for (int i = 0; i < m->N; ++i) {
+        const MpoSite &w = mpo->W[i];
+        goff[i + 1] = goff[i] + (int64_t)w.Dl * w.d * w.d * w.Dr;
+    }
+    PD_REQUIRE(n_G == goff[m->N], PDMRG_ESHAPE, "grad_mpo: expected " + std::to_string(goff[m->N]) + " elements");
+    Driver dr{ctx, m, mpo};
+    dr.prm.eps = 1e-4;
+    if (energy) *energy = dr.energy();
+    dr.gradients(G_dev, goff);
     API_CATCH
 }
 

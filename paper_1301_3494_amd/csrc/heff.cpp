@@ -165,6 +165,15 @@ void heff_build(pdmrg_ctx *ctx, pdmrg_heff *op, const Bond &bl, const Bond &br, 
     op->P.ensure(std::max<int64_t>(pl.nP, 1) * sizeof(double));
 }
 
+void grad_site_run(pdmrg_ctx *ctx, const GradPlan &plan, const double *L, const double *psi, const double *R,
+                   double *G) {
+    const size_t nU1 = std::max<int64_t>(plan.nU1, 1), nZ = std::max<int64_t>(plan.nZ, 1);
+    const size_t np = std::max<size_t>(plan.dtiles.size(), 1);
+    ctx->ws_grad.ensure((nU1 + nZ + np) * sizeof(double));
+    double *U1 = ctx->ws_grad.as<double>();
+    plan.run(L, psi, R, U1, U1 + nU1, U1 + nU1 + nZ, G, ctx->stream);
+}
+
 void heff_run(pdmrg_ctx *ctx, pdmrg_heff *op, const double *x, double *y) {
     hipStream_t s = ctx->stream;
     const HeffPlan &pl = op->plan;

@@ -44,6 +44,8 @@ struct SvdOut {
     double discarded = 0;
     int n_floored = 0;
 };
+void grad_site_run(pdmrg_ctx *ctx, const GradPlan &plan, const double *L, const double *psi, const double *R,
+                   double *G);
 void svd_truncate_run(pdmrg_ctx *ctx, const Bond &bl, const Bond &br, const Phys &p, const double *psi,
                       int max_m, double cutoff, double eps, int mode, SvdOut &out);
 

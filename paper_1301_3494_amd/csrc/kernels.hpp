@@ -68,6 +68,19 @@ struct DiagTerm {
     double coef;
 };
 
+// Frobenius product of two packed blocks of n elements: slot a at a_off and
+// slot b at b_off; its value is added into output entry g.
+struct DotTask {
+    int64_t a_off, b_off;
+    int32_t n, g;
+};
+// Tile of a dot launch: elements [chunk * kDotChunk, (chunk + 1) * kDotChunk)
+// of task `task`.
+constexpr int kDotChunk = 2048;
+struct DotTile {
+    int32_t task, chunk;
+};
+
 enum class GemmPrec { F64, F32, BF16X3 };
 
 // Output tile shapes of the FP64 / FP32 kernels (4 waves, each a 32 x 32 or
@@ -89,6 +102,13 @@ void launch_lincomb(bool f64, const Slots &slots, const LcTask *tasks, const LcS
 // cols, ld); each output block is written once (zero if it has no terms).
 void launch_diag_terms(const Slots &slots, const DiagTerm *terms, const int32_t *groups, int ngroups,
                        int max_rows, hipStream_t s);
+// partial[t] = sum over tile t's elements of a * b (fixed-order tree).
+void launch_dot_partials(const Slots &slots, int a_slot, int b_slot, const DotTask *tasks, const DotTile *tiles,
+                         int ntiles, double *partial, hipStream_t s);
+// out[g_of[k]] = sum over tiles t0[k]..t0[k+1] of partial (in order), for the
+// k = 0..ngroups-1 output entries that have tiles.
+void launch_dot_reduce(const double *partial, const int32_t *t0, const int32_t *g_of, int ngroups, double *out,
+                       hipStream_t s);
 void launch_convert_f64_f32(const double *x, float *y, int64_t n, hipStream_t s);
 void launch_convert_f32_f64(const float *x, double *y, int64_t n, hipStream_t s);
 void launch_fill(double *x, double v, int64_t n, hipStream_t s);

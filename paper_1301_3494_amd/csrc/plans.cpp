@@ -687,6 +687,120 @@ void EnvPlan::run(GemmPrec prec, const void *env_in, const void *site, void *env
     g3.launch(prec, f64, sl, s);
 }
 
+// ---------------------------------------------------------------- gradient
+void GradPlan::build(const Bond &bl_, const Bond &br_, const Phys &p_, const MpoSite &W, hipStream_t s) {
+    bl = bl_;
+    br = br_;
+    p = p_;
+    const int d = p.d();
+    PD_REQUIRE(W.d == d, PDMRG_ESHAPE, "grad: MPO local dimension mismatch");
+    Dl = W.Dl;
+    Dr = W.Dr;
+    S = site_layout(bl, br, p);
+    Lt = env_l_layout(bl, W.dl);
+    Rt = env_r_layout(br, W.dr);
+    const int nl = bl.nsec();
+    // stage 1: U1[j] = Lket[j] x psi[j]
+    g1 = GemmList();
+    std::vector<int64_t> u1base(nl, -1);
+    nU1 = 0;
+    for (int j = 0; j < nl; ++j) {
+        const int M = Lt.rows[j], N = S.cols[j], K = bl.dim[j];
+        if (M == 0 || N == 0) continue;
+        u1base[j] = nU1;
+        g1.add_item(3, nU1, M, N, N);
+        g1.add_seg(0, Lt.base[j], K, 1, S.base[j], N, K);
+        nU1 += (int64_t)M * N;
+    }
+    // stage 2: Z blocks [b'][b] = U1^T psi, then stage-3 dot tasks
+    gz = GemmList();
+    gz.ta = true;
+    dots.clear();
+    nZ = 0;
+    for (int i = 0; i < nl; ++i)
+        for (int w = 0; w < Dl; ++w) {
+            const int j = bl.find(bl.q[i] - W.dl[w]);
+            if (j < 0 || u1base[j] < 0) continue;
+            const int lro = Lt.rowo[(size_t)j * Dl + w];
+            if (lro < 0) continue;
+            for (int sp = 0; sp < d; ++sp) {
+                const int cs = S.colo[(size_t)i * d + sp];
+                if (cs < 0) continue;
+                const int qb = bl.q[i] + p.q[sp];
+                const int kb = br.find(qb);
+                for (int t = 0; t < d; ++t) {
+                    const int ct = S.colo[(size_t)j * d + t];
+                    if (ct < 0) continue;
+                    const int qbk = bl.q[j] + p.q[t];
+                    // channels w' of R with delta = qb - qbk
+                    std::vector<int> wr;
+                    for (int w2 = 0; w2 < Dr; ++w2)
+                        if (W.dr[w2] == qb - qbk && Rt.rowo[(size_t)kb * Dr + w2] >= 0) wr.push_back(w2);
+                    if (wr.empty()) continue;
+                    const int M = br.dim_of(qbk), N = br.dim[kb], K = bl.dim[i];
+                    gz.add_item(4, nZ, M, N, N);
+                    gz.add_seg(3, u1base[j] + (int64_t)lro * S.cols[j] + ct, S.cols[j], 1, S.base[i] + cs, S.cols[i],
+                               K);
+                    for (int w2 : wr) {
+                        const int64_t roff = Rt.base[kb] + (int64_t)Rt.rowo[(size_t)kb * Dr + w2] * br.dim[kb];
+                        const int g = ((w * d + sp) * d + t) * Dr + w2;
+                        dots.push_back(DotTask{nZ, roff, M * N, g});
+                    }
+                    nZ += (int64_t)M * N;
+                }
+            }
+        }
+    // dot tiles grouped by output entry, tasks of one entry in build order
+    std::vector<int> order(dots.size());
+    for (size_t k = 0; k < order.size(); ++k) order[k] = (int)k;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return dots[a].g < dots[b].g; });
+    dtiles.clear();
+    t0.clear();
+    g_of.clear();
+    for (size_t k = 0; k < order.size(); ++k) {
+        const DotTask &dt = dots[order[k]];
+        PD_REQUIRE(dt.n > 0, PDMRG_ESHAPE, "grad: empty block");
+        if (g_of.empty() || g_of.back() != dt.g) {
+            t0.push_back((int32_t)dtiles.size());
+            g_of.push_back(dt.g);
+        }
+        for (int c = 0; c * kDotChunk < dt.n; ++c) dtiles.push_back(DotTile{order[k], c});
+    }
+    t0.push_back((int32_t)dtiles.size());
+    for (const DotTask &dt : dots) {
+        PD_REQUIRE(dt.a_off >= 0 && dt.a_off + dt.n <= nZ && dt.b_off >= 0 && dt.b_off + dt.n <= Rt.size,
+                   PDMRG_ESHAPE, "grad: dot task outside its buffer");
+        flops += 2.0 * dt.n;
+    }
+    flops += g1.flops + gz.flops;
+    const std::vector<int64_t> sz = {Lt.size, S.size, Rt.size, nU1, nZ};
+    g1.validate(sz);
+    gz.validate(sz);
+    g1.pick_tile();
+    gz.pick_tile();
+    g1.finish(s);
+    gz.finish(s);
+    upload(d_dots, dots, s);
+    upload(d_dtiles, dtiles, s);
+    upload(d_t0, t0, s);
+    upload(d_gof, g_of, s);
+}
+
+void GradPlan::run(const double *L, const double *psi, const double *R, double *U1, double *Z, double *partial,
+                   double *G, hipStream_t s) const {
+    Slots sl{};
+    sl.p[0] = L;
+    sl.p[1] = psi;
+    sl.p[2] = R;
+    sl.p[3] = U1;
+    sl.p[4] = Z;
+    launch_fill(G, 0.0, (int64_t)Dl * p.d() * p.d() * Dr, s);
+    g1.launch(GemmPrec::F64, true, sl, s);
+    gz.launch(GemmPrec::F64, true, sl, s);
+    launch_dot_partials(sl, 4, 2, d_dots.as<DotTask>(), d_dtiles.as<DotTile>(), (int)dtiles.size(), partial, s);
+    launch_dot_reduce(partial, d_t0.as<int32_t>(), d_gof.as<int32_t>(), (int)g_of.size(), G, s);
+}
+
 // ---------------------------------------------------------------- merge
 void MergePlan::build(const Bond &bl_, const Bond &bm_, const Bond &br_, const Phys &p_, hipStream_t s) {
     bl = bl_;

@@ -120,6 +120,34 @@ struct MergePlan {
              hipStream_t s) const;
 };
 
+// Gradient of <psi|H|psi> with respect to one MPO tensor W[w, s, t, w'] at a
+// single-site centre psi on (bl, br):
+//   G[w, s, t, w'] = sum L[a, w, a'] psi[a, s, b] psi[a', t, b'] R[b, w', b'].
+// Stage 1: U1[j] = Lket[j] psi[j] (rows (w, a), cols (t, b')) -- the first
+// stage of an environment update.  Stage 2: per (a sector, w, s, t) the block
+// Z = U1[(w, a), (t, b')]^T psi[a, (s, b)] over a, laid out [b'][b] like the
+// R blocks.  Stage 3: G entries as Frobenius products <Z, R[w']> over the
+// channels w' whose charge matches, summed in a fixed order.
+struct GradPlan {
+    Bond bl, br;
+    Phys p;
+    int Dl = 0, Dr = 0;
+    SiteLayout S;
+    EnvLayout Lt, Rt;
+    int64_t nU1 = 0, nZ = 0;
+    GemmList g1, gz;
+    std::vector<DotTask> dots;
+    std::vector<DotTile> dtiles;
+    std::vector<int32_t> t0, g_of;   // tiles of output entry g_of[k]: t0[k] .. t0[k+1]
+    DevBuf d_dots, d_dtiles, d_t0, d_gof;
+    double flops = 0.0;
+    void build(const Bond &bl_, const Bond &br_, const Phys &p_, const MpoSite &W, hipStream_t s);
+    // slots: 0 L, 1 psi, 2 R, 3 U1, 4 Z; partial holds dtiles.size() doubles;
+    // G (Dl d d Dr) is overwritten.
+    void run(const double *L, const double *psi, const double *R, double *U1, double *Z, double *partial,
+             double *G, hipStream_t s) const;
+};
+
 std::vector<double> two_site_mpo(const MpoSite &W1, const MpoSite &W2);
 
 }  // namespace pdmrg

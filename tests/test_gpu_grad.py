@@ -1,0 +1,116 @@
+"""Backward kernel: dE/dW at fixed state (grad_site, grad_mpo) against the
+oracle's site gradient, exact Hellmann-Feynman values from exact
+diagonalisation, the TFIM closed form, homogeneity, and the torch.autograd
+route."""
+import numpy as np
+import pytest
+
+from helpers import pl, synth, say, dev, host, blocks_to_flat
+from oracle import models, mpo as M, exact, grad as ograd
+
+pytestmark = pytest.mark.gpu
+PQ = synth.SPIN_HALF_Q
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available()
+    c = pl.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.mark.parametrize("m,i,seed", [(40, 5, 11), (150, 7, 12)])
+def test_grad_site_matches_oracle(ctx, m, i, seed):
+    say("grad_site m", m, "site", i)
+    Lx, Ly = 4, 4
+    N = Lx * Ly
+    mpo = M.build_mpo(models.heisenberg_terms(models.square_cylinder_bonds(Lx, Ly)), N, models.OPS, PQ)
+    bonds = synth.binomial_bonds(N, m)
+    bl, br = bonds[i], bonds[i + 1]
+    rng = np.random.default_rng(seed)
+    psi = synth.random_site_blocks(bl, br, PQ, rng)
+    L = synth.random_env_blocks(bl, mpo.deltas[i], rng)
+    R = synth.random_env_blocks(br, mpo.deltas[i + 1], rng)
+    ref = ograd.site_gradient(L, R, psi, PQ, mpo.deltas[i], mpo.deltas[i + 1])
+    B1, B2, P = pl.Bond(bl), pl.Bond(br), pl.Phys(PQ)
+    tS, nS = pl.layout(pl.SITE, B1, B2, P)
+    tL, nL = pl.layout(pl.ENV_L, B1, deltas=mpo.deltas[i])
+    tR, nR = pl.layout(pl.ENV_R, B2, deltas=mpo.deltas[i + 1])
+    W = pl.MpoSite(mpo.W[i], mpo.deltas[i], mpo.deltas[i + 1])
+    G = pl.grad_site(ctx, B1, B2, P, W, dev(blocks_to_flat(L, tL, nL, pl.ENV_L)),
+                     dev(blocks_to_flat(psi, tS, nS, pl.SITE)), dev(blocks_to_flat(R, tR, nR, pl.ENV_R)))
+    got = host(G)
+    assert np.linalg.norm(got - ref) <= 1e-12 * np.linalg.norm(ref)
+    # entries the charges forbid are exactly zero on both sides
+    assert np.array_equal(got == 0.0, ref == 0.0)
+    # deterministic: a second call gives the same bits
+    assert np.array_equal(host(pl.grad_site(ctx, B1, B2, P, W, dev(blocks_to_flat(L, tL, nL, pl.ENV_L)),
+                                            dev(blocks_to_flat(psi, tS, nS, pl.SITE)),
+                                            dev(blocks_to_flat(R, tR, nR, pl.ENV_R)))), got)
+
+
+def _converged(ctx, lattice, Lx, Ly, couplings, m, sweeps, phys=PQ, q=0, n_regions=1, seed=1):
+    N = Lx * Ly
+    bonds, sites = synth.random_mps(N, min(m, 16), seed, phys_q=phys, q_target=q)
+    mpo = pl.Mpo(lattice, Lx, Ly, couplings)
+    mps = pl.Mps(ctx, bonds, sites, phys, q)
+    for k in range(sweeps):
+        nreg = 1 if k < 2 else n_regions
+        rep = mps.sweep(mpo, m, nreg, dav=pl.dav_params(30, 8, 1e-11), dav_shared=pl.dav_params(40, 8, 1e-11))
+    return mps, mpo, rep["energy"]
+
+
+def test_grad_mpo_xxz_hellmann_feynman_vs_ed(ctx):
+    N, Delta = 10, 0.9
+    mps, mpo, E = _converged(ctx, "chain", N, 1, (1.0, Delta), 64, 5)
+    Eg, (gJ, gD) = pl.dE_dcouplings(mps, mpo, "chain", N, 1, (1.0, Delta))
+    terms = models.xxz_terms(models.chain_bonds(N), 1.0, Delta)
+    e, v, _ = exact.ground_state(terms, N, 0)
+    Hd, _ = exact.sparse_hamiltonian([(1.0, ((i, "Sz"), (j, "Sz"))) for i, j in models.chain_bonds(N)], N, 0)
+    hf = float(v[:, 0] @ (Hd @ v[:, 0]))
+    say("xxz dE/dDelta gpu", gD, "ED", hf, "E", Eg, e[0])
+    assert abs(Eg - e[0]) <= 1e-9 * abs(e[0])
+    assert abs(gD - hf) <= 1e-9 * max(1.0, abs(hf))
+    # homogeneity of the XXZ energy in J at fixed Delta: J dE/dJ = E
+    assert abs(1.0 * gJ - Eg) <= 1e-9 * abs(Eg)
+
+
+def test_grad_mpo_tfim_closed_form(ctx):
+    N, h = 10, 0.8
+    mps, mpo, E = _converged(ctx, "tfim", N, 1, (1.0, h), 64, 5, phys=synth.TRIVIAL_Q)
+    Eg, (gJ, gh) = pl.dE_dcouplings(mps, mpo, "tfim", N, 1, (1.0, h))
+    ref = exact.tfim_chain_dE_dh(N, 1.0, h)
+    say("tfim dE/dh gpu", gh, "closed form", ref)
+    assert abs(Eg - exact.tfim_chain_energy(N, 1.0, h)) <= 1e-9 * abs(Eg)
+    assert abs(gh - ref) <= 1e-8 * max(1.0, abs(ref))
+    assert abs(gJ * 1.0 + gh * h - Eg) <= 1e-8 * abs(Eg)
+
+
+def test_grad_mpo_after_parallel_sweeps_homogeneity(ctx):
+    """Heisenberg J = 1.3 on a 12-site chain swept with 2 regions (V on the
+    shared bond): dE/dJ = E/J."""
+    N, J = 12, 1.3
+    mps, mpo, E = _converged(ctx, "chain", N, 1, (J, 1.0), 64, 5, n_regions=2)
+    Eg, (gJ, gD) = pl.dE_dcouplings(mps, mpo, "chain", N, 1, (J, 1.0))
+    say("homogeneity E", Eg, "J dE/dJ", J * gJ)
+    assert abs(Eg - E) <= 1e-10 * abs(E)
+    assert abs(J * gJ - Eg) <= 1e-9 * abs(Eg)
+    # SU(2) point: the S^z S^z part carries one third of the energy
+    assert abs(gD - Eg / 3.0) <= 1e-7 * abs(Eg)
+
+
+def test_autograd_function_matches_grad_mpo(ctx):
+    import torch
+    N = 8
+    mps, mpo, E = _converged(ctx, "chain", N, 1, (1.0, 1.0), 16, 4)
+    W = [torch.tensor(w, dtype=torch.float64, requires_grad=True) for w in mpo.W]
+    Et = pl.mpo_energy(mps, mpo.deltas, W)
+    Et.backward()
+    _, G = mps.gradients(mpo)
+    assert abs(float(Et.detach()) - E) <= 1e-10 * abs(E)
+    for w, g in zip(W, G):
+        assert torch.allclose(w.grad, g.cpu(), rtol=1e-11, atol=1e-13)
+    # each site's G contracted with its own W gives the energy
+    assert abs(float(np.sum(W[3].grad.numpy() * mpo.W[3])) - E) <= 1e-10 * abs(E)
