@@ -272,10 +272,13 @@ int merge_regions(pdmrg_ctx *ctx, const pdmrg_bond *bl, const pdmrg_bond *bm,
  * left end, even ones at their right end) and every call runs the staggered
  * pattern of Fig. 4: half-sweep A (odd regions right, even left), merge and
  * re-split at shared bonds 1|2, 3|4, ...; half-sweep B, merges at 2|3, ...
- * The regions of a half-sweep share no data, so they are processed one after
- * the other on the context's stream; the result does not depend on their
- * order.  energy: <Psi|H|Psi>/<Psi|Psi> of the whole MPS after the sweep
- * (V applied on the shared bonds). */
+ * The regions of a half-sweep share no data (and neither do the merges of
+ * one merge phase): with concurrent = 1 each region runs on its own HIP
+ * stream, driven by its own host thread, with its own work space (the
+ * paper's one process per region, on one device); with concurrent = 0 they
+ * run one after the other on the context's stream.  The result is the same
+ * bits either way.  energy: <Psi|H|Psi>/<Psi|Psi> of the whole MPS after the
+ * sweep (V applied on the shared bonds). */
 typedef struct {
     int32_t max_m;
     int32_t n_regions;
@@ -284,6 +287,8 @@ typedef struct {
     pdmrg_dav_params dav;             /* interior bonds                       */
     pdmrg_dav_params dav_shared;      /* shared (merge) bonds                 */
     double cutoff, eps;
+    int32_t concurrent;               /* 1: regions on their own streams      */
+    int32_t pad_;
 } pdmrg_sweep_params;
 typedef struct {
     double energy;                    /* full <H> after the sweep             */

@@ -39,7 +39,8 @@ class CDavParams(Structure):
 
 class CSweepParams(Structure):
     _fields_ = [("max_m", c_int32), ("n_regions", c_int32), ("prec", c_int32), ("refine", c_int32),
-                ("dav", CDavParams), ("dav_shared", CDavParams), ("cutoff", c_double), ("eps", c_double)]
+                ("dav", CDavParams), ("dav_shared", CDavParams), ("cutoff", c_double), ("eps", c_double),
+                ("concurrent", c_int32), ("pad_", c_int32)]
 
 
 class CSweepReport(Structure):
@@ -410,10 +411,10 @@ class Mps:
             check(lib().mps_set_site(h, i, flat.ctypes.data_as(POINTER(c_double)), n))
 
     def sweep(self, mpo, max_m, n_regions=1, prec=F64, refine=True, dav=None, dav_shared=None,
-              cutoff=1e-12, eps=1e-4):
+              cutoff=1e-12, eps=1e-4, concurrent=True):
         p = CSweepParams(int(max_m), int(n_regions), int(prec), int(bool(refine)),
                          dav or dav_params(4, 8, 1e-8), dav_shared or dav_params(40, 8, 1e-10),
-                         float(cutoff), float(eps))
+                         float(cutoff), float(eps), int(bool(concurrent)), 0)
         rep = CSweepReport()
         check(lib().sweep(self.ctx.h, self.h, mpo.h, byref(p), byref(rep)))
         return {f: getattr(rep, f) for f, _ in CSweepReport._fields_}

@@ -50,6 +50,12 @@ int pdmrg_ctx_destroy(pdmrg_ctx *ctx) {
     API_BEGIN
     if (!ctx) return PDMRG_OK;
     (void)hipStreamSynchronize(ctx->stream);
+    for (pdmrg_ctx *c : ctx->sub) {
+        (void)hipStreamSynchronize(c->stream);
+        for (auto &e : c->ev_pool) (void)hipEventDestroy(e);
+        if (c->owns_stream) (void)hipStreamDestroy(c->stream);
+        delete c;
+    }
     for (auto &e : ctx->ev_pool) (void)hipEventDestroy(e);
     delete ctx;
     API_END

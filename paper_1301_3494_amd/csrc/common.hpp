@@ -138,4 +138,8 @@ struct pdmrg_ctx {
     // Tile-shape autotuning of H_eff plans: 0 cost model, 1 measured and
     // cached per block signature, 2 = 1 plus a log line per tuned plan.
     int autotune = 0;
+    // Per-region contexts of concurrent sweeps (own stream and work space),
+    // created on first use and destroyed with this context.
+    std::vector<pdmrg_ctx *> sub;
+    bool owns_stream = false;
 };

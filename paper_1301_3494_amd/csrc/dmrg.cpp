@@ -14,6 +14,8 @@
 
 #include <chrono>
 #include <cmath>
+#include <functional>
+#include <thread>
 
 using namespace pdmrg;
 
@@ -116,9 +118,14 @@ struct Driver {
             env_R(i + 1);
             m->sites[i] = take(r.left, na);
             m->sites[i + 1] = take(r.right, nb);
-            m->V[i + 1] = r.V;
-            m->Vd[i + 1] = DevBuf();
-            upload(m->Vd[i + 1], r.V, s());
+            // keys of the shared bonds exist before any concurrent merge runs
+            auto vit = m->V.find(i + 1);
+            if (vit == m->V.end()) vit = m->V.emplace(i + 1, std::vector<double>()).first;
+            vit->second = r.V;
+            auto dit = m->Vd.find(i + 1);
+            if (dit == m->Vd.end()) dit = m->Vd.emplace(i + 1, DevBuf()).first;
+            dit->second = DevBuf();
+            upload(dit->second, r.V, s());
             rep.n_floored += r.n_floored;
         }
         HIP_OK(hipStreamSynchronize(s()));
@@ -195,19 +202,87 @@ struct Driver {
         m->split = true;
     }
 
+    // Context of region r for concurrent work: own non-blocking stream (default
+    // priority) and work space, same device and tuning level.
+    pdmrg_ctx *sub_ctx(int r) {
+        while ((int)ctx->sub.size() <= r) {
+            auto *c = new pdmrg_ctx();
+            c->device = ctx->device;
+            HIP_OK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+            c->owns_stream = true;
+            ctx->sub.push_back(c);
+        }
+        ctx->sub[r]->autotune = ctx->autotune;
+        return ctx->sub[r];
+    }
+
+    // Runs independent jobs (disjoint sites, bonds and environments): with
+    // prm.concurrent, one host thread and one stream per job; else one after
+    // the other here.  Reports are merged; the first error is rethrown.
+    void run_jobs(const std::vector<std::function<void(Driver &)>> &jobs) {
+        if (!prm.concurrent || jobs.size() <= 1) {
+            for (auto &j : jobs) j(*this);
+            return;
+        }
+        HIP_OK(hipStreamSynchronize(s()));
+        std::vector<Driver> ds;
+        for (size_t k = 0; k < jobs.size(); ++k) {
+            Driver d{sub_ctx((int)k), m, mpo};
+            d.prm = prm;
+            ds.push_back(d);
+        }
+        std::vector<int> codes(jobs.size(), 0);
+        std::vector<std::string> msgs(jobs.size());
+        std::vector<std::thread> th;
+        for (size_t k = 0; k < jobs.size(); ++k)
+            th.emplace_back([&, k] {
+                try {
+                    HIP_OK(hipSetDevice(ctx->device));
+                    jobs[k](ds[k]);
+                    HIP_OK(hipStreamSynchronize(ds[k].s()));
+                } catch (const Error &e) {
+                    codes[k] = e.code;
+                    msgs[k] = e.what();
+                } catch (const std::exception &e) {
+                    codes[k] = PDMRG_EINVAL;
+                    msgs[k] = e.what();
+                }
+            });
+        for (auto &t : th) t.join();
+        for (size_t k = 0; k < jobs.size(); ++k) {
+            const pdmrg_sweep_report &r = ds[k].rep;
+            rep.n_matvec += r.n_matvec;
+            rep.n_floored += r.n_floored;
+            rep.max_trunc = std::max(rep.max_trunc, r.max_trunc);
+            rep.max_bond = std::max(rep.max_bond, r.max_bond);
+            t_heff += ds[k].t_heff;
+        }
+        for (size_t k = 0; k < jobs.size(); ++k)
+            if (codes[k] != 0) throw Error(codes[k], msgs[k]);
+    }
+
     void parallel_sweep() {
-        const auto &rg = m->regions;
+        const auto rg = m->regions;
         const int n = (int)rg.size();
         for (int half = 0; half < 2; ++half) {
+            std::vector<std::function<void(Driver &)>> jobs;
             for (int r = 0; r < n; ++r) {
                 const int lo = rg[r].first, hi = rg[r].second;
                 const bool right = (r % 2 == 0) == (half == 0);
-                if (right)
-                    for (int i = lo; i < hi; ++i) optimize(i, PDMRG_ABSORB_RIGHT, prm.dav);
-                else
-                    for (int i = hi - 1; i >= lo; --i) optimize(i, PDMRG_ABSORB_LEFT, prm.dav);
+                jobs.push_back([lo, hi, right](Driver &d) {
+                    if (right)
+                        for (int i = lo; i < hi; ++i) d.optimize(i, PDMRG_ABSORB_RIGHT, d.prm.dav);
+                    else
+                        for (int i = hi - 1; i >= lo; --i) d.optimize(i, PDMRG_ABSORB_LEFT, d.prm.dav);
+                });
             }
-            for (int r = half; r < n - 1; r += 2) merge_shared(rg[r].second);
+            run_jobs(jobs);
+            std::vector<std::function<void(Driver &)>> merges;
+            for (int r = half; r < n - 1; r += 2) {
+                const int j = rg[r].second;
+                merges.push_back([j](Driver &d) { d.merge_shared(j); });
+            }
+            run_jobs(merges);
         }
     }
 

@@ -2,6 +2,8 @@
 // layouts declared in include/pdmrg.h.
 #include "common.hpp"
 
+#include <mutex>
+
 namespace pdmrg {
 
 static thread_local std::string g_last_error;
@@ -126,6 +128,7 @@ EnvLayout env_r_layout(const Bond &b, const std::vector<int> &deltas) { return g
 // handed out while a kernel launched before its release still uses it.
 // Cached blocks are kept until the process ends.
 namespace {
+std::mutex g_cache_mu;   // the allocator serves every host thread of the process
 struct DeviceCache {
     std::map<std::pair<int, size_t>, std::vector<void *>> free_, pending_;
     bool has_pending = false;
@@ -146,6 +149,7 @@ void DevBuf::alloc(size_t n) {
     int dev = 0;
     HIP_OK(hipGetDevice(&dev));
     const size_t cls = size_class(n);
+    std::lock_guard<std::mutex> lk(g_cache_mu);
     DeviceCache &c = cache();
     auto key = std::make_pair(dev, cls);
     auto it = c.free_.find(key);
@@ -193,6 +197,7 @@ void DevBuf::release() {
     if (ptr) {
         int dev = 0;
         if (hipGetDevice(&dev) == hipSuccess) {
+            std::lock_guard<std::mutex> lk(g_cache_mu);
             DeviceCache &c = cache();
             c.pending_[std::make_pair(dev, bytes)].push_back(ptr);
             c.has_pending = true;

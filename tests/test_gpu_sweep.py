@@ -100,3 +100,33 @@ def test_xx_chain_closed_form_two_regions(ctx):
     e = exact.xx_chain_energy(N)
     say("xx", reps[-1]["energy"], e)
     assert abs(reps[-1]["energy"] - e) <= 1e-9 * abs(e)
+
+
+def test_concurrent_regions_bitwise_equal_to_sequential(ctx):
+    """Regions on their own streams and host threads give the same bits as
+    one after the other (no data crosses regions between merges)."""
+    N = 16
+    bonds, sites = synth.random_mps(N, 16, 5)
+    mpo = pl.Mpo("chain", N, 1, (1.0, 1.0))
+    out = {}
+    for conc in (False, True):
+        mps = pl.Mps(ctx, bonds, sites)
+        es = []
+        for k, m in enumerate([32, 48, 48, 64]):
+            rep = mps.sweep(mpo, m, 1 if k == 0 else 4, dav=pl.dav_params(6, 8, 1e-9),
+                            dav_shared=pl.dav_params(40, 8, 1e-10), concurrent=conc)
+            es.append(rep["energy"])
+        tens = []
+        for i in range(N):
+            B1, B2 = pl.Bond(mps.bond(i)), pl.Bond(mps.bond(i + 1))
+            _, n = pl.layout(pl.SITE, B1, B2, pl.Phys((-1, 1)))
+            buf = np.zeros(n)
+            pl.check(pl.lib().mps_get_site(mps.h, i, buf.ctypes.data_as(pl.POINTER(pl.c_double)), n))
+            tens.append(buf)
+        out[conc] = (es, tens)
+        mps.free()
+    say("sequential", out[False][0], "concurrent", out[True][0])
+    assert out[False][0] == out[True][0]
+    for a, b in zip(out[False][1], out[True][1]):
+        assert np.array_equal(a, b)
+    assert abs(out[True][0][-1] - E_ED_CHAIN16) <= 1e-6 * abs(E_ED_CHAIN16)
