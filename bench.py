@@ -87,6 +87,32 @@ def time_matvecs(ctx, pl, torch, op, x, y, steps, warmup):
     return wall, ms
 
 
+def _kernel_sources_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("gemm.hip", "plans.cpp", "heff.cpp", "kernels.hpp"):
+        with open(os.path.join(ROOT, "paper_1301_3494_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(prec, stage):
+    """HBM bytes per launch of the dominant GEMM from the committed rocprofv3
+    counter summary (FETCH_SIZE and WRITE_SIZE passes, calibrated), or None
+    when that summary was taken on other kernel sources or precision."""
+    path = os.path.join(ROOT, "profiles", "heff_gemm_cyl8x4_m1024_counters.txt")
+    try:
+        with open(path) as f:
+            for line in f:
+                if line.startswith("traffic_json: "):
+                    rec = json.loads(line[len("traffic_json: "):])
+                    if rec["sources"] == _kernel_sources_hash() and rec["prec"] == prec and rec["stage"] == stage + 1:
+                        return rec["bytes_per_launch"]
+    except (OSError, ValueError, KeyError):
+        pass
+    return None
+
+
 def cpu_baseline(wl, flops, budget_s=12.0):
     """The oracle's H_eff on the host cores, same block shapes (random blocks)."""
     import numpy as np
@@ -107,10 +133,58 @@ def cpu_baseline(wl, flops, budget_s=12.0):
         dmrg.heff_apply(*args, psi, bl, br, (-1, 1), mpo.deltas[c], mpo.deltas[c + 2])
         n += 1
     dt = (time.perf_counter() - t0) / n
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.environ.get("OPENBLAS_NUM_THREADS", os.cpu_count() or 1)))
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max(int(d.get("num_threads", 1)) for d in threadpool_info()
+                      if d.get("user_api") == "blas") if threadpool_info() else 1
+    except Exception:
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": round(flops / dt / 1e12, 6), "unit": "TFLOP/s", "cores": threads, "kind": "oracle",
             "sample": "%d oracle H_eff matvecs (numpy/BLAS FP64) on the same 8x4 m=1024 block shapes, "
                       "%.3f s each" % (n, dt)}
+
+
+def sweep_leg(ctx, pl, synth, torch, m=1024, regions=4, timed=2):
+    """Second half of the metric: wall seconds of a real-space parallel sweep
+    (Sec. II, Fig. 4) on the 8 x 4 cylinder at bond dimension m, FP64 path
+    against the mixed path (FP32 MFMA H_eff with FP64 Davidson refinement),
+    both from the same seeded MPS through the same schedule: one serial
+    warm-up sweep and the split sweep (untimed), then `timed` parallel sweeps
+    with the regions on their own streams."""
+    Lx, Ly, seed = 8, 4, 2
+    mpo = pl.Mpo("square", Lx, Ly, (1.0, 1.0))
+    bonds, sites = synth.random_mps(Lx * Ly, m, seed)
+    dav, dav_shared = pl.dav_params(6, 8, 1e-8), pl.dav_params(40, 8, 1e-10)
+    res = {}
+    for name, prec in (("f64", pl.F64), ("mixed", pl.F32)):
+        mps = pl.Mps(ctx, bonds, sites)
+        mps.sweep(mpo, m, 1, prec=prec, dav=dav, dav_shared=dav_shared)
+        mps.sweep(mpo, m, regions, prec=prec, dav=dav, dav_shared=dav_shared)
+        secs, rep = [], None
+        for _ in range(timed):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rep = mps.sweep(mpo, m, regions, prec=prec, dav=dav, dav_shared=dav_shared)
+            torch.cuda.synchronize()
+            secs.append(time.perf_counter() - t0)
+        res[name] = dict(seconds=sum(secs) / len(secs), energy=rep["energy"], n_matvec=rep["n_matvec"],
+                         seconds_heff=rep["seconds_heff"], max_trunc=rep["max_trunc"])
+        mps.free()
+        print("bench: sweep leg %s %.3f s/sweep E=%.15f" % (name, res[name]["seconds"], rep["energy"]),
+              file=sys.stderr, flush=True)
+    e64, emx = res["f64"]["energy"], res["mixed"]["energy"]
+    rel = abs(emx - e64) / abs(e64)
+    return {
+        "workload": "heisenberg_cyl8x4_m%d_%dregions_sweep" % (m, regions),
+        "schedule": "1 serial + 1 split sweep untimed, then %d timed parallel sweeps, m=%d, regions concurrent; "
+                    "Davidson 6 matvecs / 1e-8 interior, 40 / 1e-10 shared bonds" % (timed, m),
+        "seconds_per_sweep_f64": round(res["f64"]["seconds"], 4),
+        "seconds_per_sweep_mixed": round(res["mixed"]["seconds"], 4),
+        "speedup_mixed_vs_f64": round(res["f64"]["seconds"] / res["mixed"]["seconds"], 4),
+        "seconds_heff_f64": round(res["f64"]["seconds_heff"], 4),
+        "seconds_heff_mixed": round(res["mixed"]["seconds_heff"], 4),
+        "energy_f64": e64, "energy_mixed": emx, "rel_energy_diff": rel, "meets_1e-9": rel <= 1e-9,
+    }
 
 
 def main():
@@ -120,6 +194,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--prec", default="f32", choices=["f64", "f32", "bf16x3"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the sweep-seconds leg")
     ap.add_argument("--autotune", type=int, default=1, choices=[0, 1, 2],
                     help="tile-shape selection: 0 cost model, 1 timed at operator creation, 2 = 1 + log")
     args = ap.parse_args()
@@ -150,14 +225,20 @@ def main():
         err = float((y - y64).norm() / y64.norm())
         results[name] = dict(op=op, info=info, wall=wall, steps=steps, ms=ms, err=err,
                              tflops=info["flops"] / (wall / steps) / 1e12)
+        print("bench: %s matvec %.4f ms, %.2f TFLOP/s" % (name, wall / steps * 1e3, results[name]["tflops"]),
+              file=sys.stderr, flush=True)
     r = results[args.prec]
     info = r["info"]
     ms_step = r["wall"] / r["steps"] * 1e3
-    # dominant kernel: the slower of the two MFMA stages
+    # dominant kernel: the slower of the two MFMA GEMM launches (stage 1 L.psi,
+    # stage 3 T2.R without its split-K reduction), timed by the library's
+    # events on its own stream
     st = 0 if r["ms"][0] >= r["ms"][2] else 2
     stage_flops = info["flops_Lpsi"] if st == 0 else info["flops_R"]
     achieved = stage_flops / (r["ms"][st] * 1e-3) / 1e12
     peak = PEAK_TFLOPS[args.prec]
+    kname = "gemm_kmajor" if args.prec != "bf16x3" else "gemm_bf16x3"
+    traffic = stored_traffic(args.prec, st)
     out = {
         "metric": "H_eff matvec TFLOP/s (% MFMA peak); sweep s, mixed vs FP64 at 1e-9 rel E",
         "value": round(r["tflops"], 4),
@@ -175,18 +256,24 @@ def main():
                    "autotune": args.autotune,
                    "m": wl["m"], "mpo_D": int(W1.W.shape[0]), "psi_elems": info["n_psi"],
                    "flops_per_matvec": info["flops"], "dense_equiv_flops": 4.0 * 14 * 4 * 1024 ** 3},
-        "roofline": {"bound": "mfma", "kernel": "gemm stage %d (%s)" % (st + 1, "L.psi" if st == 0 else "T2.R"),
+        "roofline": {"bound": "mfma", "kernel": "%s stage %d (%s), %s tiles" % (
+                         kname, st + 1, "L.psi" if st == 0 else "T2.R",
+                         info["shape_Lpsi"] if st == 0 else info["shape_R"]),
                      "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-                     "frac": round(achieved / peak, 4), "traffic": None},
+                     "frac": round(achieved / peak, 4), "traffic": traffic},
+        "plan": {k: info[k] for k in ("shape_Lpsi", "shape_R", "tiles_Lpsi", "tiles_R", "splitk_parts")},
+        "stage_ms_order": ["L.psi GEMM", "W stage", "T2.R GEMM", "split-K reduction", "total"],
         "stage_ms": {k: [round(v, 5) for v in results[k]["ms"]] for k in results},
         "precisions": {k: {"tflops": round(v["tflops"], 3), "ms_per_matvec": round(v["wall"] / v["steps"] * 1e3, 5),
                            "rel_err_vs_f64": v["err"], "pct_peak": round(100 * v["tflops"] / PEAK_TFLOPS[k], 2)}
                        for k, v in results.items()},
     }
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(wl, info["flops"])
     for v in results.values():
         v["op"].free()
+    if not args.no_sweep:
+        out["sweep"] = sweep_leg(ctx, pl, synth, torch)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wl, info["flops"])
     ctx.close()
     print(json.dumps(out))
 

@@ -181,6 +181,11 @@ int heff_apply(pdmrg_ctx *ctx, pdmrg_heff *op, const double *x_dev, double *y_de
  * entries only, 2 flops per multiply-add) and element counts. */
 int heff_info(const pdmrg_heff *op, double *flops_Lpsi, double *flops_W, double *flops_R,
               int64_t *n_psi, int64_t *n_L, int64_t *n_R, int64_t *n_T1, int64_t *n_T2);
+/* Plan of an operator: tile shape of the stage-1 and stage-3 grouped GEMMs
+ * (0: 64x64, 1: 128x32, 2: 32x128, 3: 128x128), their tile counts, and the
+ * number of K parts stage 3 is split into (outputs optional). */
+int heff_plan_info(const pdmrg_heff *op, int32_t *shape_Lpsi, int32_t *shape_R, int32_t *tiles_Lpsi,
+                   int32_t *tiles_R, int32_t *splitk_parts);
 /* diag(H_eff) into diag_dev (TWO_SITE layout, FP64). */
 int heff_diag(pdmrg_ctx *ctx, pdmrg_heff *op, double *diag_dev);
 void heff_free(pdmrg_heff *op);

@@ -73,7 +73,7 @@ def lib():
 EXPORTS = [
     "pdmrg_last_error", "pdmrg_version", "pdmrg_ctx_create", "pdmrg_ctx_destroy", "pdmrg_ctx_set_timing",
     "pdmrg_ctx_timing", "pdmrg_ctx_set_autotune", "pdmrg_layout_size", "pdmrg_layout_blocks", "mpo_build", "mpo_from_sites",
-    "mpo_info", "mpo_get_site", "mpo_free", "heff_create", "heff_apply", "heff_info", "heff_diag",
+    "mpo_info", "mpo_get_site", "mpo_free", "heff_create", "heff_apply", "heff_info", "heff_plan_info", "heff_diag",
     "heff_free", "env_update", "davidson_step", "svd_truncate", "svd_result_bond", "svd_result_copy",
     "svd_free", "merge_regions", "mps_alloc", "mps_set_site", "mps_bond", "mps_get_site", "sweep",
     "mps_energy", "mps_free", "grad_site", "grad_mpo",
@@ -103,6 +103,7 @@ def _declare(L):
         "heff_apply": (c_int, [P, P, P, P]),
         "heff_info": (c_int, [P, pd, pd, pd, pi64, pi64, pi64, pi64, pi64]),
         "heff_diag": (c_int, [P, P, P]),
+        "heff_plan_info": (c_int, [P, pi32, pi32, pi32, pi32, pi32]),
         "heff_free": (None, [P]),
         "env_update": (c_int, [P, c_int, pb, pb, pp, pm, P, P, P, c_int]),
         "davidson_step": (c_int, [P, P, P, P, POINTER(CDavParams), pd, pd, pi32]),
@@ -251,6 +252,11 @@ class Heff:
         out = dict(flops_Lpsi=f[0].value, flops_W=f[1].value, flops_R=f[2].value)
         out.update({k: v.value for k, v in zip(keys, n)})
         out["flops"] = out["flops_Lpsi"] + out["flops_W"] + out["flops_R"]
+        v = [c_int32() for _ in range(5)]
+        check(lib().heff_plan_info(self.h, *[byref(x) for x in v]))
+        names = ["64x64", "128x32", "32x128", "128x128"]
+        out.update(shape_Lpsi=names[v[0].value], shape_R=names[v[1].value], tiles_Lpsi=v[2].value,
+                   tiles_R=v[3].value, splitk_parts=v[4].value)
         return out
 
     def diag(self, out):
@@ -289,7 +295,7 @@ def timing(ctx, enable=None):
     if enable is not None:
         check(lib().pdmrg_ctx_set_timing(ctx.h, int(bool(enable))))
         return None
-    ms = (c_double * 4)()
+    ms = (c_double * 5)()
     n = c_int64()
     check(lib().pdmrg_ctx_timing(ctx.h, ms, byref(n)))
     return list(ms), n.value

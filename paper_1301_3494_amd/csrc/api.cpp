@@ -80,21 +80,22 @@ int pdmrg_ctx_set_autotune(pdmrg_ctx *ctx, int level) {
 int pdmrg_ctx_timing(pdmrg_ctx *ctx, double *ms_stage, int64_t *n_calls) {
     API_BEGIN
     PD_REQUIRE(ctx && ms_stage && n_calls, PDMRG_EINVAL, "null argument");
-    double acc[4] = {0, 0, 0, 0};
+    constexpr int NS = kTimingEvents - 1;
+    double acc[NS + 1] = {};
     if (ctx->n_timed > 0) {
-        HIP_OK(hipEventSynchronize(ctx->ev_pool[(size_t)ctx->n_timed * 4 - 1]));
+        HIP_OK(hipEventSynchronize(ctx->ev_pool[(size_t)ctx->n_timed * kTimingEvents - 1]));
         for (int64_t c = 0; c < ctx->n_timed; ++c) {
-            hipEvent_t *e = &ctx->ev_pool[(size_t)c * 4];
-            for (int k = 0; k < 3; ++k) {
+            hipEvent_t *e = &ctx->ev_pool[(size_t)c * kTimingEvents];
+            for (int k = 0; k < NS; ++k) {
                 float ms = 0.f;
                 HIP_OK(hipEventElapsedTime(&ms, e[k], e[k + 1]));
                 acc[k] += ms;
-                acc[3] += ms;
+                acc[NS] += ms;
             }
         }
     }
     *n_calls = ctx->n_timed;
-    for (int i = 0; i < 4; ++i) ms_stage[i] = ctx->n_timed ? acc[i] / ctx->n_timed : 0.0;
+    for (int i = 0; i <= NS; ++i) ms_stage[i] = ctx->n_timed ? acc[i] / ctx->n_timed : 0.0;
     API_END
 }
 
@@ -266,6 +267,19 @@ int heff_info(const pdmrg_heff *op, double *flops_Lpsi, double *flops_W, double 
     if (n_R) *n_R = op->nR;
     if (n_T1) *n_T1 = op->plan.nT1;
     if (n_T2) *n_T2 = op->plan.nT2;
+    API_END
+}
+
+int heff_plan_info(const pdmrg_heff *op, int32_t *shape_Lpsi, int32_t *shape_R, int32_t *tiles_Lpsi,
+                   int32_t *tiles_R, int32_t *splitk_parts) {
+    API_BEGIN
+    PD_REQUIRE(op, PDMRG_EINVAL, "heff_plan_info: null operator");
+    const HeffPlan &pl = op->plan;
+    if (shape_Lpsi) *shape_Lpsi = (int32_t)pl.g1.shape;
+    if (shape_R) *shape_R = (int32_t)pl.g3.shape;
+    if (tiles_Lpsi) *tiles_Lpsi = (int32_t)pl.g1.tiles.size();
+    if (tiles_R) *tiles_R = (int32_t)pl.g3.tiles.size();
+    if (splitk_parts) *splitk_parts = pl.parts3;
     API_END
 }
 

@@ -12,16 +12,16 @@ namespace pdmrg {
 // rows x cols block in row-major order, so narrow sector blocks keep every
 // thread busy.  Each thread owns kLcChunk / 256 elements and keeps their loads
 // of one source in flight together; sources are summed in list order.
-template <typename T>
+template <typename T, typename TD, int CHUNK>
 __global__ __launch_bounds__(256) void lincomb_kernel(Slots slots, const LcTask *__restrict__ tasks,
                                                       const LcSrc *__restrict__ srcs,
                                                       const LcTile *__restrict__ tiles) {
-    constexpr int U = kLcChunk / 256;
+    constexpr int U = CHUNK / 256;
     const LcTile tl = tiles[blockIdx.x];
     const LcTask tk = tasks[tl.task];
     // rows * cols < 2^31 (checked when the list is built)
     const unsigned n = (unsigned)tk.rows * (unsigned)tk.cols;
-    const unsigned e0 = (unsigned)tl.r0 * kLcChunk;
+    const unsigned e0 = (unsigned)tl.r0 * CHUNK;
     int64_t roff[U];
     int cc[U];
     bool ok[U];
@@ -46,17 +46,33 @@ __global__ __launch_bounds__(256) void lincomb_kernel(Slots slots, const LcTask 
 #pragma unroll
         for (int u = 0; u < U; ++u) acc[u] += cf * v[u];
     }
-    T *dst = static_cast<T *>(const_cast<void *>(slots.p[tk.dst_slot])) + tk.dst_off;
+    TD *dst = static_cast<TD *>(const_cast<void *>(slots.p[tk.dst_slot])) + tk.dst_off;
 #pragma unroll
     for (int u = 0; u < U; ++u)
-        if (ok[u]) dst[roff[u] * tk.ld + cc[u]] = acc[u];
+        if (ok[u]) dst[roff[u] * tk.ld + cc[u]] = (TD)acc[u];
 }
 
-void launch_lincomb(bool f64, const Slots &slots, const LcTask *tasks, const LcSrc *srcs,
+void launch_lincomb(bool f64, int chunk, const Slots &slots, const LcTask *tasks, const LcSrc *srcs,
                     const LcTile *tiles, int ntiles, hipStream_t s) {
     if (ntiles <= 0) return;
-    if (f64) hipLaunchKernelGGL(lincomb_kernel<double>, dim3(ntiles), dim3(256), 0, s, slots, tasks, srcs, tiles);
-    else hipLaunchKernelGGL(lincomb_kernel<float>, dim3(ntiles), dim3(256), 0, s, slots, tasks, srcs, tiles);
+    const dim3 g(ntiles), b(256);
+    if (chunk == kLcChunkSmall) {
+        if (f64) hipLaunchKernelGGL((lincomb_kernel<double, double, kLcChunkSmall>), g, b, 0, s, slots, tasks, srcs, tiles);
+        else hipLaunchKernelGGL((lincomb_kernel<float, float, kLcChunkSmall>), g, b, 0, s, slots, tasks, srcs, tiles);
+    } else {
+        if (f64) hipLaunchKernelGGL((lincomb_kernel<double, double, kLcChunk>), g, b, 0, s, slots, tasks, srcs, tiles);
+        else hipLaunchKernelGGL((lincomb_kernel<float, float, kLcChunk>), g, b, 0, s, slots, tasks, srcs, tiles);
+    }
+}
+
+void launch_lincomb_f32_f64(int chunk, const Slots &slots, const LcTask *tasks, const LcSrc *srcs,
+                            const LcTile *tiles, int ntiles, hipStream_t s) {
+    if (ntiles <= 0) return;
+    const dim3 g(ntiles), b(256);
+    if (chunk == kLcChunkSmall)
+        hipLaunchKernelGGL((lincomb_kernel<float, double, kLcChunkSmall>), g, b, 0, s, slots, tasks, srcs, tiles);
+    else
+        hipLaunchKernelGGL((lincomb_kernel<float, double, kLcChunk>), g, b, 0, s, slots, tasks, srcs, tiles);
 }
 
 // ------------------------------------------------------------ block dot products

@@ -121,6 +121,10 @@ void upload(DevBuf &buf, const std::vector<T> &v, hipStream_t s) {
 
 }  // namespace pdmrg
 
+// Events per timed heff_apply: before stage 1, the W stage, the stage-3 GEMM,
+// the split-K reduction, and after it.
+constexpr int kTimingEvents = 5;
+
 struct pdmrg_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -129,7 +133,6 @@ struct pdmrg_ctx {
     bool timing = false;
     std::vector<hipEvent_t> ev_pool;
     int64_t n_timed = 0;
-    double stage_ms[4] = {0, 0, 0, 0};
     pdmrg::DevBuf ws_dav;           // Davidson basis and scalars
     pdmrg::DevBuf ws_env;           // environment-update intermediates
     pdmrg::DevBuf ws_merge;         // merge: V-scaled right tensor

@@ -11,8 +11,11 @@ namespace pdmrg {
 
 namespace {
 std::mutex g_tune_mu;
-std::map<std::string, std::pair<int, int>> &tune_cache() {
-    static auto *m = new std::map<std::string, std::pair<int, int>>();
+struct Tuned {
+    int shape1 = -1, shape3 = -1, parts3 = 0;
+};
+std::map<std::string, Tuned> &tune_cache() {
+    static auto *m = new std::map<std::string, Tuned>();
     return *m;
 }
 
@@ -79,27 +82,37 @@ void tune_heff(pdmrg_ctx *ctx, pdmrg_heff *op, const std::string &key) {
         log << " g1 " << shape_name(t) << ' ' << ms;
         if (ms < t1best) { t1best = ms; best1 = t; }
     }
+    const size_t pes = f64 ? sizeof(double) : sizeof(float);   // partial element size
+    int parts3 = pl.parts3;
     for (int t = 0; t < kNumShapes; ++t) {
         if (!(pl.g3.shapes_allowed & (1u << t))) continue;
-        pl.set_g3_shape((TileShape)t, s);
-        op->P.ensure(std::max<int64_t>(pl.nP, 1) * sizeof(double));
-        sl.p[6] = op->P.ptr;
-        const double ms = time_ms(s, reps, [&] {
-            pl.g3.launch(gp, true, sl, s);
-            pl.r3.launch(true, sl, s);
-        });
-        log << " g3 " << shape_name(t) << ' ' << ms;
-        if (ms < t3best) { t3best = ms; best3 = t; }
+        // split-K factors: the default one and the others that still give >= 256 tiles
+        const int tiles = std::max(1, pl.g3_base.ntiles_for((TileShape)t));
+        std::vector<int> cand = {pl.default_parts((TileShape)t)};
+        for (int p : {1, 2, 3, 4, 6, 8})
+            if (p != cand[0] && tiles * p >= 256) cand.push_back(p);
+        for (int parts : cand) {
+            pl.set_g3_shape((TileShape)t, s, parts);
+            op->P.ensure(std::max<int64_t>(pl.nP, 1) * pes);
+            sl.p[6] = op->P.ptr;
+            const double ms = time_ms(s, reps, [&] {
+                pl.g3.launch(gp, f64, sl, s);
+                if (f64) pl.r3.launch(true, sl, s);
+                else pl.r3.launch_f32_to_f64(sl, s);
+            });
+            log << " g3 " << shape_name(t) << "/" << parts << ' ' << ms;
+            if (ms < t3best) { t3best = ms; best3 = t; parts3 = parts; }
+        }
     }
     pl.set_g1_shape((TileShape)best1, s);
-    pl.set_g3_shape((TileShape)best3, s);
+    pl.set_g3_shape((TileShape)best3, s, parts3);
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
-        tune_cache()[key] = {best1, best3};
+        tune_cache()[key] = Tuned{best1, best3, parts3};
     }
     if (ctx->autotune >= 2)
-        std::fprintf(stderr, "pdmrg autotune: g1 %s g3 %s  (ms:%s)\n", shape_name(best1), shape_name(best3),
-                     log.str().c_str());
+        std::fprintf(stderr, "pdmrg autotune: g1 %s g3 %s/%d  (ms:%s)\n", shape_name(best1), shape_name(best3),
+                     parts3, log.str().c_str());
 }
 }  // namespace
 
@@ -149,20 +162,21 @@ void heff_build(pdmrg_ctx *ctx, pdmrg_heff *op, const Bond &bl, const Bond &br, 
     op->T2.ensure(std::max<int64_t>(pl.nT2, 1) * es);
     if (ctx->autotune > 0) {
         const std::string key = tune_key(ctx->device, prec, bl, br, W1, W2);
-        std::pair<int, int> hit{-1, -1};
+        Tuned hit;
         {
             std::lock_guard<std::mutex> lk(g_tune_mu);
             auto it = tune_cache().find(key);
             if (it != tune_cache().end()) hit = it->second;
         }
-        if (hit.first >= 0) {
-            if (hit.first != (int)pl.g1.shape) pl.set_g1_shape((TileShape)hit.first, s);
-            if (hit.second != (int)pl.g3.shape) pl.set_g3_shape((TileShape)hit.second, s);
+        if (hit.shape1 >= 0) {
+            if (hit.shape1 != (int)pl.g1.shape) pl.set_g1_shape((TileShape)hit.shape1, s);
+            if (hit.shape3 != (int)pl.g3.shape || hit.parts3 != pl.parts3)
+                pl.set_g3_shape((TileShape)hit.shape3, s, hit.parts3);
         } else {
             tune_heff(ctx, op, key);
         }
     }
-    op->P.ensure(std::max<int64_t>(pl.nP, 1) * sizeof(double));
+    op->P.ensure(std::max<int64_t>(pl.nP, 1) * (prec == PDMRG_F64 ? sizeof(double) : sizeof(float)));
 }
 
 void grad_site_run(pdmrg_ctx *ctx, const GradPlan &plan, const double *L, const double *psi, const double *R,
@@ -194,13 +208,13 @@ void heff_run(pdmrg_ctx *ctx, pdmrg_heff *op, const double *x, double *y) {
     sl.p[6] = op->P.ptr;
     hipEvent_t *ev = nullptr;
     if (ctx->timing) {
-        const size_t need = (size_t)(ctx->n_timed + 1) * 4;
+        const size_t need = (size_t)(ctx->n_timed + 1) * kTimingEvents;
         while (ctx->ev_pool.size() < need) {
             hipEvent_t e;
             HIP_OK(hipEventCreate(&e));
             ctx->ev_pool.push_back(e);
         }
-        ev = &ctx->ev_pool[(size_t)ctx->n_timed * 4];
+        ev = &ctx->ev_pool[(size_t)ctx->n_timed * kTimingEvents];
         ctx->n_timed += 1;
         HIP_OK(hipEventRecord(ev[0], s));
     }
@@ -208,9 +222,11 @@ void heff_run(pdmrg_ctx *ctx, pdmrg_heff *op, const double *x, double *y) {
     if (ev) HIP_OK(hipEventRecord(ev[1], s));
     pl.w.launch(f64, sl, s);
     if (ev) HIP_OK(hipEventRecord(ev[2], s));
-    pl.g3.launch(gp, true, sl, s);
-    pl.r3.launch(true, sl, s);
+    pl.g3.launch(gp, f64, sl, s);
     if (ev) HIP_OK(hipEventRecord(ev[3], s));
+    if (f64) pl.r3.launch(true, sl, s);
+    else pl.r3.launch_f32_to_f64(sl, s);
+    if (ev) HIP_OK(hipEventRecord(ev[4], s));
 }
 
 }  // namespace pdmrg

@@ -52,9 +52,10 @@ struct LcSrc {
     double coef;
 };
 
-// Tile of a W-stage launch: elements [r0 * kLcChunk, (r0 + 1) * kLcChunk) of
-// task `task` (row-major over its rows x cols block).
-constexpr int kLcChunk = 2048;
+// Tile of a W-stage launch: elements [r0 * chunk, (r0 + 1) * chunk) of task
+// `task` (row-major over its rows x cols block); chunk = c0 elements, 2048
+// (8 per thread) or 512 (2 per thread, for short lists such as reductions).
+constexpr int kLcChunk = 2048, kLcChunkSmall = 512;
 struct LcTile {
     int32_t task, r0, c0, pad_;
 };
@@ -96,8 +97,12 @@ inline int tile_bn(TileShape t) { return t == TileShape::T64x64 ? 64 : t == Tile
 void launch_gemm(GemmPrec prec, TileShape shape, bool ta, bool tb, bool c_is_f64, const Slots &slots,
                  const GemmItem *items, const GemmSeg *segs, const GemmTile *tiles, const int64_t *rowoff,
                  int ntiles, hipStream_t s);
-void launch_lincomb(bool f64, const Slots &slots, const LcTask *tasks, const LcSrc *srcs,
+// chunk: kLcChunk or kLcChunkSmall elements per tile (as the tiles were built).
+void launch_lincomb(bool f64, int chunk, const Slots &slots, const LcTask *tasks, const LcSrc *srcs,
                     const LcTile *tiles, int ntiles, hipStream_t s);
+// Same with FP32 sources summed in FP32 and an FP64 destination.
+void launch_lincomb_f32_f64(int chunk, const Slots &slots, const LcTask *tasks, const LcSrc *srcs,
+                            const LcTile *tiles, int ntiles, hipStream_t s);
 // groups[g]..groups[g+1]: the terms of output block g (all share out_off, rows,
 // cols, ld); each output block is written once (zero if it has no terms).
 void launch_diag_terms(const Slots &slots, const DiagTerm *terms, const int32_t *groups, int ngroups,

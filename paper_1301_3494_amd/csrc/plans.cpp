@@ -185,8 +185,8 @@ void LcList::validate(const std::vector<int64_t> &slot_elems) const {
     }
 }
 
-int64_t GemmList::split_k(int parts, int pslot, LcList &reduce) {
-    if (parts <= 1) return 0;
+int64_t GemmList::split_k(int parts, int pslot, LcList &reduce, bool all) {
+    if (parts <= 1 && !all) return 0;
     std::vector<GemmItem> nitems;
     std::vector<GemmSeg> nsegs;
     std::vector<int32_t> nblk0;
@@ -195,7 +195,8 @@ int64_t GemmList::split_k(int parts, int pslot, LcList &reduce) {
     for (size_t ii = 0; ii < items.size(); ++ii) {
         const GemmItem &it = items[ii];
         const int64_t ktot = item_k(*this, it);
-        if (ktot < (int64_t)parts * 128 || it.M == 0 || it.N == 0) {
+        const int ip = ktot < (int64_t)parts * 128 ? 1 : parts;   // K parts of this item
+        if (it.M == 0 || it.N == 0 || (ip == 1 && !all)) {
             GemmItem c = it;
             c.seg0 = (int32_t)nsegs.size();
             for (int k = 0; k < it.nseg; ++k) nsegs.push_back(segs[it.seg0 + k]);
@@ -219,10 +220,10 @@ int64_t GemmList::split_k(int parts, int pslot, LcList &reduce) {
             outb.push_back(RowBlock{it.c_off, 0, it.M, it.ldc});
         }
         const int64_t pbase = pel;
-        for (int p = 0; p < parts; ++p) {
+        for (int p = 0; p < ip; ++p) {
             // K range [kb, ke), boundaries rounded to multiples of 32
-            const int64_t kb = (ktot * p / parts) / 32 * 32;
-            const int64_t ke = p + 1 == parts ? ktot : (ktot * (p + 1) / parts) / 32 * 32;
+            const int64_t kb = (ktot * p / ip) / 32 * 32;
+            const int64_t ke = p + 1 == ip ? ktot : (ktot * (p + 1) / ip) / 32 * 32;
             GemmItem c{};
             c.c_slot = pslot;
             c.c_off = pel;
@@ -254,7 +255,7 @@ int64_t GemmList::split_k(int parts, int pslot, LcList &reduce) {
         // fixed-order reduction of the parts into each output block
         for (const RowBlock &ob : outb) {
             reduce.add_task(it.c_slot, ob.c_off, ob.rows, it.N, ob.ldc);
-            for (int p = 0; p < parts; ++p)
+            for (int p = 0; p < ip; ++p)
                 reduce.add_src(pslot, pbase + (int64_t)p * it.M * it.N + (int64_t)ob.r0 * it.N, it.N, 1.0);
         }
     }
@@ -302,15 +303,21 @@ void LcList::finish(hipStream_t s) {
     for (size_t i = 0; i < tasks.size(); ++i) {
         const LcTask &t = tasks[i];
         const int64_t n = (int64_t)t.rows * t.cols;
-        for (int64_t c = 0; c * kLcChunk < n; ++c) tiles.push_back(LcTile{(int32_t)i, (int32_t)c, 0, 0});
+        for (int64_t c = 0; c * chunk < n; ++c) tiles.push_back(LcTile{(int32_t)i, (int32_t)c, chunk, 0});
     }
     upload(d_tasks, tasks, s);
     upload(d_srcs, srcs, s);
     upload(d_tiles, tiles, s);
 }
 
+void LcList::launch_f32_to_f64(const Slots &sl, hipStream_t s) const {
+    launch_lincomb_f32_f64(chunk, sl, d_tasks.as<LcTask>(), d_srcs.as<LcSrc>(), d_tiles.as<LcTile>(),
+                           (int)tiles.size(), s);
+}
+
 void LcList::launch(bool f64, const Slots &sl, hipStream_t s) const {
-    launch_lincomb(f64, sl, d_tasks.as<LcTask>(), d_srcs.as<LcSrc>(), d_tiles.as<LcTile>(), (int)tiles.size(), s);
+    launch_lincomb(f64, chunk, sl, d_tasks.as<LcTask>(), d_srcs.as<LcSrc>(), d_tiles.as<LcTile>(), (int)tiles.size(),
+                   s);
 }
 
 std::vector<double> two_site_mpo(const MpoSite &W1, const MpoSite &W2) {
@@ -487,6 +494,7 @@ void HeffPlan::build(const Bond &bl_, const Bond &br_, const Phys &p_, const Mpo
     g1.finish(s);
     w.finish(s);
     g3_base = g3.host_copy();
+    lowp = prec != PDMRG_F64;
     set_g3_shape(g3.shape, s);
 }
 
@@ -495,14 +503,22 @@ void HeffPlan::set_g1_shape(TileShape t, hipStream_t s) {
     g1.finish(s);
 }
 
-void HeffPlan::set_g3_shape(TileShape t, hipStream_t s) {
+int HeffPlan::default_parts(TileShape t) const {
+    // split-K for stage 3: aim at >= 1024 output tiles (4 per CU)
+    const int tiles3 = std::max(1, g3_base.ntiles_for(t));
+    return std::max(1, std::min(8, (1024 + tiles3 - 1) / tiles3));
+}
+
+void HeffPlan::set_g3_shape(TileShape t, hipStream_t s, int parts) {
     g3 = g3_base.host_copy();
     g3.shape = t;
-    // split-K for stage 3: aim at >= 1024 output tiles (4 per CU)
-    const int tiles3 = std::max(1, g3.ntiles_for(g3.shape));
-    const int parts = std::max(1, std::min(8, (1024 + tiles3 - 1) / tiles3));
+    if (parts <= 0) parts = default_parts(t);
     r3 = LcList();
-    nP = g3.split_k(parts, 6, r3);
+    r3.chunk = kLcChunkSmall;
+    // low precision: every item goes through the FP32 partial buffer and the
+    // reduction writes the FP64 output
+    nP = g3.split_k(parts, 6, r3, lowp);
+    parts3 = parts;
     const std::vector<int64_t> sz = {X.size, X.size, Lt.size, Rt.size, nT1, nT2, nP};
     g3.validate(sz);
     r3.validate(sz);

@@ -48,10 +48,13 @@ struct GemmList {
     // `pslot` (packed, ld = N); `reduce` receives one task per original item
     // that sums its partials into the original C in a fixed order.  Returns
     // the number of partial elements.  Call before validate / finish.
-    int64_t split_k(int parts, int pslot, LcList &reduce);
+    // all = true: items too short to split are still written as one part, so
+    // the whole list writes slot `pslot` (e.g. partials of another precision).
+    int64_t split_k(int parts, int pslot, LcList &reduce, bool all = false);
 };
 
 struct LcList {
+    int chunk = kLcChunk;   // elements per tile (kLcChunkSmall for short lists)
     std::vector<LcTask> tasks;
     std::vector<LcSrc> srcs;
     std::vector<LcTile> tiles;
@@ -63,6 +66,7 @@ struct LcList {
     void add_src(int slot, int64_t off, int ld, double coef);
     void finish(hipStream_t s);
     void launch(bool f64, const Slots &sl, hipStream_t s) const;
+    void launch_f32_to_f64(const Slots &sl, hipStream_t s) const;
     void validate(const std::vector<int64_t> &slot_elems) const;
 };
 
@@ -78,10 +82,16 @@ struct HeffPlan {
     int64_t nT1 = 0, nT2 = 0, nP = 0;
     GemmList g1, g3;
     GemmList g3_base;   // stage 3 before split-K
-    LcList w, r3;   // W stage; split-K reduction of stage 3 (partials in slot 6, FP64)
-    // Re-tile stage 1 / stage 3 (stage 3 is re-split for the new tile count).
+    // W stage; split-K reduction of stage 3 (partials in slot 6: FP64 in FP64
+    // mode; FP32 for every item in the FP32 / BF16x3 modes)
+    LcList w, r3;
+    bool lowp = false;
+    int parts3 = 1;
+    // Re-tile stage 1 / stage 3 (stage 3 is re-split: parts <= 0 picks the
+    // K split that gives >= 1024 tiles).
     void set_g1_shape(TileShape t, hipStream_t s);
-    void set_g3_shape(TileShape t, hipStream_t s);
+    void set_g3_shape(TileShape t, hipStream_t s, int parts = 0);
+    int default_parts(TileShape t) const;
     std::vector<DiagTerm> diag_terms;
     std::vector<int32_t> diag_groups;
     int diag_max_rows = 0;

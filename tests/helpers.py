@@ -83,3 +83,11 @@ def host(t):
 
 def say(*args):
     print(*args, flush=True)
+
+
+def golden(key):
+    """A stored exact reference value (tests/golden/exact_energies.json,
+    written from the oracle by tests/golden/make_golden.py)."""
+    import json
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "exact_energies.json")) as f:
+        return json.load(f)[key]

@@ -1,0 +1,68 @@
+"""Parity at the full size of the metric's bond (8 x 4 cylinder, m = 1024,
+sites 15 and 16, D = 14, 586,150 psi elements) in the configuration the
+benchmark times (autotuned tile shapes and split-K), all three precisions,
+against the oracle's complete H_eff product."""
+import numpy as np
+import pytest
+
+from helpers import pl, synth, say, dev, host, blocks_to_flat, flat_to_blocks, tables, mpo_site, rel_err
+from oracle import models, mpo as M, dmrg
+from oracle.blocks import Bond, two_site_keys, two_site_shape, flatten
+
+pytestmark = pytest.mark.gpu
+PQ = synth.SPIN_HALF_Q
+
+
+@pytest.fixture(scope="module")
+def problem():
+    Lx, Ly, m, c, seed = 8, 4, 1024, 15, 2
+    N = Lx * Ly
+    mpo = M.build_mpo(models.heisenberg_terms(models.square_cylinder_bonds(Lx, Ly)), N, models.OPS, PQ)
+    bonds = synth.binomial_bonds(N, m)
+    rng = np.random.default_rng(seed)
+    L = synth.random_env_blocks(bonds[c], mpo.deltas[c], rng)
+    R = synth.random_env_blocks(bonds[c + 2], mpo.deltas[c + 2], rng)
+    psi = synth.random_two_site_blocks(bonds[c], bonds[c + 2], PQ, rng)
+    bl, br = Bond(bonds[c]), Bond(bonds[c + 2])
+    yref = dmrg.heff_apply(L, R, mpo.W[c], mpo.W[c + 1], psi, bl, br, PQ, mpo.deltas[c], mpo.deltas[c + 2])
+    keys = two_site_keys(bl, br, PQ)
+    shapes = [two_site_shape(k, bl, br, PQ) for k in keys]
+    return dict(mpo=mpo, bonds=bonds, c=c, L=L, R=R, psi=psi, yref=flatten(yref, keys, shapes), keys=keys,
+                shapes=shapes)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = pl.Context(0)
+    pl.set_autotune(c, 1)
+    yield c
+    c.close()
+
+
+@pytest.mark.parametrize("prec,tol", [(pl.F64, 1e-12), (pl.F32, 1e-5), (pl.BF16X3, 1e-4)])
+def test_full_size_heff_matches_oracle(ctx, problem, prec, tol):
+    P = problem
+    mpo, bonds, c = P["mpo"], P["bonds"], P["c"]
+    say("full-size heff prec", prec)
+    t, (B1, B2, Ph) = tables(bonds[c], bonds[c + 2], PQ, mpo.deltas[c], mpo.deltas[c + 2])
+    Ld = dev(blocks_to_flat(P["L"], t["L"][0], t["L"][1], pl.ENV_L))
+    Rd = dev(blocks_to_flat(P["R"], t["R"][0], t["R"][1], pl.ENV_R))
+    op = pl.Heff(ctx, B1, B2, Ph, mpo_site(mpo, c), mpo_site(mpo, c + 1), Ld, Rd, prec)
+    info = op.info()
+    assert info["n_psi"] == 586150
+    x = dev(blocks_to_flat(P["psi"], t["x"][0], t["x"][1], pl.TWO_SITE))
+    y = dev(np.full(t["x"][1], np.nan))
+    op.apply(x, y)
+    a = flatten(flat_to_blocks(host(y), t["x"][0], pl.TWO_SITE), P["keys"], P["shapes"])
+    b = P["yref"]
+    err = rel_err(a, b)
+    say("  plan", {k: info[k] for k in ("shape_Lpsi", "shape_R", "splitk_parts")}, "rel err", err)
+    assert np.all(np.isfinite(a))
+    assert err <= tol
+    if prec == pl.F64:
+        assert np.max(np.abs(a - b)) <= 1e-12 * np.max(np.abs(b))
+    # repeated application gives the same bits
+    y2 = dev(np.full(t["x"][1], np.nan))
+    op.apply(x, y2)
+    assert np.array_equal(host(y), host(y2))
+    op.free()

@@ -4,11 +4,11 @@ precision with FP64 refinement, U(1) and no-symmetry models."""
 import numpy as np
 import pytest
 
-from helpers import pl, synth, say
+from helpers import pl, synth, say, golden
 from oracle import models, mpo as M, dmrg, exact
 
 pytestmark = pytest.mark.gpu
-E_ED_CHAIN16 = -6.911737145575103
+E_ED_CHAIN16 = golden("heisenberg_chain_N16_J1_E0")
 
 
 @pytest.fixture(scope="module")

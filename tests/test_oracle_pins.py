@@ -453,3 +453,18 @@ def test_jq2_homogeneity_small():
     dQ = [a - b for a, b in zip(M.build_mpo(models.jq2_terms(Lx, Ly, J, Q + 1), N, OPS, PQ).W, base)]
     gJ, gQ = grad.coupling_gradient(Gs, dJ), grad.coupling_gradient(Gs, dQ)
     assert abs(J * gJ + Q * gQ - E[-1]) < 1e-9
+
+
+def test_golden_values_reproduce():
+    """The stored exact values equal a fresh oracle computation (the stored
+    file is what the GPU tests compare against)."""
+    from helpers import golden
+    assert abs(golden("heisenberg_chain_N16_J1_E0") - E_ED_CHAIN16) < 1e-11
+    for N in (10, 12):
+        e = exact.ground_state(models.heisenberg_terms(models.chain_bonds(N)), N, 0)[0][0]
+        assert abs(golden("heisenberg_chain_N%d_J1_E0" % N) - e) < 1e-11
+    for N in (10, 16, 32):
+        assert golden("xx_chain_N%d_J1_E0" % N) == exact.xx_chain_energy(N, 1.0)
+    for N, h in ((10, 0.8), (16, 0.7)):
+        assert golden("tfim_chain_N%d_J1_h%g_E0" % (N, h)) == exact.tfim_chain_energy(N, 1.0, h)
+        assert golden("tfim_chain_N%d_J1_h%g_dE0dh" % (N, h)) == exact.tfim_chain_dE_dh(N, 1.0, h)
