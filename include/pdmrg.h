@@ -182,7 +182,9 @@ int heff_apply(pdmrg_ctx *ctx, pdmrg_heff *op, const double *x_dev, double *y_de
 int heff_info(const pdmrg_heff *op, double *flops_Lpsi, double *flops_W, double *flops_R,
               int64_t *n_psi, int64_t *n_L, int64_t *n_R, int64_t *n_T1, int64_t *n_T2);
 /* Plan of an operator: tile shape of the stage-1 and stage-3 grouped GEMMs
- * (0: 64x64, 1: 128x32, 2: 32x128, 3: 128x128), their tile counts, and the
+ * (0: 64x64, 1: 128x32, 2: 32x128, 3: 128x128; 4: 64x64 and 5: 128x32 with
+ * half-depth, 6: 64x64 and 7: 128x32 with quarter-depth K steps), their tile
+ * counts, and the
  * number of K parts stage 3 is split into (outputs optional). */
 int heff_plan_info(const pdmrg_heff *op, int32_t *shape_Lpsi, int32_t *shape_R, int32_t *tiles_Lpsi,
                    int32_t *tiles_R, int32_t *splitk_parts);

@@ -85,13 +85,14 @@ template <typename T> struct KStep;
 template <> struct KStep<double> { static constexpr int BK = 16; };
 template <> struct KStep<float> { static constexpr int BK = 32; };
 
-template <typename T, typename TC, bool TA, bool TB, int BM, int BN, int WGM>
+// KDIV = 2 / 4: a half / quarter of the K step (and LDS) of KStep.
+template <typename T, typename TC, bool TA, bool TB, int BM, int BN, int WGM, int KDIV>
 __global__ __launch_bounds__(NT) void gemm_kmajor(Slots slots, const GemmItem *__restrict__ items,
                                                   const GemmSeg *__restrict__ segs,
                                                   const GemmTile *__restrict__ tiles,
                                                   const int64_t *__restrict__ rowoff, int ntiles) {
     constexpr int WGN = 4 / WGM;
-    constexpr int BK = KStep<T>::BK, LDK = BK + 1;
+    constexpr int BK = KStep<T>::BK / KDIV, LDK = BK + 1;
     constexpr int NLA = BM * BK / NT, NLB = BN * BK / NT;   // elements per thread and step
     constexpr int SM = BM / WGM, SN = BN / WGN;              // wave sub-tile
     constexpr int WBM = SM / 16, WBN = SN / 16;              // MFMA blocks per wave
@@ -356,25 +357,31 @@ struct GemmArgs {
     int n;
 };
 
-template <typename T, typename TC, int BM, int BN, int WGM>
+template <typename T, typename TC, int BM, int BN, int WGM, int KDIV>
 static void dispatch_shape(bool ta, bool tb, dim3 g, hipStream_t s, const GemmArgs &a) {
     if (!ta && !tb)
-        hipLaunchKernelGGL((gemm_kmajor<T, TC, false, false, BM, BN, WGM>), g, dim3(NT), 0, s, a.sl, a.it, a.sg, a.tl, a.ro, a.n);
+        hipLaunchKernelGGL((gemm_kmajor<T, TC, false, false, BM, BN, WGM, KDIV>), g, dim3(NT), 0, s, a.sl, a.it, a.sg, a.tl, a.ro, a.n);
     else if (ta && !tb)
-        hipLaunchKernelGGL((gemm_kmajor<T, TC, true, false, BM, BN, WGM>), g, dim3(NT), 0, s, a.sl, a.it, a.sg, a.tl, a.ro, a.n);
+        hipLaunchKernelGGL((gemm_kmajor<T, TC, true, false, BM, BN, WGM, KDIV>), g, dim3(NT), 0, s, a.sl, a.it, a.sg, a.tl, a.ro, a.n);
     else if (!ta && tb)
-        hipLaunchKernelGGL((gemm_kmajor<T, TC, false, true, BM, BN, WGM>), g, dim3(NT), 0, s, a.sl, a.it, a.sg, a.tl, a.ro, a.n);
+        hipLaunchKernelGGL((gemm_kmajor<T, TC, false, true, BM, BN, WGM, KDIV>), g, dim3(NT), 0, s, a.sl, a.it, a.sg, a.tl, a.ro, a.n);
     else
-        hipLaunchKernelGGL((gemm_kmajor<T, TC, true, true, BM, BN, WGM>), g, dim3(NT), 0, s, a.sl, a.it, a.sg, a.tl, a.ro, a.n);
+        hipLaunchKernelGGL((gemm_kmajor<T, TC, true, true, BM, BN, WGM, KDIV>), g, dim3(NT), 0, s, a.sl, a.it, a.sg, a.tl, a.ro, a.n);
 }
 
 template <typename T, typename TC>
 static void dispatch_kmajor(TileShape shape, bool ta, bool tb, dim3 g, hipStream_t s, const GemmArgs &a) {
     switch (shape) {
-        case TileShape::T64x64: dispatch_shape<T, TC, 64, 64, 2>(ta, tb, g, s, a); break;
-        case TileShape::T128x32: dispatch_shape<T, TC, 128, 32, 4>(ta, tb, g, s, a); break;
-        case TileShape::T32x128: dispatch_shape<T, TC, 32, 128, 1>(ta, tb, g, s, a); break;
-        case TileShape::T128x128: dispatch_shape<T, TC, 128, 128, 2>(ta, tb, g, s, a); break;
+        case TileShape::T64x64: dispatch_shape<T, TC, 64, 64, 2, 1>(ta, tb, g, s, a); break;
+        case TileShape::T128x32: dispatch_shape<T, TC, 128, 32, 4, 1>(ta, tb, g, s, a); break;
+        case TileShape::T32x128: dispatch_shape<T, TC, 32, 128, 1, 1>(ta, tb, g, s, a); break;
+        case TileShape::T128x128: dispatch_shape<T, TC, 128, 128, 2, 1>(ta, tb, g, s, a); break;
+        case TileShape::T64x64_K16: dispatch_shape<T, TC, 64, 64, 2, 2>(ta, tb, g, s, a); break;
+        case TileShape::T128x32_K16: dispatch_shape<T, TC, 128, 32, 4, 2>(ta, tb, g, s, a); break;
+        // FP64 quarter-depth steps (BK = 4) would leave threads without an
+        // element of a 32-wide tile; they run at half depth instead
+        case TileShape::T64x64_K8: dispatch_shape<T, TC, 64, 64, 2, sizeof(T) == 8 ? 2 : 4>(ta, tb, g, s, a); break;
+        case TileShape::T128x32_K8: dispatch_shape<T, TC, 128, 32, 4, sizeof(T) == 8 ? 2 : 4>(ta, tb, g, s, a); break;
     }
 }
 

@@ -85,11 +85,30 @@ struct DotTile {
 enum class GemmPrec { F64, F32, BF16X3 };
 
 // Output tile shapes of the FP64 / FP32 kernels (4 waves, each a 32 x 32 or
-// 64 x 64 sub-tile of 16 x 16 MFMA blocks).  BF16X3 runs T64x64 only.
-enum class TileShape { T64x64 = 0, T128x32 = 1, T32x128 = 2, T128x128 = 3 };
-constexpr int kNumShapes = 4;
-inline int tile_bm(TileShape t) { return t == TileShape::T64x64 ? 64 : t == TileShape::T32x128 ? 32 : 128; }
-inline int tile_bn(TileShape t) { return t == TileShape::T64x64 ? 64 : t == TileShape::T128x32 ? 32 : 128; }
+// 64 x 64 sub-tile of 16 x 16 MFMA blocks); the _K16 / _K8 variants stage a
+// half / quarter as much K per step (FP32 16 / 8 instead of 32, FP64 8 / 4
+// instead of 16), so less LDS and more resident workgroups for short K loops.
+// BF16X3 runs T64x64 only.
+enum class TileShape {
+    T64x64 = 0, T128x32 = 1, T32x128 = 2, T128x128 = 3,
+    T64x64_K16 = 4, T128x32_K16 = 5,   // half-depth K steps
+    T64x64_K8 = 6, T128x32_K8 = 7      // quarter-depth K steps
+};
+constexpr int kNumShapes = 8;
+inline int tile_bm(TileShape t) {
+    switch (t) {
+        case TileShape::T32x128: return 32;
+        case TileShape::T64x64: case TileShape::T64x64_K16: case TileShape::T64x64_K8: return 64;
+        default: return 128;
+    }
+}
+inline int tile_bn(TileShape t) {
+    switch (t) {
+        case TileShape::T128x32: case TileShape::T128x32_K16: case TileShape::T128x32_K8: return 32;
+        case TileShape::T64x64: case TileShape::T64x64_K16: case TileShape::T64x64_K8: return 64;
+        default: return 128;
+    }
+}
 
 // Launchers (defined in gemm.hip / blas.hip).  All asynchronous on `s`.
 // c_is_f64: C written as double (F32 / BF16X3 inputs are float).  rowoff:

@@ -84,7 +84,7 @@ void GemmList::pick_tile() {
     // Relative MFMA throughput per padded flop, measured on uniform 64-deep
     // K loops: 128 x 128 tiles (64 x 64 per wave) reuse each LDS operand
     // twice as often as the 32 x 32-per-wave shapes.
-    static const double kRate[kNumShapes] = {1.0, 0.85, 0.85, 1.25};
+    static const double kRate[kNumShapes] = {1.0, 0.85, 0.85, 1.25, 1.1, 1.1, 1.0, 1.0};
     double best = 0.0;
     bool have = false;
     for (int t = 0; t < kNumShapes; ++t) {
