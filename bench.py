@@ -90,24 +90,24 @@ def time_matvecs(ctx, pl, torch, op, x, y, steps, warmup):
 def _kernel_sources_hash():
     import hashlib
     h = hashlib.sha256()
-    for f in ("gemm.hip", "plans.cpp", "heff.cpp", "kernels.hpp"):
+    for f in ("gemm.hip", "kernels.hpp"):
         with open(os.path.join(ROOT, "paper_1301_3494_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def stored_traffic(prec, stage):
+def stored_traffic(prec, stage, plan):
     """HBM bytes per launch of the dominant GEMM from the committed rocprofv3
     counter summary (FETCH_SIZE and WRITE_SIZE passes, calibrated), or None
-    when that summary was taken on other kernel sources or precision."""
+    when that summary was taken on other kernel sources, precision or plan."""
     path = os.path.join(ROOT, "profiles", "heff_gemm_cyl8x4_m1024_counters.txt")
     try:
         with open(path) as f:
             for line in f:
                 if line.startswith("traffic_json: "):
                     rec = json.loads(line[len("traffic_json: "):])
-                    if rec["sources"] == _kernel_sources_hash() and rec["prec"] == prec and rec["stage"] == stage + 1:
-                        return rec["bytes_per_launch"]
+                    if rec["sources"] == _kernel_sources_hash() and rec["prec"] == prec and rec["plan"] == plan:
+                        return rec["bytes_per_launch"].get(str(stage + 1))
     except (OSError, ValueError, KeyError):
         pass
     return None
@@ -144,7 +144,7 @@ def cpu_baseline(wl, flops, budget_s=12.0):
                       "%.3f s each" % (n, dt)}
 
 
-def sweep_leg(ctx, pl, synth, torch, m=1024, regions=4, timed=2):
+def sweep_leg(ctx, pl, synth, torch, m=1024, regions=4, timed=2, concurrent=True):
     """Second half of the metric: wall seconds of a real-space parallel sweep
     (Sec. II, Fig. 4) on the 8 x 4 cylinder at bond dimension m, FP64 path
     against the mixed path (FP32 MFMA H_eff with FP64 Davidson refinement),
@@ -159,12 +159,12 @@ def sweep_leg(ctx, pl, synth, torch, m=1024, regions=4, timed=2):
     for name, prec in (("f64", pl.F64), ("mixed", pl.F32)):
         mps = pl.Mps(ctx, bonds, sites)
         mps.sweep(mpo, m, 1, prec=prec, dav=dav, dav_shared=dav_shared)
-        mps.sweep(mpo, m, regions, prec=prec, dav=dav, dav_shared=dav_shared)
+        mps.sweep(mpo, m, regions, prec=prec, dav=dav, dav_shared=dav_shared, concurrent=concurrent)
         secs, rep = [], None
         for _ in range(timed):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            rep = mps.sweep(mpo, m, regions, prec=prec, dav=dav, dav_shared=dav_shared)
+            rep = mps.sweep(mpo, m, regions, prec=prec, dav=dav, dav_shared=dav_shared, concurrent=concurrent)
             torch.cuda.synchronize()
             secs.append(time.perf_counter() - t0)
         res[name] = dict(seconds=sum(secs) / len(secs), energy=rep["energy"], n_matvec=rep["n_matvec"],
@@ -176,8 +176,9 @@ def sweep_leg(ctx, pl, synth, torch, m=1024, regions=4, timed=2):
     rel = abs(emx - e64) / abs(e64)
     return {
         "workload": "heisenberg_cyl8x4_m%d_%dregions_sweep" % (m, regions),
-        "schedule": "1 serial + 1 split sweep untimed, then %d timed parallel sweeps, m=%d, regions concurrent; "
-                    "Davidson 6 matvecs / 1e-8 interior, 40 / 1e-10 shared bonds" % (timed, m),
+        "schedule": "1 serial + 1 split sweep untimed, then %d timed parallel sweeps, m=%d, regions %s; "
+                    "Davidson 6 matvecs / 1e-8 interior, 40 / 1e-10 shared bonds" % (
+                        timed, m, "concurrent" if concurrent else "one after the other"),
         "seconds_per_sweep_f64": round(res["f64"]["seconds"], 4),
         "seconds_per_sweep_mixed": round(res["mixed"]["seconds"], 4),
         "speedup_mixed_vs_f64": round(res["f64"]["seconds"] / res["mixed"]["seconds"], 4),
@@ -195,6 +196,13 @@ def main():
     ap.add_argument("--prec", default="f32", choices=["f64", "f32", "bf16x3"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sweep", action="store_true", help="skip the sweep-seconds leg")
+    ap.add_argument("--only-sweep", action="store_true", help="run only the sweep-seconds leg (for profiling)")
+    ap.add_argument("--sequential-regions", action="store_true",
+                    help="sweep leg: regions one after the other on one stream instead of concurrently")
+    ap.add_argument("--tune-db", default=os.path.join(ROOT, "paper_1301_3494_amd", "tuning", "mi355x.tsv"),
+                    help="tuned plans loaded before building (default: the package's MI355X tuning file; "
+                         "'none' to tune afresh)")
+    ap.add_argument("--tune-save", default=None, help="write the tuning cache to this file at the end")
     ap.add_argument("--autotune", type=int, default=1, choices=[0, 1, 2],
                     help="tile-shape selection: 0 cost model, 1 timed at operator creation, 2 = 1 + log")
     args = ap.parse_args()
@@ -208,8 +216,14 @@ def main():
     from paper_1301_3494_amd import _lib as pl, synth
 
     ctx = pl.Context(0)
-    wl = build_workload(ctx, pl, synth, np, torch)
     pl.set_autotune(ctx, args.autotune)
+    if args.tune_db and args.tune_db != "none":
+        pl.autotune_import(args.tune_db)
+    if args.only_sweep:
+        print(json.dumps({"sweep": sweep_leg(ctx, pl, synth, torch, concurrent=not args.sequential_regions)}))
+        ctx.close()
+        return
+    wl = build_workload(ctx, pl, synth, np, torch)
     c = wl["center"]
     W1, W2 = wl["mpo"].site(c), wl["mpo"].site(c + 1)
     results = {}
@@ -225,8 +239,10 @@ def main():
         err = float((y - y64).norm() / y64.norm())
         results[name] = dict(op=op, info=info, wall=wall, steps=steps, ms=ms, err=err,
                              tflops=info["flops"] / (wall / steps) / 1e12)
-        print("bench: %s matvec %.4f ms, %.2f TFLOP/s" % (name, wall / steps * 1e3, results[name]["tflops"]),
-              file=sys.stderr, flush=True)
+        print("bench: %s matvec %.4f ms, %.2f TFLOP/s, plan %s" % (
+            name, wall / steps * 1e3, results[name]["tflops"],
+            {k: info[k] for k in ("shape_Lpsi", "shape_R", "tiles_Lpsi", "tiles_R", "splitk_parts")}),
+            file=sys.stderr, flush=True)
     r = results[args.prec]
     info = r["info"]
     ms_step = r["wall"] / r["steps"] * 1e3
@@ -238,7 +254,7 @@ def main():
     achieved = stage_flops / (r["ms"][st] * 1e-3) / 1e12
     peak = PEAK_TFLOPS[args.prec]
     kname = "gemm_kmajor" if args.prec != "bf16x3" else "gemm_bf16x3"
-    traffic = stored_traffic(args.prec, st)
+    traffic = stored_traffic(args.prec, st, {k: info[k] for k in ("shape_Lpsi", "shape_R", "splitk_parts")})
     out = {
         "metric": "H_eff matvec TFLOP/s (% MFMA peak); sweep s, mixed vs FP64 at 1e-9 rel E",
         "value": round(r["tflops"], 4),
@@ -253,7 +269,7 @@ def main():
         "dtype": args.prec,
         "data": "synthetic (seeded random MPS, environments built on the GPU)",
         "config": {"workload": "heisenberg_cyl8x4_m1024_centre_heff", "lattice": "8x4 cylinder, snake order",
-                   "autotune": args.autotune,
+                   "autotune": args.autotune, "tune_db": os.path.basename(args.tune_db) if args.tune_db else None,
                    "m": wl["m"], "mpo_D": int(W1.W.shape[0]), "psi_elems": info["n_psi"],
                    "flops_per_matvec": info["flops"], "dense_equiv_flops": 4.0 * 14 * 4 * 1024 ** 3},
         "roofline": {"bound": "mfma", "kernel": "%s stage %d (%s), %s tiles" % (
@@ -271,9 +287,11 @@ def main():
     for v in results.values():
         v["op"].free()
     if not args.no_sweep:
-        out["sweep"] = sweep_leg(ctx, pl, synth, torch)
+        out["sweep"] = sweep_leg(ctx, pl, synth, torch, concurrent=not args.sequential_regions)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, info["flops"])
+    if args.tune_save:
+        pl.autotune_export(args.tune_save)
     ctx.close()
     print(json.dumps(out))
 

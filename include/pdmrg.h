@@ -121,14 +121,23 @@ int pdmrg_ctx_set_timing(pdmrg_ctx *ctx, int enable);
  * on this context (the contraction order of Sec. II is unchanged):
  *   0  (default) a cost model of padded MFMA work and device fill;
  *   1  each allowed shape of stage 1 and stage 3 is timed on the operator's
- *      own buffers when it is created (a few ms), and the fastest is kept in a
- *      process-wide cache keyed by device, precision, bond sectors and MPO
- *      widths, so later operators of the same shape are not re-timed;
+ *      own buffers when it is created by heff_create (a few ms), and the
+ *      fastest is kept in a process-wide cache keyed by device, precision,
+ *      bond sectors and MPO widths, so later operators of the same shape are
+ *      not re-timed (sweep() uses cached plans but never times candidates);
  *   2  as 1, with one line per tuned signature on stderr.
  * Results are identical for every shape in FP64; in FP32 / BF16x3 they can
  * differ in the last bits (the split-K partition follows the tile count).
  * Returns PDMRG_EINVAL for another level. */
 int pdmrg_ctx_set_autotune(pdmrg_ctx *ctx, int level);
+/* The process-wide tuning cache as a text file (one line per signature: key,
+ * stage-1 shape, stage-3 shape, stage-3 K parts, tab-separated).  Export
+ * writes every entry; import adds / replaces entries, so operators built
+ * afterwards with autotune >= 1 take the stored plans without timing (the
+ * same plans in another process).  n_entries (optional) receives the count.
+ * PDMRG_EINVAL if the file cannot be opened or a line is malformed. */
+int pdmrg_autotune_export(const char *path, int32_t *n_entries);
+int pdmrg_autotune_import(const char *path, int32_t *n_entries);
 int pdmrg_ctx_timing(pdmrg_ctx *ctx, double *ms_stage /*[4]: L.psi, W, .R, total*/,
                      int64_t *n_calls);
 

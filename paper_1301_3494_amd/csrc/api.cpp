@@ -77,6 +77,22 @@ int pdmrg_ctx_set_autotune(pdmrg_ctx *ctx, int level) {
     API_END
 }
 
+int pdmrg_autotune_export(const char *path, int32_t *n_entries) {
+    API_BEGIN
+    PD_REQUIRE(path, PDMRG_EINVAL, "autotune export: null path");
+    const int n = tune_export(path);
+    if (n_entries) *n_entries = n;
+    API_END
+}
+
+int pdmrg_autotune_import(const char *path, int32_t *n_entries) {
+    API_BEGIN
+    PD_REQUIRE(path, PDMRG_EINVAL, "autotune import: null path");
+    const int n = tune_import(path);
+    if (n_entries) *n_entries = n;
+    API_END
+}
+
 int pdmrg_ctx_timing(pdmrg_ctx *ctx, double *ms_stage, int64_t *n_calls) {
     API_BEGIN
     PD_REQUIRE(ctx && ms_stage && n_calls, PDMRG_EINVAL, "null argument");

@@ -137,9 +137,11 @@ struct Driver {
         const Bond &bl = m->bonds[i], &br = m->bonds[i + 2];
         const double *Ld = m->L[i].as<double>(), *Rd = m->R[i + 2].as<double>();
         pdmrg_heff op, op64;
-        heff_build(ctx, &op, bl, br, m->p, W(i), W(i + 1), Ld, Rd, prm.prec);
+        // bond shapes change from bond to bond and sweep to sweep: take tuned
+        // plans from the cache, never time candidates here
+        heff_build(ctx, &op, bl, br, m->p, W(i), W(i + 1), Ld, Rd, prm.prec, false);
         const bool refine = prm.prec != PDMRG_F64 && prm.refine;
-        if (refine) heff_build(ctx, &op64, bl, br, m->p, W(i), W(i + 1), Ld, Rd, PDMRG_F64);
+        if (refine) heff_build(ctx, &op64, bl, br, m->p, W(i), W(i + 1), Ld, Rd, PDMRG_F64, false);
         const auto t0 = std::chrono::steady_clock::now();
         DavResult r = davidson_run(ctx, &op, refine ? &op64 : nullptr, psi.as<double>(), dav);
         t_heff += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();

@@ -1,6 +1,7 @@
 // Two-site effective Hamiltonian operator (Sec. II): plan + environments in
 // the compute precision + intermediates.
 #include <cstdio>
+#include <cstdlib>
 #include <map>
 #include <mutex>
 #include <sstream>
@@ -127,7 +128,7 @@ GemmPrec gemm_prec(int prec) {
 }
 
 void heff_build(pdmrg_ctx *ctx, pdmrg_heff *op, const Bond &bl, const Bond &br, const Phys &p,
-                const MpoSite &W1, const MpoSite &W2, const double *L, const double *R, int prec) {
+                const MpoSite &W1, const MpoSite &W2, const double *L, const double *R, int prec, bool may_time) {
     hipStream_t s = ctx->stream;
     (void)gemm_prec(prec);
     op->prec = prec;
@@ -173,11 +174,55 @@ void heff_build(pdmrg_ctx *ctx, pdmrg_heff *op, const Bond &bl, const Bond &br, 
             if (hit.shape1 != (int)pl.g1.shape) pl.set_g1_shape((TileShape)hit.shape1, s);
             if (hit.shape3 != (int)pl.g3.shape || hit.parts3 != pl.parts3)
                 pl.set_g3_shape((TileShape)hit.shape3, s, hit.parts3);
-        } else {
+        } else if (may_time) {
             tune_heff(ctx, op, key);
         }
     }
     op->P.ensure(std::max<int64_t>(pl.nP, 1) * (prec == PDMRG_F64 ? sizeof(double) : sizeof(float)));
+}
+
+int tune_export(const char *path) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    FILE *f = std::fopen(path, "w");
+    PD_REQUIRE(f != nullptr, PDMRG_EINVAL, std::string("autotune export: cannot write ") + path);
+    int n = 0;
+    for (const auto &kv : tune_cache()) {
+        std::fprintf(f, "%s\t%d\t%d\t%d\n", kv.first.c_str(), kv.second.shape1, kv.second.shape3, kv.second.parts3);
+        ++n;
+    }
+    std::fclose(f);
+    return n;
+}
+
+int tune_import(const char *path) {
+    FILE *f = std::fopen(path, "r");
+    PD_REQUIRE(f != nullptr, PDMRG_EINVAL, std::string("autotune import: cannot read ") + path);
+    std::vector<std::pair<std::string, Tuned>> rows;
+    char line[1 << 14];
+    while (std::fgets(line, sizeof line, f)) {
+        std::string l(line);
+        while (!l.empty() && (l.back() == '\n' || l.back() == '\r')) l.pop_back();
+        if (l.empty()) continue;
+        const size_t t3 = l.rfind('\t'), t2 = l.rfind('\t', t3 - 1), t1 = l.rfind('\t', t2 - 1);
+        if (t1 == std::string::npos || t2 == std::string::npos || t3 == std::string::npos) {
+            std::fclose(f);
+            throw Error(PDMRG_EINVAL, "autotune import: malformed line in " + std::string(path));
+        }
+        Tuned t;
+        t.shape1 = std::atoi(l.c_str() + t1 + 1);
+        t.shape3 = std::atoi(l.c_str() + t2 + 1);
+        t.parts3 = std::atoi(l.c_str() + t3 + 1);
+        if (t.shape1 < 0 || t.shape1 >= kNumShapes || t.shape3 < 0 || t.shape3 >= kNumShapes || t.parts3 < 1 ||
+            t.parts3 > 8) {
+            std::fclose(f);
+            throw Error(PDMRG_EINVAL, "autotune import: entry out of range in " + std::string(path));
+        }
+        rows.push_back({l.substr(0, t1), t});
+    }
+    std::fclose(f);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (auto &r : rows) tune_cache()[r.first] = r.second;
+    return (int)rows.size();
 }
 
 void grad_site_run(pdmrg_ctx *ctx, const GradPlan &plan, const double *L, const double *psi, const double *R,

@@ -22,8 +22,12 @@ struct pdmrg_mpo {
 namespace pdmrg {
 
 GemmPrec gemm_prec(int prec);
+// may_time: with ctx->autotune >= 1, time the candidate plans on a cache
+// miss (false: a miss takes the cost model, as inside sweeps where bond
+// shapes rarely repeat).
 void heff_build(pdmrg_ctx *ctx, pdmrg_heff *op, const Bond &bl, const Bond &br, const Phys &p,
-                const MpoSite &W1, const MpoSite &W2, const double *L, const double *R, int prec);
+                const MpoSite &W1, const MpoSite &W2, const double *L, const double *R, int prec,
+                bool may_time = true);
 void heff_run(pdmrg_ctx *ctx, pdmrg_heff *op, const double *x, double *y);
 
 struct DavResult {
@@ -44,6 +48,9 @@ struct SvdOut {
     double discarded = 0;
     int n_floored = 0;
 };
+// Process-wide tuning cache to / from a text file (one line per signature).
+int tune_export(const char *path);
+int tune_import(const char *path);
 void grad_site_run(pdmrg_ctx *ctx, const GradPlan &plan, const double *L, const double *psi, const double *R,
                    double *G);
 void svd_truncate_run(pdmrg_ctx *ctx, const Bond &bl, const Bond &br, const Phys &p, const double *psi,

@@ -81,10 +81,10 @@ double GemmList::padded_flops(TileShape t) const {
 }
 
 void GemmList::pick_tile() {
-    // Relative MFMA throughput per padded flop, measured on uniform 64-deep
-    // K loops: 128 x 128 tiles (64 x 64 per wave) reuse each LDS operand
-    // twice as often as the 32 x 32-per-wave shapes.
-    static const double kRate[kNumShapes] = {1.0, 0.85, 0.85, 1.25, 1.1, 1.1, 1.0, 1.0};
+    // Relative throughput per padded flop of each shape, from timings of the
+    // H_eff GEMMs of the 8 x 4 cylinder (m = 1024) on MI355X: shorter K steps
+    // (more resident workgroups) win on these short, ragged K loops.
+    static const double kRate[kNumShapes] = {1.0, 1.0, 0.8, 0.75, 1.1, 1.15, 1.05, 1.2};
     double best = 0.0;
     bool have = false;
     for (int t = 0; t < kNumShapes; ++t) {

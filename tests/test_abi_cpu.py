@@ -154,3 +154,22 @@ def test_errors_are_reported_not_raised():
     n, nb = ctypes.c_int64(), ctypes.c_int32()
     P = pl.Phys((-1, 1))
     assert L.pdmrg_layout_size(pl.TWO_SITE, byref(b), byref(b), P.ref, None, 0, byref(n), byref(nb)) == -1
+
+
+def test_autotune_cache_file_round_trip(tmp_path):
+    """The tuning cache file format: an empty export, an import of a
+    hand-written entry, re-export, and rejection of malformed lines."""
+    from helpers import pl
+    p = tmp_path / "tune.txt"
+    n0 = pl.autotune_export(p)
+    p.write_text("sig-a\t1\t5\t4\n")
+    assert pl.autotune_import(p) == 1
+    q = tmp_path / "tune2.txt"
+    assert pl.autotune_export(q) == n0 + 1
+    assert "sig-a\t1\t5\t4" in q.read_text()
+    bad = tmp_path / "bad.txt"
+    bad.write_text("sig-b\t1\t99\t4\n")
+    with pytest.raises(pl.PdmrgError):
+        pl.autotune_import(bad)
+    with pytest.raises(pl.PdmrgError):
+        pl.autotune_import(tmp_path / "missing.txt")
