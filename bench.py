@@ -87,6 +87,50 @@ def time_matvecs(ctx, pl, torch, op, x, y, steps, warmup):
     return wall, ms
 
 
+def small_graph_probe(ctx, pl, synth, np, torch, steps=300):
+    """Per-matvec time of a small bond (4 x 4 cylinder, m = 128, FP32),
+    eager launches against graph replay: where launch cost matters."""
+    PQ = (-1, 1)
+    Lx, Ly, m, c = 4, 4, 128, 7
+    mpo = pl.Mpo("square", Lx, Ly, (1.0, 1.0))
+    bonds = synth.binomial_bonds(Lx * Ly, m)
+    rng = np.random.default_rng(9)
+    B1, B2, P = pl.Bond(bonds[c]), pl.Bond(bonds[c + 2]), pl.Phys(PQ)
+
+    def flat(kind, bond, deltas, blocks):
+        table, n = pl.layout(kind, bond, deltas=deltas)
+        out = np.zeros(n)
+        for key, off, rows, cols, ld in table:
+            b = blocks[key[:2]]
+            b = b.T if kind == pl.ENV_R else b
+            for r in range(rows):
+                out[off + r * ld: off + r * ld + cols] = b[r]
+        return torch.from_numpy(out).cuda()
+
+    L = flat(pl.ENV_L, B1, mpo.deltas[c], synth.random_env_blocks(bonds[c], mpo.deltas[c], rng))
+    R = flat(pl.ENV_R, B2, mpo.deltas[c + 2], synth.random_env_blocks(bonds[c + 2], mpo.deltas[c + 2], rng))
+    _, nx = pl.layout(pl.TWO_SITE, B1, B2, P)
+    x = torch.from_numpy(rng.standard_normal(nx)).cuda()
+    y = torch.empty_like(x)
+    op = pl.Heff(ctx, B1, B2, P, mpo.site(c), mpo.site(c + 1), L, R, pl.F32)
+    res = {}
+    for name, g in (("eager", False), ("graph", True)):
+        pl.set_graphs(ctx, g)
+        for _ in range(20):
+            op.apply(x, y)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            op.apply(x, y)
+        torch.cuda.synchronize()
+        res[name + "_ms_per_matvec"] = round((time.perf_counter() - t0) / steps * 1e3, 5)
+    pl.set_graphs(ctx, False)
+    res["workload"] = "heisenberg_cyl4x4_m128_centre_heff_f32 (%d psi elements, %.3g flops)" % (
+        nx, op.info()["flops"])
+    op.free()
+    return res
+
+
 def _kernel_sources_hash():
     import hashlib
     h = hashlib.sha256()
@@ -243,6 +287,14 @@ def main():
             name, wall / steps * 1e3, results[name]["tflops"],
             {k: info[k] for k in ("shape_Lpsi", "shape_R", "tiles_Lpsi", "tiles_R", "splitk_parts")}),
             file=sys.stderr, flush=True)
+    # the same products replayed from a captured HIP graph (one per (x, y))
+    rg = results[args.prec]
+    pl.set_graphs(ctx, True)
+    yg = torch.empty_like(wl["x"])
+    gwall, _ = time_matvecs(ctx, pl, torch, rg["op"], wl["x"], yg, rg["steps"], args.warmup)
+    pl.set_graphs(ctx, False)
+    graph_ms = gwall / rg["steps"] * 1e3
+    print("bench: %s matvec from a HIP graph %.4f ms" % (args.prec, graph_ms), file=sys.stderr, flush=True)
     r = results[args.prec]
     info = r["info"]
     ms_step = r["wall"] / r["steps"] * 1e3
@@ -278,6 +330,8 @@ def main():
                      "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
                      "frac": round(achieved / peak, 4), "traffic": traffic},
         "plan": {k: info[k] for k in ("shape_Lpsi", "shape_R", "tiles_Lpsi", "tiles_R", "splitk_parts")},
+        "graph_replay": {"ms_per_matvec": round(graph_ms, 5), "eager_ms_per_matvec": round(ms_step, 5),
+                         "small_bond": small_graph_probe(ctx, pl, synth, np, torch)},
         "stage_ms_order": ["L.psi GEMM", "W stage", "T2.R GEMM", "split-K reduction", "total"],
         "stage_ms": {k: [round(v, 5) for v in results[k]["ms"]] for k in results},
         "precisions": {k: {"tflops": round(v["tflops"], 3), "ms_per_matvec": round(v["wall"] / v["steps"] * 1e3, 5),

@@ -130,6 +130,13 @@ int pdmrg_ctx_set_timing(pdmrg_ctx *ctx, int enable);
  * differ in the last bits (the split-K partition follows the tile count).
  * Returns PDMRG_EINVAL for another level. */
 int pdmrg_ctx_set_autotune(pdmrg_ctx *ctx, int level);
+/* enable = 1: heff_apply (and the Davidson matvecs on this context) replay a
+ * HIP graph of the operator's kernel sequence, captured on the first call for
+ * each (x, y) pair (up to 16 pairs per operator; further pairs run
+ * eagerly); the graph holds kernel nodes only.  Saves the per-kernel launch
+ * cost when the products are short.  Bypassed while stage timing is on.  The
+ * graphs are destroyed with the operator. */
+int pdmrg_ctx_set_graphs(pdmrg_ctx *ctx, int enable);
 /* The process-wide tuning cache as a text file (one line per signature: key,
  * stage-1 shape, stage-3 shape, stage-3 K parts, tab-separated).  Export
  * writes every entry; import adds / replaces entries, so operators built

@@ -72,7 +72,7 @@ def lib():
 
 EXPORTS = [
     "pdmrg_last_error", "pdmrg_version", "pdmrg_ctx_create", "pdmrg_ctx_destroy", "pdmrg_ctx_set_timing",
-    "pdmrg_ctx_timing", "pdmrg_ctx_set_autotune", "pdmrg_autotune_export", "pdmrg_autotune_import", "pdmrg_layout_size", "pdmrg_layout_blocks", "mpo_build", "mpo_from_sites",
+    "pdmrg_ctx_timing", "pdmrg_ctx_set_autotune", "pdmrg_ctx_set_graphs", "pdmrg_autotune_export", "pdmrg_autotune_import", "pdmrg_layout_size", "pdmrg_layout_blocks", "mpo_build", "mpo_from_sites",
     "mpo_info", "mpo_get_site", "mpo_free", "heff_create", "heff_apply", "heff_info", "heff_plan_info", "heff_diag",
     "heff_free", "env_update", "davidson_step", "svd_truncate", "svd_result_bond", "svd_result_copy",
     "svd_free", "merge_regions", "mps_alloc", "mps_set_site", "mps_bond", "mps_get_site", "sweep",
@@ -92,6 +92,7 @@ def _declare(L):
         "pdmrg_ctx_set_timing": (c_int, [P, c_int]),
         "pdmrg_ctx_timing": (c_int, [P, pd, pi64]),
         "pdmrg_ctx_set_autotune": (c_int, [P, c_int]),
+        "pdmrg_ctx_set_graphs": (c_int, [P, c_int]),
         "pdmrg_autotune_export": (c_int, [c_char_p, pi32]),
         "pdmrg_autotune_import": (c_int, [c_char_p, pi32]),
         "pdmrg_layout_size": (c_int, [c_int, pb, pb, pp, pi32, c_int32, pi64, pi32]),
@@ -313,6 +314,11 @@ def autotune_import(path):
     n = c_int32()
     check(lib().pdmrg_autotune_import(str(path).encode(), byref(n)))
     return n.value
+
+
+def set_graphs(ctx, enable):
+    """heff_apply through captured HIP graphs (one per (x, y) pair)."""
+    check(lib().pdmrg_ctx_set_graphs(ctx.h, int(bool(enable))))
 
 
 def set_autotune(ctx, level):

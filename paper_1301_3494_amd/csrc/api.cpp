@@ -54,10 +54,19 @@ int pdmrg_ctx_destroy(pdmrg_ctx *ctx) {
         (void)hipStreamSynchronize(c->stream);
         for (auto &e : c->ev_pool) (void)hipEventDestroy(e);
         if (c->owns_stream) (void)hipStreamDestroy(c->stream);
+        if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
         delete c;
     }
     for (auto &e : ctx->ev_pool) (void)hipEventDestroy(e);
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     delete ctx;
+    API_END
+}
+
+int pdmrg_ctx_set_graphs(pdmrg_ctx *ctx, int enable) {
+    API_BEGIN
+    PD_REQUIRE(ctx, PDMRG_EINVAL, "null ctx");
+    ctx->graphs = enable != 0;
     API_END
 }
 

@@ -145,4 +145,8 @@ struct pdmrg_ctx {
     // created on first use and destroyed with this context.
     std::vector<pdmrg_ctx *> sub;
     bool owns_stream = false;
+    // heff_apply through captured graphs (replayed on `stream`); the capture
+    // happens on cap_stream, created on first use.
+    bool graphs = false;
+    hipStream_t cap_stream = nullptr;
 };

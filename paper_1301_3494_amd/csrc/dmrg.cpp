@@ -215,6 +215,7 @@ struct Driver {
             ctx->sub.push_back(c);
         }
         ctx->sub[r]->autotune = ctx->autotune;
+        ctx->sub[r]->graphs = ctx->graphs;
         return ctx->sub[r];
     }
 

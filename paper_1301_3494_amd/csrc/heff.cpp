@@ -234,12 +234,14 @@ void grad_site_run(pdmrg_ctx *ctx, const GradPlan &plan, const double *L, const 
     plan.run(L, psi, R, U1, U1 + nU1, U1 + nU1 + nZ, G, ctx->stream);
 }
 
-void heff_run(pdmrg_ctx *ctx, pdmrg_heff *op, const double *x, double *y) {
-    hipStream_t s = ctx->stream;
+// The kernels of one product on stream s (no memset or copy nodes, so the
+// sequence can be captured into a graph).
+static void heff_launch(pdmrg_heff *op, const double *x, double *y, hipStream_t s, hipEvent_t *ev) {
     const HeffPlan &pl = op->plan;
     const GemmPrec gp = gemm_prec(op->prec);
     const bool f64 = op->prec == PDMRG_F64;
     Slots sl{};
+    if (ev) HIP_OK(hipEventRecord(ev[0], s));
     if (f64) {
         sl.p[0] = x;
     } else {
@@ -252,18 +254,6 @@ void heff_run(pdmrg_ctx *ctx, pdmrg_heff *op, const double *x, double *y) {
     sl.p[4] = op->T1.ptr;
     sl.p[5] = op->T2.ptr;
     sl.p[6] = op->P.ptr;
-    hipEvent_t *ev = nullptr;
-    if (ctx->timing) {
-        const size_t need = (size_t)(ctx->n_timed + 1) * kTimingEvents;
-        while (ctx->ev_pool.size() < need) {
-            hipEvent_t e;
-            HIP_OK(hipEventCreate(&e));
-            ctx->ev_pool.push_back(e);
-        }
-        ev = &ctx->ev_pool[(size_t)ctx->n_timed * kTimingEvents];
-        ctx->n_timed += 1;
-        HIP_OK(hipEventRecord(ev[0], s));
-    }
     pl.g1.launch(gp, f64, sl, s);
     if (ev) HIP_OK(hipEventRecord(ev[1], s));
     pl.w.launch(f64, sl, s);
@@ -273,6 +263,53 @@ void heff_run(pdmrg_ctx *ctx, pdmrg_heff *op, const double *x, double *y) {
     if (f64) pl.r3.launch(true, sl, s);
     else pl.r3.launch_f32_to_f64(sl, s);
     if (ev) HIP_OK(hipEventRecord(ev[4], s));
+}
+
+void heff_run(pdmrg_ctx *ctx, pdmrg_heff *op, const double *x, double *y) {
+    hipStream_t s = ctx->stream;
+    if (ctx->timing) {
+        const size_t need = (size_t)(ctx->n_timed + 1) * kTimingEvents;
+        while (ctx->ev_pool.size() < need) {
+            hipEvent_t e;
+            HIP_OK(hipEventCreate(&e));
+            ctx->ev_pool.push_back(e);
+        }
+        hipEvent_t *ev = &ctx->ev_pool[(size_t)ctx->n_timed * kTimingEvents];
+        ctx->n_timed += 1;
+        heff_launch(op, x, y, s, ev);
+        return;
+    }
+    if (!ctx->graphs) {
+        heff_launch(op, x, y, s, nullptr);
+        return;
+    }
+    // graph replay: one captured kernel sequence per (x, y) pair
+    for (auto &gr : op->graphs)
+        if (gr.x == x && gr.y == y) {
+            HIP_OK(hipGraphLaunch(gr.exec, s));
+            return;
+        }
+    if (op->graphs.size() >= pdmrg_heff::kMaxGraphs) {
+        heff_launch(op, x, y, s, nullptr);
+        return;
+    }
+    if (!ctx->cap_stream) HIP_OK(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+    pdmrg_heff::Graph gr;
+    gr.x = x;
+    gr.y = y;
+    HIP_OK(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
+    try {
+        heff_launch(op, x, y, ctx->cap_stream, nullptr);
+    } catch (...) {
+        hipGraph_t g = nullptr;
+        (void)hipStreamEndCapture(ctx->cap_stream, &g);
+        if (g) (void)hipGraphDestroy(g);
+        throw;
+    }
+    HIP_OK(hipStreamEndCapture(ctx->cap_stream, &gr.graph));
+    HIP_OK(hipGraphInstantiate(&gr.exec, gr.graph, nullptr, nullptr, 0));
+    op->graphs.push_back(gr);
+    HIP_OK(hipGraphLaunch(gr.exec, s));
 }
 
 }  // namespace pdmrg

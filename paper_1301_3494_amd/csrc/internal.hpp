@@ -11,6 +11,21 @@ struct pdmrg_heff {
     pdmrg::DevBuf diag;            // diag(H_eff), FP64
     pdmrg::DevBuf diag_terms, diag_groups;
     int64_t nX = 0, nL = 0, nR = 0;
+    // captured kernel sequences of heff_apply, one per (x, y) pair
+    struct Graph {
+        const double *x = nullptr;
+        double *y = nullptr;
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+    };
+    static constexpr size_t kMaxGraphs = 16;
+    std::vector<Graph> graphs;
+    ~pdmrg_heff() {
+        for (auto &g : graphs) {
+            if (g.exec) (void)hipGraphExecDestroy(g.exec);
+            if (g.graph) (void)hipGraphDestroy(g.graph);
+        }
+    }
 };
 
 struct pdmrg_mpo {
