@@ -139,6 +139,41 @@ def heff_apply(L, R, W1, W2, psi, bl, br, phys_q, dl, dr):
     return y
 
 
+def heff_apply_rows(L, R, W1, W2, psi, bl, br, phys_q, dl, dr, key, rows):
+    """Selected rows of one output block of heff_apply: y[key][rows, :].
+    Row a of y depends on row a of L[(q_a, w)] only, so the same sum is taken
+    with those rows alone (for checking full-size products one row at a
+    time)."""
+    d = len(phys_q)
+    W12 = two_site_mpo(W1, W2)
+    qa, s1, s2 = key
+    rows = np.asarray(rows)
+    out = np.zeros((len(rows),) + two_site_shape(key, bl, br, phys_q)[1:])
+    qb = qa + phys_q[s1] + phys_q[s2]
+    for w in range(W12.shape[0]):
+        Lb = L.get((qa, w))
+        if Lb is None:
+            continue
+        qk = qa - dl[w]
+        for t1 in range(d):
+            for t2 in range(d):
+                pb = psi.get((qk, t1, t2))
+                if pb is None:
+                    continue
+                coefs = W12[w, s1, t1, s2, t2, :]
+                nz = np.nonzero(coefs)[0]
+                if len(nz) == 0:
+                    continue
+                T = Lb[rows] @ pb
+                for w2 in nz:
+                    Rb = R.get((qb, int(w2)))
+                    if Rb is None:
+                        continue
+                    assert qb - dr[w2] == qk + phys_q[t1] + phys_q[t2]
+                    out += coefs[w2] * (T @ Rb.T)
+    return out
+
+
 def heff_diag(L, R, W1, W2, bl, br, phys_q, dl, dr):
     """Diagonal of H_eff (Davidson preconditioner)."""
     d = len(phys_q)

@@ -66,3 +66,69 @@ def test_full_size_heff_matches_oracle(ctx, problem, prec, tol):
     op.apply(x, y2)
     assert np.array_equal(host(y), host(y2))
     op.free()
+
+
+CONFIGS = {
+    # name: (lattice for mpo_build, oracle terms, Lx, Ly, couplings, m)
+    "cyl24x8_m2000": ("square", lambda: models.heisenberg_terms(models.square_cylinder_bonds(24, 8)), 24, 8,
+                      (1.0, 1.0), 2000),
+    "tri12x6_m3000": ("triangular", lambda: models.xxz_terms(models.triangular_cylinder_bonds(12, 6), 1.0, 1.0),
+                      12, 6, (1.0, 1.0), 3000),
+    "jq2_16x8_m4000": ("jq2", lambda: models.jq2_terms(16, 8, 1.0, 1.0), 16, 8, (1.0, 1.0), 4000),
+}
+
+
+@pytest.mark.parametrize("name", list(CONFIGS))
+def test_large_config_heff_sampled_rows(name):
+    """H_eff at the centre bond of the larger configurations (24 x 8 cylinder
+    m = 2000, triangular 12 x 6 m = 3000, J-Q2 16 x 8 m = 4000), FP64 and FP32,
+    with the plans sweeps use (cost model): sampled output rows against the
+    oracle computed row by row."""
+    import torch
+    lattice, terms_fn, Lx, Ly, couplings, m = CONFIGS[name]
+    N = Lx * Ly
+    c = N // 2 - 1
+    say("large config", name)
+    omp = M.build_mpo(terms_fn(), N, models.OPS, PQ)
+    # the library's own MPO has the same bond dimensions (its channel order
+    # may differ); both sides contract the oracle's W with the same inputs
+    gmp = pl.Mpo(lattice, Lx, Ly, couplings)
+    assert [w.shape for w in gmp.W] == [w.shape for w in omp.W]
+    gmp.free()
+    bonds = synth.binomial_bonds(N, m)
+    rng = np.random.default_rng(3)
+    L = synth.random_env_blocks(bonds[c], omp.deltas[c], rng)
+    R = synth.random_env_blocks(bonds[c + 2], omp.deltas[c + 2], rng)
+    psi = synth.random_two_site_blocks(bonds[c], bonds[c + 2], PQ, rng)
+    t, (B1, B2, P) = tables(bonds[c], bonds[c + 2], PQ, omp.deltas[c], omp.deltas[c + 2])
+    Ld = dev(blocks_to_flat(L, t["L"][0], t["L"][1], pl.ENV_L))
+    Rd = dev(blocks_to_flat(R, t["R"][0], t["R"][1], pl.ENV_R))
+    x = dev(blocks_to_flat(psi, t["x"][0], t["x"][1], pl.TWO_SITE))
+    bl, br = Bond(bonds[c]), Bond(bonds[c + 2])
+    keys = sorted(psi, key=lambda k: -psi[k].size)[:2] + [sorted(psi, key=lambda k: psi[k].size)[0]]
+    table = {k: (off, rows, cols, ld) for k, off, rows, cols, ld in t["x"][0]}
+    ref = {}
+    for k in keys:
+        rows = sorted({0, psi[k].shape[0] // 2, psi[k].shape[0] - 1})
+        ref[k] = (rows, dmrg.heff_apply_rows(L, R, omp.W[c], omp.W[c + 1], psi, bl, br, PQ, omp.deltas[c],
+                                             omp.deltas[c + 2], k, rows))
+    ctx = pl.Context(0)
+    for prec, tol in ((pl.F64, 1e-12), (pl.F32, 1e-5)):
+        op = pl.Heff(ctx, B1, B2, P, mpo_site(omp, c), mpo_site(omp, c + 1), Ld, Rd, prec)
+        y = torch.full_like(x, float("nan"))
+        op.apply(x, y)
+        yh = host(y)
+        num = den = 0.0
+        for k in keys:
+            off, rows_k, cols, ld = table[k]
+            rows, want = ref[k]
+            got = np.stack([yh[off + r * ld: off + r * ld + cols] for r in rows])
+            assert np.all(np.isfinite(got))
+            num += float(np.sum((got - want) ** 2))
+            den += float(np.sum(want ** 2))
+        err = np.sqrt(num / den)
+        say("  prec", prec, "sampled rel err", err, "flops", op.info()["flops"])
+        assert err <= tol
+        assert np.all(np.isfinite(yh))
+        op.free()
+    ctx.close()

@@ -114,3 +114,39 @@ def test_autograd_function_matches_grad_mpo(ctx):
         assert torch.allclose(w.grad, g.cpu(), rtol=1e-11, atol=1e-13)
     # each site's G contracted with its own W gives the energy
     assert abs(float(np.sum(W[3].grad.numpy() * mpo.W[3])) - E) <= 1e-10 * abs(E)
+
+
+def test_triangular_xxz_dE_dDelta_vs_ed_and_finite_difference(ctx):
+    """Triangular-lattice XXZ cylinder (the backward kernel's workload, at a
+    size exact diagonalisation covers): grad_mpo's dE/dDelta against the exact
+    Hellmann-Feynman value and against central differences of converged GPU
+    energies (h = 1e-4)."""
+    Lx, Ly, Delta, h = 4, 3, 0.9, 1e-4
+    N = Lx * Ly
+    mps, mpo, E = _converged(ctx, "triangular", Lx, Ly, (1.0, Delta), 200, 6)
+    Eg, (gJ, gD) = pl.dE_dcouplings(mps, mpo, "triangular", Lx, Ly, (1.0, Delta))
+    bonds = models.triangular_cylinder_bonds(Lx, Ly)
+    e, v, _ = exact.ground_state(models.xxz_terms(bonds, 1.0, Delta), N, 0)
+    Hzz, _ = exact.sparse_hamiltonian([(1.0, ((i, "Sz"), (j, "Sz"))) for i, j in bonds], N, 0)
+    hf = float(v[:, 0] @ (Hzz @ v[:, 0]))
+    Ep = _converged(ctx, "triangular", Lx, Ly, (1.0, Delta + h), 200, 6)[2]
+    Em = _converged(ctx, "triangular", Lx, Ly, (1.0, Delta - h), 200, 6)[2]
+    fd = (Ep - Em) / (2 * h)
+    say("triangular dE/dDelta grad", gD, "ED", hf, "FD", fd, "E", Eg, e[0])
+    assert abs(Eg - e[0]) <= 1e-9 * abs(e[0])
+    assert abs(gD - hf) <= 1e-8 * max(1.0, abs(hf))
+    assert abs(gD - fd) <= 1e-6 * max(1.0, abs(fd))
+    assert abs(gJ - Eg) <= 1e-8 * abs(Eg)        # E is linear in J at fixed Delta
+
+
+def test_jq2_homogeneity_on_gpu(ctx):
+    """J-Q2 cylinder: J dE/dJ + Q dE/dQ = E (degree-1 homogeneity), with E
+    equal to exact diagonalisation."""
+    Lx, Ly, J, Q = 3, 3, 1.0, 0.6
+    N = Lx * Ly
+    mps, mpo, E = _converged(ctx, "jq2", Lx, Ly, (J, Q), 200, 6, q=1)
+    Eg, (gJ, gQ) = pl.dE_dcouplings(mps, mpo, "jq2", Lx, Ly, (J, Q))
+    e = exact.ground_state(models.jq2_terms(Lx, Ly, J, Q), N, 1)[0][0]
+    say("jq2 E", Eg, "ED", e, "J gJ + Q gQ", J * gJ + Q * gQ)
+    assert abs(Eg - e) <= 1e-9 * abs(e)
+    assert abs(J * gJ + Q * gQ - Eg) <= 1e-9 * abs(Eg)

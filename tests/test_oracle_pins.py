@@ -468,3 +468,21 @@ def test_golden_values_reproduce():
     for N, h in ((10, 0.8), (16, 0.7)):
         assert golden("tfim_chain_N%d_J1_h%g_E0" % (N, h)) == exact.tfim_chain_energy(N, 1.0, h)
         assert golden("tfim_chain_N%d_J1_h%g_dE0dh" % (N, h)) == exact.tfim_chain_dE_dh(N, 1.0, h)
+
+
+def test_heff_apply_rows_equals_full_product():
+    """The row-restricted product used for full-size sampling equals the rows
+    of the complete product."""
+    rng = np.random.default_rng(5)
+    N, m, i = 10, 24, 4
+    mpo = M.build_mpo(models.heisenberg_terms(models.chain_bonds(N)), N, models.OPS, PQ)
+    bonds = synth.binomial_bonds(N, m)
+    L = synth.random_env_blocks(bonds[i], mpo.deltas[i], rng)
+    R = synth.random_env_blocks(bonds[i + 2], mpo.deltas[i + 2], rng)
+    psi = synth.random_two_site_blocks(bonds[i], bonds[i + 2], PQ, rng)
+    bl, br = Bond(bonds[i]), Bond(bonds[i + 2])
+    args = (L, R, mpo.W[i], mpo.W[i + 1], psi, bl, br, PQ, mpo.deltas[i], mpo.deltas[i + 2])
+    y = dmrg.heff_apply(*args)
+    for key in list(y)[:6]:
+        rows = [0, y[key].shape[0] - 1]
+        assert np.allclose(dmrg.heff_apply_rows(*args, key, rows), y[key][rows], rtol=1e-13, atol=1e-13)
