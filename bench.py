@@ -87,6 +87,59 @@ def time_matvecs(ctx, pl, torch, op, x, y, steps, warmup):
     return wall, ms
 
 
+def large_bond_rates(ctx, pl, synth, np, torch, steps=10):
+    """Matvec rate at the centre bonds of the larger lattices (the m >= 2000
+    contractions): 24 x 8 Heisenberg cylinder m = 2000 (D = 26), triangular
+    12 x 6 m = 3000 (D = 23) and J-Q2 16 x 8 m = 4000 (D = 110); synthetic
+    seeded environments, FP32 and FP64, plans as for the headline bond."""
+    PQ = (-1, 1)
+    out = {}
+    for name, lattice, Lx, Ly, m in (("cyl24x8_m2000", "square", 24, 8, 2000),
+                                     ("tri12x6_m3000", "triangular", 12, 6, 3000),
+                                     ("jq2_16x8_m4000", "jq2", 16, 8, 4000)):
+        N = Lx * Ly
+        c = N // 2 - 1
+        mpo = pl.Mpo(lattice, Lx, Ly, (1.0, 1.0))
+        bonds = synth.binomial_bonds(N, m)
+        rng = np.random.default_rng(3)
+        B1, B2, P = pl.Bond(bonds[c]), pl.Bond(bonds[c + 2]), pl.Phys(PQ)
+
+        def flat(kind, bond, deltas, blocks):
+            table, n = pl.layout(kind, bond, deltas=deltas)
+            v = np.zeros(n)
+            for key, off, rows, cols, ld in table:
+                b = blocks[key[:2]]
+                b = b.T if kind == pl.ENV_R else b
+                v[off: off + rows * ld].reshape(rows, ld)[:, :cols] = b
+            return torch.from_numpy(v).cuda()
+
+        L = flat(pl.ENV_L, B1, mpo.deltas[c], synth.random_env_blocks(bonds[c], mpo.deltas[c], rng))
+        R = flat(pl.ENV_R, B2, mpo.deltas[c + 2], synth.random_env_blocks(bonds[c + 2], mpo.deltas[c + 2], rng))
+        _, nx = pl.layout(pl.TWO_SITE, B1, B2, P)
+        x = torch.from_numpy(rng.standard_normal(nx)).cuda()
+        y = torch.empty_like(x)
+        rec = {"D": int(mpo.W[c].shape[3]), "psi_elems": nx}
+        for pname, prec in (("f32", pl.F32), ("f64", pl.F64)):
+            op = pl.Heff(ctx, B1, B2, P, mpo.site(c), mpo.site(c + 1), L, R, prec)
+            info = op.info()
+            wall, ms = time_matvecs(ctx, pl, torch, op, x, y, steps, 2)
+            t = wall / steps
+            rec[pname] = {"ms_per_matvec": round(t * 1e3, 4), "tflops": round(info["flops"] / t / 1e12, 3),
+                          "pct_peak": round(100 * info["flops"] / t / 1e12 / PEAK_TFLOPS[pname], 2),
+                          "gemm_pct_peak": [round(100 * info["flops_Lpsi"] / (ms[0] * 1e-3) / 1e12 / PEAK_TFLOPS[pname], 2),
+                                            round(100 * info["flops_R"] / (ms[2] * 1e-3) / 1e12 / PEAK_TFLOPS[pname], 2)],
+                          "plan": [info["shape_Lpsi"], info["shape_R"], info["splitk_parts"]]}
+            rec["flops_per_matvec"] = info["flops"]
+            op.free()
+        print("bench: large bond %s f32 %.2f TFLOP/s, f64 %.2f TFLOP/s" % (name, rec["f32"]["tflops"],
+              rec["f64"]["tflops"]), file=sys.stderr, flush=True)
+        out[name] = rec
+        mpo.free()
+        del L, R, x, y
+        torch.cuda.empty_cache()
+    return out
+
+
 def small_graph_probe(ctx, pl, synth, np, torch, steps=300):
     """Per-matvec time of a small bond (4 x 4 cylinder, m = 128, FP32),
     eager launches against graph replay: where launch cost matters."""
@@ -240,6 +293,7 @@ def main():
     ap.add_argument("--prec", default="f32", choices=["f64", "f32", "bf16x3"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sweep", action="store_true", help="skip the sweep-seconds leg")
+    ap.add_argument("--no-large", action="store_true", help="skip the matvec rates of the m >= 2000 bonds")
     ap.add_argument("--only-sweep", action="store_true", help="run only the sweep-seconds leg (for profiling)")
     ap.add_argument("--sequential-regions", action="store_true",
                     help="sweep leg: regions one after the other on one stream instead of concurrently")
@@ -340,6 +394,8 @@ def main():
     }
     for v in results.values():
         v["op"].free()
+    if not args.no_large:
+        out["large_bonds"] = large_bond_rates(ctx, pl, synth, np, torch)
     if not args.no_sweep:
         out["sweep"] = sweep_leg(ctx, pl, synth, torch, concurrent=not args.sequential_regions)
     if not args.no_cpu_baseline:
