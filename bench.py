@@ -65,7 +65,8 @@ def build_workload(ctx, pl, synth, np, torch):
     g = torch.Generator(device="cpu").manual_seed(seed)
     x = torch.randn(nx, dtype=torch.float64, generator=g)
     x = (x / x.norm()).cuda()
-    return dict(mpo=mpo, bonds=bonds, center=center, L=L, R=R, x=x, B1=B1, B2=B2, P=P, N=N, m=m)
+    return dict(mpo=mpo, bonds=bonds, center=center, L=L, R=R, x=x, B1=B1, B2=B2, P=P, N=N, m=m,
+                flat_site=flat_site)
 
 
 def time_matvecs(ctx, pl, torch, op, x, y, steps, warmup):
@@ -85,6 +86,116 @@ def time_matvecs(ctx, pl, torch, op, x, y, steps, warmup):
     pl.timing(ctx, False)
     torch.cuda.synchronize()
     return wall, ms
+
+
+def _timed(torch, fn, reps=3):
+    fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps
+
+
+def _otimed(fn, budget_s=2.0):
+    fn()
+    n, t0 = 0, time.perf_counter()
+    while n < 1 or time.perf_counter() - t0 < budget_s:
+        fn()
+        n += 1
+    return (time.perf_counter() - t0) / n
+
+
+def steps_leg(ctx, pl, synth, np, torch, wl):
+    """Each step of the path at the metric's bond (8 x 4 cylinder, m = 1024,
+    sites 15, 16) on the GPU, with the oracle's own implementation of the same
+    step timed beside it on the host (same block shapes, seeded synthetic
+    values)."""
+    from oracle import dmrg as od, grad as og
+    from oracle.blocks import Bond as OB, two_site_keys, two_site_shape, flatten, unflatten
+    PQ = (-1, 1)
+    c, mpo, bonds = wl["center"], wl["mpo"], wl["bonds"]
+    B1, B2, P = wl["B1"], wl["B2"], wl["P"]
+    Bm = pl.Bond(bonds[c + 1])
+    rng = np.random.default_rng(11)
+    out = {}
+    # env_update: L on bond c -> bond c+1 with site c
+    site_c = wl["flat_site"](c)
+    f_env, n_env = pl.env_update_info(1, B1, Bm, P, mpo.site(c))
+    Lnext = torch.empty(n_env, dtype=torch.float64, device="cuda")
+    t = _timed(torch, lambda: pl.env_update(ctx, 1, B1, Bm, P, mpo.site(c), wl["L"], site_c, Lnext))
+    Lo = synth.random_env_blocks(bonds[c], mpo.deltas[c], rng)
+    Ao = synth.random_site_blocks(bonds[c], bonds[c + 1], PQ, rng)
+    to = _otimed(lambda: od.update_L(Lo, Ao, mpo.W[c], PQ, mpo.deltas[c], mpo.deltas[c + 1]))
+    out["env_update"] = {"ms": round(t * 1e3, 4), "tflops": round(f_env / t / 1e12, 3),
+                         "pct_fp64_peak": round(100 * f_env / t / 1e12 / PEAK_TFLOPS["f64"], 2),
+                         "oracle_ms": round(to * 1e3, 2)}
+    # Davidson: FP64, and FP32 with FP64 refinement
+    op64 = pl.Heff(ctx, B1, B2, P, mpo.site(c), mpo.site(c + 1), wl["L"], wl["R"], pl.F64)
+    op32 = pl.Heff(ctx, B1, B2, P, mpo.site(c), mpo.site(c + 1), wl["L"], wl["R"], pl.F32)
+    dav = {}
+    psi64 = None
+    for name, op, ref in (("f64", op64, None), ("mixed", op32, op64)):
+        psi = wl["x"].clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        # from a random start: converges in about 160 products with a 16-vector subspace
+        E, r, n, code = pl.davidson_step(ctx, op, psi, max_matvec=400, max_sub=16, tol=1e-8, op64=ref)
+        torch.cuda.synchronize()
+        dav[name] = {"ms": round((time.perf_counter() - t0) * 1e3, 3), "energy": E, "resid": r, "n_matvec": n,
+                     "converged": code == 0}
+        if name == "f64":
+            psi64 = psi
+    dav["rel_energy_diff"] = abs(dav["mixed"]["energy"] - dav["f64"]["energy"]) / abs(dav["f64"]["energy"])
+    bl, br = OB(bonds[c]), OB(bonds[c + 2])
+    Lr = synth.random_env_blocks(bonds[c], mpo.deltas[c], rng)
+    Rr = synth.random_env_blocks(bonds[c + 2], mpo.deltas[c + 2], rng)
+    keys = two_site_keys(bl, br, PQ)
+    shapes = [two_site_shape(k, bl, br, PQ) for k in keys]
+    x0 = flatten(synth.random_two_site_blocks(bonds[c], bonds[c + 2], PQ, rng), keys, shapes)
+    mv = lambda v: flatten(od.heff_apply(Lr, Rr, mpo.W[c], mpo.W[c + 1], unflatten(v, keys, shapes), bl, br, PQ,
+                                         mpo.deltas[c], mpo.deltas[c + 2]), keys, shapes)
+    dg = flatten(od.heff_diag(Lr, Rr, mpo.W[c], mpo.W[c + 1], bl, br, PQ, mpo.deltas[c], mpo.deltas[c + 2]),
+                 keys, shapes)
+    t0 = time.perf_counter()
+    od.davidson(mv, x0, dg, od.DavidsonParams(max_matvec=8, tol=1e-30, max_sub=16))
+    dav["oracle_ms_per_8_matvecs"] = round((time.perf_counter() - t0) * 1e3, 1)
+    dav["start"] = "seeded random vector, tol 1e-8 on the FP64 residual, subspace 16"
+    out["davidson_step"] = dav
+    op32.free()
+    # svd_truncate (split mode, V = 1/lambda) of the FP64 Davidson state
+    holder = {}
+    t = _timed(torch, lambda: holder.__setitem__("r", pl.SvdResult(ctx, B1, B2, P, psi64, 1024, mode=pl.SPLIT)),
+               reps=2)
+    sv = holder["r"]
+    psi_o = synth.random_two_site_blocks(bonds[c], bonds[c + 2], PQ, rng)
+    to = _otimed(lambda: od.svd_truncate(psi_o, bl, br, PQ, 1024, "split"), budget_s=1.0)
+    out["svd_truncate"] = {"ms": round(t * 1e3, 3), "kept": int(sum(sv.bond.values())),
+                           "discarded": sv.discarded, "oracle_ms": round(to * 1e3, 1)}
+    # merge_regions: psi' = (A Lambda) V (Lambda B) at the new middle bond
+    Bn = pl.Bond(sv.bond)
+    Vd = torch.from_numpy(np.ascontiguousarray(sv.V)).cuda()
+    merged = torch.empty_like(psi64)
+    t = _timed(torch, lambda: pl.merge_regions(ctx, B1, Bn, B2, P, sv.left, Vd, sv.right, merged))
+    mid = OB(sv.bond)
+    pL = synth.random_site_blocks(bonds[c], sv.bond, PQ, rng)
+    pR = synth.random_site_blocks(sv.bond, bonds[c + 2], PQ, rng)
+    Vo = {q: rng.random(d) for q, d in sv.bond.items()}
+    to = _otimed(lambda: od.merge(pL, Vo, pR, PQ))
+    out["merge_regions"] = {"ms": round(t * 1e3, 4), "oracle_ms": round(to * 1e3, 2)}
+    # grad_site at site c+1: L on bond c+1 (from the env_update above), R on bond c+2
+    Wg = mpo.site(c + 1)
+    site_c1 = wl["flat_site"](c + 1)
+    t = _timed(torch, lambda: pl.grad_site(ctx, Bm, B2, P, Wg, Lnext, site_c1, wl["R"]))
+    Lg = synth.random_env_blocks(bonds[c + 1], mpo.deltas[c + 1], rng)
+    Rg = synth.random_env_blocks(bonds[c + 2], mpo.deltas[c + 2], rng)
+    pg = synth.random_site_blocks(bonds[c + 1], bonds[c + 2], PQ, rng)
+    to = _otimed(lambda: og.site_gradient(Lg, Rg, pg, PQ, mpo.deltas[c + 1], mpo.deltas[c + 2]))
+    out["grad_site"] = {"ms": round(t * 1e3, 4), "oracle_ms": round(to * 1e3, 2)}
+    op64.free()
+    print("bench: steps %s" % json.dumps(out), file=sys.stderr, flush=True)
+    return out
 
 
 def large_bond_rates(ctx, pl, synth, np, torch, steps=10):
@@ -294,6 +405,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sweep", action="store_true", help="skip the sweep-seconds leg")
     ap.add_argument("--no-large", action="store_true", help="skip the matvec rates of the m >= 2000 bonds")
+    ap.add_argument("--no-steps", action="store_true", help="skip the per-step timings beside the oracle")
     ap.add_argument("--only-sweep", action="store_true", help="run only the sweep-seconds leg (for profiling)")
     ap.add_argument("--sequential-regions", action="store_true",
                     help="sweep leg: regions one after the other on one stream instead of concurrently")
@@ -394,6 +506,8 @@ def main():
     }
     for v in results.values():
         v["op"].free()
+    if not args.no_steps:
+        out["steps_at_bond"] = steps_leg(ctx, pl, synth, np, torch, wl)
     if not args.no_large:
         out["large_bonds"] = large_bond_rates(ctx, pl, synth, np, torch)
     if not args.no_sweep:

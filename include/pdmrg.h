@@ -228,6 +228,11 @@ int grad_site(pdmrg_ctx *ctx, const pdmrg_bond *bl, const pdmrg_bond *br, const 
  * dir = -1: R_out (ENV_R on bl) from R_in (ENV_R on br) and B:
  *           R'[a,w,a'] = sum B[a,s,b] W[w,s,s',w'] R[b,w',b'] B[a',s',b'].
  * (Sec. II, transformation of the projected operators while sweeping.) */
+/* Host-only: algorithmic flops of env_update with these arguments (allowed
+ * blocks and nonzero MPO entries only, 2 per multiply-add) and the element
+ * count of its output layout. */
+int env_update_info(int dir, const pdmrg_bond *bl, const pdmrg_bond *br, const pdmrg_phys *phys,
+                    const pdmrg_mpo_site *W, double *flops, int64_t *n_out);
 int env_update(pdmrg_ctx *ctx, int dir, const pdmrg_bond *bl, const pdmrg_bond *br,
                const pdmrg_phys *phys, const pdmrg_mpo_site *W, const double *env_in_dev,
                const double *site_dev, double *env_out_dev, int prec);

@@ -352,6 +352,17 @@ int grad_site(pdmrg_ctx *ctx, const pdmrg_bond *bl, const pdmrg_bond *br, const 
     API_END
 }
 
+int env_update_info(int dir, const pdmrg_bond *bl, const pdmrg_bond *br, const pdmrg_phys *phys,
+                    const pdmrg_mpo_site *W, double *flops, int64_t *n_out) {
+    API_BEGIN
+    PD_REQUIRE(dir == 1 || dir == -1, PDMRG_EINVAL, "env_update_info: dir must be +1 or -1");
+    EnvPlan plan;
+    plan.build(dir, Bond::from(bl), Bond::from(br), Phys::from(phys), MpoSite::from(W), nullptr, false);
+    if (flops) *flops = plan.g1.flops + plan.w.flops + plan.g3.flops;
+    if (n_out) *n_out = plan.Eout.size;
+    API_END
+}
+
 // ------------------------------------------------------------------ Davidson
 int davidson_step(pdmrg_ctx *ctx, pdmrg_heff *op, pdmrg_heff *op64, double *psi_dev, const pdmrg_dav_params *p,
                   double *energy, double *resid, int32_t *n_matvec) {

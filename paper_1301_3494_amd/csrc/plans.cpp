@@ -527,7 +527,8 @@ void HeffPlan::set_g3_shape(TileShape t, hipStream_t s, int parts) {
 }
 
 // ---------------------------------------------------------------- environments
-void EnvPlan::build(int dir_, const Bond &bl_, const Bond &br_, const Phys &p_, const MpoSite &W, hipStream_t s) {
+void EnvPlan::build(int dir_, const Bond &bl_, const Bond &br_, const Phys &p_, const MpoSite &W, hipStream_t s,
+                    bool upload) {
     dir = dir_;
     bl = bl_;
     br = br_;
@@ -684,6 +685,7 @@ void EnvPlan::build(int dir_, const Bond &bl_, const Bond &br_, const Phys &p_, 
     g3.validate(sz);
     g1.pick_tile();
     g3.pick_tile();
+    if (!upload) return;
     g1.finish(s);
     w.finish(s);
     g3.finish(s);

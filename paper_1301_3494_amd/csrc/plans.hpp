@@ -109,7 +109,9 @@ struct EnvPlan {
     int64_t nU1 = 0, nU2 = 0;
     GemmList g1, g3;
     LcList w;
-    void build(int dir_, const Bond &bl_, const Bond &br_, const Phys &p_, const MpoSite &W, hipStream_t s);
+    // upload = false: host work lists only (counts, no device buffers).
+    void build(int dir_, const Bond &bl_, const Bond &br_, const Phys &p_, const MpoSite &W, hipStream_t s,
+               bool upload = true);
     // slots: 0 env_in, 1 site, 2 env_out, 3 U1, 4 U2
     void run(GemmPrec prec, const void *env_in, const void *site, void *env_out, void *U1, void *U2,
              hipStream_t s) const;
