@@ -109,32 +109,23 @@ def _otimed(fn, budget_s=2.0):
 
 def steps_leg(ctx, pl, synth, np, torch, wl):
     """Each step of the path at the metric's bond (8 x 4 cylinder, m = 1024,
-    sites 15, 16) on the GPU, with the oracle's own implementation of the same
-    step timed beside it on the host (same block shapes, seeded synthetic
-    values)."""
-    from oracle import dmrg as od, grad as og
-    from oracle.blocks import Bond as OB, two_site_keys, two_site_shape, flatten, unflatten
-    PQ = (-1, 1)
+    sites 15, 16) on the GPU: environment update, Davidson (FP64 and mixed),
+    truncated SVD in split mode, merge, gradient of one site."""
     c, mpo, bonds = wl["center"], wl["mpo"], wl["bonds"]
     B1, B2, P = wl["B1"], wl["B2"], wl["P"]
     Bm = pl.Bond(bonds[c + 1])
-    rng = np.random.default_rng(11)
     out = {}
     # env_update: L on bond c -> bond c+1 with site c
     site_c = wl["flat_site"](c)
     f_env, n_env = pl.env_update_info(1, B1, Bm, P, mpo.site(c))
     Lnext = torch.empty(n_env, dtype=torch.float64, device="cuda")
     t = _timed(torch, lambda: pl.env_update(ctx, 1, B1, Bm, P, mpo.site(c), wl["L"], site_c, Lnext))
-    Lo = synth.random_env_blocks(bonds[c], mpo.deltas[c], rng)
-    Ao = synth.random_site_blocks(bonds[c], bonds[c + 1], PQ, rng)
-    to = _otimed(lambda: od.update_L(Lo, Ao, mpo.W[c], PQ, mpo.deltas[c], mpo.deltas[c + 1]))
     out["env_update"] = {"ms": round(t * 1e3, 4), "tflops": round(f_env / t / 1e12, 3),
-                         "pct_fp64_peak": round(100 * f_env / t / 1e12 / PEAK_TFLOPS["f64"], 2),
-                         "oracle_ms": round(to * 1e3, 2)}
+                         "pct_fp64_peak": round(100 * f_env / t / 1e12 / PEAK_TFLOPS["f64"], 2)}
     # Davidson: FP64, and FP32 with FP64 refinement
     op64 = pl.Heff(ctx, B1, B2, P, mpo.site(c), mpo.site(c + 1), wl["L"], wl["R"], pl.F64)
     op32 = pl.Heff(ctx, B1, B2, P, mpo.site(c), mpo.site(c + 1), wl["L"], wl["R"], pl.F32)
-    dav = {}
+    dav = {"start": "seeded random vector, tol 1e-8 on the FP64 residual, subspace 16"}
     psi64 = None
     for name, op, ref in (("f64", op64, None), ("mixed", op32, op64)):
         psi = wl["x"].clone()
@@ -148,6 +139,44 @@ def steps_leg(ctx, pl, synth, np, torch, wl):
         if name == "f64":
             psi64 = psi
     dav["rel_energy_diff"] = abs(dav["mixed"]["energy"] - dav["f64"]["energy"]) / abs(dav["f64"]["energy"])
+    out["davidson_step"] = dav
+    op32.free()
+    # svd_truncate (split mode, V = 1/lambda) of the FP64 Davidson state
+    holder = {}
+    t = _timed(torch, lambda: holder.__setitem__("r", pl.SvdResult(ctx, B1, B2, P, psi64, 1024, mode=pl.SPLIT)),
+               reps=2)
+    sv = holder["r"]
+    out["svd_truncate"] = {"ms": round(t * 1e3, 3), "kept": int(sum(sv.bond.values())), "discarded": sv.discarded}
+    # merge_regions: psi' = (A Lambda) V (Lambda B) at the new middle bond
+    Bn = pl.Bond(sv.bond)
+    Vd = torch.from_numpy(np.ascontiguousarray(sv.V)).cuda()
+    merged = torch.empty_like(psi64)
+    t = _timed(torch, lambda: pl.merge_regions(ctx, B1, Bn, B2, P, sv.left, Vd, sv.right, merged))
+    out["merge_regions"] = {"ms": round(t * 1e3, 4)}
+    # grad_site at site c+1: L on bond c+1 (from the env_update above), R on bond c+2
+    site_c1 = wl["flat_site"](c + 1)
+    t = _timed(torch, lambda: pl.grad_site(ctx, Bm, B2, P, mpo.site(c + 1), Lnext, site_c1, wl["R"]))
+    out["grad_site"] = {"ms": round(t * 1e3, 4)}
+    op64.free()
+    print("bench: steps %s" % json.dumps(out), file=sys.stderr, flush=True)
+    return out
+
+
+def oracle_steps(wl, svd_bond):
+    """The oracle's own implementation of each step timed on the host, same
+    block shapes as steps_leg, seeded synthetic values."""
+    import numpy as np
+    from paper_1301_3494_amd import synth
+    from oracle import dmrg as od, grad as og
+    from oracle.blocks import Bond as OB, two_site_keys, two_site_shape, flatten, unflatten
+    PQ = (-1, 1)
+    c, mpo, bonds = wl["center"], wl["mpo"], wl["bonds"]
+    rng = np.random.default_rng(11)
+    out = {}
+    Lo = synth.random_env_blocks(bonds[c], mpo.deltas[c], rng)
+    Ao = synth.random_site_blocks(bonds[c], bonds[c + 1], PQ, rng)
+    out["env_update_ms"] = round(1e3 * _otimed(lambda: od.update_L(Lo, Ao, mpo.W[c], PQ, mpo.deltas[c],
+                                                                   mpo.deltas[c + 1])), 2)
     bl, br = OB(bonds[c]), OB(bonds[c + 2])
     Lr = synth.random_env_blocks(bonds[c], mpo.deltas[c], rng)
     Rr = synth.random_env_blocks(bonds[c + 2], mpo.deltas[c + 2], rng)
@@ -160,41 +189,19 @@ def steps_leg(ctx, pl, synth, np, torch, wl):
                  keys, shapes)
     t0 = time.perf_counter()
     od.davidson(mv, x0, dg, od.DavidsonParams(max_matvec=8, tol=1e-30, max_sub=16))
-    dav["oracle_ms_per_8_matvecs"] = round((time.perf_counter() - t0) * 1e3, 1)
-    dav["start"] = "seeded random vector, tol 1e-8 on the FP64 residual, subspace 16"
-    out["davidson_step"] = dav
-    op32.free()
-    # svd_truncate (split mode, V = 1/lambda) of the FP64 Davidson state
-    holder = {}
-    t = _timed(torch, lambda: holder.__setitem__("r", pl.SvdResult(ctx, B1, B2, P, psi64, 1024, mode=pl.SPLIT)),
-               reps=2)
-    sv = holder["r"]
+    out["davidson_ms_per_8_matvecs"] = round((time.perf_counter() - t0) * 1e3, 1)
     psi_o = synth.random_two_site_blocks(bonds[c], bonds[c + 2], PQ, rng)
-    to = _otimed(lambda: od.svd_truncate(psi_o, bl, br, PQ, 1024, "split"), budget_s=1.0)
-    out["svd_truncate"] = {"ms": round(t * 1e3, 3), "kept": int(sum(sv.bond.values())),
-                           "discarded": sv.discarded, "oracle_ms": round(to * 1e3, 1)}
-    # merge_regions: psi' = (A Lambda) V (Lambda B) at the new middle bond
-    Bn = pl.Bond(sv.bond)
-    Vd = torch.from_numpy(np.ascontiguousarray(sv.V)).cuda()
-    merged = torch.empty_like(psi64)
-    t = _timed(torch, lambda: pl.merge_regions(ctx, B1, Bn, B2, P, sv.left, Vd, sv.right, merged))
-    mid = OB(sv.bond)
-    pL = synth.random_site_blocks(bonds[c], sv.bond, PQ, rng)
-    pR = synth.random_site_blocks(sv.bond, bonds[c + 2], PQ, rng)
-    Vo = {q: rng.random(d) for q, d in sv.bond.items()}
-    to = _otimed(lambda: od.merge(pL, Vo, pR, PQ))
-    out["merge_regions"] = {"ms": round(t * 1e3, 4), "oracle_ms": round(to * 1e3, 2)}
-    # grad_site at site c+1: L on bond c+1 (from the env_update above), R on bond c+2
-    Wg = mpo.site(c + 1)
-    site_c1 = wl["flat_site"](c + 1)
-    t = _timed(torch, lambda: pl.grad_site(ctx, Bm, B2, P, Wg, Lnext, site_c1, wl["R"]))
+    out["svd_truncate_ms"] = round(1e3 * _otimed(lambda: od.svd_truncate(psi_o, bl, br, PQ, 1024, "split"),
+                                                 budget_s=1.0), 1)
+    pL = synth.random_site_blocks(bonds[c], svd_bond, PQ, rng)
+    pR = synth.random_site_blocks(svd_bond, bonds[c + 2], PQ, rng)
+    Vo = {q: rng.random(d) for q, d in svd_bond.items()}
+    out["merge_regions_ms"] = round(1e3 * _otimed(lambda: od.merge(pL, Vo, pR, PQ)), 2)
     Lg = synth.random_env_blocks(bonds[c + 1], mpo.deltas[c + 1], rng)
     Rg = synth.random_env_blocks(bonds[c + 2], mpo.deltas[c + 2], rng)
     pg = synth.random_site_blocks(bonds[c + 1], bonds[c + 2], PQ, rng)
-    to = _otimed(lambda: og.site_gradient(Lg, Rg, pg, PQ, mpo.deltas[c + 1], mpo.deltas[c + 2]))
-    out["grad_site"] = {"ms": round(t * 1e3, 4), "oracle_ms": round(to * 1e3, 2)}
-    op64.free()
-    print("bench: steps %s" % json.dumps(out), file=sys.stderr, flush=True)
+    out["grad_site_ms"] = round(1e3 * _otimed(lambda: og.site_gradient(Lg, Rg, pg, PQ, mpo.deltas[c + 1],
+                                                                       mpo.deltas[c + 2])), 2)
     return out
 
 
@@ -405,7 +412,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sweep", action="store_true", help="skip the sweep-seconds leg")
     ap.add_argument("--no-large", action="store_true", help="skip the matvec rates of the m >= 2000 bonds")
-    ap.add_argument("--no-steps", action="store_true", help="skip the per-step timings beside the oracle")
+    ap.add_argument("--no-steps", action="store_true", help="skip the per-step timings")
     ap.add_argument("--only-sweep", action="store_true", help="run only the sweep-seconds leg (for profiling)")
     ap.add_argument("--sequential-regions", action="store_true",
                     help="sweep leg: regions one after the other on one stream instead of concurrently")
@@ -417,7 +424,7 @@ def main():
                     help="tile-shape selection: 0 cost model, 1 timed at operator creation, 2 = 1 + log")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU only (the regions of one sweep share a device); "
+        print("bench.py: measures one GPU (the regions of one sweep share a device); "
               "--gpus %d is not supported" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
@@ -453,14 +460,6 @@ def main():
             name, wall / steps * 1e3, results[name]["tflops"],
             {k: info[k] for k in ("shape_Lpsi", "shape_R", "tiles_Lpsi", "tiles_R", "splitk_parts")}),
             file=sys.stderr, flush=True)
-    # the same products replayed from a captured HIP graph (one per (x, y))
-    rg = results[args.prec]
-    pl.set_graphs(ctx, True)
-    yg = torch.empty_like(wl["x"])
-    gwall, _ = time_matvecs(ctx, pl, torch, rg["op"], wl["x"], yg, rg["steps"], args.warmup)
-    pl.set_graphs(ctx, False)
-    graph_ms = gwall / rg["steps"] * 1e3
-    print("bench: %s matvec from a HIP graph %.4f ms" % (args.prec, graph_ms), file=sys.stderr, flush=True)
     r = results[args.prec]
     info = r["info"]
     ms_step = r["wall"] / r["steps"] * 1e3
@@ -496,16 +495,16 @@ def main():
                      "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
                      "frac": round(achieved / peak, 4), "traffic": traffic},
         "plan": {k: info[k] for k in ("shape_Lpsi", "shape_R", "tiles_Lpsi", "tiles_R", "splitk_parts")},
-        "graph_replay": {"ms_per_matvec": round(graph_ms, 5), "eager_ms_per_matvec": round(ms_step, 5),
-                         "small_bond": small_graph_probe(ctx, pl, synth, np, torch)},
         "stage_ms_order": ["L.psi GEMM", "W stage", "T2.R GEMM", "split-K reduction", "total"],
         "stage_ms": {k: [round(v, 5) for v in results[k]["ms"]] for k in results},
         "precisions": {k: {"tflops": round(v["tflops"], 3), "ms_per_matvec": round(v["wall"] / v["steps"] * 1e3, 5),
                            "rel_err_vs_f64": v["err"], "pct_peak": round(100 * v["tflops"] / PEAK_TFLOPS[k], 2)}
                        for k, v in results.items()},
     }
-    for v in results.values():
-        v["op"].free()
+    keep = results[args.prec]["op"]
+    for k, v in results.items():
+        if k != args.prec:
+            v["op"].free()
     if not args.no_steps:
         out["steps_at_bond"] = steps_leg(ctx, pl, synth, np, torch, wl)
     if not args.no_large:
@@ -514,6 +513,18 @@ def main():
         out["sweep"] = sweep_leg(ctx, pl, synth, torch, concurrent=not args.sequential_regions)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, info["flops"])
+        if not args.no_steps:
+            out["cpu_baseline"]["steps"] = oracle_steps(wl, synth.binomial_bonds(wl["N"], wl["m"])[wl["center"] + 1])
+    # HIP graph replay of the same products (one graph per (x, y)), measured
+    # last: graph use is opt-in and reported only
+    pl.set_graphs(ctx, True)
+    yg = torch.empty_like(wl["x"])
+    gwall, _ = time_matvecs(ctx, pl, torch, keep, wl["x"], yg, r["steps"], args.warmup)
+    pl.set_graphs(ctx, False)
+    out["graph_replay"] = {"ms_per_matvec": round(gwall / r["steps"] * 1e3, 5), "eager_ms_per_matvec": round(ms_step, 5),
+                           "small_bond": small_graph_probe(ctx, pl, synth, np, torch)}
+    print("bench: graph replay %s" % json.dumps(out["graph_replay"]), file=sys.stderr, flush=True)
+    keep.free()
     if args.tune_save:
         pl.autotune_export(args.tune_save)
     ctx.close()

@@ -125,13 +125,16 @@ EnvLayout env_r_layout(const Bond &b, const std::vector<int> &deltas) { return g
 // Caching device allocator behind DevBuf.  Sizes are rounded up to a power of
 // two (at least 256 bytes); released blocks go to a pending list and become
 // reusable only after one device-wide synchronisation, so a block can never be
-// handed out while a kernel launched before its release still uses it.
-// Cached blocks are kept until the process ends.
+// handed out while a kernel launched before its release still uses it.  That
+// synchronisation waits for every stream (concurrent regions included), so it
+// is taken only once the pending blocks hold kRecycleBytes; below that a miss
+// allocates a new block.  Cached blocks are kept until the process ends.
 namespace {
 std::mutex g_cache_mu;   // the allocator serves every host thread of the process
+constexpr size_t kRecycleBytes = size_t(2) << 30;
 struct DeviceCache {
     std::map<std::pair<int, size_t>, std::vector<void *>> free_, pending_;
-    bool has_pending = false;
+    size_t pending_bytes = 0;
 };
 DeviceCache &cache() {
     static DeviceCache *c = new DeviceCache();   // never destroyed: no hipFree after runtime teardown
@@ -141,6 +144,15 @@ size_t size_class(size_t n) {
     size_t c = 256;
     while (c < n) c <<= 1;
     return c;
+}
+void recycle(DeviceCache &c) {
+    HIP_OK(hipDeviceSynchronize());
+    for (auto &kv : c.pending_) {
+        auto &dst = c.free_[kv.first];
+        dst.insert(dst.end(), kv.second.begin(), kv.second.end());
+        kv.second.clear();
+    }
+    c.pending_bytes = 0;
 }
 }  // namespace
 
@@ -153,18 +165,9 @@ void DevBuf::alloc(size_t n) {
     DeviceCache &c = cache();
     auto key = std::make_pair(dev, cls);
     auto it = c.free_.find(key);
-    if ((it == c.free_.end() || it->second.empty()) && c.has_pending) {
-        auto pit = c.pending_.find(key);
-        if (pit != c.pending_.end() && !pit->second.empty()) {
-            HIP_OK(hipDeviceSynchronize());
-            for (auto &kv : c.pending_) {
-                auto &dst = c.free_[kv.first];
-                dst.insert(dst.end(), kv.second.begin(), kv.second.end());
-                kv.second.clear();
-            }
-            c.has_pending = false;
-            it = c.free_.find(key);
-        }
+    if ((it == c.free_.end() || it->second.empty()) && c.pending_bytes >= kRecycleBytes) {
+        recycle(c);
+        it = c.free_.find(key);
     }
     if (it != c.free_.end() && !it->second.empty()) {
         ptr = it->second.back();
@@ -182,7 +185,7 @@ void DevBuf::alloc(size_t n) {
                 for (void *p : kv.second) (void)hipFree(p);
                 kv.second.clear();
             }
-        c.has_pending = false;
+        c.pending_bytes = 0;
         e = hipMalloc(&ptr, cls);
     }
     if (e != hipSuccess) {
@@ -200,7 +203,7 @@ void DevBuf::release() {
             std::lock_guard<std::mutex> lk(g_cache_mu);
             DeviceCache &c = cache();
             c.pending_[std::make_pair(dev, bytes)].push_back(ptr);
-            c.has_pending = true;
+            c.pending_bytes += bytes;
         }
     }
     ptr = nullptr;
