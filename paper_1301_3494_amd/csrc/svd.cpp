@@ -86,6 +86,8 @@ void svd_batch(pdmrg_ctx *ctx, const std::vector<Mat> &mats, std::vector<SvdRes>
         const Mat &m = mats[i];
         const bool wide = m.nr <= m.nc;
         const int nv = std::min(m.nr, m.nc), len = std::max(m.nr, m.nc);
+        // the Jacobi kernel addresses W and Z with 32-bit byte offsets
+        PD_REQUIRE((int64_t)nv * len * 8 < (int64_t(1) << 31), PDMRG_EINVAL, "svd: block too large");
         items[i].nv = nv;
         items[i].len = len;
         items[i].W = ar.take((size_t)nv * len);

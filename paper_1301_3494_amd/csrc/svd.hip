@@ -2,33 +2,117 @@
 //
 // Each matrix is stored as nv row vectors of length len (W, row-major).  One
 // Jacobi round rotates disjoint pairs of 8-row blocks: a workgroup forms the
-// 16 x 16 Gram matrix of its two blocks, diagonalises it with cyclic Jacobi
-// in LDS and replaces the rows by the eigenvector combinations, making all
-// 16 rows mutually orthogonal; the same rotation is applied to the
-// accumulator Z (nv x nv, starts at I).  Rounds follow the circle schedule,
-// so every block pair meets once per sweep.  When no pair of a sweep needed a
-// rotation (relative off-diagonal |G_ij| / sqrt(G_ii G_jj) <= tol) the rows
-// are orthogonal: W = Z M, row norms are the singular values.
+// 16 x 16 Gram matrix of its two blocks, applies one cyclic Jacobi sweep to it
+// in LDS and replaces the rows by the resulting combinations, sorted by
+// decreasing norm; the same rotation is applied to the accumulator Z (nv x nv,
+// starts at I).  Rounds follow the circle schedule, so every block pair meets
+// once per sweep.  When no pair of a sweep needed a rotation (relative
+// off-diagonal |G_ij| / sqrt(G_ii G_jj) <= tol) the rows are orthogonal:
+// W = Z M, row norms are the singular values.
 //
-// The 16 rows are staged through LDS in 512-column chunks (coalesced, all
-// loads in flight together); the Gram matrix and the row rotations are
-// 16 x 16 x K products on the FP64 matrix cores (v_mfma_f64_16x16x4, 4 waves
-// over disjoint K / column ranges).
-// The 16 x 16 eigenproblem runs in LDS with one matrix entry per thread: a
-// round's 8 disjoint rotations J are applied as A <- J^T A J, Q <- Q J from
-// the previous round's copy (double buffer), two barriers per round.
+// Rows of W and Z are staged in LDS in 512-column chunks, both first chunks
+// fetched at entry with all loads in flight; global accesses are raw buffer
+// operations whose out-of-range offsets read zero / drop the store, so rows
+// absent from the matrix need no branches.  The Gram matrix and the row
+// rotations are 16 x 16 x K products on the FP64 matrix cores
+// (v_mfma_f64_16x16x4).  A round of the inner sweep applies its 8 disjoint
+// rotations J as A <- J^T A J, Q <- Q J from the previous round's copy
+// (double buffer), one barrier per round: every wave computes the 8 angles
+// itself (one pair per lane) and hands them to the lanes that use them by
+// cross-lane shuffles while the operands of the update are already being
+// read, since a round's partner indices follow from the schedule alone.
+//
+// Measured alternatives: 16-row blocks (32 x 32 inner problem) halve the
+// rounds per sweep but cost more than twice as much per round; up to three
+// inner sweeps per meeting save fewer outer rounds than they cost.
 #include "svd.hpp"
 
 namespace pdmrg {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef unsigned u2 __attribute__((ext_vector_type(2)));
 
-constexpr int JB = 8, J2 = 16;
-constexpr int JT = 256;   // 4 waves; one 16 x 16 entry per thread in the eigensolver
-constexpr int JCH = 512;  // columns of the 16 rows staged in LDS at a time
+constexpr int JB = 8;            // rows per block
+constexpr int J2 = 2 * JB;       // rows of a pair
+constexpr int M = J2 - 1;        // circle schedule modulus
+constexpr int JT = 256;          // 4 waves; one 16 x 16 entry per thread
+constexpr int CH = 512;          // columns staged in LDS at a time
+constexpr int U = J2 * CH / JT;  // staged elements per thread and chunk
+constexpr unsigned kOut = 0x80000000u;   // buffer offset past every record
 
 __device__ __forceinline__ d4 mfma_f64(double a, double b, d4 c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Raw buffer descriptor over the n doubles at p (p is the same in every lane).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rows_rsrc(const double *p, int64_t n) {
+    const uint64_t v = reinterpret_cast<uint64_t>(p);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    void *q = reinterpret_cast<void *>(((uint64_t)hi << 32) | lo);
+    return __builtin_amdgcn_make_buffer_rsrc(q, 0, (int)(n * 8), 0x00020000);
+}
+__device__ __forceinline__ double bload(__amdgpu_buffer_rsrc_t r, unsigned off) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, unsigned off, double v) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, off, 0, 0);
+}
+
+// Circle schedule on J2 = M + 1 positions, round r: position M meets r, every
+// other position i meets (2 r - i) mod M.  Pair l (0 <= l < J2 / 2) is
+// {M, r} for l = 0 and {(r + l) mod M, (r - l) mod M} otherwise.
+__device__ __forceinline__ int sched_partner(int i, int r) {
+    if (i == M) return r;
+    if (i == r) return M;
+    return (2 * r - i + 2 * M) % M;
+}
+__device__ __forceinline__ int sched_pair(int i, int r) {
+    if (i == M || i == r) return 0;
+    const int d = (i - r + M) % M;
+    return d <= M / 2 ? d : M - d;
+}
+
+// Rotation that zeroes a_pq of the symmetric 2 x 2 block (app, apq, aqq),
+// p < q: column p becomes c col_p - s col_q, column q becomes s col_p + c col_q,
+// with t = tan(angle) = 2 a_pq / (d + sign(d) sqrt(d^2 + 4 a_pq^2)),
+// d = a_qq - a_pp (the root of smaller magnitude, |t| <= 1), c = 1 / sqrt(1 + t^2),
+// s = t c.  d and 2 a_pq are first scaled by a power of two so the larger
+// magnitude lies in [1/2, 1); then u = d^2 + 4 a_pq^2 lies in [1/4, 2],
+// |d| + sqrt(u) in [1/2, 3] and 1 + t^2 in [1, 2], so hardware reciprocal and
+// reciprocal square root estimates refined by Newton-type steps give full
+// precision without range handling.
+// The angle only decides how well a_pq is annihilated; the rotation is
+// orthogonal to working precision whatever t is, because c and s follow from
+// t.  Skipped (c = 1, s = 0) when a_pq^2 <= 1e-32 |a_pp a_qq| (the relative
+// rule that resolves the small eigenvalues of a graded Gram matrix).
+__device__ __forceinline__ void jacobi_angle(double app, double apq, double aqq, double &c, double &s) {
+    const double d0 = aqq - app;
+    const double big = fmax(fabs(d0), fabs(2.0 * apq));
+    const int e = big > 0.0 ? __builtin_amdgcn_frexp_exp(big) : 0;
+    const double d = __builtin_amdgcn_ldexp(d0, -e), a2 = __builtin_amdgcn_ldexp(2.0 * apq, -e);
+    // h = sqrt(u): Goldschmidt iteration from the reciprocal square root estimate
+    const double u = fma(d, d, a2 * a2);
+    const double y0 = __builtin_amdgcn_rsq(u);
+    double g = u * y0, hh = 0.5 * y0;
+    const double r = fma(-hh, g, 0.5);
+    g = fma(g, r, g);
+    hh = fma(hh, r, hh);
+    const double h = fma(fma(-g, g, u), hh, g);
+    // t = a2 / den: reciprocal estimate and two Newton steps
+    const double den = d >= 0.0 ? d + h : d - h;
+    double q = __builtin_amdgcn_rcp(den);
+    q = fma(q, fma(-den, q, 1.0), q);
+    q = fma(q, fma(-den, q, 1.0), q);
+    const double t = a2 * q;
+    // c = (1 + t^2)^(-1/2): estimate y, w = 1 - v y^2, c = y (1 + w / 2 + 3 w^2 / 8)
+    const double v = fma(t, t, 1.0);
+    const double y = __builtin_amdgcn_rsq(v);
+    const double w = fma(-v * y, y, 1.0);
+    const double ct = fma(y * w, fma(w, 0.375, 0.5), y);
+    const bool skip = apq == 0.0 || apq * apq <= 1e-32 * fabs(app * aqq);
+    c = skip ? 1.0 : ct;
+    s = skip ? 0.0 : t * ct;
 }
 
 __global__ __launch_bounds__(JT) void jac_pair_kernel(const JacItem *__restrict__ items,
@@ -36,60 +120,71 @@ __global__ __launch_bounds__(JT) void jac_pair_kernel(const JacItem *__restrict_
                                                       const int32_t *__restrict__ active,
                                                       unsigned long long *__restrict__ offmax, double tol) {
     const JacPair pr = pairs[blockIdx.x];
-    if (!active[pr.item]) return;
     const JacItem it = items[pr.item];
-    __shared__ double rows[J2][JCH + 1];
+    if (!active[pr.item]) return;
+    __shared__ double wrows[J2][CH + 1];   // W rows, current chunk
+    __shared__ double zrows[J2][CH + 1];   // Z rows, current chunk
     __shared__ double Gp[4][J2][J2 + 1];
     __shared__ double A[2][J2][J2 + 1];
     __shared__ double Q[2][J2][J2 + 1];
-    __shared__ double cself[J2], cother[J2];
-    __shared__ int partner[J2];
-    __shared__ int rowid[J2], ev[J2], vp[J2];
-    __shared__ int nvalid;
+    __shared__ int ev[J2];
     __shared__ double wred[4];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int r16 = lane & 15, g = lane >> 4;
-    if (tid < J2) {
-        const int r = tid < JB ? pr.bi * JB + tid : pr.bj * JB + (tid - JB);
-        rowid[tid] = r < it.nv ? r : -1;
-    }
-    __syncthreads();
+    if (tid < J2) ev[tid] = tid;
+    // rows of the pair present in the matrix form a prefix 0..n-1 (only the
+    // last block of a matrix is partial, and a pair never holds two blocks
+    // past it)
+    const int n = min(max(it.nv - pr.bi * JB, 0), JB) + min(max(it.nv - pr.bj * JB, 0), JB);
+    auto grow = [&](int r) { return r < JB ? pr.bi * JB + r : pr.bj * JB + (r - JB); };
+    const __amdgpu_buffer_rsrc_t rW = rows_rsrc(it.W, (int64_t)it.nv * it.len);
+    const __amdgpu_buffer_rsrc_t rZ = rows_rsrc(it.Z, (int64_t)it.nv * it.nv);
 
-    // Stage the 16 rows through LDS in chunks of JCH columns (coalesced
-    // loads, all in flight together); rows absent from the matrix read as 0.
-    auto stage = [&](const double *M, int len, int c0) {
-        constexpr int U = J2 * JCH / JT;
-        const int w = min(JCH, len - c0);
-        double v[U];
+    // Element u of this thread in a chunk: row u / 2, column tid + 256 (u % 2).
+    auto load_chunk = [&](__amdgpu_buffer_rsrc_t rs, int len, int c0, double (&v)[U]) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int e = tid + u * JT, r = e / JCH, c = e % JCH;
-            v[u] = (rowid[r] >= 0 && c < w) ? M[(int64_t)rowid[r] * len + c0 + c] : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int e = tid + u * JT;
-            rows[e / JCH][e % JCH] = v[u];
+            const int r = u >> 1, c = c0 + tid + JT * (u & 1);
+            const unsigned off = (r < n && c < len) ? (unsigned)(((int64_t)grow(r) * len + c) * 8) : kOut;
+            v[u] = bload(rs, off);
         }
     };
+    auto store_chunk = [&](double (*dst)[CH + 1], const double (&v)[U]) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) dst[u >> 1][tid + JT * (u & 1)] = v[u];
+    };
+    {
+        double v[U], z[U];
+        load_chunk(rW, it.len, 0, v);
+        load_chunk(rZ, it.nv, 0, z);
+        store_chunk(wrows, v);
+        store_chunk(zrows, z);
+    }
 
     // ---- Gram matrix G = Wp Wp^T (Wp: the 16 rows).  MFMA j of a 16-wide K
-    // chunk takes k = kk + 4 g + j from lane group g; A and B operands are the
-    // same element Wp[r16][k].
+    // step takes k = kk + 4 g + j from lane group g; A and B operands are the
+    // same element Wp[r16][k]; the four waves split K and their partial tiles
+    // are summed in a fixed order.
+    const int nch = (it.len + CH - 1) / CH;
     {
         d4 acc = {0.0, 0.0, 0.0, 0.0};
-        for (int c0 = 0; c0 < it.len; c0 += JCH) {
-            stage(it.W, it.len, c0);
-            __syncthreads();
-            const int w = min(JCH, it.len - c0);
-            for (int kk = wave * 16; kk < w; kk += 64) {
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const double v = rows[r16][kk + 4 * g + j];
-                    acc = mfma_f64(v, v, acc);
-                }
+        for (int ch = 0; ch < nch; ++ch) {
+            const int c0 = ch * CH;
+            if (ch > 0) {
+                double v[U];
+                load_chunk(rW, it.len, c0, v);
+                __syncthreads();
+                store_chunk(wrows, v);
             }
             __syncthreads();
+            const int w = min(CH, it.len - c0);
+            for (int kk = wave * 16; kk < w; kk += 64) {
+                double v[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) v[j] = wrows[r16][kk + 4 * g + j];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc = mfma_f64(v[j], v[j], acc);
+            }
         }
         // v_mfma_f64_16x16x4 result: register r of lane l is row 4 r + l / 16, column l % 16
 #pragma unroll
@@ -102,7 +197,7 @@ __global__ __launch_bounds__(JT) void jac_pair_kernel(const JacItem *__restrict_
     __syncthreads();
     // ---- relative off-diagonal of this pair
     double off = 0.0;
-    if (ei < ej && rowid[ei] >= 0 && rowid[ej] >= 0) {
+    if (ei < ej && ej < n) {
         const double dd = A[0][ei][ei] * A[0][ej][ej];
         if (dd > 0.0) off = fabs(gij) / sqrt(dd);
     }
@@ -113,114 +208,91 @@ __global__ __launch_bounds__(JT) void jac_pair_kernel(const JacItem *__restrict_
     if (tid == 0) atomicMax(&offmax[pr.item], (unsigned long long)__double_as_longlong(poff));
     if (poff <= tol) return;
     // rows absent from the matrix: isolated with eigenvalue -1 (never rotated)
-    {
-        double v = gij;
-        if (rowid[ei] < 0 || rowid[ej] < 0) v = (ei == ej) ? -1.0 : 0.0;
-        A[0][ei][ej] = v;
-        Q[0][ei][ej] = (ei == ej) ? 1.0 : 0.0;
-    }
+    A[0][ei][ej] = (ei >= n || ej >= n) ? (ei == ej ? -1.0 : 0.0) : gij;
+    Q[0][ei][ej] = ei == ej ? 1.0 : 0.0;
     __syncthreads();
 
-    // ---- 16 x 16 cyclic Jacobi, at most 3 sweeps.  Relative skipping rule
-    // |a_pq| <= 1e-16 sqrt(|a_pp a_qq|), so the small eigenvalues of a graded
-    // Gram matrix are resolved in relative terms.  A partial
+    // ---- one cyclic Jacobi sweep on the 16 x 16 Gram matrix.  A partial
     // diagonalisation is still an exact rotation of the rows; the outer
     // iteration measures orthogonality on fresh Gram matrices.
     int cur = 0;
-    for (int sweep = 0; sweep < 3; ++sweep) {
-        if (sweep > 0) {
-            // stop once every off-diagonal entry is below 1e-15 of sqrt(a_ii a_jj)
-            double o = 0.0;
-            if (ei != ej) {
-                const double v = fabs(A[cur][ei][ej]);
-                if (v != 0.0) {
-                    const double dd = sqrt(fabs(A[cur][ei][ei] * A[cur][ej][ej]));
-                    o = dd > 0.0 ? v / dd : 1.0;
-                }
-            }
-            for (int w = 32; w > 0; w >>= 1) o = fmax(o, __shfl_xor(o, w));
-            if (lane == 0) wred[wave] = o;
-            __syncthreads();
-            const double ro = fmax(fmax(wred[0], wred[1]), fmax(wred[2], wred[3]));
-            __syncthreads();
-            if (ro <= 1e-15) break;
-        }
-        for (int r = 0; r < J2 - 1; ++r) {
-            if (tid < J2 / 2) {
-                int p = (tid == 0) ? J2 - 1 : (r + tid) % (J2 - 1);
-                int q = (r - tid + (J2 - 1)) % (J2 - 1);
-                if (p > q) { const int t = p; p = q; q = t; }
-                double c = 1.0, sn = 0.0;
-                const double apq = A[cur][p][q];
-                const double app = A[cur][p][p], aqq = A[cur][q][q];
-                if (apq != 0.0 && fabs(apq) > 1e-16 * sqrt(fabs(app * aqq))) {
-                    const double tau = (aqq - app) / (2.0 * apq);
-                    const double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-                    c = 1.0 / sqrt(1.0 + t * t);
-                    sn = t * c;
-                }
-                // new column p = c col_p - s col_q, new column q = s col_p + c col_q
-                partner[p] = q; cself[p] = c; cother[p] = -sn;
-                partner[q] = p; cself[q] = c; cother[q] = sn;
-            }
-            __syncthreads();
-            {
-                const int pi = partner[ei], pj = partner[ej];
-                const double si = cself[ei], oi = cother[ei], sj = cself[ej], oj = cother[ej];
-                const double (*Ac)[J2 + 1] = A[cur];
-                const double v = si * (sj * Ac[ei][ej] + oj * Ac[ei][pj]) + oi * (sj * Ac[pi][ej] + oj * Ac[pi][pj]);
-                A[cur ^ 1][ei][ej] = v;
-                Q[cur ^ 1][ei][ej] = sj * Q[cur][ei][ej] + oj * Q[cur][ei][pj];
-            }
-            __syncthreads();
-            cur ^= 1;
-        }
+    const int lp = lane % (J2 / 2);   // the pair whose angle this lane computes
+    for (int r = 0; r < M; ++r) {
+        const double(*Ac)[J2 + 1] = A[cur];
+        const double(*Qc)[J2 + 1] = Q[cur];
+        const int pa = lp == 0 ? M : (r + lp) % M, pb = (r - lp + M) % M;
+        const int lo = min(pa, pb), hi = max(pa, pb);
+        const double app = Ac[lo][lo], apq = Ac[lo][hi], aqq = Ac[hi][hi];
+        const int pi = sched_partner(ei, r), pj = sched_partner(ej, r);
+        const double a0 = Ac[ei][ej], a1 = Ac[ei][pj], a2 = Ac[pi][ej], a3 = Ac[pi][pj];
+        const double q0 = Qc[ei][ej], q1 = Qc[ei][pj];
+        double c, s;
+        jacobi_angle(app, apq, aqq, c, s);
+        // the lower index of a pair takes -s, the upper +s
+        const int li = sched_pair(ei, r), lj = sched_pair(ej, r);
+        const double ci = __shfl(c, li), si = __shfl(s, li);
+        const double cj = __shfl(c, lj), sj = __shfl(s, lj);
+        const double oi = ei < pi ? -si : si, oj = ej < pj ? -sj : sj;
+        A[cur ^ 1][ei][ej] = ci * (cj * a0 + oj * a1) + oi * (cj * a2 + oj * a3);
+        Q[cur ^ 1][ei][ej] = cj * q0 + oj * q1;
+        __syncthreads();
+        cur ^= 1;
     }
-    if (tid == 0) {
-        // valid positions in order; valid eigenvectors sorted by descending eigenvalue
-        int n = 0;
-        for (int j = 0; j < J2; ++j)
-            if (rowid[j] >= 0) { vp[n] = j; ev[n] = j; ++n; }
-        for (int a = 0; a < n; ++a) {
-            int best = a;
-            for (int b = a + 1; b < n; ++b)
-                if (A[cur][ev[b]][ev[b]] > A[cur][ev[best]][ev[best]]) best = b;
-            const int t = ev[a]; ev[a] = ev[best]; ev[best] = t;
+    // rank of each present row's eigenvalue, descending (ties: lower index first)
+    if (tid < n) {
+        const double di = A[cur][tid][tid];
+        int rank = 0;
+#pragma unroll
+        for (int j = 0; j < J2; ++j) {
+            const double dj = A[cur][j][j];
+            rank += (j < n && (dj > di || (dj == di && j < tid))) ? 1 : 0;
         }
-        nvalid = n;
+        ev[rank] = tid;
     }
     __syncthreads();
-    const int n = nvalid;
 
-    // ---- rotate the W rows and Z rows: new row vp[o] = sum_k Q[k][ev[o]] old row k,
-    // as (16 x 16) x (16 x JCH) MFMA products from the staged rows; every
-    // chunk is staged completely before any of its columns is written.
-    const double qa[4] = {r16 < n ? Q[cur][g][ev[r16]] : 0.0, r16 < n ? Q[cur][4 + g][ev[r16]] : 0.0,
-                          r16 < n ? Q[cur][8 + g][ev[r16]] : 0.0, r16 < n ? Q[cur][12 + g][ev[r16]] : 0.0};
-    int dst[4];
+    // ---- new row o = sum_k Q[k][ev[o]] old row k, stored at row o of the
+    // pair, as (16 x 16) x (16 x CH) MFMA products from the staged rows.
+    double qa[4];
+    unsigned dbase[4];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) dst[r] = (4 * r + g) < n ? rowid[vp[4 * r + g]] : -1;
+    for (int j = 0; j < 4; ++j) qa[j] = r16 < n ? Q[cur][4 * j + g][ev[r16]] : 0.0;
     for (int pass = 0; pass < 2; ++pass) {
-        double *M = pass == 0 ? it.W : it.Z;
+        const __amdgpu_buffer_rsrc_t rs = pass == 0 ? rW : rZ;
+        double(*src)[CH + 1] = pass == 0 ? wrows : zrows;
         const int len = pass == 0 ? it.len : it.nv;
-        // W rows are still staged when they fit in one chunk
-        const bool staged = pass == 0 && it.len <= JCH;
-        for (int c0 = 0; c0 < len; c0 += JCH) {
-            if (!staged) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int o = 4 * r + g;
+            dbase[r] = o < n ? (unsigned)((int64_t)grow(o) * len) : kOut;
+        }
+        // W: the last chunk of the Gram pass is still staged, so go backwards;
+        // Z: chunk 0 is staged
+        const int nc = (len + CH - 1) / CH;
+        for (int i = 0; i < nc; ++i) {
+            const int ch = pass == 0 ? nc - 1 - i : i;
+            const int c0 = ch * CH;
+            if (i > 0) {
+                double v[U];
+                load_chunk(rs, len, c0, v);
                 __syncthreads();
-                stage(M, len, c0);
+                store_chunk(src, v);
             }
             __syncthreads();
-            const int w = min(JCH, len - c0);
+            const int w = min(CH, len - c0);
             for (int n0 = wave * 16; n0 < w; n0 += 64) {
                 const int col = n0 + r16;
+                double b[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) b[j] = src[4 * j + g][col];
                 d4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-                for (int j = 0; j < 4; ++j) acc = mfma_f64(qa[j], rows[4 * j + g][col], acc);
-                if (col < w)
+                for (int j = 0; j < 4; ++j) acc = mfma_f64(qa[j], b[j], acc);
 #pragma unroll
-                    for (int r = 0; r < 4; ++r)
-                        if (dst[r] >= 0) M[(int64_t)dst[r] * len + c0 + col] = acc[r];
+                for (int r = 0; r < 4; ++r) {
+                    const unsigned offr = (dbase[r] != kOut && col < w) ? (dbase[r] + c0 + col) * 8u : kOut;
+                    bstore(rs, offr, acc[r]);
+                }
             }
         }
     }
