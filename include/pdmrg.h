@@ -347,6 +347,52 @@ int mps_energy(pdmrg_ctx *ctx, pdmrg_mps *mps, const pdmrg_mpo *mpo, double *ene
  * before the gauge changes.  PDMRG_ESHAPE if n_G is not the total size. */
 int grad_mpo(pdmrg_ctx *ctx, pdmrg_mps *mps, const pdmrg_mpo *mpo, double *G_dev, int64_t n_G, double *energy);
 
+/* ---------------------------------------------------------------------------
+ * Inverse canonical gauge and local measurements (Sec. IV, Figs. imps_step
+ * and inversecmps).  In this gauge every site tensor is an orthogonality
+ * centre, psi_j = Lambda_j Gamma_j Lambda_{j+1}, and every inner bond b
+ * carries V_b = Lambda_b^{-1}:  |Psi> = psi_0 V_1 psi_1 ... V_{N-1} psi_{N-1}.
+ *
+ * mps_inverse_canonical converts the MPS in place (same state, normalised):
+ * any V of a region split is folded back, the MPS is brought to
+ * right-canonical form with its centre on site 0, then the split of
+ * Eqs. eqn:inverse, eqn:isvd is applied at bonds 1..N-1 in order, each
+ * Lambda multiplied into both neighbours and V stored on the bond.  Singular
+ * values below cutoff * lambda_max are dropped (bond dimensions can only
+ * shrink); V is floored as in the sweep's split (1/max(lambda, 1e-12
+ * lambda_max)), *n_floored (optional) counts the floored entries; eps is the
+ * Appendix recursion threshold of the SVDs.  Afterwards mps_get_site returns
+ * psi_j, mps_get_v returns V_b, mps_energy works unchanged, and the next
+ * sweep or grad_mpo folds V back and re-canonicalises first.  No MPO needed.
+ *
+ * mps_get_v: V on bond b (host, bond order = sectors ascending in charge,
+ * mps_bond dims) into V[0 .. total); PDMRG_EINVAL if the bond carries none
+ * or cap is too small.
+ *
+ * mps_expect_site: out[j] = <Psi|O_j|Psi> for every site j (host, N doubles)
+ * from the centres alone, sum psi_j[a,s,b] O[s][t] psi_j[a,t,b]; op is the
+ * host d x d matrix <s|O|t> (row-major, local basis order of the MPS).  Only
+ * charge-conserving entries can contribute.  One device launch covers all
+ * sites.  PDMRG_EINVAL unless the MPS is in the inverse canonical gauge.
+ *
+ * mps_expect_pairs: out[p] = sum_t coef[t] <Psi| A_t(i_p) B_t(k_p) |Psi> for
+ * npairs site pairs 0 <= i_p < k_p < N (host arrays).  opA / opB: nterms
+ * host d x d matrices each (row-major <s|O|t>); every A_t must carry one
+ * definite charge and B_t the opposite one (else PDMRG_EINVAL).  Needs only
+ * the tensors on sites i..k: the left transfer starts from the identity on
+ * bond i, passes psi_i and then V_j psi_j for j = i+1..k, and closes with the
+ * trace on bond k+1 (F64 environment updates, one channel per term).
+ * concurrent = 1 spreads the pairs over up to 8 host threads with their own
+ * HIP streams (default priority); results are the same bits either way.
+ * Example: S_i . S_k is {1, Sz, Sz}, {1/2, S+, S-}, {1/2, S-, S+}.
+ * PDMRG_EINVAL unless the MPS is in the inverse canonical gauge. */
+int mps_inverse_canonical(pdmrg_ctx *ctx, pdmrg_mps *mps, double cutoff, double eps, int32_t *n_floored);
+int mps_get_v(const pdmrg_mps *mps, int bond, double *V, int64_t cap);
+int mps_expect_site(pdmrg_ctx *ctx, pdmrg_mps *mps, const double *op, double *out);
+int mps_expect_pairs(pdmrg_ctx *ctx, pdmrg_mps *mps, int nterms, const double *coef, const double *opA,
+                     const double *opB, int npairs, const int32_t *site_i, const int32_t *site_k, int concurrent,
+                     double *out);
+
 void mps_free(pdmrg_mps *mps);
 
 #ifdef __cplusplus

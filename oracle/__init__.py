@@ -18,6 +18,8 @@ dmrg      environments, two-site H_eff, Davidson / Lanczos, truncated SVD with
           the Appendix recursion, split / merge (Eqs. eqn:inverse, eqn:isvd,
           eqn:merge), serial and real-space parallel sweeps (Sec. II, Fig. 4)
 grad      Hellmann-Feynman gradients dE/dW and finite-difference driver
+gauge     inverse canonical gauge (Sec. IV) and local measurements from the
+          orthogonality centres
 
 Parity status of each function is stated in its docstring; everything here
 is pinned by the ``-m "not gpu"`` tests against exact diagonalisation,

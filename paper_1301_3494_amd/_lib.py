@@ -76,7 +76,8 @@ EXPORTS = [
     "mpo_info", "mpo_get_site", "mpo_free", "heff_create", "heff_apply", "heff_info", "heff_plan_info", "heff_diag",
     "heff_free", "env_update", "env_update_info", "davidson_step", "svd_truncate", "svd_result_bond", "svd_result_copy",
     "svd_free", "merge_regions", "mps_alloc", "mps_set_site", "mps_bond", "mps_get_site", "sweep",
-    "mps_energy", "mps_free", "grad_site", "grad_mpo",
+    "mps_energy", "mps_free", "grad_site", "grad_mpo", "mps_inverse_canonical", "mps_get_v", "mps_expect_site",
+    "mps_expect_pairs",
 ]
 
 
@@ -125,6 +126,10 @@ def _declare(L):
         "mps_free": (None, [P]),
         "grad_site": (c_int, [P, pb, pb, pp, pm, P, P, P, P]),
         "grad_mpo": (c_int, [P, P, P, P, c_int64, pd]),
+        "mps_inverse_canonical": (c_int, [P, P, c_double, c_double, pi32]),
+        "mps_get_v": (c_int, [P, c_int, pd, c_int64]),
+        "mps_expect_site": (c_int, [P, P, pd, pd]),
+        "mps_expect_pairs": (c_int, [P, P, c_int, pd, pd, pd, c_int, pi32, pi32, c_int, pd]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -473,6 +478,58 @@ class Mps:
             out.append(G[o:o + k].view(*sh))
             o += k
         return e.value, out
+
+    def site_blocks(self, i):
+        """mps_get_site: the site tensor as {(q_left, s): array}."""
+        B = [Bond(self.bond(i)), Bond(self.bond(i + 1))]
+        table, n = layout(SITE, B[0], B[1], self.phys)
+        flat = np.zeros(max(n, 1))
+        check(lib().mps_get_site(self.h, i, flat.ctypes.data_as(POINTER(c_double)), n))
+        out = {}
+        for key, off, rows, cols, ld in table:
+            out[key[:2]] = np.array([flat[off + r * ld: off + r * ld + cols] for r in range(rows)]).reshape(rows, cols)
+        return out
+
+    def inverse_canonical(self, cutoff=1e-14, eps=1e-4):
+        """mps_inverse_canonical: in place; returns the number of floored V entries."""
+        nf = c_int32()
+        check(lib().mps_inverse_canonical(self.ctx.h, self.h, float(cutoff), float(eps), byref(nf)))
+        return nf.value
+
+    def get_v(self, b):
+        """mps_get_v: {q: V on the sector} of bond b."""
+        bd = self.bond(b)
+        tot = sum(bd.values())
+        v = np.zeros(max(tot, 1))
+        check(lib().mps_get_v(self.h, b, v.ctypes.data_as(POINTER(c_double)), tot))
+        out, o = {}, 0
+        for q in sorted(bd):
+            out[q] = v[o:o + bd[q]].copy()
+            o += bd[q]
+        return out
+
+    def expect_site(self, op):
+        """mps_expect_site: <O_j> for every site j."""
+        op = np.ascontiguousarray(op, dtype=np.float64)
+        out = np.zeros(self.N)
+        check(lib().mps_expect_site(self.ctx.h, self.h, op.ctypes.data_as(POINTER(c_double)),
+                                    out.ctypes.data_as(POINTER(c_double))))
+        return out
+
+    def expect_pairs(self, terms, pairs, concurrent=True):
+        """mps_expect_pairs: sum_t c_t <A_t(i) B_t(k)> for each (i, k) in pairs;
+        terms = [(c, A, B), ...] with d x d operators."""
+        c = np.ascontiguousarray([t[0] for t in terms], dtype=np.float64)
+        A = np.ascontiguousarray(np.stack([t[1] for t in terms]), dtype=np.float64)
+        Bm = np.ascontiguousarray(np.stack([t[2] for t in terms]), dtype=np.float64)
+        i = np.ascontiguousarray([p[0] for p in pairs], dtype=np.int32)
+        k = np.ascontiguousarray([p[1] for p in pairs], dtype=np.int32)
+        out = np.zeros(max(len(pairs), 1))
+        pd_ = lambda a: a.ctypes.data_as(POINTER(c_double))
+        check(lib().mps_expect_pairs(self.ctx.h, self.h, len(terms), pd_(c), pd_(A), pd_(Bm), len(pairs),
+                                     i.ctypes.data_as(POINTER(c_int32)), k.ctypes.data_as(POINTER(c_int32)),
+                                     int(bool(concurrent)), pd_(out)))
+        return out[:len(pairs)]
 
     def bond(self, b):
         n = c_int32()

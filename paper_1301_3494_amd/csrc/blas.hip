@@ -416,4 +416,66 @@ void launch_small_eig(const double *G, int k, int ld, double *theta_out, double 
     hipLaunchKernelGGL(small_eig_kernel, dim3(1), dim3(64), 0, s, G, k, ld, theta_out, c_out);
 }
 
+// ------------------------------------------------------------ local measurements
+__global__ __launch_bounds__(256) void seg_dot_kernel(const SegDot *__restrict__ tasks,
+                                                      const SegTile *__restrict__ tiles,
+                                                      double *__restrict__ partial) {
+    __shared__ double red[256];
+    const SegTile tl = tiles[blockIdx.x];
+    const SegDot tk = tasks[tl.task];
+    const int nr = min(kSegRows, tk.rows - tl.r0);
+    const int n = nr * tk.width;
+    double acc = 0.0;
+    for (int e = threadIdx.x; e < n; e += 256) {
+        const int r = tl.r0 + e / tk.width, c = e % tk.width;
+        const double *row = tk.x + (int64_t)r * tk.ld;
+        acc += row[tk.ca + c] * row[tk.cb + c];
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+void launch_seg_dot_partials(const SegDot *tasks, const SegTile *tiles, int ntiles, double *partial, hipStream_t s) {
+    if (ntiles > 0) hipLaunchKernelGGL(seg_dot_kernel, dim3(ntiles), dim3(256), 0, s, tasks, tiles, partial);
+}
+
+__global__ void set_identity_kernel(const SqBlock *__restrict__ blocks) {
+    const SqBlock b = blocks[blockIdx.y];
+    const int64_t n2 = (int64_t)b.n * b.n;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n2; e += (int64_t)gridDim.x * blockDim.x)
+        b.p[e] = (e / b.n == e % b.n) ? 1.0 : 0.0;
+}
+
+void launch_set_identity(const SqBlock *blocks, int nblocks, int max_n, hipStream_t s) {
+    if (nblocks <= 0 || max_n <= 0) return;
+    const int g = (int)std::min<int64_t>(1024, ((int64_t)max_n * max_n + 255) / 256);
+    hipLaunchKernelGGL(set_identity_kernel, dim3(g, nblocks), dim3(256), 0, s, blocks);
+}
+
+__global__ __launch_bounds__(256) void trace_sum_kernel(const SqBlock *__restrict__ blocks, int nblocks,
+                                                        double *__restrict__ out) {
+    __shared__ double red[256];
+    double acc = 0.0;
+    for (int k = 0; k < nblocks; ++k) {
+        const SqBlock b = blocks[k];
+        for (int r = threadIdx.x; r < b.n; r += 256) acc += b.p[(int64_t)r * b.n + r];
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = red[0];
+}
+
+void launch_trace_sum(const SqBlock *blocks, int nblocks, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(trace_sum_kernel, dim3(1), dim3(256), 0, s, blocks, nblocks, out);
+}
+
 }  // namespace pdmrg

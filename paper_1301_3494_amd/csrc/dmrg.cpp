@@ -30,6 +30,7 @@ struct pdmrg_mps {
     bool ready = false;                      // canonical form + environments
     int n_regions = 1;
     bool split = false;
+    bool icanon = false;                     // inverse canonical gauge: V on every inner bond
     std::vector<std::pair<int, int>> regions;
 };
 
@@ -42,6 +43,7 @@ struct Driver {
     pdmrg_sweep_params prm{};
     pdmrg_sweep_report rep{};
     double t_heff = 0.0;
+    bool envs = true;   // gauge moves update environments (off: no MPO needed)
 
     hipStream_t s() const { return ctx->stream; }
     const MpoSite &W(int i) const { return mpo->W[i]; }
@@ -105,11 +107,11 @@ struct Driver {
         if (mode == PDMRG_ABSORB_RIGHT) {
             m->sites[i] = take(r.A, na);
             m->sites[i + 1] = take(r.right, nb);
-            env_L(i);
+            if (envs) env_L(i);
         } else if (mode == PDMRG_ABSORB_LEFT) {
             m->sites[i] = take(r.left, na);
             m->sites[i + 1] = take(r.B, nb);
-            env_R(i + 1);
+            if (envs) env_R(i + 1);
         } else {
             // environments from the orthonormal factors A and B
             m->sites[i] = take(r.A, na);
@@ -289,6 +291,26 @@ struct Driver {
         }
     }
 
+    // E[a, w, a'] *= V[a] V[a'] for a left environment E on bond b (ENV_L
+    // layout El, channel charges dr): carries a transfer across a bond with V.
+    void scale_env_v(DevBuf &E, const EnvLayout &El, const Bond &b, const std::vector<int> &dr, const double *V) {
+        std::vector<CopyTask> ct;
+        for (int j = 0; j < b.nsec(); ++j)
+            for (int w = 0; w < El.D; ++w) {
+                const int ro = El.rowo[(size_t)j * El.D + w];
+                if (ro < 0) continue;
+                const int k = b.find(b.q[j] + dr[w]);
+                double *blk = E.as<double>() + El.base[j] + (int64_t)ro * b.dim[j];
+                ct.push_back(CopyTask{blk, blk, V + b.off[k], V + b.off[j], b.dim[k], b.dim[j], b.dim[j], b.dim[j], 0, 0});
+            }
+        DevBuf d;
+        upload(d, ct, s());
+        int64_t mx = 0;
+        for (auto &t : ct) mx = std::max<int64_t>(mx, (int64_t)t.rows * t.cols);
+        launch_copies(d.as<CopyTask>(), (int)ct.size(), mx, s());
+        HIP_OK(hipStreamSynchronize(s()));
+    }
+
     // <Psi|O|Psi> of the whole MPS (V applied on shared bonds) by left transfer
     double expectation(bool identity) {
         const int N = m->N;
@@ -315,28 +337,7 @@ struct Driver {
             double *U1 = ctx->ws_env.as<double>();
             ep.run(GemmPrec::F64, E.ptr, m->sites[i].ptr, out.ptr, U1, U1 + std::max<int64_t>(ep.nU1, 1), s());
             auto it = m->Vd.find(i + 1);
-            if (it != m->Vd.end() && m->split) {
-                // E[a, w, a'] *= V[a] V[a']
-                const Bond &b = m->bonds[i + 1];
-                const EnvLayout &El = ep.Eout;
-                const double *V = it->second.as<double>();
-                std::vector<CopyTask> ct;
-                for (int j = 0; j < b.nsec(); ++j)
-                    for (int w = 0; w < El.D; ++w) {
-                        const int ro = El.rowo[(size_t)j * El.D + w];
-                        if (ro < 0) continue;
-                        const int k = b.find(b.q[j] + Wi.dr[w]);
-                        double *blk = out.as<double>() + El.base[j] + (int64_t)ro * b.dim[j];
-                        ct.push_back(CopyTask{blk, blk, V + b.off[k], V + b.off[j], b.dim[k], b.dim[j], b.dim[j],
-                                              b.dim[j], 0, 0});
-                    }
-                DevBuf d;
-                upload(d, ct, s());
-                int64_t mx = 0;
-                for (auto &t : ct) mx = std::max<int64_t>(mx, (int64_t)t.rows * t.cols);
-                launch_copies(d.as<CopyTask>(), (int)ct.size(), mx, s());
-                HIP_OK(hipStreamSynchronize(s()));
-            }
+            if (it != m->Vd.end() && m->split) scale_env_v(out, ep.Eout, m->bonds[i + 1], Wi.dr, it->second.as<double>());
             HIP_OK(hipStreamSynchronize(s()));
             E = std::move(out);
         }
@@ -367,8 +368,143 @@ struct Driver {
         m->V.clear();
         m->Vd.clear();
         m->split = false;
+        m->icanon = false;
         m->regions.clear();
         m->n_regions = 1;
+    }
+
+    // Inverse canonical gauge (Sec. IV): right-canonical form with the centre
+    // on site 0, then the split of Eqs. eqn:inverse, eqn:isvd at bonds
+    // 1..N-1 in order -- Theta = C_i B_{i+1} = (A Lambda) V (Lambda B), the
+    // left factor stays as psi_i = Lambda_i Gamma_i Lambda_{i+1}, the right one
+    // is the next centre.  Keeps every singular value >= cutoff * lambda_max.
+    // Environments are not kept (the next sweep rebuilds them).
+    int inverse_canonical(double cutoff) {
+        unsplit();
+        envs = false;
+        init();
+        int nfl = 0;
+        for (int i = 0; i + 1 < m->N; ++i) {
+            DevBuf psi = contract(i, nullptr);
+            SvdOut r;
+            svd_truncate_run(ctx, m->bonds[i], m->bonds[i + 2], m->p, psi.as<double>(), 1 << 30, cutoff, prm.eps,
+                             PDMRG_SPLIT, r);
+            m->bonds[i + 1] = r.bnew;
+            m->sites[i] = take(r.left, site_layout(m->bonds[i], r.bnew, m->p).size);
+            m->sites[i + 1] = take(r.right, site_layout(r.bnew, m->bonds[i + 2], m->p).size);
+            m->V[i + 1] = r.V;
+            DevBuf vd;
+            upload(vd, r.V, s());
+            m->Vd[i + 1] = std::move(vd);
+            nfl += r.n_floored;
+            HIP_OK(hipStreamSynchronize(s()));
+        }
+        m->L.clear();
+        m->R.clear();
+        m->L.resize(m->N + 1);
+        m->R.resize(m->N + 1);
+        m->split = true;
+        m->icanon = true;
+        m->ready = false;
+        m->regions.clear();
+        m->n_regions = 1;
+        return nfl;
+    }
+
+    // <O_j> for every site j: one launch of column-segment products
+    // <psi_j[:, s, :], psi_j[:, t, :]> over all sites and charge-conserving
+    // (s, t) with O[s][t] != 0, weighted by O[s][t] on the host in task order.
+    void expect_site(const std::vector<double> &op, double *out) {
+        const int d = m->p.d();
+        std::vector<SegDot> tasks;
+        std::vector<int> site_of;
+        std::vector<double> wt;
+        for (int j = 0; j < m->N; ++j) {
+            const SiteLayout S = site_layout(m->bonds[j], m->bonds[j + 1], m->p);
+            for (int k = 0; k < m->bonds[j].nsec(); ++k)
+                for (int a = 0; a < d; ++a)
+                    for (int b = 0; b < d; ++b) {
+                        const double c = op[(size_t)a * d + b];
+                        const int wa = S.width[(size_t)k * d + a], wb = S.width[(size_t)k * d + b];
+                        if (c == 0.0 || m->p.q[a] != m->p.q[b] || wa == 0 || wb == 0 || S.rows[k] == 0) continue;
+                        tasks.push_back(SegDot{m->sites[j].as<double>() + S.base[k], S.cols[k], S.rows[k],
+                                               S.colo[(size_t)k * d + a], S.colo[(size_t)k * d + b], wa, 0});
+                        site_of.push_back(j);
+                        wt.push_back(c);
+                    }
+        }
+        for (int j = 0; j < m->N; ++j) out[j] = 0.0;
+        if (tasks.empty()) return;
+        std::vector<SegTile> tiles;
+        std::vector<int32_t> t0, g_of;
+        for (size_t t = 0; t < tasks.size(); ++t) {
+            t0.push_back((int32_t)tiles.size());
+            g_of.push_back((int32_t)t);
+            for (int r0 = 0; r0 < tasks[t].rows; r0 += kSegRows) tiles.push_back(SegTile{(int32_t)t, r0});
+        }
+        t0.push_back((int32_t)tiles.size());
+        DevBuf d_tasks, d_tiles, d_t0, d_g, partial, res;
+        upload(d_tasks, tasks, s());
+        upload(d_tiles, tiles, s());
+        upload(d_t0, t0, s());
+        upload(d_g, g_of, s());
+        partial.ensure(tiles.size() * sizeof(double));
+        res.ensure(tasks.size() * sizeof(double));
+        launch_seg_dot_partials(d_tasks.as<SegDot>(), d_tiles.as<SegTile>(), (int)tiles.size(), partial.as<double>(),
+                                s());
+        launch_dot_reduce(partial.as<double>(), d_t0.as<int32_t>(), d_g.as<int32_t>(), (int)tasks.size(),
+                          res.as<double>(), s());
+        std::vector<double> h(tasks.size());
+        HIP_OK(hipMemcpyAsync(h.data(), res.ptr, h.size() * sizeof(double), hipMemcpyDeviceToHost, s()));
+        HIP_OK(hipStreamSynchronize(s()));
+        for (size_t t = 0; t < tasks.size(); ++t) out[site_of[t]] += wt[t] * h[t];
+    }
+
+    // sum_t c_t <A_t(i) B_t(k)>, i < k, from the centres: identity on bond i,
+    // left transfer through psi_i with W_i = [A_t], then through
+    // B_j = V_j psi_j (V applied to the environment on bond j) with the
+    // identity per channel, the last site with W_k = [c_t B_t], and the trace
+    // on bond k+1.
+    double correlator(int i, int k, const MpoSite &Wi, const MpoSite &Wm, const MpoSite &Wk) {
+        const Bond &b0 = m->bonds[i];
+        const EnvLayout E0 = env_l_layout(b0, std::vector<int>{0});
+        DevBuf E(std::max<int64_t>(E0.size, 1) * sizeof(double));
+        std::vector<SqBlock> sq;
+        int mx = 0;
+        for (int j = 0; j < b0.nsec(); ++j) {
+            sq.push_back(SqBlock{E.as<double>() + E0.base[j], b0.dim[j], 0});
+            mx = std::max(mx, b0.dim[j]);
+        }
+        DevBuf d_sq;
+        upload(d_sq, sq, s());
+        launch_set_identity(d_sq.as<SqBlock>(), (int)sq.size(), mx, s());
+        HIP_OK(hipStreamSynchronize(s()));
+        EnvLayout last;
+        for (int j = i; j <= k; ++j) {
+            const MpoSite &W = j == i ? Wi : (j < k ? Wm : Wk);
+            EnvPlan ep;
+            ep.build(1, m->bonds[j], m->bonds[j + 1], m->p, W, s());
+            DevBuf out(std::max<int64_t>(ep.Eout.size, 1) * sizeof(double));
+            ctx->ws_env.ensure((size_t)(std::max<int64_t>(ep.nU1, 1) + std::max<int64_t>(ep.nU2, 1)) * sizeof(double));
+            double *U1 = ctx->ws_env.as<double>();
+            ep.run(GemmPrec::F64, E.ptr, m->sites[j].ptr, out.ptr, U1, U1 + std::max<int64_t>(ep.nU1, 1), s());
+            if (j < k) scale_env_v(out, ep.Eout, m->bonds[j + 1], W.dr, m->Vd.at(j + 1).as<double>());
+            HIP_OK(hipStreamSynchronize(s()));
+            E = std::move(out);
+            last = ep.Eout;
+        }
+        const Bond &bk = m->bonds[k + 1];
+        std::vector<SqBlock> tr;
+        for (int j = 0; j < bk.nsec(); ++j)
+            if (last.rowo[j] >= 0) tr.push_back(SqBlock{E.as<double>() + last.base[j], bk.dim[j], 0});
+        DevBuf d_tr, d_val;
+        upload(d_tr, tr, s());
+        d_val.ensure(sizeof(double));
+        launch_trace_sum(d_tr.as<SqBlock>(), (int)tr.size(), d_val.as<double>(), s());
+        double v = 0.0;
+        HIP_OK(hipMemcpyAsync(&v, d_val.ptr, sizeof(double), hipMemcpyDeviceToHost, s()));
+        HIP_OK(hipStreamSynchronize(s()));
+        return v;
     }
 
     // Measurement sweep: right-canonical form with the centre on site 0, then
@@ -403,6 +539,22 @@ struct Driver {
         m->ready = false;   // centre now on the last site: the next sweep re-canonicalises
     }
 };
+
+// Charge q_s - q_t shared by every nonzero <s|op|t>; 0 for the zero operator.
+int op_charge(const double *op, const Phys &p, const char *who) {
+    const int d = p.d();
+    int q = 0;
+    bool seen = false;
+    for (int a = 0; a < d; ++a)
+        for (int b = 0; b < d; ++b)
+            if (op[a * d + b] != 0.0) {
+                const int c = p.q[a] - p.q[b];
+                PD_REQUIRE(!seen || c == q, PDMRG_EINVAL, std::string(who) + ": operator without a definite charge");
+                q = c;
+                seen = true;
+            }
+    return q;
+}
 
 void check_mpo(const pdmrg_mps *m, const pdmrg_mpo *mpo) {
     PD_REQUIRE(mpo->N == m->N, PDMRG_ESHAPE, "sweep: MPO and MPS lengths differ");
@@ -460,6 +612,9 @@ int mps_set_site(pdmrg_mps *m, int site, const double *host_data, int64_t n) {
     HIP_OK(hipMemcpy(m->sites[site].ptr, host_data, n * sizeof(double), hipMemcpyHostToDevice));
     m->ready = false;
     m->split = false;
+    m->icanon = false;
+    m->V.clear();
+    m->Vd.clear();
     API_CATCH
 }
 
@@ -495,6 +650,7 @@ int sweep(pdmrg_ctx *ctx, pdmrg_mps *m, const pdmrg_mpo *mpo, const pdmrg_sweep_
     const auto t0 = std::chrono::steady_clock::now();
     Driver dr{ctx, m, mpo};
     dr.prm = *p;
+    if (m->icanon) dr.unsplit();   // fold V back before re-canonicalising
     if (!m->ready) dr.init();
     if (p->n_regions != m->n_regions || m->regions.empty()) {
         PD_REQUIRE(!m->split, PDMRG_EINVAL, "sweep: the region count cannot change after the split");
@@ -540,6 +696,89 @@ int grad_mpo(pdmrg_ctx *ctx, pdmrg_mps *m, const pdmrg_mpo *mpo, double *G_dev, 
     dr.prm.eps = 1e-4;
     if (energy) *energy = dr.energy();
     dr.gradients(G_dev, goff);
+    API_CATCH
+}
+
+int mps_inverse_canonical(pdmrg_ctx *ctx, pdmrg_mps *m, double cutoff, double eps, int32_t *n_floored) {
+    API_TRY
+    PD_REQUIRE(ctx && m, PDMRG_EINVAL, "mps_inverse_canonical: null argument");
+    PD_REQUIRE(cutoff >= 0.0 && cutoff < 1.0 && eps >= 0.0 && eps < 1.0, PDMRG_EINVAL,
+               "mps_inverse_canonical: cutoff and eps must lie in [0, 1)");
+    Driver dr{ctx, m, nullptr};
+    dr.prm.eps = eps;
+    const int nfl = dr.inverse_canonical(cutoff);
+    if (n_floored) *n_floored = nfl;
+    API_CATCH
+}
+
+int mps_get_v(const pdmrg_mps *m, int bond, double *V, int64_t cap) {
+    API_TRY
+    PD_REQUIRE(m && V && bond >= 0 && bond <= m->N, PDMRG_EINVAL, "mps_get_v: bad arguments");
+    auto it = m->V.find(bond);
+    PD_REQUIRE(it != m->V.end() && m->split, PDMRG_EINVAL, "mps_get_v: no V on this bond");
+    PD_REQUIRE(cap >= (int64_t)it->second.size(), PDMRG_EINVAL, "mps_get_v: capacity too small");
+    std::copy(it->second.begin(), it->second.end(), V);
+    API_CATCH
+}
+
+int mps_expect_site(pdmrg_ctx *ctx, pdmrg_mps *m, const double *op, double *out) {
+    API_TRY
+    PD_REQUIRE(ctx && m && op && out, PDMRG_EINVAL, "mps_expect_site: null argument");
+    PD_REQUIRE(m->icanon, PDMRG_EINVAL, "mps_expect_site: the MPS is not in the inverse canonical gauge");
+    const int d = m->p.d();
+    Driver dr{ctx, m, nullptr};
+    dr.expect_site(std::vector<double>(op, op + (size_t)d * d), out);
+    API_CATCH
+}
+
+int mps_expect_pairs(pdmrg_ctx *ctx, pdmrg_mps *m, int nterms, const double *coef, const double *opA,
+                     const double *opB, int npairs, const int32_t *site_i, const int32_t *site_k, int concurrent,
+                     double *out) {
+    API_TRY
+    PD_REQUIRE(ctx && m && coef && opA && opB && out && nterms >= 1 && npairs >= 0 && (npairs == 0 || (site_i && site_k)),
+               PDMRG_EINVAL, "mps_expect_pairs: bad arguments");
+    PD_REQUIRE(m->icanon, PDMRG_EINVAL, "mps_expect_pairs: the MPS is not in the inverse canonical gauge");
+    for (int p = 0; p < npairs; ++p)
+        PD_REQUIRE(site_i[p] >= 0 && site_i[p] < site_k[p] && site_k[p] < m->N, PDMRG_EINVAL,
+                   "mps_expect_pairs: each pair needs 0 <= i < k < N");
+    const int d = m->p.d(), T = nterms;
+    MpoSite Wi, Wm, Wk;
+    Wi.Dl = 1, Wi.Dr = T, Wi.d = d;
+    Wm.Dl = T, Wm.Dr = T, Wm.d = d;
+    Wk.Dl = T, Wk.Dr = 1, Wk.d = d;
+    Wi.W.assign((size_t)d * d * T, 0.0);
+    Wm.W.assign((size_t)T * d * d * T, 0.0);
+    Wk.W.assign((size_t)T * d * d, 0.0);
+    std::vector<int> deltas(T);
+    for (int t = 0; t < T; ++t) {
+        const double *A = opA + (size_t)t * d * d, *B = opB + (size_t)t * d * d;
+        deltas[t] = op_charge(A, m->p, "mps_expect_pairs");
+        const int qb = op_charge(B, m->p, "mps_expect_pairs");
+        bool bz = true;
+        for (int e = 0; e < d * d; ++e) bz = bz && B[e] == 0.0;
+        PD_REQUIRE(bz || qb == -deltas[t], PDMRG_EINVAL, "mps_expect_pairs: the charges of A_t and B_t must cancel");
+        for (int a = 0; a < d; ++a)
+            for (int b = 0; b < d; ++b) {
+                Wi.W[((size_t)a * d + b) * T + t] = A[a * d + b];
+                Wk.W[(((size_t)t * d + a) * d + b)] = coef[t] * B[a * d + b];
+            }
+        for (int a = 0; a < d; ++a) Wm.W[(((size_t)t * d + a) * d + a) * T + t] = 1.0;
+    }
+    Wi.dl = {0};
+    Wi.dr = deltas;
+    Wm.dl = deltas;
+    Wm.dr = deltas;
+    Wk.dl = deltas;
+    Wk.dr = {0};
+    Driver dr{ctx, m, nullptr};
+    dr.prm.concurrent = concurrent ? 1 : 0;
+    const int njobs = std::min(npairs, 8);
+    std::vector<std::function<void(Driver &)>> jobs;
+    for (int q = 0; q < njobs; ++q)
+        jobs.push_back([=, &Wi, &Wm, &Wk](Driver &d) {
+            for (int p = q; p < npairs; p += njobs) out[p] = d.correlator(site_i[p], site_k[p], Wi, Wm, Wk);
+        });
+    dr.run_jobs(jobs);
     API_CATCH
 }
 

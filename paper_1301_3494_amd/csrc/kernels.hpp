@@ -168,4 +168,28 @@ void launch_scale_by_inv_sqrt(const double *x, const double *nrm2, double *y, in
 // with c[0] >= 0.
 void launch_small_eig(const double *G, int k, int ld, double *theta_out, double *c_out, hipStream_t s);
 
+// ---------------------------------------------------------------- local measurements
+// Frobenius product of two column segments of one row-major block:
+// sum_{r < rows, c < width} x[r * ld + ca + c] * x[r * ld + cb + c].
+struct SegDot {
+    const double *x;
+    int32_t ld, rows, ca, cb, width, pad_;
+};
+// Rows [r0, r0 + kSegRows) of task `task`.
+constexpr int kSegRows = 16;
+struct SegTile {
+    int32_t task, r0;
+};
+// partial[t] = tile t's share (fixed-order tree); reduce with launch_dot_reduce.
+void launch_seg_dot_partials(const SegDot *tasks, const SegTile *tiles, int ntiles, double *partial, hipStream_t s);
+// A square row-major block of n x n doubles.
+struct SqBlock {
+    double *p;
+    int32_t n, pad_;
+};
+// Every block set to the identity.
+void launch_set_identity(const SqBlock *blocks, int nblocks, int max_n, hipStream_t s);
+// *out = sum over the blocks, in order, of their traces (one workgroup).
+void launch_trace_sum(const SqBlock *blocks, int nblocks, double *out, hipStream_t s);
+
 }  // namespace pdmrg

@@ -91,3 +91,40 @@ def golden(key):
     import json
     with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "exact_energies.json")) as f:
         return json.load(f)[key]
+
+
+# ---------------------------------------------------------------- brute force on dense states
+def dense_state(sites, bonds, N, V=None):
+    """Brute-force contraction of an MPS into the 2^N amplitudes, index
+    sum_i bit_i 2^i with bit_i = 1 for site i up (s = 1); V (optional) is
+    applied on the bonds that carry one."""
+    part = {0: np.ones((1, 1))}
+    for j in range(N):
+        new = {}
+        rows = 1 << j
+        for (qa, s), X in sites[j].items():
+            if qa not in part:
+                continue
+            qb = qa + (-1, 1)[s]
+            blk = part[qa] @ X
+            tgt = new.setdefault(qb, np.zeros((2 * rows, X.shape[1])))
+            tgt[s * rows:(s + 1) * rows] += blk
+        if V is not None and (j + 1) in V:
+            new = {q: blk * V[j + 1][q][None, :] for q, blk in new.items()}
+        part = new
+    (q, vec), = part.items()
+    return vec[:, 0]
+
+
+def dense_sz(psi, N, j):
+    bits = (np.arange(psi.size) >> j) & 1
+    return float(np.sum(psi ** 2 * np.where(bits == 1, 0.5, -0.5)))
+
+
+def dense_exchange(psi, N, i, k):
+    idx = np.arange(psi.size)
+    bi, bk = (idx >> i) & 1, (idx >> k) & 1
+    zz = np.sum(psi ** 2 * np.where(bi == bk, 0.25, -0.25))
+    flip = idx ^ ((1 << i) | (1 << k))
+    xy = 0.5 * np.sum(np.where(bi != bk, psi * psi[flip], 0.0))
+    return float(zz + xy)
