@@ -202,6 +202,18 @@ def oracle_steps(wl, svd_bond):
     pg = synth.random_site_blocks(bonds[c + 1], bonds[c + 2], PQ, rng)
     out["grad_site_ms"] = round(1e3 * _otimed(lambda: og.site_gradient(Lg, Rg, pg, PQ, mpo.deltas[c + 1],
                                                                        mpo.deltas[c + 2])), 2)
+    # local measurements from the centres (inverse canonical gauge): one
+    # centre-column exchange at snake distance 2 Ly - 1 and <S^z> on all sites
+    from oracle import gauge as ogauge, models as omodels
+    N = wl["N"]
+    psi = [synth.random_site_blocks(bonds[j], bonds[j + 1], PQ, rng) for j in range(N)]
+    Vr = {b: {q: 0.5 + rng.random(d) for q, d in bonds[b].items()} for b in range(1, N)}
+    ic = ogauge.InverseCanonical([OB(b) for b in bonds], psi, Vr, Vr, PQ, 0)
+    ex = ogauge.heisenberg_exchange(omodels.OPS)
+    i0, k0 = 16, 23
+    out["measure_pair_ms"] = round(1e3 * _otimed(lambda: ogauge.correlator(ic, i0, k0, ex), budget_s=2.0), 1)
+    out["measure_sites_ms"] = round(1e3 * _otimed(lambda: [ogauge.expect_site(ic, j, omodels.OPS["Sz"])
+                                                           for j in range(N)]), 2)
     return out
 
 
@@ -359,13 +371,14 @@ def cpu_baseline(wl, flops, budget_s=12.0):
                       "%.3f s each" % (n, dt)}
 
 
-def sweep_leg(ctx, pl, synth, torch, m=1024, regions=4, timed=2, concurrent=True):
+def sweep_leg(ctx, pl, synth, torch, m=1024, regions=4, timed=2, concurrent=True, keep=None):
     """Second half of the metric: wall seconds of a real-space parallel sweep
     (Sec. II, Fig. 4) on the 8 x 4 cylinder at bond dimension m, FP64 path
     against the mixed path (FP32 MFMA H_eff with FP64 Davidson refinement),
     both from the same seeded MPS through the same schedule: one serial
     warm-up sweep and the split sweep (untimed), then `timed` parallel sweeps
-    with the regions on their own streams."""
+    with the regions on their own streams.  keep (a dict): receives the FP64
+    state and its MPO instead of freeing them."""
     Lx, Ly, seed = 8, 4, 2
     mpo = pl.Mpo("square", Lx, Ly, (1.0, 1.0))
     bonds, sites = synth.random_mps(Lx * Ly, m, seed)
@@ -384,7 +397,10 @@ def sweep_leg(ctx, pl, synth, torch, m=1024, regions=4, timed=2, concurrent=True
             secs.append(time.perf_counter() - t0)
         res[name] = dict(seconds=sum(secs) / len(secs), energy=rep["energy"], n_matvec=rep["n_matvec"],
                          seconds_heff=rep["seconds_heff"], max_trunc=rep["max_trunc"])
-        mps.free()
+        if keep is not None and name == "f64":
+            keep.update(mps=mps, mpo=mpo, Lx=Lx, Ly=Ly)
+        else:
+            mps.free()
         print("bench: sweep leg %s %.3f s/sweep E=%.15f" % (name, res[name]["seconds"], rep["energy"]),
               file=sys.stderr, flush=True)
     e64, emx = res["f64"]["energy"], res["mixed"]["energy"]
@@ -400,6 +416,94 @@ def sweep_leg(ctx, pl, synth, torch, m=1024, regions=4, timed=2, concurrent=True
         "seconds_heff_f64": round(res["f64"]["seconds_heff"], 4),
         "seconds_heff_mixed": round(res["mixed"]["seconds_heff"], 4),
         "energy_f64": e64, "energy_mixed": emx, "rel_energy_diff": rel, "meets_1e-9": rel <= 1e-9,
+    }
+
+
+SPIN_OPS = {
+    "Sz": [[-0.5, 0.0], [0.0, 0.5]],
+    "Sp": [[0.0, 0.0], [1.0, 0.0]],   # |up><down| (local basis: down, up)
+    "Sm": [[0.0, 1.0], [0.0, 0.0]],
+}
+
+
+def cylinder_sites(Lx, Ly):
+    """Snake numbering of the cylinder (column by column, alternating)."""
+    return lambda x, y: x * Ly + (y if x % 2 == 0 else Ly - 1 - y)
+
+
+def measure_leg(ctx, pl, np, torch, state, reps=5):
+    """Inverse canonical gauge (Sec. IV) of the swept FP64 state, then local
+    measurements from the orthogonality centres: <S^z_j> on all sites (one
+    launch) and <S_i . S_k> on every Hamiltonian bond plus the centre-column
+    pairs of the dimer order parameter D_x, the pairs spread over concurrent
+    streams.  The pair transfers are FP64 environment updates; their
+    algorithmic flops come from env_update_info."""
+    mps, mpo, Lx, Ly = state["mps"], state["mpo"], state["Lx"], state["Ly"]
+    site = cylinder_sites(Lx, Ly)
+    E = mps.energy(mpo)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    nfl = mps.inverse_canonical()
+    torch.cuda.synchronize()
+    t_conv = time.perf_counter() - t0
+    ops = {k: np.array(v) for k, v in SPIN_OPS.items()}
+    exch = [(1.0, ops["Sz"], ops["Sz"]), (0.5, ops["Sp"], ops["Sm"]), (0.5, ops["Sm"], ops["Sp"])]
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        sz = mps.expect_site(ops["Sz"])
+    t_site = (time.perf_counter() - t0) / reps
+    hb = []
+    for x in range(Lx):
+        for y in range(Ly):
+            if x + 1 < Lx:
+                hb.append((site(x, y), site(x + 1, y)))
+            hb.append((site(x, y), site(x, (y + 1) % Ly)))
+    hb = sorted({(min(a, b), max(a, b)) for a, b in hb})
+    xc = Lx // 2
+    dx = [[(site(xc + o, y), site(xc + o + 1, y)) for y in range(Ly)] for o in (-1, 0, 1)]
+    dx = [[(min(a, b), max(a, b)) for a, b in row] for row in dx]
+    pairs = hb + [p for row in dx for p in row]
+    times = {}
+    for conc in (True, False):
+        t0 = time.perf_counter()
+        vals = mps.expect_pairs(exch, pairs, concurrent=conc)
+        times[conc] = time.perf_counter() - t0
+    bonds = [pl.Bond(mps.bond(b)) for b in range(mps.N + 1)]
+    P = pl.Phys((-1, 1))
+    deltas = [0, 2, -2]
+    Wi = np.zeros((1, 2, 2, 3))
+    Wm = np.zeros((3, 2, 2, 3))
+    Wk = np.zeros((3, 2, 2, 1))
+    for t, (c, A, B) in enumerate(exch):
+        Wi[0, :, :, t] = A
+        Wk[t, :, :, 0] = c * B
+        Wm[t, :, :, t] = np.eye(2)
+    Si, Sm_, Sk = pl.MpoSite(Wi, [0], deltas), pl.MpoSite(Wm, deltas, deltas), pl.MpoSite(Wk, deltas, [0])
+    flops, steps = 0.0, 0
+    for i, k in pairs:
+        for j in range(i, k + 1):
+            W = Si if j == i else (Sm_ if j < k else Sk)
+            flops += pl.env_update_info(1, bonds[j], bonds[j + 1], P, W)[0]
+            steps += 1
+    nh = len(hb)
+    e_bonds = float(np.sum(vals[:nh]))
+    row = [vals[nh + r * Ly: nh + (r + 1) * Ly] for r in range(3)]
+    Dx = float(np.mean(row[1] - 0.5 * row[0] - 0.5 * row[2]))
+    rate = flops / times[True] / 1e12
+    print("bench: measure leg conversion %.3f s, sites %.3f ms, %d pairs %.1f ms (%.2f TFLOP/s), "
+          "sum of bond energies %.12f vs E %.12f" % (t_conv, 1e3 * t_site, len(pairs), 1e3 * times[True], rate,
+                                                     e_bonds, E), file=sys.stderr, flush=True)
+    mps.free()
+    return {
+        "workload": "inverse canonical gauge + local measurements of the swept 8x4 m=1024 FP64 state",
+        "conversion_s": round(t_conv, 4), "n_floored": nfl,
+        "sites_ms": round(1e3 * t_site, 3), "sum_sz": float(np.sum(sz)),
+        "pairs": len(pairs), "pairs_ms_concurrent": round(1e3 * times[True], 2),
+        "pairs_ms_sequential": round(1e3 * times[False], 2),
+        "pair_env_steps": steps, "pair_flops": flops, "pair_tflops": round(rate, 3),
+        "pair_pct_fp64_peak": round(100 * rate / 78.6, 2),
+        "sum_bond_energies": e_bonds, "energy": E, "rel_diff": abs(e_bonds - E) / abs(E),
+        "Dx_centre_column": Dx,
     }
 
 
@@ -510,7 +614,9 @@ def main():
     if not args.no_large:
         out["large_bonds"] = large_bond_rates(ctx, pl, synth, np, torch)
     if not args.no_sweep:
-        out["sweep"] = sweep_leg(ctx, pl, synth, torch, concurrent=not args.sequential_regions)
+        state = {}
+        out["sweep"] = sweep_leg(ctx, pl, synth, torch, concurrent=not args.sequential_regions, keep=state)
+        out["measure"] = measure_leg(ctx, pl, np, torch, state)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, info["flops"])
         if not args.no_steps:
