@@ -28,8 +28,6 @@ namespace pdmrg {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
-typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
-typedef unsigned short us8 __attribute__((ext_vector_type(8)));
 
 constexpr int NT = 256;
 
@@ -229,119 +227,180 @@ __global__ __launch_bounds__(NT) void gemm_kmajor(Slots slots, const GemmItem *_
 }
 
 // ---------------------------------------------------------------- BF16 x3
-__device__ __forceinline__ unsigned short bf16_rne(float x) {
-    // bfloat16 = upper 16 bits of binary32, rounded to nearest even
-    unsigned int u = __float_as_uint(x);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return (unsigned short)(u >> 16);
-}
-__device__ __forceinline__ float bf16_to_f32(unsigned short h) {
-    return __uint_as_float(((unsigned int)h) << 16);
-}
+// Same tiles, buffer loads, double-buffered LDS and single barrier per K-step
+// as the FP32 kernel; each thread stages pairs of consecutive k of one row
+// (column) of A (B), splits them in registers into bf16 hi and lo halves
+// (x = hi + lo, both rounded to nearest even by the hardware's packed
+// convert) and stores each half with one 4-byte LDS write.  The K-contiguous
+// LDS rows feed v_mfma_f32_16x16x16_bf16 with 8-byte reads; per 16 x 16 block
+// and K-step the products lo*hi', hi*lo', hi*hi' accumulate in FP32, the
+// small terms first.  K steps of 16 keep the LDS at 2 x (BM + BN) x 80 bytes,
+// so several workgroups share a CU and hide each other's load latency (the
+// short K loops of these contractions are latency-bound, not MFMA-bound).
+typedef float f2v __attribute__((ext_vector_type(2)));
+typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
+typedef short s4v __attribute__((ext_vector_type(4)));
 
-template <typename TC, bool TA, bool TB>
+template <typename TC, bool TA, bool TB, int BM, int BN, int WGM>
 __global__ __launch_bounds__(NT) void gemm_bf16x3(Slots slots, const GemmItem *__restrict__ items,
                                                   const GemmSeg *__restrict__ segs,
                                                   const GemmTile *__restrict__ tiles,
                                                   const int64_t *__restrict__ rowoff, int ntiles) {
-    constexpr int BM = 64, BN = 64;
-    constexpr int BK = 32, LD = BK + 8;   // 80-byte LDS rows keep 16-byte alignment
+    constexpr int WGN = 4 / WGM;
+    constexpr int BK = 16, LDK = BK + 4;          // 40-byte LDS rows: 8-byte aligned reads
+    constexpr int KG = BK / 2;                    // k pairs per row
+    constexpr int NGA = BM * KG / NT, NGB = BN * KG / NT;   // groups per thread and step
+    constexpr int SM = BM / WGM, SN = BN / WGN;
+    constexpr int WBM = SM / 16, WBN = SN / 16;
+    static_assert(NGA >= 1 && NGB >= 1 && WBM >= 1 && WBN >= 1, "tile shape");
+    static_assert((BM * KG) % NT == 0 && (BN * KG) % NT == 0, "tile shape");
     const int t = map_tile(ntiles);
     if (t >= ntiles) return;
     const GemmTile tile = tiles[t];
     const GemmItem it = items[tile.item];
-    __shared__ __attribute__((aligned(16))) unsigned short Ah[BM][LD], Al[BM][LD];
-    __shared__ __attribute__((aligned(16))) unsigned short Bh[BN][LD], Bl[BN][LD];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+    __shared__ __attribute__((aligned(16))) unsigned short Ah[2][BM][LDK], Al[2][BM][LDK];
+    __shared__ __attribute__((aligned(16))) unsigned short Bh[2][BN][LDK], Bl[2][BN][LDK];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wm = (wave / WGN) * SM, wn = (wave % WGN) * SN;
     const int m0 = tile.m0, n0 = tile.n0;
-    f4 acc[2][2];
+    f4 acc[WBM][WBN];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < WBM; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = f4{0, 0, 0, 0};
+        for (int j = 0; j < WBN; ++j) acc[i][j] = f4{0, 0, 0, 0};
 
-    // 8 elements of A and of B per thread and K-step
-    const int a_r = TA ? (tid & 7) * 8 : tid >> 2;
-    const int a_k = TA ? tid >> 3 : (tid & 3) * 8;
-    const int b_n = TB ? tid >> 2 : (tid & 7) * 8;
-    const int b_k = TB ? (tid & 3) * 8 : tid >> 3;
-
-    float ra[8], rb[8];
-    auto load = [&](const GemmSeg &sg, int k0) {
-        const float *A = static_cast<const float *>(slots.p[sg.a_slot]) + sg.a_off;
-        const float *B = static_cast<const float *>(slots.p[sg.b_slot]) + sg.b_off;
+    // group g of this thread: row (column) index and first k.  K-contiguous
+    // operands: 8 consecutive threads cover the 16 k of one row; otherwise
+    // consecutive threads take consecutive rows (coalesced per k).
+    auto a_grp = [&](int g, int &m, int &k) {
+        if (TA) { m = tid % BM; k = 2 * (tid / BM + g * (NT / BM)); }
+        else    { k = 2 * (tid % KG); m = tid / KG + g * (NT / KG); }
+    };
+    auto b_grp = [&](int g, int &n, int &k) {
+        if (TB) { k = 2 * (tid % KG); n = tid / KG + g * (NT / KG); }
+        else    { n = tid % BN; k = 2 * (tid / BN + g * (NT / BN)); }
+    };
+    float ra[NGA][2], rb[NGB][2];
+    int K = 0, lda = 0, ldb = 0;
+    __amdgpu_buffer_rsrc_t rA, rB;
+    auto set_seg = [&](const GemmSeg &sg) {
+        K = __builtin_amdgcn_readfirstlane(sg.K);
+        lda = __builtin_amdgcn_readfirstlane(sg.lda);
+        ldb = __builtin_amdgcn_readfirstlane(sg.ldb);
+        rA = operand_rsrc(static_cast<const float *>(slots.p[sg.a_slot]) + sg.a_off);
+        rB = operand_rsrc(static_cast<const float *>(slots.p[sg.b_slot]) + sg.b_off);
+    };
+    auto load = [&](int k0) {
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int gm = m0 + a_r + (TA ? u : 0), gk = k0 + a_k + (TA ? 0 : u);
-            ra[u] = (gm < it.M && gk < sg.K)
-                        ? (TA ? A[(int64_t)gk * sg.lda + gm] : A[(int64_t)gm * sg.lda + gk])
-                        : 0.f;
-            const int gn = n0 + b_n + (TB ? 0 : u), gkb = k0 + b_k + (TB ? u : 0);
-            rb[u] = (gn < it.N && gkb < sg.K)
-                        ? (TB ? B[(int64_t)gn * sg.ldb + gkb] : B[(int64_t)gkb * sg.ldb + gn])
-                        : 0.f;
+        for (int g = 0; g < NGA; ++g) {
+            int m, k;
+            a_grp(g, m, k);
+            const int gm = m0 + m;
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int gk = k0 + k + u;
+                const unsigned off = TA ? (unsigned)(gk * lda + gm) : (unsigned)(gm * lda + gk);
+                ra[g][u] = buf_load(rA, (gm < it.M && gk < K) ? off * 4u : kOutOfRange, float());
+            }
+        }
+#pragma unroll
+        for (int g = 0; g < NGB; ++g) {
+            int n, k;
+            b_grp(g, n, k);
+            const int gn = n0 + n;
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int gk = k0 + k + u;
+                const unsigned off = TB ? (unsigned)(gn * ldb + gk) : (unsigned)(gk * ldb + gn);
+                rb[g][u] = buf_load(rB, (gn < it.N && gk < K) ? off * 4u : kOutOfRange, float());
+            }
+        }
+    };
+    // split 2 floats into packed hi and lo halves (one 32-bit word each)
+    auto split2 = [](const float (&x)[2], unsigned &hi, unsigned &lo) {
+        const f2v x0 = {x[0], x[1]};
+        const bf2 h = __builtin_convertvector(x0, bf2);
+        const bf2 l = __builtin_convertvector(x0 - __builtin_convertvector(h, f2v), bf2);
+        hi = __builtin_bit_cast(unsigned, h);
+        lo = __builtin_bit_cast(unsigned, l);
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int g = 0; g < NGA; ++g) {
+            int m, k;
+            a_grp(g, m, k);
+            unsigned hi, lo;
+            split2(ra[g], hi, lo);
+            *reinterpret_cast<unsigned *>(&Ah[buf][m][k]) = hi;
+            *reinterpret_cast<unsigned *>(&Al[buf][m][k]) = lo;
+        }
+#pragma unroll
+        for (int g = 0; g < NGB; ++g) {
+            int n, k;
+            b_grp(g, n, k);
+            unsigned hi, lo;
+            split2(rb[g], hi, lo);
+            *reinterpret_cast<unsigned *>(&Bh[buf][n][k]) = hi;
+            *reinterpret_cast<unsigned *>(&Bl[buf][n][k]) = lo;
         }
     };
 
     int sidx = 0, k0 = 0;
     while (sidx < it.nseg && segs[it.seg0 + sidx].K <= 0) ++sidx;
-    GemmSeg sg;
+    int buf = 0;
     if (sidx < it.nseg) {
-        sg = segs[it.seg0 + sidx];
-        load(sg, 0);
+        set_seg(segs[it.seg0 + sidx]);
+        load(0);
+        store(0);
     }
+    __syncthreads();
+    const int r16 = lane & 15, kq = (lane >> 4) * 4;
     while (sidx < it.nseg) {
-        __syncthreads();
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const unsigned short ha = bf16_rne(ra[u]);
-            const unsigned short la = bf16_rne(ra[u] - bf16_to_f32(ha));
-            const unsigned short hb = bf16_rne(rb[u]);
-            const unsigned short lb = bf16_rne(rb[u] - bf16_to_f32(hb));
-            if (TA) { Ah[a_r + u][a_k] = ha; Al[a_r + u][a_k] = la; }
-            else    { Ah[a_r][a_k + u] = ha; Al[a_r][a_k + u] = la; }
-            if (TB) { Bh[b_n][b_k + u] = hb; Bl[b_n][b_k + u] = lb; }
-            else    { Bh[b_n + u][b_k] = hb; Bl[b_n + u][b_k] = lb; }
-        }
-        __syncthreads();
         k0 += BK;
-        if (k0 >= sg.K) {
+        if (k0 >= K) {
             k0 = 0;
             ++sidx;
             while (sidx < it.nseg && segs[it.seg0 + sidx].K <= 0) ++sidx;
-            if (sidx < it.nseg) sg = segs[it.seg0 + sidx];
+            if (sidx < it.nseg) set_seg(segs[it.seg0 + sidx]);
         }
-        if (sidx < it.nseg) load(sg, k0);
-        const int r = lane & 15, kq = (lane >> 4) * 8;
-        bf8 ah[2], al[2], bh[2], bl[2];
+        const bool more = sidx < it.nseg;
+        if (more) load(k0);
+        s4v ah[WBM], al[WBM], bh[WBN], bl[WBN];
 #pragma unroll
-        for (int i = 0; i < 2; ++i) {
-            ah[i] = __builtin_bit_cast(bf8, *reinterpret_cast<const us8 *>(&Ah[wm + i * 16 + r][kq]));
-            al[i] = __builtin_bit_cast(bf8, *reinterpret_cast<const us8 *>(&Al[wm + i * 16 + r][kq]));
-            bh[i] = __builtin_bit_cast(bf8, *reinterpret_cast<const us8 *>(&Bh[wn + i * 16 + r][kq]));
-            bl[i] = __builtin_bit_cast(bf8, *reinterpret_cast<const us8 *>(&Bl[wn + i * 16 + r][kq]));
+        for (int i = 0; i < WBM; ++i) {
+            ah[i] = *reinterpret_cast<const s4v *>(&Ah[buf][wm + i * 16 + r16][kq]);
+            al[i] = *reinterpret_cast<const s4v *>(&Al[buf][wm + i * 16 + r16][kq]);
         }
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < WBN; ++j) {
+            bh[j] = *reinterpret_cast<const s4v *>(&Bh[buf][wn + j * 16 + r16][kq]);
+            bl[j] = *reinterpret_cast<const s4v *>(&Bl[buf][wn + j * 16 + r16][kq]);
+        }
 #pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+        for (int i = 0; i < WBM; ++i)
+#pragma unroll
+            for (int j = 0; j < WBN; ++j) {
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al[i], bh[j], acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[i], bl[j], acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[i], bh[j], acc[i][j], 0, 0, 0);
             }
+        if (more) store(buf ^ 1);
+        __syncthreads();
+        buf ^= 1;
     }
+    // v_mfma_f32_16x16x16_bf16 result: register r of lane l is row 4 (l / 16) + r, column l % 16
     TC *C = static_cast<TC *>(const_cast<void *>(slots.p[it.c_slot])) + it.c_off;
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < WBM; ++i)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int gm = m0 + wm + i * 16 + (lane >> 4) * 4 + r;
             if (gm >= it.M) continue;
             TC *Cr = C + c_row(it, rowoff, gm);
 #pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                const int gn = n0 + wn + j * 16 + (lane & 15);
+            for (int j = 0; j < WBN; ++j) {
+                const int gn = n0 + wn + j * 16 + r16;
                 if (gn < it.N) Cr[gn] = (TC)acc[i][j][r];
             }
         }
@@ -385,12 +444,25 @@ static void dispatch_kmajor(TileShape shape, bool ta, bool tb, dim3 g, hipStream
     }
 }
 
+template <typename TC, int BM, int BN, int WGM>
+static void dispatch_bf16_shape(bool ta, bool tb, dim3 g, hipStream_t s, const GemmArgs &a) {
+    if (!ta && !tb) hipLaunchKernelGGL((gemm_bf16x3<TC, false, false, BM, BN, WGM>), g, dim3(NT), 0, s, a.sl, a.it, a.sg, a.tl, a.ro, a.n);
+    else if (ta && !tb) hipLaunchKernelGGL((gemm_bf16x3<TC, true, false, BM, BN, WGM>), g, dim3(NT), 0, s, a.sl, a.it, a.sg, a.tl, a.ro, a.n);
+    else if (!ta && tb) hipLaunchKernelGGL((gemm_bf16x3<TC, false, true, BM, BN, WGM>), g, dim3(NT), 0, s, a.sl, a.it, a.sg, a.tl, a.ro, a.n);
+    else hipLaunchKernelGGL((gemm_bf16x3<TC, true, true, BM, BN, WGM>), g, dim3(NT), 0, s, a.sl, a.it, a.sg, a.tl, a.ro, a.n);
+}
+
+// BF16x3 runs the four base tile shapes; the half / quarter-depth variants
+// map to their base shape (its K step is fixed at 16).
 template <typename TC>
-static void dispatch_bf16(bool ta, bool tb, dim3 g, hipStream_t s, const GemmArgs &a) {
-    if (!ta && !tb) hipLaunchKernelGGL((gemm_bf16x3<TC, false, false>), g, dim3(NT), 0, s, a.sl, a.it, a.sg, a.tl, a.ro, a.n);
-    else if (ta && !tb) hipLaunchKernelGGL((gemm_bf16x3<TC, true, false>), g, dim3(NT), 0, s, a.sl, a.it, a.sg, a.tl, a.ro, a.n);
-    else if (!ta && tb) hipLaunchKernelGGL((gemm_bf16x3<TC, false, true>), g, dim3(NT), 0, s, a.sl, a.it, a.sg, a.tl, a.ro, a.n);
-    else hipLaunchKernelGGL((gemm_bf16x3<TC, true, true>), g, dim3(NT), 0, s, a.sl, a.it, a.sg, a.tl, a.ro, a.n);
+static void dispatch_bf16(TileShape shape, bool ta, bool tb, dim3 g, hipStream_t s, const GemmArgs &a) {
+    switch (shape) {
+        case TileShape::T128x32: case TileShape::T128x32_K16: case TileShape::T128x32_K8:
+            dispatch_bf16_shape<TC, 128, 32, 4>(ta, tb, g, s, a); break;
+        case TileShape::T32x128: dispatch_bf16_shape<TC, 32, 128, 1>(ta, tb, g, s, a); break;
+        case TileShape::T128x128: dispatch_bf16_shape<TC, 128, 128, 2>(ta, tb, g, s, a); break;
+        default: dispatch_bf16_shape<TC, 64, 64, 2>(ta, tb, g, s, a); break;
+    }
 }
 
 void launch_gemm(GemmPrec prec, TileShape shape, bool ta, bool tb, bool c_is_f64, const Slots &slots,
@@ -409,8 +481,8 @@ void launch_gemm(GemmPrec prec, TileShape shape, bool ta, bool tb, bool c_is_f64
             else dispatch_kmajor<float, float>(shape, ta, tb, grid, s, a);
             break;
         case GemmPrec::BF16X3:
-            if (c_is_f64) dispatch_bf16<double>(ta, tb, grid, s, a);
-            else dispatch_bf16<float>(ta, tb, grid, s, a);
+            if (c_is_f64) dispatch_bf16<double>(shape, ta, tb, grid, s, a);
+            else dispatch_bf16<float>(shape, ta, tb, grid, s, a);
             break;
     }
 }

@@ -484,8 +484,10 @@ void HeffPlan::build(const Bond &bl_, const Bond &br_, const Phys &p_, const Mpo
             diag_groups.push_back((int32_t)diag_terms.size());
         }
 
-    // tile shapes (the BF16x3 kernel has 64 x 64 tiles only)
-    if (prec == PDMRG_BF16X3) g1.shapes_allowed = g3.shapes_allowed = 1u << (int)TileShape::T64x64;
+    // tile shapes (the BF16x3 kernel runs the four base shapes, K step 32)
+    if (prec == PDMRG_BF16X3)
+        g1.shapes_allowed = g3.shapes_allowed = (1u << (int)TileShape::T64x64) | (1u << (int)TileShape::T128x32) |
+                                                (1u << (int)TileShape::T32x128) | (1u << (int)TileShape::T128x128);
     g1.pick_tile();
     g3.pick_tile();
     const std::vector<int64_t> sz = {X.size, X.size, Lt.size, Rt.size, nT1, nT2, 0};

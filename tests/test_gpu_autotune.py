@@ -54,3 +54,37 @@ def test_autotuned_heff_matches_model_plan(case, prec):
     assert np.array_equal(y1, y2)
     tol = {"f64": 1e-12, "f32": 1e-5, "bf16x3": 1e-5}[prec]
     assert np.linalg.norm(y1 - y0) <= tol * np.linalg.norm(y0)
+
+
+@pytest.mark.parametrize("shape", [0, 1, 2, 3])
+def test_bf16x3_every_tile_shape(case, shape, tmp_path):
+    """Each tile shape of the BF16x3 kernel (64x64, 128x32, 32x128, 128x128),
+    forced through an imported tuning entry, against the FP64 product."""
+    import torch
+    from paper_1301_3494_amd import _lib as pl
+    B1, B2, P, W1, W2, L, R, x = case
+    y0 = _apply(pl, torch, 0, pl.F64, case)
+    ctx = pl.Context(0)
+    pl.set_autotune(ctx, 1)
+    pl.Heff(ctx, B1, B2, P, W1, W2, L, R, pl.BF16X3).free()      # creates this operator's entry
+    f = tmp_path / "plans.tsv"
+    pl.autotune_export(str(f))
+    rows = [r.split("\t") for r in f.read_text().splitlines() if r]
+    mine = [r[0] for r in rows if r[0].split("|")[1] == str(pl.BF16X3)]
+    assert mine
+    f.write_text("".join("%s\t%d\t%d\t%d\n" % (k, shape, shape, 2) for k in mine))
+    pl.autotune_import(str(f))
+    op = pl.Heff(ctx, B1, B2, P, W1, W2, L, R, pl.BF16X3)
+    info = op.info()
+    names = ["64x64", "128x32", "32x128", "128x128"]
+    say(f"bf16x3 forced shape {names[shape]}: plan {info['shape_Lpsi']} / {info['shape_R']}, parts {info['splitk_parts']}")
+    assert info["shape_Lpsi"] == names[shape] and info["shape_R"] == names[shape]
+    y = torch.empty_like(x)
+    op.apply(x, y)
+    torch.cuda.synchronize()
+    y = y.cpu().numpy()
+    op.free()
+    ctx.close()
+    err = np.linalg.norm(y - y0) / np.linalg.norm(y0)
+    say(f"bf16x3 shape {names[shape]} rel err {err:.3e}")
+    assert err <= 1e-5
