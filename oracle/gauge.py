@@ -153,3 +153,24 @@ def oc_residuals(ic):
             e = max(e, float(np.max(np.abs(G - np.diag(lam_l[qa] ** 2)))))
         out.append(e)
     return out
+
+
+def order_dx(ic, Lx, Ly, ops, snake):
+    """Columnar dimer order of the J-Q2 study (Sec. III): the average over y of
+    <S_r.S_{r+x}> - <S_{r-x}.S_r>/2 - <S_{r+x}.S_{r+2x}>/2 at r = (Lx/2 - 1, y)
+    (zero-based: the centre bond of an even-length cylinder)."""
+    xc = Lx // 2 - 1
+    ex = heisenberg_exchange(ops)
+
+    def bond(x, y):
+        a, b = snake(x, y, Ly), snake(x + 1, y, Ly)
+        return correlator(ic, min(a, b), max(a, b), ex)
+    return sum(bond(xc, y) - 0.5 * bond(xc - 1, y) - 0.5 * bond(xc + 1, y) for y in range(Ly)) / Ly
+
+
+def order_mz(ic, Lx, Ly, ops, snake, sublattice):
+    """Sublattice magnetisation of the triangular study (Sec. III): <S^z>
+    averaged over the sites (xc, y) of sublattice 0, xc = (Lx - 1)//2."""
+    xc = (Lx - 1) // 2
+    vals = [expect_site(ic, snake(xc, y, Ly), ops["Sz"]) for y in range(Ly) if sublattice(xc, y) == 0]
+    return sum(vals) / len(vals)

@@ -105,11 +105,40 @@ def tfim_terms(N, J=1.0, h=1.0):
     return terms
 
 
-def jq2_terms(Lx, Ly, J=1.0, Q=1.0):
+def tri_sublattice(x, y):
+    """Three-colouring of the triangular cylinder (bonds (x,y)-(x,y+1),
+    (x,y)-(x+1,y), (x,y)-(x+1,y-1)): neighbours differ by 1 or 2 mod 3."""
+    return (x - y) % 3
+
+
+def triangular_pin_terms(Lx, Ly, h):
+    """Sec. III pinning of the triangular study: the field -h S^z on the sites
+    of the open edge columns that belong to sublattice 0 (the paper: h = J/2)."""
+    assert Ly % 3 == 0
+    return [(-h, ((snake_site(x, y, Ly), "Sz"),)) for x in (0, Lx - 1) for y in range(Ly)
+            if tri_sublattice(x, y) == 0]
+
+
+def jq2_pin_terms(Lx, Ly, Q=1.0, pin=1.0):
+    """Sec. III strong pinning of the J-Q2 study: pin * (Q/4)(S_r.S_{r+y} - 1/4)
+    on every vertical bond of the two open edge columns; the constant is
+    returned separately."""
+    terms, const = [], 0.0
+    for x in (0, Lx - 1):
+        for y in range(Ly):
+            a, b = snake_site(x, y, Ly), snake_site(x, (y + 1) % Ly, Ly)
+            for c, oa, ob in _dot_parts(a, b):
+                terms.append(_sorted_term(pin * 0.25 * Q * c, [(a, oa), (b, ob)]))
+            const += -pin * Q / 16.0
+    return terms, const
+
+
+def jq2_terms(Lx, Ly, J=1.0, Q=1.0, pin=0.0):
     """J-Q2 model on the square cylinder:
     H = J sum_<ij> S_i.S_j - Q sum_plaq (S_a.S_b - 1/4)(S_c.S_d - 1/4),
     the Q sum running over both pairs of opposite plaquette bonds
-    (pure-Q2 form of Eq. eqn:q2 plus the Heisenberg J term)."""
+    (pure-Q2 form of Eq. eqn:q2 plus the Heisenberg J term), plus the edge
+    pinning of Sec. III when pin != 0."""
     terms = heisenberg_terms(square_cylinder_bonds(Lx, Ly), J)
     const = 0.0
     for (a, b), (c, d) in square_plaquette_bond_pairs(Lx, Ly):
@@ -122,5 +151,9 @@ def jq2_terms(Lx, Ly, J=1.0, Q=1.0):
             for cx, ox, oy in _dot_parts(x, y):
                 terms.append(_sorted_term(Q * 0.25 * cx, [(x, ox), (y, oy)]))
         const += -Q / 16.0
+    if pin:
+        pt, pc = jq2_pin_terms(Lx, Ly, Q, pin)
+        terms += pt
+        const += pc
     terms.append((const, ((0, "I"),)))      # kept at Q = 0: structure independent of couplings
     return terms

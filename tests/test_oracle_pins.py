@@ -22,6 +22,9 @@ E_ED_CHAIN16 = -6.911737145575103     # Heisenberg open chain N=16, J=1 (recompu
     ("cyl3x3", models.heisenberg_terms(models.square_cylinder_bonds(3, 3)), 9),
     ("tri3x3", models.xxz_terms(models.triangular_cylinder_bonds(3, 3), 1.0, 0.9), 9),
     ("jq2_3x3", models.jq2_terms(3, 3, 1.0, 0.7), 9),
+    ("jq2_3x3_pinned", models.jq2_terms(3, 3, 0.4, 0.7, pin=1.0), 9),
+    ("tri2x3_pinned", models.xxz_terms(models.triangular_cylinder_bonds(2, 3), 1.0, 0.9)
+     + models.triangular_pin_terms(2, 3, 0.5), 6),
 ])
 def test_mpo_equals_kronecker_sum(name, terms, N):
     mpo = M.build_mpo(terms, N, OPS, PQ)
