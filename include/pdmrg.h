@@ -170,8 +170,14 @@ int pdmrg_layout_blocks(int kind, const pdmrg_bond *b1, const pdmrg_bond *b2,
  * Host-only.  lattice: 0 = open chain (Lx sites), 1 = square cylinder
  * Lx x Ly (open x, periodic y, snake order), 2 = triangular cylinder,
  * 3 = J-Q2 square cylinder, 4 = transverse-field Ising chain (no symmetry:
- * all charges 0).  couplings[]: chain/square/triangular {J, Delta};
- * J-Q2 {J, Q}; TFIM {J, h}. */
+ * all charges 0).  couplings[]: chain/square {J, Delta}; triangular
+ * {J, Delta} or {J, Delta, h}; J-Q2 {J, Q} or {J, Q, pin}; TFIM {J, h}.
+ * Edge pinning of Sec. III (optional third coupling, 0 = off): J-Q2 adds
+ * pin * (Q/4)(S_r . S_{r+y} - 1/4) on every vertical bond of the columns
+ * x = 0 and x = Lx - 1 (the paper's strong-pinning term at pin = 1);
+ * triangular adds the field -h S^z on the sites of those two columns that
+ * belong to sublattice (x - y) mod 3 = 0 (the paper uses h = J/2; needs
+ * Ly % 3 == 0). */
 int mpo_build(int lattice, int Lx, int Ly, const double *couplings, int ncouplings,
               pdmrg_mpo **out);
 /* MPO from caller tensors (copied). */
@@ -392,6 +398,21 @@ int mps_expect_site(pdmrg_ctx *ctx, pdmrg_mps *mps, const double *op, double *ou
 int mps_expect_pairs(pdmrg_ctx *ctx, pdmrg_mps *mps, int nterms, const double *coef, const double *opA,
                      const double *opB, int npairs, const int32_t *site_i, const int32_t *site_k, int concurrent,
                      double *out);
+/* Order parameters of Sec. III from the centres (MPS in the inverse canonical
+ * gauge, spin-1/2 sites, N = Lx * Ly in the snake order of mpo_build; host
+ * scalar *value):
+ *   kind 0: columnar dimer order of the J-Q2 study,
+ *     D_x = (1/Ly) sum_y <S_r.S_{r+x}> - <S_{r-x}.S_r>/2 - <S_{r+x}.S_{r+2x}>/2,
+ *     r = (Lx/2 - 1, y) zero-based (the centre bond of an even-length
+ *     cylinder); needs Lx >= 4;
+ *   kind 1: sublattice magnetisation of the triangular study,
+ *     M_z = <S^z> averaged over the sites (xc, y) of sublattice
+ *     (x - y) mod 3 = 0 (the one mpo_build pins), xc = (Lx - 1)/2 zero-based;
+ *     needs Ly % 3 == 0.
+ * The pair values come from mps_expect_pairs (concurrent streams), the site
+ * values from mps_expect_site.  PDMRG_EINVAL on a gauge, size or kind
+ * mismatch. */
+int mps_order_parameter(pdmrg_ctx *ctx, pdmrg_mps *mps, int kind, int Lx, int Ly, double *value);
 
 void mps_free(pdmrg_mps *mps);
 

@@ -77,7 +77,7 @@ EXPORTS = [
     "heff_free", "env_update", "env_update_info", "davidson_step", "svd_truncate", "svd_result_bond", "svd_result_copy",
     "svd_free", "merge_regions", "mps_alloc", "mps_set_site", "mps_bond", "mps_get_site", "sweep",
     "mps_energy", "mps_free", "grad_site", "grad_mpo", "mps_inverse_canonical", "mps_get_v", "mps_expect_site",
-    "mps_expect_pairs",
+    "mps_expect_pairs", "mps_order_parameter",
 ]
 
 
@@ -130,6 +130,7 @@ def _declare(L):
         "mps_get_v": (c_int, [P, c_int, pd, c_int64]),
         "mps_expect_site": (c_int, [P, P, pd, pd]),
         "mps_expect_pairs": (c_int, [P, P, c_int, pd, pd, pd, c_int, pi32, pi32, c_int, pd]),
+        "mps_order_parameter": (c_int, [P, P, c_int, c_int, c_int, pd]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -530,6 +531,13 @@ class Mps:
                                      i.ctypes.data_as(POINTER(c_int32)), k.ctypes.data_as(POINTER(c_int32)),
                                      int(bool(concurrent)), pd_(out)))
         return out[:len(pairs)]
+
+    def order_parameter(self, kind, Lx, Ly):
+        """mps_order_parameter: kind "Dx" (0) or "Mz" (1)."""
+        v = c_double()
+        k = {"Dx": 0, "Mz": 1}.get(kind, kind)
+        check(lib().mps_order_parameter(self.ctx.h, self.h, int(k), int(Lx), int(Ly), byref(v)))
+        return v.value
 
     def bond(self, b):
         n = c_int32()

@@ -782,6 +782,64 @@ int mps_expect_pairs(pdmrg_ctx *ctx, pdmrg_mps *m, int nterms, const double *coe
     API_CATCH
 }
 
+int mps_order_parameter(pdmrg_ctx *ctx, pdmrg_mps *m, int kind, int Lx, int Ly, double *value) {
+    API_TRY
+    PD_REQUIRE(ctx && m && value, PDMRG_EINVAL, "mps_order_parameter: null argument");
+    PD_REQUIRE(m->icanon, PDMRG_EINVAL, "mps_order_parameter: the MPS is not in the inverse canonical gauge");
+    PD_REQUIRE(Lx >= 1 && Ly >= 1 && Lx * Ly == m->N, PDMRG_EINVAL, "mps_order_parameter: Lx * Ly must equal N");
+    PD_REQUIRE(m->p.d() == 2, PDMRG_EINVAL, "mps_order_parameter: spin-1/2 sites only");
+    const double sz[4] = {0.5 * m->p.q[0], 0.0, 0.0, 0.5 * m->p.q[1]};
+    // |up><down| and its transpose, up = the larger charge
+    const int up = m->p.q[1] > m->p.q[0] ? 1 : 0, dn = 1 - up;
+    double sp[4] = {0, 0, 0, 0}, sm[4] = {0, 0, 0, 0};
+    sp[up * 2 + dn] = 1.0;
+    sm[dn * 2 + up] = 1.0;
+    Driver dr{ctx, m, nullptr};
+    if (kind == 0) {
+        // columnar dimer order D_x of the centre column x = Lx/2 - 1 (0-based)
+        PD_REQUIRE(Lx >= 4, PDMRG_EINVAL, "mps_order_parameter: D_x needs Lx >= 4");
+        const int xc = Lx / 2 - 1;
+        std::vector<int32_t> si, sk;
+        for (int o = -1; o <= 1; ++o)
+            for (int y = 0; y < Ly; ++y) {
+                const int a = lattice_snake(xc + o, y, Ly), b = lattice_snake(xc + o + 1, y, Ly);
+                si.push_back(std::min(a, b));
+                sk.push_back(std::max(a, b));
+            }
+        double A[12], B[12];
+        const double coef[3] = {1.0, 0.5, 0.5};
+        for (int e = 0; e < 4; ++e) {
+            A[e] = sz[e], B[e] = sz[e];
+            A[4 + e] = sp[e], B[4 + e] = sm[e];
+            A[8 + e] = sm[e], B[8 + e] = sp[e];
+        }
+        std::vector<double> v(si.size());
+        const int rc = mps_expect_pairs(ctx, m, 3, coef, A, B, (int)si.size(), si.data(), sk.data(), 1, v.data());
+        if (rc != PDMRG_OK) return rc;
+        double acc = 0.0;
+        for (int y = 0; y < Ly; ++y) acc += v[Ly + y] - 0.5 * v[y] - 0.5 * v[2 * Ly + y];
+        *value = acc / Ly;
+    } else if (kind == 1) {
+        // sublattice magnetisation M_z of the centre column x = (Lx - 1)/2 on
+        // the pinned sublattice (x - y) mod 3 = 0
+        PD_REQUIRE(Ly % 3 == 0, PDMRG_EINVAL, "mps_order_parameter: M_z needs Ly % 3 == 0");
+        const int xc = (Lx - 1) / 2;
+        std::vector<double> all(m->N);
+        dr.expect_site(std::vector<double>(sz, sz + 4), all.data());
+        double acc = 0.0;
+        int n = 0;
+        for (int y = 0; y < Ly; ++y)
+            if (tri_sublattice(xc, y) == 0) {
+                acc += all[lattice_snake(xc, y, Ly)];
+                ++n;
+            }
+        *value = acc / n;
+    } else {
+        throw Error(PDMRG_EINVAL, "mps_order_parameter: kind must be 0 (D_x) or 1 (M_z)");
+    }
+    API_CATCH
+}
+
 void mps_free(pdmrg_mps *m) { delete m; }
 
 }  // extern "C"

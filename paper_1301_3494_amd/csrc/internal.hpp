@@ -64,6 +64,12 @@ struct SvdOut {
     int n_floored = 0;
 };
 // Process-wide tuning cache to / from a text file (one line per signature).
+// Cylinder geometry of the Sec. III lattices: site (x, y) in the snake order
+// (column by column, alternating direction) and the three-colouring of the
+// triangular cylinder's bonds (x,y)-(x,y+1), (x,y)-(x+1,y), (x,y)-(x+1,y-1).
+inline int lattice_snake(int x, int y, int Ly) { return x * Ly + ((x % 2 == 0) ? y : Ly - 1 - y); }
+inline int tri_sublattice(int x, int y) { return ((x - y) % 3 + 3) % 3; }
+
 int tune_export(const char *path);
 int tune_import(const char *path);
 void grad_site_run(pdmrg_ctx *ctx, const GradPlan &plan, const double *L, const double *psi, const double *R,

@@ -36,7 +36,7 @@ const double kOps[5][2][2] = {
 };
 const int kOpCharge[5] = {0, 0, 2, -2, 0};
 
-int snake(int x, int y, int Ly) { return x * Ly + ((x % 2 == 0) ? y : Ly - 1 - y); }
+int snake(int x, int y, int Ly) { return lattice_snake(x, y, Ly); }
 
 std::vector<std::pair<int, int>> square_bonds(int Lx, int Ly) {
     std::set<std::pair<int, int>> b;
@@ -106,10 +106,20 @@ extern "C" int mpo_build(int lattice, int Lx, int Ly, const double *couplings, i
                 N = Lx * Ly;
                 add_xxz(terms, square_bonds(Lx, Ly), c0, c1);
                 break;
-            case 2:   // triangular cylinder, {J, Delta}
+            case 2: { // triangular cylinder, {J, Delta} or {J, Delta, h}
                 N = Lx * Ly;
                 add_xxz(terms, triangular_bonds(Lx, Ly), c0, c1);
+                const double h = ncouplings >= 3 ? couplings[2] : 0.0;
+                if (h != 0.0) {
+                    // pinning field -h S^z on the sites of sublattice (x - y) mod 3 = 0 of
+                    // the two open edge columns (a 3-colouring of the bond set: needs Ly % 3 == 0)
+                    PD_REQUIRE(Ly % 3 == 0 && Lx >= 2, PDMRG_EINVAL, "mpo_build: triangular pinning needs Ly % 3 == 0");
+                    for (int x : {0, Lx - 1})
+                        for (int y = 0; y < Ly; ++y)
+                            if (tri_sublattice(x, y) == 0) terms.push_back(make(-h, {{snake(x, y, Ly), SZ}}));
+                }
                 break;
+            }
             case 3: { // J-Q2 cylinder, {J, Q}
                 PD_REQUIRE(Ly >= 3, PDMRG_EINVAL, "mpo_build: J-Q2 needs Ly >= 3");
                 N = Lx * Ly;
@@ -134,6 +144,18 @@ extern "C" int mpo_build(int lattice, int Lx, int Ly, const double *couplings, i
                             cst += -Q / 16.0;
                         }
                     }
+                const double pin = ncouplings >= 3 ? couplings[2] : 0.0;
+                if (pin != 0.0) {
+                    // edge pinning: pin (Q/4)(S_r . S_{r+y} - 1/4) on every vertical bond
+                    // of the two open edge columns
+                    for (int x : {0, Lx - 1})
+                        for (int y = 0; y < Ly; ++y) {
+                            const int a = snake(x, y, Ly), b = snake(x, (y + 1) % Ly, Ly);
+                            for (auto [cx, o0, o1] : kDot)
+                                terms.push_back(make(pin * 0.25 * Q * cx, {{std::min(a, b), o0}, {std::max(a, b), o1}}));
+                            cst += -pin * Q / 16.0;
+                        }
+                }
                 terms.push_back(make(cst, {{0, I}}));
                 break;
             }
