@@ -459,7 +459,7 @@ def measure_leg(ctx, pl, np, torch, state, reps=5):
                 hb.append((site(x, y), site(x + 1, y)))
             hb.append((site(x, y), site(x, (y + 1) % Ly)))
     hb = sorted({(min(a, b), max(a, b)) for a, b in hb})
-    xc = Lx // 2
+    xc = Lx // 2 - 1      # the centre bond of the even-length cylinder (as mps_order_parameter)
     dx = [[(site(xc + o, y), site(xc + o + 1, y)) for y in range(Ly)] for o in (-1, 0, 1)]
     dx = [[(min(a, b), max(a, b)) for a, b in row] for row in dx]
     pairs = hb + [p for row in dx for p in row]
@@ -505,6 +505,39 @@ def measure_leg(ctx, pl, np, torch, state, reps=5):
         "sum_bond_energies": e_bonds, "energy": E, "rel_diff": abs(e_bonds - E) / abs(E),
         "Dx_centre_column": Dx,
     }
+
+
+def order_leg(ctx, pl, synth, torch, m=256, sweeps=4):
+    """The order-parameter pipeline of Sec. III at reduced sizes: pinned
+    pure-Q2 cylinder (J = 0, Q = 1, L = 4: 8 x 4, 4 regions) -> D_x, and
+    pinned triangular Heisenberg cylinder (6 x 6, h = J/2, 2 regions) -> M_z;
+    sweeps at bond dimension m (one serial, then parallel), inverse canonical
+    gauge, order parameter from the centres."""
+    out = {}
+    for name, lattice, Lx, Ly, cpl, kind, nreg in (("jq2_pinned_8x4", "jq2", 8, 4, (0.0, 1.0, 1.0), "Dx", 4),
+                                                   ("tri_pinned_6x6", "triangular", 6, 6, (1.0, 1.0, 0.5), "Mz", 2)):
+        mpo = pl.Mpo(lattice, Lx, Ly, cpl)
+        bonds, sites = synth.random_mps(Lx * Ly, 64, 9)
+        mps = pl.Mps(ctx, bonds, sites)
+        dav = pl.dav_params(8, 8, 1e-9)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        E = []
+        for k in range(sweeps):
+            E.append(mps.sweep(mpo, m, 1 if k == 0 else nreg, dav=dav)["energy"])
+        torch.cuda.synchronize()
+        t_sw = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        mps.inverse_canonical()
+        val = mps.order_parameter(kind, Lx, Ly)
+        torch.cuda.synchronize()
+        t_op = time.perf_counter() - t0
+        mps.free()
+        out[name] = {kind: val, "energy_per_sweep": E, "seconds_sweeps": round(t_sw, 3),
+                     "seconds_gauge_and_measure": round(t_op, 3), "m": m, "regions": nreg}
+        print("bench: order leg %s %s = %.6f, E = %.10f, sweeps %.2f s, gauge + measure %.2f s" % (
+            name, kind, val, E[-1], t_sw, t_op), file=sys.stderr, flush=True)
+    return out
 
 
 def main():
@@ -617,6 +650,7 @@ def main():
         state = {}
         out["sweep"] = sweep_leg(ctx, pl, synth, torch, concurrent=not args.sequential_regions, keep=state)
         out["measure"] = measure_leg(ctx, pl, np, torch, state)
+        out["order_parameters"] = order_leg(ctx, pl, synth, torch)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, info["flops"])
         if not args.no_steps:
