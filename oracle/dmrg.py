@@ -649,6 +649,14 @@ def split_regions(st, regions, m, p):
                 gauge_move(st, i, "left", m, p)
 
 
+def prediction_infidelity(pred, psi):
+    """Fig. 3's measure of the merge prediction: 1 - |<Psi'|Psi>| / (|Psi'| |Psi|)
+    for the merged state Psi' = psi_L V psi_R and the optimised Psi."""
+    ov = sum(float(np.sum(pred[k] * psi[k])) for k in pred if k in psi)
+    den = norm(pred) * norm(psi)
+    return max(0.0, 1.0 - abs(ov) / den) if den > 0 else 1.0
+
+
 def merge_shared(st, j, m, p):
     """Merge at the shared bond between sites j and j+1 with the stored V
     (Eq. eqn:merge), optimise the merged state, and split it again."""
@@ -656,11 +664,13 @@ def merge_shared(st, j, m, p):
     psi = merge(st.sites[j], st.V[j + 1], st.sites[j + 1], pq)
     nrm = norm(psi)
     psi = {k: v / nrm for k, v in psi.items()}
+    pred = psi
     E, psi, rn, nmv = _solve_bond(st, j, psi, p.dav_shared)
+    infid = prediction_infidelity(pred, psi)
     res = svd_truncate(psi, st.bonds[j], st.bonds[j + 2], pq, m, "split", p.cutoff, p.eps)
     _store(st, j, res, "split")
     st.log.append(dict(kind="merge", site=j, E=E, resid=rn, nmv=nmv, trunc=res.discarded,
-                       m=res.bond.total(), floored=res.n_floored))
+                       m=res.bond.total(), floored=res.n_floored, infidelity=infid))
     return E
 
 

@@ -23,6 +23,17 @@ OPS = {
 }
 
 
+# Spin 1 (the Fig. 3 chains): local states m = -1, 0, 1, charges q = 2 m.
+SPIN_ONE_Q = (-2, 0, 2)
+_R2 = np.sqrt(2.0)
+OPS_S1 = {
+    "I": np.eye(3),
+    "Sz": np.diag([-1.0, 0.0, 1.0]),
+    "Sp": np.array([[0.0, 0.0, 0.0], [_R2, 0.0, 0.0], [0.0, _R2, 0.0]]),   # S+|m> = sqrt(2)|m+1>
+    "Sm": np.array([[0.0, _R2, 0.0], [0.0, 0.0, _R2], [0.0, 0.0, 0.0]]),
+}
+
+
 def snake_site(x, y, Ly):
     return x * Ly + (y if x % 2 == 0 else Ly - 1 - y)
 

@@ -61,6 +61,51 @@ def binomial_bonds(N, m, q_target=0, trivial=False):
     return [binomial_bond(N, l, m, q_target) for l in range(N + 1)]
 
 
+def _charge_counts(n, phys_q):
+    """Number of product states of n sites per total charge."""
+    cnt = {0: 1}
+    for _ in range(n):
+        nxt = {}
+        for q, c in cnt.items():
+            for s in phys_q:
+                nxt[q + s] = nxt.get(q + s, 0) + c
+        cnt = nxt
+    return cnt
+
+
+def counted_bonds(N, m, phys_q, q_target=0):
+    """Sector dims of every bond for any local charges: at a bond with l sites
+    on the left the weight of charge q is min(#left states of charge q,
+    #right states of charge q_target - q), apportioned to m by largest
+    remainder (the binomial rule generalised)."""
+    out = []
+    for l in range(N + 1):
+        left, right = _charge_counts(l, phys_q), _charge_counts(N - l, phys_q)
+        w = {q: min(c, right.get(q_target - q, 0)) for q, c in left.items()}
+        w = {q: c for q, c in sorted(w.items()) if c > 0}
+        total = sum(w.values())
+        if total <= m:
+            out.append(dict(w))
+            continue
+        quota = {q: m * c / total for q, c in w.items()}
+        o = {q: min(int(np.floor(quota[q])), w[q]) for q in w}
+        left_over = m - sum(o.values())
+        order = sorted(w, key=lambda q: (-(quota[q] - np.floor(quota[q])), q))
+        while left_over > 0:
+            progressed = False
+            for q in order:
+                if left_over == 0:
+                    break
+                if o[q] < w[q]:
+                    o[q] += 1
+                    left_over -= 1
+                    progressed = True
+            if not progressed:
+                break
+        out.append({q: n for q, n in o.items() if n > 0})
+    return out
+
+
 def random_site_blocks(bl, br, phys_q, rng):
     """Gaussian blocks {(q_left, s): array} of one MPS site tensor between
     bonds with sector dicts bl, br (allowed charge combinations only)."""
@@ -76,7 +121,10 @@ def random_site_blocks(bl, br, phys_q, rng):
 def random_mps(N, m, seed, phys_q=SPIN_HALF_Q, q_target=0):
     """Bond sector dicts and Gaussian site blocks of a random MPS."""
     rng = np.random.default_rng(seed)
-    bonds = binomial_bonds(N, m, q_target, trivial=all(q == 0 for q in phys_q))
+    if tuple(phys_q) == (-1, 1) or all(q == 0 for q in phys_q):
+        bonds = binomial_bonds(N, m, q_target, trivial=all(q == 0 for q in phys_q))
+    else:
+        bonds = counted_bonds(N, m, phys_q, q_target)
     sites = [random_site_blocks(bonds[i], bonds[i + 1], phys_q, rng) for i in range(N)]
     return bonds, sites
 
