@@ -170,7 +170,9 @@ int pdmrg_layout_blocks(int kind, const pdmrg_bond *b1, const pdmrg_bond *b2,
  * Host-only.  lattice: 0 = open chain (Lx sites), 1 = square cylinder
  * Lx x Ly (open x, periodic y, snake order), 2 = triangular cylinder,
  * 3 = J-Q2 square cylinder, 4 = transverse-field Ising chain (no symmetry:
- * all charges 0).  couplings[]: chain/square {J, Delta}; triangular
+ * all charges 0), 5 = open S = 1 chain (d = 3, local charges q = 2 S^z =
+ * -2, 0, 2; the Fig. 3 study).  couplings[]: chain/square/S = 1 chain
+ * {J, Delta}; triangular
  * {J, Delta} or {J, Delta, h}; J-Q2 {J, Q} or {J, Q, pin}; TFIM {J, h}.
  * Edge pinning of Sec. III (optional third coupling, 0 = off): J-Q2 adds
  * pin * (Q/4)(S_r . S_{r+y} - 1/4) on every vertical bond of the columns
@@ -332,6 +334,9 @@ typedef struct {
     int64_t n_matvec;
     int32_t n_floored;
     int32_t max_bond;
+    double max_infidelity;            /* largest 1 - |<Psi'|Psi>| over the merges:
+                                         Psi' = psi_L V psi_R (Eq. eqn:merge), Psi the
+                                         shared-bond eigenvector (Fig. 3); 0 without merges */
 } pdmrg_sweep_report;
 int mps_alloc(pdmrg_ctx *ctx, int nsites, const pdmrg_phys *phys, int32_t q_target,
               const pdmrg_bond *bonds, pdmrg_mps **out);

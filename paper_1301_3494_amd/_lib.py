@@ -46,7 +46,7 @@ class CSweepParams(Structure):
 class CSweepReport(Structure):
     _fields_ = [("energy", c_double), ("max_trunc", c_double), ("seconds", c_double),
                 ("seconds_heff", c_double), ("n_matvec", c_int64), ("n_floored", c_int32),
-                ("max_bond", c_int32)]
+                ("max_bond", c_int32), ("max_infidelity", c_double)]
 
 
 class PdmrgError(RuntimeError):
@@ -341,7 +341,7 @@ def set_autotune(ctx, level):
     check(lib().pdmrg_ctx_set_autotune(ctx.h, int(level)))
 
 
-LATTICES = {"chain": 0, "square": 1, "triangular": 2, "jq2": 3, "tfim": 4}
+LATTICES = {"chain": 0, "square": 1, "triangular": 2, "jq2": 3, "tfim": 4, "chain_s1": 5}
 
 
 class Mpo:

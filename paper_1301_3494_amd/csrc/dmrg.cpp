@@ -167,9 +167,30 @@ struct Driver {
         store(i, r, mode);
     }
 
+    // 1 - |<a|b>| / (|a| |b|) of two device vectors (fixed-order reductions)
+    double infidelity(const double *a, const double *b, int64_t n) {
+        constexpr int kBlocks = 240;
+        DevBuf part((size_t)kBlocks * 3 * sizeof(double)), out(3 * sizeof(double));
+        const double *pairs[3][2] = {{a, b}, {a, a}, {b, b}};
+        for (int k = 0; k < 3; ++k) {
+            launch_multidot(pairs[k][0], n, 1, pairs[k][1], n, part.as<double>() + (size_t)k * kBlocks, kBlocks, s());
+            launch_reduce_partials(part.as<double>() + (size_t)k * kBlocks, kBlocks, 1, out.as<double>() + k, 1, s());
+        }
+        double h[3];
+        HIP_OK(hipMemcpyAsync(h, out.ptr, sizeof h, hipMemcpyDeviceToHost, s()));
+        HIP_OK(hipStreamSynchronize(s()));
+        const double den = std::sqrt(h[1] * h[2]);
+        return den > 0.0 ? std::max(0.0, 1.0 - std::fabs(h[0]) / den) : 1.0;
+    }
+
     void merge_shared(int j) {
         DevBuf psi = contract(j, m->Vd.at(j + 1).as<double>());
+        // prediction fidelity of the merged state (Fig. 3): psi_L V psi_R
+        // against the state the shared-bond eigensolver converges to
+        const int64_t n = two_site_layout(m->bonds[j], m->bonds[j + 2], m->p).size;
+        DevBuf pred = take(psi, n);
         solve(j, psi, prm.dav_shared);   // Davidson normalises its start vector
+        rep.max_infidelity = std::max(rep.max_infidelity, infidelity(pred.as<double>(), psi.as<double>(), n));
         SvdOut r;
         svd_truncate_run(ctx, m->bonds[j], m->bonds[j + 2], m->p, psi.as<double>(), prm.max_m, prm.cutoff, prm.eps,
                          PDMRG_SPLIT, r);
@@ -260,6 +281,7 @@ struct Driver {
             rep.n_floored += r.n_floored;
             rep.max_trunc = std::max(rep.max_trunc, r.max_trunc);
             rep.max_bond = std::max(rep.max_bond, r.max_bond);
+            rep.max_infidelity = std::max(rep.max_infidelity, r.max_infidelity);
             t_heff += ds[k].t_heff;
         }
         for (size_t k = 0; k < jobs.size(); ++k)

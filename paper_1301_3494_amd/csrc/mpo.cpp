@@ -12,6 +12,7 @@
 // its last operator.
 #include "internal.hpp"
 
+#include <cmath>
 #include <map>
 #include <set>
 #include <tuple>
@@ -165,12 +166,36 @@ extern "C" int mpo_build(int lattice, int Lx, int Ly, const double *couplings, i
                 for (int i = 0; i + 1 < N; ++i) terms.push_back(make(-4.0 * c0, {{i, SZ}, {i + 1, SZ}}));
                 for (int i = 0; i < N; ++i) terms.push_back(make(-2.0 * c1, {{i, SX}}));
                 break;
+            case 5:   // open S = 1 chain, {J, Delta}; local states q = 2 S^z = -2, 0, 2
+                N = Lx;
+                phys_q = {-2, 0, 2};
+                {
+                    std::vector<std::pair<int, int>> b;
+                    for (int i = 0; i + 1 < N; ++i) b.push_back({i, i + 1});
+                    add_xxz(terms, b, c0, c1);
+                }
+                break;
             default:
                 throw Error(PDMRG_EINVAL, "mpo_build: unknown lattice");
         }
         PD_REQUIRE(N >= 2, PDMRG_EINVAL, "mpo_build: need at least two sites");
-        const int d = 2;
-        const bool trivial = phys_q[0] == 0 && phys_q[1] == 0;
+        const int d = (int)phys_q.size();
+        bool trivial = true;
+        for (int q : phys_q) trivial = trivial && q == 0;
+        // local operators <s|O|t> (row-major d x d): spin 1/2 (down, up) or spin 1 (m = -1, 0, 1)
+        std::vector<std::vector<double>> ops(5);
+        if (d == 2) {
+            for (int o = 0; o < 5; ++o)
+                for (int a = 0; a < 2; ++a)
+                    for (int c = 0; c < 2; ++c) ops[o].push_back(kOps[o][a][c]);
+        } else {
+            const double r2 = std::sqrt(2.0);
+            ops[I] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+            ops[SZ] = {-1, 0, 0, 0, 0, 0, 0, 0, 1};
+            ops[SP] = {0, 0, 0, r2, 0, 0, 0, r2, 0};   // S+ |m> = sqrt(2) |m + 1>
+            ops[SM] = {0, r2, 0, 0, 0, r2, 0, 0, 0};
+            ops[SX] = {0, r2 / 2, 0, r2 / 2, 0, r2 / 2, 0, r2 / 2, 0};
+        }
 
         // channel sets
         using Prefix = std::vector<std::pair<int, int>>;
@@ -231,7 +256,7 @@ extern "C" int mpo_build(int lattice, int Lx, int Ly, const double *couplings, i
             for (int s = 0; s < d; ++s)
                 for (int t = 0; t < d; ++t) {
                     double &e = W.W[(((size_t)wl * d + s) * d + t) * W.Dr + wr];
-                    const double v = c * kOps[op][s][t];
+                    const double v = c * ops[op][(size_t)s * d + t];
                     if (add) e += v;
                     else {
                         PD_REQUIRE(e == 0.0 || e == v, PDMRG_EINVAL, "mpo_build: inconsistent shared transition");
