@@ -540,6 +540,36 @@ def order_leg(ctx, pl, synth, torch, m=256, sweeps=4):
     return out
 
 
+def fidelity_leg(ctx, pl, synth, torch, N=100, warm=2, sched=(100, 150, 200, 200)):
+    """The Fig. 3 study at reduced size: open S = 1/2 and S = 1 Heisenberg
+    chains of N sites in 2 regions; `warm` serial warm-up sweeps at m = 50,
+    then parallel sweeps at the bond dimensions of `sched`; per sweep the
+    largest prediction infidelity 1 - |<Psi'|Psi>| of the merged state
+    (shared bond converged to 1e-10) and the sweep seconds."""
+    out = {}
+    for name, lattice, q in (("s_half_chain", "chain", (-1, 1)), ("s_one_chain", "chain_s1", (-2, 0, 2))):
+        mpo = pl.Mpo(lattice, N, 1, (1.0, 1.0))
+        bonds, sites = synth.random_mps(N, 16, 12, phys_q=q)
+        mps = pl.Mps(ctx, bonds, sites, q, 0)
+        dav, davs = pl.dav_params(4, 8, 1e-8), pl.dav_params(40, 8, 1e-10)
+        for _ in range(warm):
+            mps.sweep(mpo, 50, 1, dav=dav, dav_shared=davs)
+        rows = []
+        for m in sched:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rep = mps.sweep(mpo, m, 2, dav=dav, dav_shared=davs)
+            torch.cuda.synchronize()
+            rows.append({"m": m, "infidelity": rep["max_infidelity"], "energy": rep["energy"],
+                         "seconds": round(time.perf_counter() - t0, 3)})
+        mps.free()
+        out[name] = rows
+        print("bench: fidelity leg %s %s" % (name, ["%.2e" % r["infidelity"] for r in rows]),
+              file=sys.stderr, flush=True)
+    out["workload"] = "open Heisenberg chains, N = %d, 2 regions, %d warm-up sweeps at m = 50" % (N, warm)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -651,6 +681,7 @@ def main():
         out["sweep"] = sweep_leg(ctx, pl, synth, torch, concurrent=not args.sequential_regions, keep=state)
         out["measure"] = measure_leg(ctx, pl, np, torch, state)
         out["order_parameters"] = order_leg(ctx, pl, synth, torch)
+        out["prediction_fidelity"] = fidelity_leg(ctx, pl, synth, torch)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, info["flops"])
         if not args.no_steps:
