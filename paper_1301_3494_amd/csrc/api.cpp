@@ -302,8 +302,8 @@ int heff_plan_info(const pdmrg_heff *op, int32_t *shape_Lpsi, int32_t *shape_R, 
     const HeffPlan &pl = op->plan;
     if (shape_Lpsi) *shape_Lpsi = (int32_t)pl.g1.shape;
     if (shape_R) *shape_R = (int32_t)pl.g3.shape;
-    if (tiles_Lpsi) *tiles_Lpsi = (int32_t)pl.g1.tiles.size();
-    if (tiles_R) *tiles_R = (int32_t)pl.g3.tiles.size();
+    if (tiles_Lpsi) *tiles_Lpsi = (int32_t)pl.g1.ntiles_real;
+    if (tiles_R) *tiles_R = (int32_t)pl.g3.ntiles_real;
     if (splitk_parts) *splitk_parts = pl.parts3;
     API_END
 }

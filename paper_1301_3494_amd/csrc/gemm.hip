@@ -19,9 +19,9 @@
 // Operands are read with buffer loads: the descriptor of each segment spans
 // its operand and an offset outside it returns zero, so ragged tile edges need
 // no branches.  Global loads of the next K-step are issued before the MFMAs of
-// the current one.  Tiles are mapped XCD-major: the 8 XCDs each receive a
-// contiguous run of the tile list, so the tiles that share an operand panel
-// share an L2.
+// the current one.  Workgroup b runs tiles[b]: the host places the tiles so
+// that every XCD (b % 8) receives an even share of the work and the tiles
+// that share an A panel share one XCD's L2.
 #include "kernels.hpp"
 
 namespace pdmrg {
@@ -41,11 +41,6 @@ __device__ __forceinline__ f4 mfma16(float a, float b, f4 c) {
 template <typename T> struct Acc;
 template <> struct Acc<double> { using type = d4; };
 template <> struct Acc<float> { using type = f4; };
-
-__device__ __forceinline__ int map_tile(int ntiles) {
-    const int chunk = (ntiles + 7) / 8;
-    return (blockIdx.x % 8) * chunk + blockIdx.x / 8;
-}
 
 // A pointer that is the same in every lane, held in scalar registers.
 __device__ __forceinline__ void *uniform_ptr(const void *p) {
@@ -95,9 +90,10 @@ __global__ __launch_bounds__(NT) void gemm_kmajor(Slots slots, const GemmItem *_
     constexpr int SM = BM / WGM, SN = BN / WGN;              // wave sub-tile
     constexpr int WBM = SM / 16, WBN = SN / 16;              // MFMA blocks per wave
     static_assert(NT % BK == 0 && NT % BM == 0 && NT % BN == 0 && WBM >= 1 && WBN >= 1, "tile shape");
-    const int t = map_tile(ntiles);
-    if (t >= ntiles) return;
-    const GemmTile tile = tiles[t];
+    // the host has placed the tiles in launch order (idle tiles: item < 0)
+    if ((int)blockIdx.x >= ntiles) return;
+    const GemmTile tile = tiles[blockIdx.x];
+    if (tile.item < 0) return;
     const GemmItem it = items[tile.item];
     __shared__ T As[2][BM][LDK];
     __shared__ T Bs[2][BN][LDK];
@@ -254,9 +250,10 @@ __global__ __launch_bounds__(NT) void gemm_bf16x3(Slots slots, const GemmItem *_
     constexpr int WBM = SM / 16, WBN = SN / 16;
     static_assert(NGA >= 1 && NGB >= 1 && WBM >= 1 && WBN >= 1, "tile shape");
     static_assert((BM * KG) % NT == 0 && (BN * KG) % NT == 0, "tile shape");
-    const int t = map_tile(ntiles);
-    if (t >= ntiles) return;
-    const GemmTile tile = tiles[t];
+    // the host has placed the tiles in launch order (idle tiles: item < 0)
+    if ((int)blockIdx.x >= ntiles) return;
+    const GemmTile tile = tiles[blockIdx.x];
+    if (tile.item < 0) return;
     const GemmItem it = items[tile.item];
     __shared__ __attribute__((aligned(16))) unsigned short Ah[2][BM][LDK], Al[2][BM][LDK];
     __shared__ __attribute__((aligned(16))) unsigned short Bh[2][BN][LDK], Bl[2][BN][LDK];
@@ -469,8 +466,7 @@ void launch_gemm(GemmPrec prec, TileShape shape, bool ta, bool tb, bool c_is_f64
                  const GemmItem *items, const GemmSeg *segs, const GemmTile *tiles, const int64_t *rowoff,
                  int ntiles, hipStream_t s) {
     if (ntiles <= 0) return;
-    const int chunk = (ntiles + 7) / 8;
-    dim3 grid(chunk * 8);
+    dim3 grid(ntiles);
     const GemmArgs a{slots, items, segs, tiles, rowoff, ntiles};
     switch (prec) {
         case GemmPrec::F64:

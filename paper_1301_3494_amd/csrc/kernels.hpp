@@ -113,6 +113,8 @@ inline int tile_bn(TileShape t) {
 // Launchers (defined in gemm.hip / blas.hip).  All asynchronous on `s`.
 // c_is_f64: C written as double (F32 / BF16X3 inputs are float).  rowoff:
 // row-offset table of the items with rmap >= 0 (may be null otherwise).
+// launch_gemm: one workgroup per entry of `tiles` (in launch order; entries
+// with item < 0 are idle).
 void launch_gemm(GemmPrec prec, TileShape shape, bool ta, bool tb, bool c_is_f64, const Slots &slots,
                  const GemmItem *items, const GemmSeg *segs, const GemmTile *tiles, const int64_t *rowoff,
                  int ntiles, hipStream_t s);

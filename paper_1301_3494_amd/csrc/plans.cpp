@@ -121,15 +121,54 @@ GemmList GemmList::host_copy() const {
     return g;
 }
 
+// Launch order of the tiles.  Workgroup b of a launch runs on XCD b % 8 (the
+// dispatcher deals workgroups to the 8 XCDs in turn) and tiles[b]; the tiles
+// of one item row (same item and m0) share their A panel, so each such row is
+// kept on one XCD and its L2.  Rows are dealt to XCDs largest first, each to
+// the XCD of least work so far (work = K + a fixed prologue/epilogue cost per
+// tile), then every XCD's list runs largest row first and the lists are
+// interleaved; shorter lists are padded with idle tiles (item = -1).
+static std::vector<GemmTile> place_tiles(const std::vector<GemmItem> &items, const std::vector<int64_t> &kof,
+                                         int bm, int bn) {
+    constexpr int kXcd = 8;
+    constexpr double kTileCost = 64.0;   // prologue + epilogue, in K units
+    struct Row { int item, m0; double cost; };
+    std::vector<Row> rows;
+    for (size_t i = 0; i < items.size(); ++i) {
+        const GemmItem &it = items[i];
+        if (it.M <= 0 || it.N <= 0) continue;
+        const int nt = (it.N + bn - 1) / bn;
+        for (int m0 = 0; m0 < it.M; m0 += bm) rows.push_back(Row{(int)i, m0, nt * ((double)kof[i] + kTileCost)});
+    }
+    std::stable_sort(rows.begin(), rows.end(), [](const Row &a, const Row &b) { return a.cost > b.cost; });
+    std::vector<std::vector<GemmTile>> lists(kXcd);
+    double load[kXcd] = {};
+    for (const Row &r : rows) {
+        const int x = (int)(std::min_element(load, load + kXcd) - load);
+        load[x] += r.cost;
+        for (int n0 = 0; n0 < items[r.item].N; n0 += bn) lists[x].push_back(GemmTile{r.item, r.m0, n0, 0});
+    }
+    size_t len = 0;
+    for (const auto &l : lists) len = std::max(len, l.size());
+    std::vector<GemmTile> out(len * kXcd, GemmTile{-1, 0, 0, 0});
+    for (int x = 0; x < kXcd; ++x)
+        for (size_t j = 0; j < lists[x].size(); ++j) out[j * kXcd + x] = lists[x][j];
+    return out;
+}
+
 void GemmList::finish(hipStream_t s) {
     if (!(shapes_allowed & (1u << (int)shape))) shape = TileShape::T64x64;
     const int bm = tile_bm(shape), bn = tile_bn(shape);
-    tiles.clear();
+    std::vector<int64_t> kof(items.size());
+    ntiles_real = 0;
     for (size_t i = 0; i < items.size(); ++i) {
-        const GemmItem &it = items[i];
-        for (int m0 = 0; m0 < it.M; m0 += bm)
-            for (int n0 = 0; n0 < it.N; n0 += bn) tiles.push_back(GemmTile{(int32_t)i, m0, n0, 0});
+        kof[i] = item_k(*this, items[i]);
+        if (items[i].M > 0 && items[i].N > 0)
+            ntiles_real += ((items[i].M + bm - 1) / bm) * ((items[i].N + bn - 1) / bn);
     }
+    tiles = place_tiles(items, kof, bm, bn);
+    PD_REQUIRE(std::count_if(tiles.begin(), tiles.end(), [](const GemmTile &t) { return t.item >= 0; }) ==
+                   ntiles_real, PDMRG_ESHAPE, "gemm: tile placement lost tiles");
     upload(d_items, items, s);
     upload(d_segs, segs, s);
     upload(d_tiles, tiles, s);
@@ -192,10 +231,16 @@ int64_t GemmList::split_k(int parts, int pslot, LcList &reduce, bool all) {
     std::vector<int32_t> nblk0;
     std::vector<RowBlock> nblocks;
     int64_t pel = 0;
+    // K range length of the longest item's parts; every item is cut into
+    // ranges of about that length, so no tile's K loop is much longer than
+    // another's (the longest tile bounds the launch), each range >= 64
+    int64_t kmax = 0;
+    for (const GemmItem &it : items) kmax = std::max(kmax, item_k(*this, it));
+    const double krange = std::max(1.0, (double)kmax / std::max(parts, 1));
     for (size_t ii = 0; ii < items.size(); ++ii) {
         const GemmItem &it = items[ii];
         const int64_t ktot = item_k(*this, it);
-        const int ip = ktot < (int64_t)parts * 128 ? 1 : parts;   // K parts of this item
+        const int ip = (int)std::max<int64_t>(1, std::min<int64_t>({8, std::llround(ktot / krange), ktot / 64}));
         if (it.M == 0 || it.N == 0 || (ip == 1 && !all)) {
             GemmItem c = it;
             c.seg0 = (int32_t)nsegs.size();

@@ -20,7 +20,8 @@ struct GemmList {
     unsigned shapes_allowed = (1u << kNumShapes) - 1;
     std::vector<GemmItem> items;
     std::vector<GemmSeg> segs;
-    std::vector<GemmTile> tiles;
+    std::vector<GemmTile> tiles;           // in launch order (workgroup b runs tiles[b]); item < 0: idle
+    int ntiles_real = 0;                   // tiles that compute (without the idle padding)
     std::vector<int64_t> rowoff;           // row offsets of stacked items
     std::vector<int32_t> blk0;             // per item: first RowBlock, -1 for a plain item
     std::vector<RowBlock> blocks;
@@ -36,15 +37,18 @@ struct GemmList {
     void pick_tile();
     int ntiles_for(TileShape t) const;
     double padded_flops(TileShape t) const;
-    void finish(hipStream_t s);   // build tiles, upload
+    // Build the tiles and place them for the launch (see place_tiles), upload.
+    void finish(hipStream_t s);
     void launch(GemmPrec prec, bool c_is_f64, const Slots &sl, hipStream_t s) const;
     // Copy of the host-side lists (no device buffers).
     GemmList host_copy() const;
     // Throws unless every element an item touches lies inside its slot's
     // buffer (sizes in elements, per slot).
     void validate(const std::vector<int64_t> &slot_elems) const;
-    // Split-K: every item whose total K allows it is cut into `parts` items
-    // over consecutive K ranges, each writing a partial product into slot
+    // Split-K: the item of longest K is cut into `parts` items over
+    // consecutive K ranges and every other item into as many as keep its
+    // ranges near the same length (at most 8, at least 1), each writing a
+    // partial product into slot
     // `pslot` (packed, ld = N); `reduce` receives one task per original item
     // that sums its partials into the original C in a fixed order.  Returns
     // the number of partial elements.  Call before validate / finish.
