@@ -264,7 +264,8 @@ class Heff:
         out["flops"] = out["flops_Lpsi"] + out["flops_W"] + out["flops_R"]
         v = [c_int32() for _ in range(5)]
         check(lib().heff_plan_info(self.h, *[byref(x) for x in v]))
-        names = ["64x64", "128x32", "32x128", "128x128", "64x64k16", "128x32k16", "64x64k8", "128x32k8"]
+        names = ["64x64", "128x32", "32x128", "128x128", "64x64k16", "128x32k16", "64x64k8", "128x32k8",
+                 "128x32dma", "64x64dma", "32x128dma"]
         out.update(shape_Lpsi=names[v[0].value], shape_R=names[v[1].value], tiles_Lpsi=v[2].value,
                    tiles_R=v[3].value, splitk_parts=v[4].value)
         return out

@@ -10,46 +10,63 @@ namespace pdmrg {
 // ------------------------------------------------------------ W stage
 // One workgroup per tile = a run of kLcChunk consecutive elements of a task's
 // rows x cols block in row-major order, so narrow sector blocks keep every
-// thread busy.  Each thread owns kLcChunk / 256 elements and keeps their loads
-// of one source in flight together; sources are summed in list order.
+// thread busy.  Each thread owns kLcChunk / 256 elements; the loads of four
+// sources are issued together before they are summed (in list order), so a
+// task's latency is a quarter of one load chain per source.  Offsets inside a
+// block are 32-bit (the list's validation bounds them).
 template <typename T, typename TD, int CHUNK>
 __global__ __launch_bounds__(256) void lincomb_kernel(Slots slots, const LcTask *__restrict__ tasks,
                                                       const LcSrc *__restrict__ srcs,
                                                       const LcTile *__restrict__ tiles) {
-    constexpr int U = CHUNK / 256;
+    constexpr int U = CHUNK / 256, J = 4;
     const LcTile tl = tiles[blockIdx.x];
     const LcTask tk = tasks[tl.task];
     // rows * cols < 2^31 (checked when the list is built)
     const unsigned n = (unsigned)tk.rows * (unsigned)tk.cols;
     const unsigned e0 = (unsigned)tl.r0 * CHUNK;
-    int64_t roff[U];
-    int cc[U];
+    unsigned rr[U], cc[U];
     bool ok[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const unsigned e = e0 + threadIdx.x + 256 * u;
         ok[u] = e < n;
         const unsigned r = ok[u] ? e / (unsigned)tk.cols : 0u;
-        cc[u] = ok[u] ? (int)(e - r * (unsigned)tk.cols) : 0;
-        roff[u] = r;
+        cc[u] = ok[u] ? e - r * (unsigned)tk.cols : 0u;
+        rr[u] = r;
     }
     T acc[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) acc[u] = 0;
-    for (int j = 0; j < tk.nsrc; ++j) {
+    int j = 0;
+    for (; j + J <= tk.nsrc; j += J) {
+        T v[J][U], cf[J];
+#pragma unroll
+        for (int q = 0; q < J; ++q) {
+            const LcSrc sj = srcs[tk.src0 + j + q];
+            const T *src = static_cast<const T *>(slots.p[sj.slot]) + sj.off;
+            cf[q] = (T)sj.coef;
+#pragma unroll
+            for (int u = 0; u < U; ++u) v[q][u] = ok[u] ? src[rr[u] * (unsigned)sj.ld + cc[u]] : T(0);
+        }
+#pragma unroll
+        for (int q = 0; q < J; ++q)
+#pragma unroll
+            for (int u = 0; u < U; ++u) acc[u] += cf[q] * v[q][u];
+    }
+    for (; j < tk.nsrc; ++j) {
         const LcSrc sj = srcs[tk.src0 + j];
         const T *src = static_cast<const T *>(slots.p[sj.slot]) + sj.off;
         const T cf = (T)sj.coef;
         T v[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) v[u] = ok[u] ? src[roff[u] * sj.ld + cc[u]] : T(0);
+        for (int u = 0; u < U; ++u) v[u] = ok[u] ? src[rr[u] * (unsigned)sj.ld + cc[u]] : T(0);
 #pragma unroll
         for (int u = 0; u < U; ++u) acc[u] += cf * v[u];
     }
     TD *dst = static_cast<TD *>(const_cast<void *>(slots.p[tk.dst_slot])) + tk.dst_off;
 #pragma unroll
     for (int u = 0; u < U; ++u)
-        if (ok[u]) dst[roff[u] * tk.ld + cc[u]] = (TD)acc[u];
+        if (ok[u]) dst[rr[u] * (unsigned)tk.ld + cc[u]] = (TD)acc[u];
 }
 
 void launch_lincomb(bool f64, int chunk, const Slots &slots, const LcTask *tasks, const LcSrc *srcs,

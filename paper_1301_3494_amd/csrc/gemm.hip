@@ -222,6 +222,201 @@ __global__ __launch_bounds__(NT) void gemm_kmajor(Slots slots, const GemmItem *_
         }
 }
 
+// ---------------------------------------------------------------- FP32, LDS DMA
+// Non-transposed FP32 operands (A: K contiguous, B: N contiguous) staged by
+// buffer loads that write LDS directly (no register staging), NS stages deep:
+// the loads of the next NS - 1 K-steps are in flight while the MFMAs of the
+// current one run, and one barrier separates steps.  Each load instruction
+// writes 64 consecutive dwords (lane i -> dword i), so the LDS layout follows
+// from which element each lane fetches:
+//   A stage: groups of 4 rows x 16 k (64 dwords, one instruction, 4 x 64-byte
+//     row pieces from global memory), consecutive groups 68 dwords apart;
+//   B stage: the 16 x BN tile row-major in 64-dword chunks (one instruction
+//     each, whole row pieces), chunks 64 + 256 / BN dwords apart.
+// Within a K-step, lane group g (lane / 16) of MFMA s (0..3) takes k = 4 g + s
+// (the same permutation of k for A and B, so the sum is unchanged): a lane's
+// four A values are adjacent (one 16-byte LDS read), and with the paddings
+// above every LDS read of the MFMA operands touches each bank once.
+// The loads are written in inline assembly because the compiler, which tracks
+// LDS written by its own direct loads, waits for all of them before any LDS
+// read and so would drain the pipeline at every step; these loads have no
+// register results, and the stage waits below are explicit.
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ u32x4 dma_rsrc(const void *p) {
+    const uint64_t a = reinterpret_cast<uint64_t>(p);
+    u32x4 r;
+    r.x = __builtin_amdgcn_readfirstlane((uint32_t)a);
+    r.y = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32)) & 0xffffu;
+    r.z = 0x7fffffffu;   // 2 GiB range: offsets >= kOutOfRange read zero
+    r.w = 0x00020000u;   // 32-bit data format
+    return r;
+}
+
+#pragma clang diagnostic push
+#pragma clang diagnostic ignored "-Winline-asm"
+// LDS[lds + 4 lane] = dword at byte offset voff of the buffer (0 if out of range)
+__device__ __forceinline__ void dma_dword(u32x4 rsrc, uint32_t lds, uint32_t voff) {
+    asm volatile("s_mov_b32 m0, %0\n\tbuffer_load_dword %1, %2, 0 offen lds"
+                 :: "s"(lds), "v"(voff), "s"(rsrc) : "memory", "m0");
+}
+#pragma clang diagnostic pop
+
+template <int N> __device__ __forceinline__ void wait_vm() {
+    asm volatile("s_waitcnt vmcnt(%0)" :: "n"(N) : "memory");
+}
+
+template <typename TC, int BM, int BN, int WGM, int NS>
+__global__ __launch_bounds__(NT) void gemm_dma_f32(Slots slots, const GemmItem *__restrict__ items,
+                                                   const GemmSeg *__restrict__ segs,
+                                                   const GemmTile *__restrict__ tiles,
+                                                   const int64_t *__restrict__ rowoff, int ntiles) {
+    constexpr int BK = 16;
+    constexpr int WGN = 4 / WGM;
+    constexpr int SM = BM / WGM, SN = BN / WGN;
+    constexpr int WBM = SM / 16, WBN = SN / 16;
+    constexpr int AGS = 68, A_DW = (BM / 4) * AGS;               // A: groups of 4 rows
+    constexpr int PB = 256 / BN, BCS = 64 + PB, B_DW = (BK * BN / 64) * BCS;
+    constexpr int ST_DW = A_DW + B_DW;                           // one stage, dwords
+    constexpr int NA = BM / 16, NB = BN / 16;                    // loads per wave and step
+    constexpr int NL = NA + NB;
+    static_assert(NS >= 2 && NS <= 4 && WBM >= 1 && WBN >= 1 && BN <= 128 && (NS - 2) * NL <= 63, "shape");
+    static_assert(A_DW % 4 == 0 && ST_DW % 4 == 0, "16-byte aligned A reads");
+    __shared__ __attribute__((aligned(16))) float sm[NS * ST_DW];
+
+    if ((int)blockIdx.x >= ntiles) return;
+    const GemmTile tile = tiles[blockIdx.x];
+    if (tile.item < 0) return;
+    const GemmItem it = items[tile.item];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wm = (wave / WGN) * SM, wn = (wave % WGN) * SN;
+    const int m0 = tile.m0, n0 = tile.n0;
+    const uint32_t lds0 = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) float *)sm;
+
+    f4 acc[WBM][WBN];
+#pragma unroll
+    for (int i = 0; i < WBM; ++i)
+#pragma unroll
+        for (int j = 0; j < WBN; ++j) acc[i][j] = f4{0, 0, 0, 0};
+
+    // steps over all segments
+    int nsteps = 0;
+    for (int q = 0; q < it.nseg; ++q) {
+        const int K = segs[it.seg0 + q].K;
+        if (K > 0) nsteps += (K + BK - 1) / BK;
+    }
+
+    // producer: segment, K position and per-lane row / column offsets
+    int ps = -1, pk0 = 0, pK = 0, pldb = 0;
+    u32x4 rA{}, rB{};
+    uint32_t arow[NA], bcol[NB];
+    auto next_seg = [&]() {
+        do { ++ps; } while (ps < it.nseg && segs[it.seg0 + ps].K <= 0);
+        if (ps >= it.nseg) return;
+        const GemmSeg sg = segs[it.seg0 + ps];
+        pK = __builtin_amdgcn_readfirstlane(sg.K);
+        const int lda = __builtin_amdgcn_readfirstlane(sg.lda);
+        pldb = __builtin_amdgcn_readfirstlane(sg.ldb);
+        rA = dma_rsrc(static_cast<const float *>(slots.p[sg.a_slot]) + sg.a_off);
+        rB = dma_rsrc(static_cast<const float *>(slots.p[sg.b_slot]) + sg.b_off);
+        pk0 = 0;
+#pragma unroll
+        for (int u = 0; u < NA; ++u) {
+            const int m = m0 + 4 * (wave * NA + u) + (lane >> 4);
+            arow[u] = m < it.M ? (uint32_t)m * (uint32_t)lda * 4u : kOutOfRange;
+        }
+#pragma unroll
+        for (int v = 0; v < NB; ++v) {
+            const int n = n0 + ((64 * (wave * NB + v) + lane) % BN);
+            bcol[v] = n < it.N ? (uint32_t)n * 4u : kOutOfRange;
+        }
+    };
+    int issued = 0;
+    auto issue = [&]() {
+        if (issued >= nsteps) return;
+        const uint32_t sa = lds0 + (uint32_t)((issued % NS) * ST_DW) * 4u, sb = sa + A_DW * 4u;
+        const int ka = pk0 + (lane & 15);
+        const bool kav = ka < pK;
+#pragma unroll
+        for (int u = 0; u < NA; ++u)
+            dma_dword(rA, sa + (uint32_t)((wave * NA + u) * AGS) * 4u, kav ? arow[u] + (uint32_t)ka * 4u : kOutOfRange);
+#pragma unroll
+        for (int v = 0; v < NB; ++v) {
+            const int x = wave * NB + v;                  // chunk of the B stage
+            const int kb = pk0 + (64 * x + lane) / BN;
+            dma_dword(rB, sb + (uint32_t)(x * BCS) * 4u,
+                      kb < pK ? bcol[v] + (uint32_t)kb * (uint32_t)pldb * 4u : kOutOfRange);
+        }
+        ++issued;
+        pk0 += BK;
+        if (pk0 >= pK) next_seg();
+    };
+
+    // per-lane LDS read offsets (dwords within a stage)
+    const int c = lane & 15, g = lane >> 4;
+    int aoff[WBM], boff[WBN];
+#pragma unroll
+    for (int i = 0; i < WBM; ++i) {
+        const int r = wm + i * 16 + c;
+        aoff[i] = (r >> 2) * AGS + (r & 3) * 16 + 4 * g;
+    }
+#pragma unroll
+    for (int j = 0; j < WBN; ++j) {
+        const int f = (4 * g) * BN + wn + j * 16 + c;
+        boff[j] = f + (f >> 6) * PB;
+    }
+
+    next_seg();
+#pragma unroll
+    for (int p = 0; p < NS - 1; ++p) issue();
+    for (int s = 0; s < nsteps; ++s) {
+        // this wave's loads of step s are done once at most `newer` later steps remain in flight
+        const int newer = min(nsteps - s - 1, NS - 2);
+        if (NS >= 4 && newer >= 2) wait_vm<2 * NL>();
+        else if (NS >= 3 && newer >= 1) wait_vm<NL>();
+        else wait_vm<0>();
+        __syncthreads();
+        issue();
+        const float *st = sm + (s % NS) * ST_DW;
+        f4 a[WBM];
+        float b[WBN][4];
+#pragma unroll
+        for (int i = 0; i < WBM; ++i) a[i] = *reinterpret_cast<const f4 *>(st + aoff[i]);
+#pragma unroll
+        for (int j = 0; j < WBN; ++j)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                // k = 4 g + q: flat index + q * BN, chunk padding included
+                const int f = (4 * g + q) * BN + wn + j * 16 + c;
+                b[j][q] = st[A_DW + f + (f >> 6) * PB];
+            }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int i = 0; i < WBM; ++i)
+#pragma unroll
+                for (int j = 0; j < WBN; ++j) acc[i][j] = mfma16(a[i][q], b[j][q], acc[i][j]);
+    }
+    (void)boff;
+
+    TC *C = static_cast<TC *>(const_cast<void *>(slots.p[it.c_slot])) + it.c_off;
+#pragma unroll
+    for (int i = 0; i < WBM; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = (lane >> 4) * 4 + r;
+            const int gm = m0 + wm + i * 16 + row;
+            if (gm >= it.M) continue;
+            TC *Cr = C + c_row(it, rowoff, gm);
+#pragma unroll
+            for (int j = 0; j < WBN; ++j) {
+                const int gn = n0 + wn + j * 16 + c;
+                if (gn < it.N) Cr[gn] = (TC)acc[i][j][r];
+            }
+        }
+}
+
 // ---------------------------------------------------------------- BF16 x3
 // Same tiles, buffer loads, double-buffered LDS and single barrier per K-step
 // as the FP32 kernel; each thread stages pairs of consecutive k of one row
@@ -425,6 +620,12 @@ static void dispatch_shape(bool ta, bool tb, dim3 g, hipStream_t s, const GemmAr
         hipLaunchKernelGGL((gemm_kmajor<T, TC, true, true, BM, BN, WGM, KDIV>), g, dim3(NT), 0, s, a.sl, a.it, a.sg, a.tl, a.ro, a.n);
 }
 
+constexpr int kDmaStages = 4;
+template <typename TC, int BM, int BN, int WGM>
+static void dispatch_dma(dim3 g, hipStream_t s, const GemmArgs &a) {
+    hipLaunchKernelGGL((gemm_dma_f32<TC, BM, BN, WGM, kDmaStages>), g, dim3(NT), 0, s, a.sl, a.it, a.sg, a.tl, a.ro, a.n);
+}
+
 template <typename T, typename TC>
 static void dispatch_kmajor(TileShape shape, bool ta, bool tb, dim3 g, hipStream_t s, const GemmArgs &a) {
     switch (shape) {
@@ -438,6 +639,20 @@ static void dispatch_kmajor(TileShape shape, bool ta, bool tb, dim3 g, hipStream
         // element of a 32-wide tile; they run at half depth instead
         case TileShape::T64x64_K8: dispatch_shape<T, TC, 64, 64, 2, sizeof(T) == 8 ? 2 : 4>(ta, tb, g, s, a); break;
         case TileShape::T128x32_K8: dispatch_shape<T, TC, 128, 32, 4, sizeof(T) == 8 ? 2 : 4>(ta, tb, g, s, a); break;
+        // LDS-DMA pipeline: FP32 non-transposed operands; otherwise the
+        // half-depth kernel of the same tile
+        case TileShape::T128x32_D:
+            if (sizeof(T) == 4 && !ta && !tb) dispatch_dma<TC, 128, 32, 4>(g, s, a);
+            else dispatch_shape<T, TC, 128, 32, 4, 2>(ta, tb, g, s, a);
+            break;
+        case TileShape::T64x64_D:
+            if (sizeof(T) == 4 && !ta && !tb) dispatch_dma<TC, 64, 64, 2>(g, s, a);
+            else dispatch_shape<T, TC, 64, 64, 2, 2>(ta, tb, g, s, a);
+            break;
+        case TileShape::T32x128_D:
+            if (sizeof(T) == 4 && !ta && !tb) dispatch_dma<TC, 32, 128, 1>(g, s, a);
+            else dispatch_shape<T, TC, 32, 128, 1, 1>(ta, tb, g, s, a);
+            break;
     }
 }
 

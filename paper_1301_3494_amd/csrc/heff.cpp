@@ -52,7 +52,8 @@ double time_ms(hipStream_t s, int reps, F &&fn) {
 
 const char *shape_name(int t) {
     static const char *n[kNumShapes] = {"64x64", "128x32", "32x128", "128x128",
-                                        "64x64k16", "128x32k16", "64x64k8", "128x32k8"};
+                                        "64x64k16", "128x32k16", "64x64k8", "128x32k8",
+                                        "128x32dma", "64x64dma", "32x128dma"};
     return n[t];
 }
 

@@ -92,20 +92,27 @@ enum class GemmPrec { F64, F32, BF16X3 };
 enum class TileShape {
     T64x64 = 0, T128x32 = 1, T32x128 = 2, T128x128 = 3,
     T64x64_K16 = 4, T128x32_K16 = 5,   // half-depth K steps
-    T64x64_K8 = 6, T128x32_K8 = 7      // quarter-depth K steps
+    T64x64_K8 = 6, T128x32_K8 = 7,     // quarter-depth K steps
+    // FP32, non-transposed operands: K steps of 16 staged by direct-to-LDS
+    // loads several steps ahead (other operands: the half-depth kernel)
+    T128x32_D = 8, T64x64_D = 9, T32x128_D = 10
 };
-constexpr int kNumShapes = 8;
+constexpr int kNumShapes = 11;
+constexpr unsigned kDmaShapes = (1u << 8) | (1u << 9) | (1u << 10);
 inline int tile_bm(TileShape t) {
     switch (t) {
-        case TileShape::T32x128: return 32;
-        case TileShape::T64x64: case TileShape::T64x64_K16: case TileShape::T64x64_K8: return 64;
+        case TileShape::T32x128: case TileShape::T32x128_D: return 32;
+        case TileShape::T64x64: case TileShape::T64x64_K16: case TileShape::T64x64_K8: case TileShape::T64x64_D:
+            return 64;
         default: return 128;
     }
 }
 inline int tile_bn(TileShape t) {
     switch (t) {
-        case TileShape::T128x32: case TileShape::T128x32_K16: case TileShape::T128x32_K8: return 32;
-        case TileShape::T64x64: case TileShape::T64x64_K16: case TileShape::T64x64_K8: return 64;
+        case TileShape::T128x32: case TileShape::T128x32_K16: case TileShape::T128x32_K8: case TileShape::T128x32_D:
+            return 32;
+        case TileShape::T64x64: case TileShape::T64x64_K16: case TileShape::T64x64_K8: case TileShape::T64x64_D:
+            return 64;
         default: return 128;
     }
 }

@@ -84,7 +84,7 @@ void GemmList::pick_tile() {
     // Relative throughput per padded flop of each shape, from timings of the
     // H_eff GEMMs of the 8 x 4 cylinder (m = 1024) on MI355X: shorter K steps
     // (more resident workgroups) win on these short, ragged K loops.
-    static const double kRate[kNumShapes] = {1.0, 1.0, 0.8, 0.75, 1.1, 1.15, 1.05, 1.2};
+    static const double kRate[kNumShapes] = {1.0, 1.0, 0.8, 0.75, 1.1, 1.15, 1.05, 1.2, 1.25, 1.2, 0.9};
     double best = 0.0;
     bool have = false;
     for (int t = 0; t < kNumShapes; ++t) {
@@ -216,6 +216,12 @@ void GemmList::validate(const std::vector<int64_t> &slot_elems) const {
 void LcList::validate(const std::vector<int64_t> &slot_elems) const {
     for (const LcTask &t : tasks) {
         PD_REQUIRE((int64_t)t.rows * t.cols < ((int64_t)1 << 31), PDMRG_ESHAPE, "W stage: block too large");
+        // the kernel forms row * ld + col in 32 bits
+        PD_REQUIRE(t.rows == 0 || (int64_t)(t.rows - 1) * t.ld + t.cols < ((int64_t)1 << 32), PDMRG_ESHAPE,
+                   "W stage: block span too large");
+        for (int j = 0; j < t.nsrc; ++j)
+            PD_REQUIRE(t.rows == 0 || (int64_t)(t.rows - 1) * srcs[t.src0 + j].ld + t.cols < ((int64_t)1 << 32),
+                       PDMRG_ESHAPE, "W stage: source span too large");
         check_span(slot_elems, t.dst_slot, t.dst_off, t.rows, t.cols, t.ld, "W stage dst");
         for (int j = 0; j < t.nsrc; ++j) {
             const LcSrc &sj = srcs[t.src0 + j];
@@ -533,6 +539,10 @@ void HeffPlan::build(const Bond &bl_, const Bond &br_, const Phys &p_, const Mpo
     if (prec == PDMRG_BF16X3)
         g1.shapes_allowed = g3.shapes_allowed = (1u << (int)TileShape::T64x64) | (1u << (int)TileShape::T128x32) |
                                                 (1u << (int)TileShape::T32x128) | (1u << (int)TileShape::T128x128);
+    if (prec == PDMRG_F32) {   // both lists are non-transposed
+        g1.shapes_allowed |= kDmaShapes;
+        g3.shapes_allowed |= kDmaShapes;
+    }
     g1.pick_tile();
     g3.pick_tile();
     const std::vector<int64_t> sz = {X.size, X.size, Lt.size, Rt.size, nT1, nT2, 0};

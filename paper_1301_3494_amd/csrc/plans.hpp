@@ -17,7 +17,7 @@ struct RowBlock {
 struct GemmList {
     bool ta = false, tb = false;
     TileShape shape = TileShape::T64x64;   // set by pick_tile()
-    unsigned shapes_allowed = (1u << kNumShapes) - 1;
+    unsigned shapes_allowed = ((1u << kNumShapes) - 1) & ~kDmaShapes;   // FP32 plans add kDmaShapes
     std::vector<GemmItem> items;
     std::vector<GemmSeg> segs;
     std::vector<GemmTile> tiles;           // in launch order (workgroup b runs tiles[b]); item < 0: idle

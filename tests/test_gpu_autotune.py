@@ -88,3 +88,44 @@ def test_bf16x3_every_tile_shape(case, shape, tmp_path):
     err = np.linalg.norm(y - y0) / np.linalg.norm(y0)
     say(f"bf16x3 shape {names[shape]} rel err {err:.3e}")
     assert err <= 1e-5
+
+
+SHAPES = ["64x64", "128x32", "32x128", "128x128", "64x64k16", "128x32k16", "64x64k8", "128x32k8",
+          "128x32dma", "64x64dma", "32x128dma"]
+
+
+@pytest.mark.parametrize("parts", [1, 3])
+@pytest.mark.parametrize("shape", list(range(len(SHAPES))))
+def test_f32_every_tile_shape(case, shape, parts, tmp_path):
+    """Each FP32 tile shape (register-staged K steps of 32, 16 and 8; LDS-DMA
+    pipelined steps of 16) for both stages, forced through an imported tuning
+    entry, with and without split-K, against the FP64 product."""
+    import torch
+    from paper_1301_3494_amd import _lib as pl
+    B1, B2, P, W1, W2, L, R, x = case
+    y0 = _apply(pl, torch, 0, pl.F64, case)
+    ctx = pl.Context(0)
+    pl.set_autotune(ctx, 1)
+    pl.Heff(ctx, B1, B2, P, W1, W2, L, R, pl.F32).free()      # creates this operator's entry
+    f = tmp_path / "plans.tsv"
+    pl.autotune_export(str(f))
+    rows = [r.split("\t") for r in f.read_text().splitlines() if r]
+    mine = [r[0] for r in rows if r[0].split("|")[1] == str(pl.F32)]
+    assert mine
+    f.write_text("".join("%s\t%d\t%d\t%d\n" % (k, shape, shape, parts) for k in mine))
+    pl.autotune_import(str(f))
+    op = pl.Heff(ctx, B1, B2, P, W1, W2, L, R, pl.F32)
+    info = op.info()
+    assert info["shape_Lpsi"] == SHAPES[shape] and info["shape_R"] == SHAPES[shape]
+    y = torch.empty_like(x)
+    op.apply(x, y)
+    y1 = torch.empty_like(x)
+    op.apply(x, y1)
+    torch.cuda.synchronize()
+    y, y1 = y.cpu().numpy(), y1.cpu().numpy()
+    op.free()
+    ctx.close()
+    err = np.linalg.norm(y - y0) / np.linalg.norm(y0)
+    say(f"f32 shape {SHAPES[shape]} parts {parts}: tiles {info['tiles_Lpsi']} / {info['tiles_R']}, rel err {err:.3e}")
+    assert np.array_equal(y, y1)
+    assert err <= 1e-5
