@@ -130,6 +130,13 @@ int pdmrg_ctx_set_timing(pdmrg_ctx *ctx, int enable);
  * differ in the last bits (the split-K partition follows the tile count).
  * Returns PDMRG_EINVAL for another level. */
 int pdmrg_ctx_set_autotune(pdmrg_ctx *ctx, int level);
+/* Debugging aid, process-wide: on != 0 fills every device buffer the library
+ * allocates or takes from its cache (workspaces, plans, MPS storage) with
+ * 0xFF bytes, a NaN in FP64 and FP32, before first use, so that a kernel
+ * reading memory nothing wrote shows up as NaN instead of as whatever an
+ * earlier call left there.  Synchronises the device at each allocation (slow;
+ * not for use during stream capture).  on = 0 (the default) turns it off. */
+int pdmrg_set_alloc_poison(int on);
 /* enable = 1: heff_apply (and the Davidson matvecs on this context) replay a
  * HIP graph of the operator's kernel sequence, captured on the first call for
  * each (x, y) pair (up to 16 pairs per operator; further pairs run

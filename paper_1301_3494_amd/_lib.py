@@ -72,7 +72,7 @@ def lib():
 
 EXPORTS = [
     "pdmrg_last_error", "pdmrg_version", "pdmrg_ctx_create", "pdmrg_ctx_destroy", "pdmrg_ctx_set_timing",
-    "pdmrg_ctx_timing", "pdmrg_ctx_set_autotune", "pdmrg_ctx_set_graphs", "pdmrg_autotune_export", "pdmrg_autotune_import", "pdmrg_layout_size", "pdmrg_layout_blocks", "mpo_build", "mpo_from_sites",
+    "pdmrg_ctx_timing", "pdmrg_ctx_set_autotune", "pdmrg_set_alloc_poison", "pdmrg_ctx_set_graphs", "pdmrg_autotune_export", "pdmrg_autotune_import", "pdmrg_layout_size", "pdmrg_layout_blocks", "mpo_build", "mpo_from_sites",
     "mpo_info", "mpo_get_site", "mpo_free", "heff_create", "heff_apply", "heff_info", "heff_plan_info", "heff_diag",
     "heff_free", "env_update", "env_update_info", "davidson_step", "svd_truncate", "svd_result_bond", "svd_result_copy",
     "svd_free", "merge_regions", "mps_alloc", "mps_set_site", "mps_bond", "mps_get_site", "sweep",
@@ -95,6 +95,7 @@ def _declare(L):
         "pdmrg_ctx_set_autotune": (c_int, [P, c_int]),
         "pdmrg_ctx_set_graphs": (c_int, [P, c_int]),
         "pdmrg_autotune_export": (c_int, [c_char_p, pi32]),
+        "pdmrg_set_alloc_poison": (c_int, [c_int]),
         "pdmrg_autotune_import": (c_int, [c_char_p, pi32]),
         "pdmrg_layout_size": (c_int, [c_int, pb, pb, pp, pi32, c_int32, pi64, pi32]),
         "pdmrg_layout_blocks": (c_int, [c_int, pb, pb, pp, pi32, c_int32, pi32, pi64, pi32, pi32, pi32]),
@@ -317,6 +318,11 @@ def timing(ctx, enable=None):
     n = c_int64()
     check(lib().pdmrg_ctx_timing(ctx.h, ms, byref(n)))
     return list(ms), n.value
+
+
+def set_alloc_poison(on):
+    """Debugging aid: NaN-fill every device buffer the library hands out."""
+    check(lib().pdmrg_set_alloc_poison(1 if on else 0))
 
 
 def autotune_export(path):

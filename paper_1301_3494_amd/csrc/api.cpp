@@ -86,6 +86,12 @@ int pdmrg_ctx_set_autotune(pdmrg_ctx *ctx, int level) {
     API_END
 }
 
+int pdmrg_set_alloc_poison(int on) {
+    API_BEGIN
+    pdmrg::g_alloc_poison.store(on != 0);
+    API_END
+}
+
 int pdmrg_autotune_export(const char *path, int32_t *n_entries) {
     API_BEGIN
     PD_REQUIRE(path, PDMRG_EINVAL, "autotune export: null path");

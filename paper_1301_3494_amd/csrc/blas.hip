@@ -278,7 +278,8 @@ __global__ void combine_kernel(const double *V, int64_t ldv, int nvec, const dou
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         double acc = 0.0;
         for (int v = 0; v < nvec; ++v) acc += c[v] * V[v * ldv + i];
-        y[i] = beta * y[i] + sign * acc;
+        // beta = 0: y is output only (its old contents, possibly NaN, are not read)
+        y[i] = beta == 0.0 ? sign * acc : beta * y[i] + sign * acc;
     }
 }
 

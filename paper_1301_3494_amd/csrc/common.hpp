@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdint>
 #include <cstring>
 #include <map>
@@ -94,6 +95,9 @@ struct MpoSite {
 };
 
 // ---------------------------------------------------------------- device memory
+// pdmrg_set_alloc_poison: fill buffers with NaN bytes as they are handed out
+extern std::atomic<bool> g_alloc_poison;
+
 struct DevBuf {
     void *ptr = nullptr;
     size_t bytes = 0;

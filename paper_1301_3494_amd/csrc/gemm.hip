@@ -240,7 +240,10 @@ __global__ __launch_bounds__(NT) void gemm_kmajor(Slots slots, const GemmItem *_
 // The loads are written in inline assembly because the compiler, which tracks
 // LDS written by its own direct loads, waits for all of them before any LDS
 // read and so would drain the pipeline at every step; these loads have no
-// register results, and the stage waits below are explicit.
+// register results, and the stage waits below are explicit.  A tile arrives
+// as one FlatTile record (one scalar load): with several workgroups starting
+// together on a CU, a chain of dependent descriptor loads (tile, item,
+// segment) left the CU idle for microseconds at every tile start.
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ u32x4 dma_rsrc(const void *p) {
@@ -267,9 +270,7 @@ template <int N> __device__ __forceinline__ void wait_vm() {
 }
 
 template <typename TC, int BM, int BN, int WGM, int NS>
-__global__ __launch_bounds__(NT) void gemm_dma_f32(Slots slots, const GemmItem *__restrict__ items,
-                                                   const GemmSeg *__restrict__ segs,
-                                                   const GemmTile *__restrict__ tiles,
+__global__ __launch_bounds__(NT) void gemm_dma_f32(Slots slots, const FlatTile *__restrict__ tiles,
                                                    const int64_t *__restrict__ rowoff, int ntiles) {
     constexpr int BK = 16;
     constexpr int WGN = 4 / WGM;
@@ -285,14 +286,30 @@ __global__ __launch_bounds__(NT) void gemm_dma_f32(Slots slots, const GemmItem *
     __shared__ __attribute__((aligned(16))) float sm[NS * ST_DW];
 
     if ((int)blockIdx.x >= ntiles) return;
-    const GemmTile tile = tiles[blockIdx.x];
-    if (tile.item < 0) return;
-    const GemmItem it = items[tile.item];
+    const FlatTile ft = tiles[blockIdx.x];
+    if (ft.M <= 0) return;
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wm = (wave / WGN) * SM, wn = (wave % WGN) * SN;
-    const int m0 = tile.m0, n0 = tile.n0;
+    const int M = ft.M, N = ft.N, K = ft.K, m0 = ft.m0, n0 = ft.n0;
     const uint32_t lds0 = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) float *)sm;
+    const u32x4 rA = dma_rsrc(static_cast<const float *>(slots.p[ft.a_slot]) + ft.a_off);
+    const u32x4 rB = dma_rsrc(static_cast<const float *>(slots.p[ft.b_slot]) + ft.b_off);
+    const int nsteps = K > 0 ? (K + BK - 1) / BK : 0;
+
+    // per-lane byte offsets of this lane's A rows and B columns (out of range: kOutOfRange)
+    uint32_t arow[NA], bcol[NB];
+#pragma unroll
+    for (int u = 0; u < NA; ++u) {
+        const int m = m0 + 4 * (wave * NA + u) + (lane >> 4);
+        arow[u] = m < M ? (uint32_t)m * (uint32_t)ft.lda * 4u : kOutOfRange;
+    }
+#pragma unroll
+    for (int v = 0; v < NB; ++v) {
+        const int n = n0 + ((64 * (wave * NB + v) + lane) % BN);
+        bcol[v] = n < N ? (uint32_t)n * 4u : kOutOfRange;
+    }
+    const uint32_t ldb4 = (uint32_t)ft.ldb * 4u;
 
     f4 acc[WBM][WBN];
 #pragma unroll
@@ -300,76 +317,43 @@ __global__ __launch_bounds__(NT) void gemm_dma_f32(Slots slots, const GemmItem *
 #pragma unroll
         for (int j = 0; j < WBN; ++j) acc[i][j] = f4{0, 0, 0, 0};
 
-    // steps over all segments
-    int nsteps = 0;
-    for (int q = 0; q < it.nseg; ++q) {
-        const int K = segs[it.seg0 + q].K;
-        if (K > 0) nsteps += (K + BK - 1) / BK;
-    }
-
-    // producer: segment, K position and per-lane row / column offsets
-    int ps = -1, pk0 = 0, pK = 0, pldb = 0;
-    u32x4 rA{}, rB{};
-    uint32_t arow[NA], bcol[NB];
-    auto next_seg = [&]() {
-        do { ++ps; } while (ps < it.nseg && segs[it.seg0 + ps].K <= 0);
-        if (ps >= it.nseg) return;
-        const GemmSeg sg = segs[it.seg0 + ps];
-        pK = __builtin_amdgcn_readfirstlane(sg.K);
-        const int lda = __builtin_amdgcn_readfirstlane(sg.lda);
-        pldb = __builtin_amdgcn_readfirstlane(sg.ldb);
-        rA = dma_rsrc(static_cast<const float *>(slots.p[sg.a_slot]) + sg.a_off);
-        rB = dma_rsrc(static_cast<const float *>(slots.p[sg.b_slot]) + sg.b_off);
-        pk0 = 0;
-#pragma unroll
-        for (int u = 0; u < NA; ++u) {
-            const int m = m0 + 4 * (wave * NA + u) + (lane >> 4);
-            arow[u] = m < it.M ? (uint32_t)m * (uint32_t)lda * 4u : kOutOfRange;
-        }
-#pragma unroll
-        for (int v = 0; v < NB; ++v) {
-            const int n = n0 + ((64 * (wave * NB + v) + lane) % BN);
-            bcol[v] = n < it.N ? (uint32_t)n * 4u : kOutOfRange;
-        }
-    };
-    int issued = 0;
-    auto issue = [&]() {
-        if (issued >= nsteps) return;
-        const uint32_t sa = lds0 + (uint32_t)((issued % NS) * ST_DW) * 4u, sb = sa + A_DW * 4u;
-        const int ka = pk0 + (lane & 15);
-        const bool kav = ka < pK;
+    // step `st` of the K loop into stage buffer st % NS
+    auto issue = [&](int st) {
+        const uint32_t sa = lds0 + (uint32_t)((st % NS) * ST_DW) * 4u, sb = sa + A_DW * 4u;
+        const int k0 = st * BK;
+        const int ka = k0 + (lane & 15);
+        const bool kav = ka < K;
 #pragma unroll
         for (int u = 0; u < NA; ++u)
             dma_dword(rA, sa + (uint32_t)((wave * NA + u) * AGS) * 4u, kav ? arow[u] + (uint32_t)ka * 4u : kOutOfRange);
 #pragma unroll
         for (int v = 0; v < NB; ++v) {
             const int x = wave * NB + v;                  // chunk of the B stage
-            const int kb = pk0 + (64 * x + lane) / BN;
-            dma_dword(rB, sb + (uint32_t)(x * BCS) * 4u,
-                      kb < pK ? bcol[v] + (uint32_t)kb * (uint32_t)pldb * 4u : kOutOfRange);
+            const int kb = k0 + (64 * x + lane) / BN;
+            dma_dword(rB, sb + (uint32_t)(x * BCS) * 4u, kb < K ? bcol[v] + (uint32_t)kb * ldb4 : kOutOfRange);
         }
-        ++issued;
-        pk0 += BK;
-        if (pk0 >= pK) next_seg();
     };
 
     // per-lane LDS read offsets (dwords within a stage)
     const int c = lane & 15, g = lane >> 4;
-    int aoff[WBM], boff[WBN];
+    int aoff[WBM], boff[WBN][4];
 #pragma unroll
     for (int i = 0; i < WBM; ++i) {
         const int r = wm + i * 16 + c;
         aoff[i] = (r >> 2) * AGS + (r & 3) * 16 + 4 * g;
     }
 #pragma unroll
-    for (int j = 0; j < WBN; ++j) {
-        const int f = (4 * g) * BN + wn + j * 16 + c;
-        boff[j] = f + (f >> 6) * PB;
-    }
-
-    next_seg();
+    for (int j = 0; j < WBN; ++j)
 #pragma unroll
-    for (int p = 0; p < NS - 1; ++p) issue();
+        for (int q = 0; q < 4; ++q) {
+            // k = 4 g + q: row-major index in the 16 x BN tile, plus the padding of its chunk
+            const int f = (4 * g + q) * BN + wn + j * 16 + c;
+            boff[j][q] = A_DW + f + (f >> 6) * PB;
+        }
+
+#pragma unroll
+    for (int p = 0; p < NS - 1; ++p)
+        if (p < nsteps) issue(p);
     for (int s = 0; s < nsteps; ++s) {
         // this wave's loads of step s are done once at most `newer` later steps remain in flight
         const int newer = min(nsteps - s - 1, NS - 2);
@@ -377,7 +361,7 @@ __global__ __launch_bounds__(NT) void gemm_dma_f32(Slots slots, const GemmItem *
         else if (NS >= 3 && newer >= 1) wait_vm<NL>();
         else wait_vm<0>();
         __syncthreads();
-        issue();
+        if (s + NS - 1 < nsteps) issue(s + NS - 1);
         const float *st = sm + (s % NS) * ST_DW;
         f4 a[WBM];
         float b[WBN][4];
@@ -386,11 +370,7 @@ __global__ __launch_bounds__(NT) void gemm_dma_f32(Slots slots, const GemmItem *
 #pragma unroll
         for (int j = 0; j < WBN; ++j)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                // k = 4 g + q: flat index + q * BN, chunk padding included
-                const int f = (4 * g + q) * BN + wn + j * 16 + c;
-                b[j][q] = st[A_DW + f + (f >> 6) * PB];
-            }
+            for (int q = 0; q < 4; ++q) b[j][q] = st[boff[j][q]];
 #pragma unroll
         for (int q = 0; q < 4; ++q)
 #pragma unroll
@@ -398,21 +378,20 @@ __global__ __launch_bounds__(NT) void gemm_dma_f32(Slots slots, const GemmItem *
 #pragma unroll
                 for (int j = 0; j < WBN; ++j) acc[i][j] = mfma16(a[i][q], b[j][q], acc[i][j]);
     }
-    (void)boff;
 
-    TC *C = static_cast<TC *>(const_cast<void *>(slots.p[it.c_slot])) + it.c_off;
+    TC *C = static_cast<TC *>(const_cast<void *>(slots.p[ft.c_slot])) + ft.c_off;
 #pragma unroll
     for (int i = 0; i < WBM; ++i)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int row = (lane >> 4) * 4 + r;
             const int gm = m0 + wm + i * 16 + row;
-            if (gm >= it.M) continue;
-            TC *Cr = C + c_row(it, rowoff, gm);
+            if (gm >= M) continue;
+            TC *Cr = C + (ft.rmap >= 0 ? rowoff[ft.rmap + gm] : (int64_t)gm * ft.ldc);
 #pragma unroll
             for (int j = 0; j < WBN; ++j) {
                 const int gn = n0 + wn + j * 16 + c;
-                if (gn < it.N) Cr[gn] = (TC)acc[i][j][r];
+                if (gn < N) Cr[gn] = (TC)acc[i][j][r];
             }
         }
 }
@@ -620,10 +599,13 @@ static void dispatch_shape(bool ta, bool tb, dim3 g, hipStream_t s, const GemmAr
         hipLaunchKernelGGL((gemm_kmajor<T, TC, true, true, BM, BN, WGM, KDIV>), g, dim3(NT), 0, s, a.sl, a.it, a.sg, a.tl, a.ro, a.n);
 }
 
-constexpr int kDmaStages = 4;
+// Pipeline depth of the LDS-DMA kernel: two stages (loads one K step ahead)
+// keep 8 workgroups of 64 x 64 resident per CU, which measured faster on the
+// H_eff GEMMs than three or four stages at lower occupancy.
+constexpr int kDmaStages = 2;
 template <typename TC, int BM, int BN, int WGM>
-static void dispatch_dma(dim3 g, hipStream_t s, const GemmArgs &a) {
-    hipLaunchKernelGGL((gemm_dma_f32<TC, BM, BN, WGM, kDmaStages>), g, dim3(NT), 0, s, a.sl, a.it, a.sg, a.tl, a.ro, a.n);
+static void dispatch_dma(dim3 g, hipStream_t s, const Slots &sl, const FlatTile *t, const int64_t *ro, int n) {
+    hipLaunchKernelGGL((gemm_dma_f32<TC, BM, BN, WGM, kDmaStages>), g, dim3(NT), 0, s, sl, t, ro, n);
 }
 
 template <typename T, typename TC>
@@ -641,18 +623,12 @@ static void dispatch_kmajor(TileShape shape, bool ta, bool tb, dim3 g, hipStream
         case TileShape::T128x32_K8: dispatch_shape<T, TC, 128, 32, 4, sizeof(T) == 8 ? 2 : 4>(ta, tb, g, s, a); break;
         // LDS-DMA pipeline: FP32 non-transposed operands; otherwise the
         // half-depth kernel of the same tile
-        case TileShape::T128x32_D:
-            if (sizeof(T) == 4 && !ta && !tb) dispatch_dma<TC, 128, 32, 4>(g, s, a);
-            else dispatch_shape<T, TC, 128, 32, 4, 2>(ta, tb, g, s, a);
-            break;
-        case TileShape::T64x64_D:
-            if (sizeof(T) == 4 && !ta && !tb) dispatch_dma<TC, 64, 64, 2>(g, s, a);
-            else dispatch_shape<T, TC, 64, 64, 2, 2>(ta, tb, g, s, a);
-            break;
-        case TileShape::T32x128_D:
-            if (sizeof(T) == 4 && !ta && !tb) dispatch_dma<TC, 32, 128, 1>(g, s, a);
-            else dispatch_shape<T, TC, 32, 128, 1, 1>(ta, tb, g, s, a);
-            break;
+        // LDS-DMA shapes run through launch_gemm_flat; lists it cannot take
+        // (FP64, transposed operands, several segments per item) run the
+        // register-staged kernel of the same tile
+        case TileShape::T128x32_D: dispatch_shape<T, TC, 128, 32, 4, 2>(ta, tb, g, s, a); break;
+        case TileShape::T64x64_D: dispatch_shape<T, TC, 64, 64, 2, 2>(ta, tb, g, s, a); break;
+        case TileShape::T32x128_D: dispatch_shape<T, TC, 32, 128, 1, 1>(ta, tb, g, s, a); break;
     }
 }
 
@@ -674,6 +650,28 @@ static void dispatch_bf16(TileShape shape, bool ta, bool tb, dim3 g, hipStream_t
         case TileShape::T32x128: dispatch_bf16_shape<TC, 32, 128, 1>(ta, tb, g, s, a); break;
         case TileShape::T128x128: dispatch_bf16_shape<TC, 128, 128, 2>(ta, tb, g, s, a); break;
         default: dispatch_bf16_shape<TC, 64, 64, 2>(ta, tb, g, s, a); break;
+    }
+}
+
+void launch_gemm_flat(TileShape shape, bool c_is_f64, const Slots &slots, const FlatTile *tiles,
+                      const int64_t *rowoff, int ntiles, hipStream_t s) {
+    if (ntiles <= 0) return;
+    const dim3 g(ntiles);
+    switch (shape) {
+        case TileShape::T128x32_D:
+            if (c_is_f64) dispatch_dma<double, 128, 32, 4>(g, s, slots, tiles, rowoff, ntiles);
+            else dispatch_dma<float, 128, 32, 4>(g, s, slots, tiles, rowoff, ntiles);
+            break;
+        case TileShape::T64x64_D:
+            if (c_is_f64) dispatch_dma<double, 64, 64, 2>(g, s, slots, tiles, rowoff, ntiles);
+            else dispatch_dma<float, 64, 64, 2>(g, s, slots, tiles, rowoff, ntiles);
+            break;
+        case TileShape::T32x128_D:
+            if (c_is_f64) dispatch_dma<double, 32, 128, 1>(g, s, slots, tiles, rowoff, ntiles);
+            else dispatch_dma<float, 32, 128, 1>(g, s, slots, tiles, rowoff, ntiles);
+            break;
+        default:
+            break;
     }
 }
 

@@ -39,6 +39,14 @@ struct GemmTile {
     int32_t item, m0, n0, pad_;
 };
 
+// A tile of a single-segment item with everything the tile needs in one
+// record (the LDS-DMA kernel reads it with one scalar load); M <= 0: idle.
+struct FlatTile {
+    int64_t a_off, b_off, c_off;
+    int32_t a_slot, b_slot, c_slot, rmap;
+    int32_t M, N, K, lda, ldb, ldc, m0, n0;
+};
+
 // Scaled sum of same-shaped strided blocks: dst = sum_j coef_j * src_j.
 struct LcTask {
     int64_t dst_off;
@@ -125,6 +133,10 @@ inline int tile_bn(TileShape t) {
 void launch_gemm(GemmPrec prec, TileShape shape, bool ta, bool tb, bool c_is_f64, const Slots &slots,
                  const GemmItem *items, const GemmSeg *segs, const GemmTile *tiles, const int64_t *rowoff,
                  int ntiles, hipStream_t s);
+// FP32 operands, non-transposed, one segment per item, LDS-DMA tile shape
+// (T128x32_D, T64x64_D, T32x128_D); one workgroup per entry of `tiles`.
+void launch_gemm_flat(TileShape shape, bool c_is_f64, const Slots &slots, const FlatTile *tiles,
+                      const int64_t *rowoff, int ntiles, hipStream_t s);
 // chunk: kLcChunk or kLcChunkSmall elements per tile (as the tiles were built).
 void launch_lincomb(bool f64, int chunk, const Slots &slots, const LcTask *tasks, const LcSrc *srcs,
                     const LcTile *tiles, int ntiles, hipStream_t s);

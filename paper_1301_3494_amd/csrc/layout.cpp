@@ -2,6 +2,7 @@
 // layouts declared in include/pdmrg.h.
 #include "common.hpp"
 
+#include <atomic>
 #include <mutex>
 
 namespace pdmrg {
@@ -129,8 +130,18 @@ EnvLayout env_r_layout(const Bond &b, const std::vector<int> &deltas) { return g
 // synchronisation waits for every stream (concurrent regions included), so it
 // is taken only once the pending blocks hold kRecycleBytes; below that a miss
 // allocates a new block.  Cached blocks are kept until the process ends.
+std::atomic<bool> g_alloc_poison{false};
+
 namespace {
 std::mutex g_cache_mu;   // the allocator serves every host thread of the process
+
+// debugging aid: NaN bytes in a buffer about to be handed out
+void poison(void *ptr, size_t bytes) {
+    if (!g_alloc_poison.load(std::memory_order_relaxed)) return;
+    HIP_OK(hipDeviceSynchronize());
+    HIP_OK(hipMemset(ptr, 0xFF, bytes));
+    HIP_OK(hipDeviceSynchronize());
+}
 constexpr size_t kRecycleBytes = size_t(2) << 30;
 struct DeviceCache {
     std::map<std::pair<int, size_t>, std::vector<void *>> free_, pending_;
@@ -173,6 +184,7 @@ void DevBuf::alloc(size_t n) {
         ptr = it->second.back();
         it->second.pop_back();
         bytes = cls;
+        poison(ptr, cls);
         return;
     }
     hipError_t e = hipMalloc(&ptr, cls);
@@ -194,6 +206,7 @@ void DevBuf::alloc(size_t n) {
         throw Error(PDMRG_ENOMEM, "hipMalloc of " + std::to_string(cls) + " bytes failed: " + hipGetErrorString(e));
     }
     bytes = cls;
+    poison(ptr, cls);
 }
 
 void DevBuf::release() {

@@ -169,9 +169,41 @@ void GemmList::finish(hipStream_t s) {
     tiles = place_tiles(items, kof, bm, bn);
     PD_REQUIRE(std::count_if(tiles.begin(), tiles.end(), [](const GemmTile &t) { return t.item >= 0; }) ==
                    ntiles_real, PDMRG_ESHAPE, "gemm: tile placement lost tiles");
+    ftiles.clear();
+    bool single = !ta && !tb;
+    for (const GemmItem &it : items) single = single && it.nseg <= 1;
+    if (single && ((kDmaShapes >> (int)shape) & 1u)) {
+        for (const GemmTile &t : tiles) {
+            FlatTile f{};
+            if (t.item >= 0) {
+                const GemmItem &it = items[t.item];
+                f.c_off = it.c_off;
+                f.c_slot = f.a_slot = f.b_slot = it.c_slot;
+                f.rmap = it.rmap;
+                f.M = it.M;
+                f.N = it.N;
+                f.ldc = it.ldc;
+                f.m0 = t.m0;
+                f.n0 = t.n0;
+                if (it.nseg == 1) {
+                    const GemmSeg &sg = segs[it.seg0];
+                    f.a_off = sg.a_off;
+                    f.b_off = sg.b_off;
+                    f.a_slot = sg.a_slot;
+                    f.b_slot = sg.b_slot;
+                    f.K = std::max(sg.K, 0);
+                    f.lda = sg.lda;
+                    f.ldb = sg.ldb;
+                }
+            }
+            ftiles.push_back(f);
+        }
+    }
     upload(d_items, items, s);
     upload(d_segs, segs, s);
     upload(d_tiles, tiles, s);
+    if (ftiles.empty()) d_ftiles.release();
+    else upload(d_ftiles, ftiles, s);
     if (rowoff.empty()) d_rowoff.release();
     else upload(d_rowoff, rowoff, s);
 }
@@ -318,6 +350,10 @@ int64_t GemmList::split_k(int parts, int pslot, LcList &reduce, bool all) {
 }
 
 void GemmList::launch(GemmPrec prec, bool c_is_f64, const Slots &sl, hipStream_t s) const {
+    if (prec == GemmPrec::F32 && !ftiles.empty()) {
+        launch_gemm_flat(shape, c_is_f64, sl, d_ftiles.as<FlatTile>(), d_rowoff.as<int64_t>(), (int)ftiles.size(), s);
+        return;
+    }
     launch_gemm(prec, shape, ta, tb, c_is_f64, sl, d_items.as<GemmItem>(), d_segs.as<GemmSeg>(),
                 d_tiles.as<GemmTile>(), d_rowoff.as<int64_t>(), (int)tiles.size(), s);
 }

@@ -27,6 +27,10 @@ struct GemmList {
     std::vector<RowBlock> blocks;
     double flops = 0.0;
     DevBuf d_items, d_segs, d_tiles, d_rowoff;
+    // LDS-DMA shapes on lists of single-segment items: the tiles as FlatTile
+    // records in the same launch order (used by launch() for FP32 inputs)
+    std::vector<FlatTile> ftiles;
+    DevBuf d_ftiles;
 
     int add_item(int c_slot, int64_t c_off, int M, int N, int ldc);
     // An item whose M rows stack the given output blocks (each N wide).
