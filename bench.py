@@ -637,7 +637,11 @@ def main():
     stage_flops = info["flops_Lpsi"] if st == 0 else info["flops_R"]
     achieved = stage_flops / (r["ms"][st] * 1e-3) / 1e12
     peak = PEAK_TFLOPS[args.prec]
-    kname = "gemm_kmajor" if args.prec != "bf16x3" else "gemm_bf16x3"
+    shape = info["shape_Lpsi"] if st == 0 else info["shape_R"]
+    if args.prec == "bf16x3":
+        kname = "gemm_bf16x3"
+    else:
+        kname = "gemm_dma_f32" if args.prec == "f32" and shape.endswith("dma") else "gemm_kmajor"
     traffic = stored_traffic(args.prec, st, {k: info[k] for k in ("shape_Lpsi", "shape_R", "splitk_parts")})
     out = {
         "metric": "H_eff matvec TFLOP/s (% MFMA peak); sweep s, mixed vs FP64 at 1e-9 rel E",
@@ -657,8 +661,7 @@ def main():
                    "m": wl["m"], "mpo_D": int(W1.W.shape[0]), "psi_elems": info["n_psi"],
                    "flops_per_matvec": info["flops"], "dense_equiv_flops": 4.0 * 14 * 4 * 1024 ** 3},
         "roofline": {"bound": "mfma", "kernel": "%s stage %d (%s), %s tiles" % (
-                         kname, st + 1, "L.psi" if st == 0 else "T2.R",
-                         info["shape_Lpsi"] if st == 0 else info["shape_R"]),
+                         kname, st + 1, "L.psi" if st == 0 else "T2.R", shape),
                      "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
                      "frac": round(achieved / peak, 4), "traffic": traffic},
         "plan": {k: info[k] for k in ("shape_Lpsi", "shape_R", "tiles_Lpsi", "tiles_R", "splitk_parts")},
