@@ -122,31 +122,48 @@ GemmList GemmList::host_copy() const {
 }
 
 // Launch order of the tiles.  Workgroup b of a launch runs on XCD b % 8 (the
-// dispatcher deals workgroups to the 8 XCDs in turn) and tiles[b]; the tiles
-// of one item row (same item and m0) share their A panel, so each such row is
-// kept on one XCD and its L2.  Rows are dealt to XCDs largest first, each to
-// the XCD of least work so far (work = K + a fixed prologue/epilogue cost per
-// tile), then every XCD's list runs largest row first and the lists are
-// interleaved; shorter lists are padded with idle tiles (item = -1).
+// dispatcher deals workgroups to the 8 XCDs in turn) and tiles[b].  The tiles
+// of an item are cut into chunks of consecutive rows, each about 1/128 of
+// the launch's work (work = K + a fixed prologue/epilogue cost per tile), so an
+// item, or a large item's row range, stays on one XCD and its L2 (the tiles
+// of a row share the A panel, the rows of an item the B panel).  Chunks are
+// dealt to XCDs largest first, each to the XCD of least work so far, then
+// every XCD's list runs largest chunk first and the lists are interleaved;
+// shorter lists are padded with idle tiles (item = -1).
 static std::vector<GemmTile> place_tiles(const std::vector<GemmItem> &items, const std::vector<int64_t> &kof,
                                          int bm, int bn) {
-    constexpr int kXcd = 8;
+    constexpr int kXcd = 8, kChunksPerXcd = 16;
     constexpr double kTileCost = 64.0;   // prologue + epilogue, in K units
-    struct Row { int item, m0; double cost; };
-    std::vector<Row> rows;
+    double total = 0.0;
+    for (size_t i = 0; i < items.size(); ++i)
+        if (items[i].M > 0 && items[i].N > 0)
+            total += ((items[i].M + bm - 1) / bm) * (double)((items[i].N + bn - 1) / bn) * ((double)kof[i] + kTileCost);
+    const double target = total / (kXcd * kChunksPerXcd);
+    struct Chunk { int item, m_begin, m_end; double cost; };
+    std::vector<Chunk> chunks;
     for (size_t i = 0; i < items.size(); ++i) {
         const GemmItem &it = items[i];
         if (it.M <= 0 || it.N <= 0) continue;
-        const int nt = (it.N + bn - 1) / bn;
-        for (int m0 = 0; m0 < it.M; m0 += bm) rows.push_back(Row{(int)i, m0, nt * ((double)kof[i] + kTileCost)});
+        const double row_cost = ((it.N + bn - 1) / bn) * ((double)kof[i] + kTileCost);
+        Chunk c{(int)i, 0, 0, 0.0};
+        for (int m0 = 0; m0 < it.M; m0 += bm) {
+            c.m_end = std::min(m0 + bm, it.M);
+            c.cost += row_cost;
+            if (c.cost >= target) {
+                chunks.push_back(c);
+                c = Chunk{(int)i, c.m_end, c.m_end, 0.0};
+            }
+        }
+        if (c.m_end > c.m_begin) chunks.push_back(c);
     }
-    std::stable_sort(rows.begin(), rows.end(), [](const Row &a, const Row &b) { return a.cost > b.cost; });
+    std::stable_sort(chunks.begin(), chunks.end(), [](const Chunk &a, const Chunk &b) { return a.cost > b.cost; });
     std::vector<std::vector<GemmTile>> lists(kXcd);
     double load[kXcd] = {};
-    for (const Row &r : rows) {
+    for (const Chunk &c : chunks) {
         const int x = (int)(std::min_element(load, load + kXcd) - load);
-        load[x] += r.cost;
-        for (int n0 = 0; n0 < items[r.item].N; n0 += bn) lists[x].push_back(GemmTile{r.item, r.m0, n0, 0});
+        load[x] += c.cost;
+        for (int m0 = c.m_begin; m0 < c.m_end; m0 += bm)
+            for (int n0 = 0; n0 < items[c.item].N; n0 += bn) lists[x].push_back(GemmTile{c.item, m0, n0, 0});
     }
     size_t len = 0;
     for (const auto &l : lists) len = std::max(len, l.size());
