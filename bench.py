@@ -317,7 +317,7 @@ def small_graph_probe(ctx, pl, synth, np, torch, steps=300):
 def _kernel_sources_hash():
     import hashlib
     h = hashlib.sha256()
-    for f in ("gemm.hip", "kernels.hpp"):
+    for f in ("gemm.hip", "kernels.hpp", "plans.cpp"):   # kernels, and the tile placement
         with open(os.path.join(ROOT, "paper_1301_3494_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
