@@ -641,7 +641,7 @@ def main():
     if args.prec == "bf16x3":
         kname = "gemm_bf16x3"
     else:
-        kname = "gemm_dma_f32" if args.prec == "f32" and shape.endswith("dma") else "gemm_kmajor"
+        kname = "gemm_dma" if shape.endswith("dma") else "gemm_kmajor"
     traffic = stored_traffic(args.prec, st, {k: info[k] for k in ("shape_Lpsi", "shape_R", "splitk_parts")})
     out = {
         "metric": "H_eff matvec TFLOP/s (% MFMA peak); sweep s, mixed vs FP64 at 1e-9 rel E",

@@ -222,21 +222,25 @@ __global__ __launch_bounds__(NT) void gemm_kmajor(Slots slots, const GemmItem *_
         }
 }
 
-// ---------------------------------------------------------------- FP32, LDS DMA
-// Non-transposed FP32 operands (A: K contiguous, B: N contiguous) staged by
+// ---------------------------------------------------------------- LDS DMA
+// Non-transposed FP32 / FP64 operands (A: K contiguous, B: N contiguous) staged by
 // buffer loads that write LDS directly (no register staging), NS stages deep:
 // the loads of the next NS - 1 K-steps are in flight while the MFMAs of the
 // current one run, and one barrier separates steps.  Each load instruction
 // writes 64 consecutive dwords (lane i -> dword i), so the LDS layout follows
 // from which element each lane fetches:
-//   A stage: groups of 4 rows x 16 k (64 dwords, one instruction, 4 x 64-byte
-//     row pieces from global memory), consecutive groups 68 dwords apart;
+//   A stage: groups of 4 FP32 (2 FP64) rows x 16 k (64 dwords, one
+//     instruction, whole 64-byte (128-byte) row pieces from global memory),
+//     consecutive groups 68 dwords apart;
 //   B stage: the 16 x BN tile row-major in 64-dword chunks (one instruction
-//     each, whole row pieces), chunks 64 + 256 / BN dwords apart.
+//     each, whole row pieces), FP32 chunks 64 + 256 / BN dwords apart, FP64
+//     chunks unpadded.
 // Within a K-step, lane group g (lane / 16) of MFMA s (0..3) takes k = 4 g + s
 // (the same permutation of k for A and B, so the sum is unchanged): a lane's
-// four A values are adjacent (one 16-byte LDS read), and with the paddings
-// above every LDS read of the MFMA operands touches each bank once.
+// four A values are adjacent (one 16-byte LDS read in FP32, two in FP64), and
+// with the layouts above every LDS read of the MFMA operands touches each
+// bank once per cycle (FP32 B reads serve 32 lanes a cycle, across k rows,
+// hence the padding; FP64 B reads serve 16 lanes, one k row).
 // The loads are written in inline assembly because the compiler, which tracks
 // LDS written by its own direct loads, waits for all of them before any LDS
 // read and so would drain the pipeline at every step; these loads have no
@@ -245,6 +249,7 @@ __global__ __launch_bounds__(NT) void gemm_kmajor(Slots slots, const GemmItem *_
 // together on a CU, a chain of dependent descriptor loads (tile, item,
 // segment) left the CU idle for microseconds at every tile start.
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+typedef float f2v __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ u32x4 dma_rsrc(const void *p) {
     const uint64_t a = reinterpret_cast<uint64_t>(p);
@@ -269,20 +274,26 @@ template <int N> __device__ __forceinline__ void wait_vm() {
     asm volatile("s_waitcnt vmcnt(%0)" :: "n"(N) : "memory");
 }
 
-template <typename TC, int BM, int BN, int WGM, int NS>
-__global__ __launch_bounds__(NT) void gemm_dma_f32(Slots slots, const FlatTile *__restrict__ tiles,
-                                                   const int64_t *__restrict__ rowoff, int ntiles) {
+template <typename T, typename TC, int BM, int BN, int WGM, int NS>
+__global__ __launch_bounds__(NT) void gemm_dma(Slots slots, const FlatTile *__restrict__ tiles,
+                                               const int64_t *__restrict__ rowoff, int ntiles) {
     constexpr int BK = 16;
+    constexpr int EW = sizeof(T) / 4;                            // dwords per element
+    constexpr int RG = 4 / EW;                                   // rows per A load group (64 dwords)
     constexpr int WGN = 4 / WGM;
     constexpr int SM = BM / WGM, SN = BN / WGN;
     constexpr int WBM = SM / 16, WBN = SN / 16;
-    constexpr int AGS = 68, A_DW = (BM / 4) * AGS;               // A: groups of 4 rows
-    constexpr int PB = 256 / BN, BCS = 64 + PB, B_DW = (BK * BN / 64) * BCS;
+    constexpr int AGS = 68, A_DW = (BM / RG) * AGS;              // A: groups of RG rows
+    // B: 64-dword chunks of the row-major 16 x BN tile; FP32 reads (32 lanes a
+    // cycle, four k rows) need the padding, FP64 reads (16 lanes) do not
+    constexpr int PB = EW == 1 ? 256 / BN : 0, BCS = 64 + PB, B_DW = (BK * BN * EW / 64) * BCS;
     constexpr int ST_DW = A_DW + B_DW;                           // one stage, dwords
-    constexpr int NA = BM / 16, NB = BN / 16;                    // loads per wave and step
+    constexpr int NA = BM / RG / 4, NB = BK * BN * EW / 256;     // loads per wave and step
     constexpr int NL = NA + NB;
-    static_assert(NS >= 2 && NS <= 4 && WBM >= 1 && WBN >= 1 && BN <= 128 && (NS - 2) * NL <= 63, "shape");
+    static_assert(NS >= 2 && NS <= 4 && WBM >= 1 && WBN >= 1 && BN <= 128 && NA >= 1 && NB >= 1 &&
+                  (NS - 2) * NL <= 63, "shape");
     static_assert(A_DW % 4 == 0 && ST_DW % 4 == 0, "16-byte aligned A reads");
+    using V4 = typename Acc<T>::type;
     __shared__ __attribute__((aligned(16))) float sm[NS * ST_DW];
 
     if ((int)blockIdx.x >= ntiles) return;
@@ -293,44 +304,48 @@ __global__ __launch_bounds__(NT) void gemm_dma_f32(Slots slots, const FlatTile *
     const int wm = (wave / WGN) * SM, wn = (wave % WGN) * SN;
     const int M = ft.M, N = ft.N, K = ft.K, m0 = ft.m0, n0 = ft.n0;
     const uint32_t lds0 = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) float *)sm;
-    const u32x4 rA = dma_rsrc(static_cast<const float *>(slots.p[ft.a_slot]) + ft.a_off);
-    const u32x4 rB = dma_rsrc(static_cast<const float *>(slots.p[ft.b_slot]) + ft.b_off);
+    const u32x4 rA = dma_rsrc(static_cast<const T *>(slots.p[ft.a_slot]) + ft.a_off);
+    const u32x4 rB = dma_rsrc(static_cast<const T *>(slots.p[ft.b_slot]) + ft.b_off);
     const int nsteps = K > 0 ? (K + BK - 1) / BK : 0;
 
+    // A load: lane -> row a_r of the group, element a_k of the 16, dword a_h of it
+    const int a_r = lane / (16 * EW), a_k = (lane % (16 * EW)) / EW, a_h = lane % EW;
     // per-lane byte offsets of this lane's A rows and B columns (out of range: kOutOfRange)
     uint32_t arow[NA], bcol[NB];
 #pragma unroll
     for (int u = 0; u < NA; ++u) {
-        const int m = m0 + 4 * (wave * NA + u) + (lane >> 4);
-        arow[u] = m < M ? (uint32_t)m * (uint32_t)ft.lda * 4u : kOutOfRange;
+        const int m = m0 + RG * (wave * NA + u) + a_r;
+        arow[u] = m < M ? (uint32_t)m * (uint32_t)ft.lda * (uint32_t)sizeof(T) + 4u * a_h : kOutOfRange;
     }
 #pragma unroll
     for (int v = 0; v < NB; ++v) {
-        const int n = n0 + ((64 * (wave * NB + v) + lane) % BN);
-        bcol[v] = n < N ? (uint32_t)n * 4u : kOutOfRange;
+        const int f = 64 * (wave * NB + v) + lane;                // dword of the B stage (unpadded)
+        const int n = n0 + (f / EW) % BN;
+        bcol[v] = n < N ? (uint32_t)n * (uint32_t)sizeof(T) + 4u * (f % EW) : kOutOfRange;
     }
-    const uint32_t ldb4 = (uint32_t)ft.ldb * 4u;
+    const uint32_t ldbb = (uint32_t)ft.ldb * (uint32_t)sizeof(T);
 
-    f4 acc[WBM][WBN];
+    V4 acc[WBM][WBN];
 #pragma unroll
     for (int i = 0; i < WBM; ++i)
 #pragma unroll
-        for (int j = 0; j < WBN; ++j) acc[i][j] = f4{0, 0, 0, 0};
+        for (int j = 0; j < WBN; ++j) acc[i][j] = V4{0, 0, 0, 0};
 
     // step `st` of the K loop into stage buffer st % NS
     auto issue = [&](int st) {
         const uint32_t sa = lds0 + (uint32_t)((st % NS) * ST_DW) * 4u, sb = sa + A_DW * 4u;
         const int k0 = st * BK;
-        const int ka = k0 + (lane & 15);
+        const int ka = k0 + a_k;
         const bool kav = ka < K;
 #pragma unroll
         for (int u = 0; u < NA; ++u)
-            dma_dword(rA, sa + (uint32_t)((wave * NA + u) * AGS) * 4u, kav ? arow[u] + (uint32_t)ka * 4u : kOutOfRange);
+            dma_dword(rA, sa + (uint32_t)((wave * NA + u) * AGS) * 4u,
+                      kav ? arow[u] + (uint32_t)ka * (uint32_t)sizeof(T) : kOutOfRange);
 #pragma unroll
         for (int v = 0; v < NB; ++v) {
             const int x = wave * NB + v;                  // chunk of the B stage
-            const int kb = k0 + (64 * x + lane) / BN;
-            dma_dword(rB, sb + (uint32_t)(x * BCS) * 4u, kb < K ? bcol[v] + (uint32_t)kb * ldb4 : kOutOfRange);
+            const int kb = k0 + (64 * x + lane) / EW / BN;
+            dma_dword(rB, sb + (uint32_t)(x * BCS) * 4u, kb < K ? bcol[v] + (uint32_t)kb * ldbb : kOutOfRange);
         }
     };
 
@@ -340,14 +355,14 @@ __global__ __launch_bounds__(NT) void gemm_dma_f32(Slots slots, const FlatTile *
 #pragma unroll
     for (int i = 0; i < WBM; ++i) {
         const int r = wm + i * 16 + c;
-        aoff[i] = (r >> 2) * AGS + (r & 3) * 16 + 4 * g;
+        aoff[i] = (r / RG) * AGS + (r % RG) * 16 * EW + 4 * g * EW;
     }
 #pragma unroll
     for (int j = 0; j < WBN; ++j)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            // k = 4 g + q: row-major index in the 16 x BN tile, plus the padding of its chunk
-            const int f = (4 * g + q) * BN + wn + j * 16 + c;
+            // k = 4 g + q: row-major dword of the 16 x BN tile, plus the padding of its chunk
+            const int f = ((4 * g + q) * BN + wn + j * 16 + c) * EW;
             boff[j][q] = A_DW + f + (f >> 6) * PB;
         }
 
@@ -363,14 +378,25 @@ __global__ __launch_bounds__(NT) void gemm_dma_f32(Slots slots, const FlatTile *
         __syncthreads();
         if (s + NS - 1 < nsteps) issue(s + NS - 1);
         const float *st = sm + (s % NS) * ST_DW;
-        f4 a[WBM];
-        float b[WBN][4];
+        T a[WBM][4], b[WBN][4];
 #pragma unroll
-        for (int i = 0; i < WBM; ++i) a[i] = *reinterpret_cast<const f4 *>(st + aoff[i]);
+        for (int i = 0; i < WBM; ++i) {
+            // the lane's four consecutive k of its row: EW 16-byte reads
+            const f4 lo = *reinterpret_cast<const f4 *>(st + aoff[i]);
+            if constexpr (EW == 1) {
+                a[i][0] = lo.x; a[i][1] = lo.y; a[i][2] = lo.z; a[i][3] = lo.w;
+            } else {
+                const f4 hi = *reinterpret_cast<const f4 *>(st + aoff[i] + 4);
+                a[i][0] = __builtin_bit_cast(double, f2v{lo.x, lo.y});
+                a[i][1] = __builtin_bit_cast(double, f2v{lo.z, lo.w});
+                a[i][2] = __builtin_bit_cast(double, f2v{hi.x, hi.y});
+                a[i][3] = __builtin_bit_cast(double, f2v{hi.z, hi.w});
+            }
+        }
 #pragma unroll
         for (int j = 0; j < WBN; ++j)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) b[j][q] = st[boff[j][q]];
+            for (int q = 0; q < 4; ++q) b[j][q] = *reinterpret_cast<const T *>(st + boff[j][q]);
 #pragma unroll
         for (int q = 0; q < 4; ++q)
 #pragma unroll
@@ -379,12 +405,14 @@ __global__ __launch_bounds__(NT) void gemm_dma_f32(Slots slots, const FlatTile *
                 for (int j = 0; j < WBN; ++j) acc[i][j] = mfma16(a[i][q], b[j][q], acc[i][j]);
     }
 
+    // result rows held by (lane, register r): v_mfma_f64_16x16x4 returns row
+    // 4 r + lane/16, v_mfma_f32_16x16x4 row 4 (lane/16) + r; column lane % 16
     TC *C = static_cast<TC *>(const_cast<void *>(slots.p[ft.c_slot])) + ft.c_off;
 #pragma unroll
     for (int i = 0; i < WBM; ++i)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int row = (lane >> 4) * 4 + r;
+            const int row = EW == 2 ? r * 4 + (lane >> 4) : (lane >> 4) * 4 + r;
             const int gm = m0 + wm + i * 16 + row;
             if (gm >= M) continue;
             TC *Cr = C + (ft.rmap >= 0 ? rowoff[ft.rmap + gm] : (int64_t)gm * ft.ldc);
@@ -407,7 +435,6 @@ __global__ __launch_bounds__(NT) void gemm_dma_f32(Slots slots, const FlatTile *
 // small terms first.  K steps of 16 keep the LDS at 2 x (BM + BN) x 80 bytes,
 // so several workgroups share a CU and hide each other's load latency (the
 // short K loops of these contractions are latency-bound, not MFMA-bound).
-typedef float f2v __attribute__((ext_vector_type(2)));
 typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
 typedef short s4v __attribute__((ext_vector_type(4)));
 
@@ -600,12 +627,22 @@ static void dispatch_shape(bool ta, bool tb, dim3 g, hipStream_t s, const GemmAr
 }
 
 // Pipeline depth of the LDS-DMA kernel: two stages (loads one K step ahead)
-// keep 8 workgroups of 64 x 64 resident per CU, which measured faster on the
-// H_eff GEMMs than three or four stages at lower occupancy.
+// keep 8 FP32 workgroups of 64 x 64 resident per CU, which measured faster on
+// the H_eff GEMMs than three or four stages at lower occupancy.
 constexpr int kDmaStages = 2;
-template <typename TC, int BM, int BN, int WGM>
+template <typename T, typename TC, int BM, int BN, int WGM>
 static void dispatch_dma(dim3 g, hipStream_t s, const Slots &sl, const FlatTile *t, const int64_t *ro, int n) {
-    hipLaunchKernelGGL((gemm_dma_f32<TC, BM, BN, WGM, kDmaStages>), g, dim3(NT), 0, s, sl, t, ro, n);
+    hipLaunchKernelGGL((gemm_dma<T, TC, BM, BN, WGM, kDmaStages>), g, dim3(NT), 0, s, sl, t, ro, n);
+}
+template <typename T, typename TC>
+static void dispatch_dma_shape(TileShape shape, dim3 g, hipStream_t s, const Slots &sl, const FlatTile *t,
+                               const int64_t *ro, int n) {
+    switch (shape) {
+        case TileShape::T128x32_D: dispatch_dma<T, TC, 128, 32, 4>(g, s, sl, t, ro, n); break;
+        case TileShape::T64x64_D: dispatch_dma<T, TC, 64, 64, 2>(g, s, sl, t, ro, n); break;
+        case TileShape::T32x128_D: dispatch_dma<T, TC, 32, 128, 1>(g, s, sl, t, ro, n); break;
+        default: break;
+    }
 }
 
 template <typename T, typename TC>
@@ -653,26 +690,13 @@ static void dispatch_bf16(TileShape shape, bool ta, bool tb, dim3 g, hipStream_t
     }
 }
 
-void launch_gemm_flat(TileShape shape, bool c_is_f64, const Slots &slots, const FlatTile *tiles,
+void launch_gemm_flat(GemmPrec prec, TileShape shape, bool c_is_f64, const Slots &slots, const FlatTile *tiles,
                       const int64_t *rowoff, int ntiles, hipStream_t s) {
     if (ntiles <= 0) return;
     const dim3 g(ntiles);
-    switch (shape) {
-        case TileShape::T128x32_D:
-            if (c_is_f64) dispatch_dma<double, 128, 32, 4>(g, s, slots, tiles, rowoff, ntiles);
-            else dispatch_dma<float, 128, 32, 4>(g, s, slots, tiles, rowoff, ntiles);
-            break;
-        case TileShape::T64x64_D:
-            if (c_is_f64) dispatch_dma<double, 64, 64, 2>(g, s, slots, tiles, rowoff, ntiles);
-            else dispatch_dma<float, 64, 64, 2>(g, s, slots, tiles, rowoff, ntiles);
-            break;
-        case TileShape::T32x128_D:
-            if (c_is_f64) dispatch_dma<double, 32, 128, 1>(g, s, slots, tiles, rowoff, ntiles);
-            else dispatch_dma<float, 32, 128, 1>(g, s, slots, tiles, rowoff, ntiles);
-            break;
-        default:
-            break;
-    }
+    if (prec == GemmPrec::F64) dispatch_dma_shape<double, double>(shape, g, s, slots, tiles, rowoff, ntiles);
+    else if (c_is_f64) dispatch_dma_shape<float, double>(shape, g, s, slots, tiles, rowoff, ntiles);
+    else dispatch_dma_shape<float, float>(shape, g, s, slots, tiles, rowoff, ntiles);
 }
 
 void launch_gemm(GemmPrec prec, TileShape shape, bool ta, bool tb, bool c_is_f64, const Slots &slots,

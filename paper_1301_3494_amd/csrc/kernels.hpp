@@ -101,8 +101,8 @@ enum class TileShape {
     T64x64 = 0, T128x32 = 1, T32x128 = 2, T128x128 = 3,
     T64x64_K16 = 4, T128x32_K16 = 5,   // half-depth K steps
     T64x64_K8 = 6, T128x32_K8 = 7,     // quarter-depth K steps
-    // FP32, non-transposed operands: K steps of 16 staged by direct-to-LDS
-    // loads several steps ahead (other operands: the half-depth kernel)
+    // FP32 / FP64, non-transposed operands: K steps of 16 staged by
+    // direct-to-LDS loads (other operands: the half-depth kernel)
     T128x32_D = 8, T64x64_D = 9, T32x128_D = 10
 };
 constexpr int kNumShapes = 11;
@@ -133,9 +133,10 @@ inline int tile_bn(TileShape t) {
 void launch_gemm(GemmPrec prec, TileShape shape, bool ta, bool tb, bool c_is_f64, const Slots &slots,
                  const GemmItem *items, const GemmSeg *segs, const GemmTile *tiles, const int64_t *rowoff,
                  int ntiles, hipStream_t s);
-// FP32 operands, non-transposed, one segment per item, LDS-DMA tile shape
-// (T128x32_D, T64x64_D, T32x128_D); one workgroup per entry of `tiles`.
-void launch_gemm_flat(TileShape shape, bool c_is_f64, const Slots &slots, const FlatTile *tiles,
+// FP32 or FP64 operands (prec F32 / F64), non-transposed, one segment per
+// item, LDS-DMA tile shape (T128x32_D, T64x64_D, T32x128_D); one workgroup per
+// entry of `tiles`.
+void launch_gemm_flat(GemmPrec prec, TileShape shape, bool c_is_f64, const Slots &slots, const FlatTile *tiles,
                       const int64_t *rowoff, int ntiles, hipStream_t s);
 // chunk: kLcChunk or kLcChunkSmall elements per tile (as the tiles were built).
 void launch_lincomb(bool f64, int chunk, const Slots &slots, const LcTask *tasks, const LcSrc *srcs,

@@ -367,8 +367,8 @@ int64_t GemmList::split_k(int parts, int pslot, LcList &reduce, bool all) {
 }
 
 void GemmList::launch(GemmPrec prec, bool c_is_f64, const Slots &sl, hipStream_t s) const {
-    if (prec == GemmPrec::F32 && !ftiles.empty()) {
-        launch_gemm_flat(shape, c_is_f64, sl, d_ftiles.as<FlatTile>(), d_rowoff.as<int64_t>(), (int)ftiles.size(), s);
+    if ((prec == GemmPrec::F32 || prec == GemmPrec::F64) && !ftiles.empty()) {
+        launch_gemm_flat(prec, shape, c_is_f64, sl, d_ftiles.as<FlatTile>(), d_rowoff.as<int64_t>(), (int)ftiles.size(), s);
         return;
     }
     launch_gemm(prec, shape, ta, tb, c_is_f64, sl, d_items.as<GemmItem>(), d_segs.as<GemmSeg>(),
@@ -592,7 +592,7 @@ void HeffPlan::build(const Bond &bl_, const Bond &br_, const Phys &p_, const Mpo
     if (prec == PDMRG_BF16X3)
         g1.shapes_allowed = g3.shapes_allowed = (1u << (int)TileShape::T64x64) | (1u << (int)TileShape::T128x32) |
                                                 (1u << (int)TileShape::T32x128) | (1u << (int)TileShape::T128x128);
-    if (prec == PDMRG_F32) {   // both lists are non-transposed
+    if (prec != PDMRG_BF16X3) {   // both lists are non-transposed
         g1.shapes_allowed |= kDmaShapes;
         g3.shapes_allowed |= kDmaShapes;
     }

@@ -17,7 +17,7 @@ struct RowBlock {
 struct GemmList {
     bool ta = false, tb = false;
     TileShape shape = TileShape::T64x64;   // set by pick_tile()
-    unsigned shapes_allowed = ((1u << kNumShapes) - 1) & ~kDmaShapes;   // FP32 plans add kDmaShapes
+    unsigned shapes_allowed = ((1u << kNumShapes) - 1) & ~kDmaShapes;   // H_eff plans add kDmaShapes
     std::vector<GemmItem> items;
     std::vector<GemmSeg> segs;
     std::vector<GemmTile> tiles;           // in launch order (workgroup b runs tiles[b]); item < 0: idle
@@ -28,7 +28,7 @@ struct GemmList {
     double flops = 0.0;
     DevBuf d_items, d_segs, d_tiles, d_rowoff;
     // LDS-DMA shapes on lists of single-segment items: the tiles as FlatTile
-    // records in the same launch order (used by launch() for FP32 inputs)
+    // records in the same launch order (used by launch() for FP32 and FP64)
     std::vector<FlatTile> ftiles;
     DevBuf d_ftiles;
 

@@ -129,3 +129,37 @@ def test_f32_every_tile_shape(case, shape, parts, tmp_path):
     say(f"f32 shape {SHAPES[shape]} parts {parts}: tiles {info['tiles_Lpsi']} / {info['tiles_R']}, rel err {err:.3e}")
     assert np.array_equal(y, y1)
     assert err <= 1e-5
+
+
+@pytest.mark.parametrize("parts", [1, 3])
+@pytest.mark.parametrize("shape", [8, 9, 10])
+def test_f64_lds_dma_tile_shapes(case, shape, parts, tmp_path):
+    """The LDS-DMA tile shapes in FP64, forced for both stages, against the
+    cost-model FP64 plan (register-staged kernel) to 1e-12."""
+    import torch
+    from paper_1301_3494_amd import _lib as pl
+    B1, B2, P, W1, W2, L, R, x = case
+    y0 = _apply(pl, torch, 0, pl.F64, case)
+    ctx = pl.Context(0)
+    pl.set_autotune(ctx, 1)
+    pl.Heff(ctx, B1, B2, P, W1, W2, L, R, pl.F64).free()
+    f = tmp_path / "plans.tsv"
+    pl.autotune_export(str(f))
+    rows = [r.split("\t") for r in f.read_text().splitlines() if r]
+    mine = [r[0] for r in rows if r[0].split("|")[1] == str(pl.F64)]
+    assert mine
+    f.write_text("".join("%s\t%d\t%d\t%d\n" % (k, shape, shape, parts) for k in mine))
+    pl.autotune_import(str(f))
+    op = pl.Heff(ctx, B1, B2, P, W1, W2, L, R, pl.F64)
+    info = op.info()
+    assert info["shape_Lpsi"] == SHAPES[shape] and info["shape_R"] == SHAPES[shape]
+    y = torch.empty_like(x)
+    op.apply(x, y)
+    torch.cuda.synchronize()
+    y = y.cpu().numpy()
+    op.free()
+    ctx.close()
+    err = np.linalg.norm(y - y0) / np.linalg.norm(y0)
+    say(f"f64 shape {SHAPES[shape]} parts {parts}: rel err {err:.3e}")
+    assert err <= 1e-12
+    assert np.max(np.abs(y - y0)) <= 1e-12 * np.max(np.abs(y0))

@@ -68,23 +68,24 @@ def test_full_size_heff_matches_oracle(ctx, problem, prec, tol):
     op.free()
 
 
+@pytest.mark.parametrize("prec,tol", [(pl.F32, 1e-5), (pl.F64, 1e-12)])
 @pytest.mark.parametrize("shape", [8, 9, 10])
-def test_full_size_f32_lds_dma_shapes(ctx, problem, shape, tmp_path):
-    """The LDS-DMA FP32 tiles (128x32, 64x64, 32x128), forced for both stages
-    with 8 K parts at the full-size bond, against the oracle."""
+def test_full_size_lds_dma_shapes(ctx, problem, shape, prec, tol, tmp_path):
+    """The LDS-DMA tiles (128x32, 64x64, 32x128) in FP32 and FP64, forced for
+    both stages with 8 K parts at the full-size bond, against the oracle."""
     P = problem
     mpo, bonds, c = P["mpo"], P["bonds"], P["c"]
     t, (B1, B2, Ph) = tables(bonds[c], bonds[c + 2], PQ, mpo.deltas[c], mpo.deltas[c + 2])
     Ld = dev(blocks_to_flat(P["L"], t["L"][0], t["L"][1], pl.ENV_L))
     Rd = dev(blocks_to_flat(P["R"], t["R"][0], t["R"][1], pl.ENV_R))
     W1, W2 = mpo_site(mpo, c), mpo_site(mpo, c + 1)
-    pl.Heff(ctx, B1, B2, Ph, W1, W2, Ld, Rd, pl.F32).free()      # this operator's tuning entry
+    pl.Heff(ctx, B1, B2, Ph, W1, W2, Ld, Rd, prec).free()      # this operator's tuning entry
     f0, f = tmp_path / "tuned.tsv", tmp_path / "plans.tsv"
     pl.autotune_export(str(f0))
-    keys = [r.split("\t")[0] for r in f0.read_text().splitlines() if r and r.split("|")[1] == str(pl.F32)]
+    keys = [r.split("\t")[0] for r in f0.read_text().splitlines() if r and r.split("|")[1] == str(prec)]
     f.write_text("".join("%s\t%d\t%d\t8\n" % (k, shape, shape) for k in keys))
     pl.autotune_import(str(f))
-    op = pl.Heff(ctx, B1, B2, Ph, W1, W2, Ld, Rd, pl.F32)
+    op = pl.Heff(ctx, B1, B2, Ph, W1, W2, Ld, Rd, prec)
     info = op.info()
     assert info["shape_Lpsi"] == info["shape_R"] and info["shape_R"].endswith("dma")
     x = dev(blocks_to_flat(P["psi"], t["x"][0], t["x"][1], pl.TWO_SITE))
@@ -92,9 +93,11 @@ def test_full_size_f32_lds_dma_shapes(ctx, problem, shape, tmp_path):
     op.apply(x, y)
     a = flatten(flat_to_blocks(host(y), t["x"][0], pl.TWO_SITE), P["keys"], P["shapes"])
     err = rel_err(a, P["yref"])
-    say("  forced", info["shape_R"], "parts", info["splitk_parts"], "rel err", err)
+    say("  forced", info["shape_R"], "prec", prec, "parts", info["splitk_parts"], "rel err", err)
     assert np.all(np.isfinite(a))
-    assert err <= 1e-5
+    assert err <= tol
+    if prec == pl.F64:
+        assert np.max(np.abs(a - P["yref"])) <= 1e-12 * np.max(np.abs(P["yref"]))
     op.free()
     pl.autotune_import(str(f0))   # the tuned plans again
 
