@@ -596,8 +596,14 @@ void HeffPlan::build(const Bond &bl_, const Bond &br_, const Phys &p_, const Mpo
         g1.shapes_allowed |= kDmaShapes;
         g3.shapes_allowed |= kDmaShapes;
     }
-    g1.pick_tile();
-    g3.pick_tile();
+    for (GemmList *g : {&g1, &g3}) {
+        // the cost model keeps FP64 on the register-staged kernel, which measured
+        // faster than the LDS-DMA one in FP64 (the autotuner still times both)
+        const unsigned all = g->shapes_allowed;
+        if (prec == PDMRG_F64) g->shapes_allowed &= ~kDmaShapes;
+        g->pick_tile();
+        g->shapes_allowed = all;
+    }
     const std::vector<int64_t> sz = {X.size, X.size, Lt.size, Rt.size, nT1, nT2, 0};
     g1.validate(sz);
     w.validate(sz);
