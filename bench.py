@@ -570,6 +570,39 @@ def fidelity_leg(ctx, pl, synth, torch, N=100, warm=2, sched=(100, 150, 200, 200
     return out
 
 
+def fig3_run(ctx, pl, synth, torch, N=200, warm=5, mmax=600):
+    """The Fig. 3 study at the paper's size: open S = 1/2 and S = 1 Heisenberg
+    chains of 200 sites in 2 regions, without and with 5 serial warm-up sweeps
+    at m = 50; parallel sweeps at m = 100, 100, 200, 200, ..., mmax, mmax (m
+    raised after every other sweep); per sweep the prediction infidelity at
+    the shared centre bond (its Davidson converged to 1e-10), the energy and
+    the sweep seconds."""
+    sched = [m for m in range(100, mmax + 1, 100) for _ in range(2)]
+    out = {"workload": "open Heisenberg chains, N = %d, 2 regions, parallel m schedule %s" % (N, sched)}
+    for name, lattice, q in (("s_half_chain", "chain", (-1, 1)), ("s_one_chain", "chain_s1", (-2, 0, 2))):
+        mpo = pl.Mpo(lattice, N, 1, (1.0, 1.0))
+        for nw in (0, warm):
+            bonds, sites = synth.random_mps(N, 16, 12, phys_q=q)
+            mps = pl.Mps(ctx, bonds, sites, q, 0)
+            dav, davs = pl.dav_params(4, 8, 1e-8), pl.dav_params(60, 10, 1e-10)
+            for _ in range(nw):
+                mps.sweep(mpo, 50, 1, dav=dav, dav_shared=davs)
+            rows = []
+            for m in sched:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                rep = mps.sweep(mpo, m, 2, dav=dav, dav_shared=davs)
+                torch.cuda.synchronize()
+                rows.append({"m": m, "infidelity": rep["max_infidelity"], "energy": rep["energy"],
+                             "seconds": round(time.perf_counter() - t0, 3)})
+                print("bench: fig3 %s warm-up %d m %d infidelity %.3e energy %.12f %.2f s" % (
+                    name, nw, m, rows[-1]["infidelity"], rows[-1]["energy"], rows[-1]["seconds"]),
+                    file=sys.stderr, flush=True)
+            mps.free()
+            out["%s_warmup%d" % (name, nw)] = rows
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -581,6 +614,9 @@ def main():
     ap.add_argument("--no-large", action="store_true", help="skip the matvec rates of the m >= 2000 bonds")
     ap.add_argument("--no-steps", action="store_true", help="skip the per-step timings")
     ap.add_argument("--only-sweep", action="store_true", help="run only the sweep-seconds leg (for profiling)")
+    ap.add_argument("--fig3", action="store_true",
+                    help="run only the prediction-fidelity study at the paper's size (200-site chains, m up to "
+                         "600; minutes) and print its JSON")
     ap.add_argument("--sequential-regions", action="store_true",
                     help="sweep leg: regions one after the other on one stream instead of concurrently")
     ap.add_argument("--tune-db", default=os.path.join(ROOT, "paper_1301_3494_amd", "tuning", "mi355x.tsv"),
@@ -605,6 +641,10 @@ def main():
         pl.autotune_import(args.tune_db)
     if args.only_sweep:
         print(json.dumps({"sweep": sweep_leg(ctx, pl, synth, torch, concurrent=not args.sequential_regions)}))
+        ctx.close()
+        return
+    if args.fig3:
+        print(json.dumps({"prediction_fidelity_fig3": fig3_run(ctx, pl, synth, torch)}))
         ctx.close()
         return
     wl = build_workload(ctx, pl, synth, np, torch)
