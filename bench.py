@@ -603,6 +603,42 @@ def fig3_run(ctx, pl, synth, torch, N=200, warm=5, mmax=600):
     return out
 
 
+def fig1_run(ctx, pl, synth, torch, regions=(1, 2, 4, 8), sched=(100, 200, 400, 600, 800, 1000, 1300, 1600, 2000, 2000)):
+    """The Fig. 1 timing on one GPU: DMRG of the S = 1/2 Heisenberg model on
+    the 24 x 8 cylinder, 10 sweeps ending with two at m = 2000, run with n
+    real-space regions whose work goes to n concurrent streams of the one
+    device (the paper's n nodes); the first sweep is serial for every n.
+    Speedup S(n) = T(1) / T(n) over the whole calculation, and the final
+    energies (the paper's calculations agree to 1e-5)."""
+    Lx, Ly = 24, 8
+    N = Lx * Ly
+    mpo = pl.Mpo("square", Lx, Ly, (1.0, 1.0))
+    out = {"workload": "Heisenberg 24x8 cylinder, sweeps at m = %s, FP64" % (list(sched),)}
+    for n in regions:
+        bonds, sites = synth.random_mps(N, 16, 5)
+        mps = pl.Mps(ctx, bonds, sites, (-1, 1), 0)
+        dav, davs = pl.dav_params(4, 8, 1e-8), pl.dav_params(40, 8, 1e-10)
+        rows = []
+        t_all = 0.0
+        for k, m in enumerate(sched):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rep = mps.sweep(mpo, m, 1 if k == 0 else n, dav=dav, dav_shared=davs)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            t_all += dt
+            rows.append({"m": m, "energy": rep["energy"], "seconds": round(dt, 3)})
+            print("bench: fig1 regions %d sweep %d m %d energy %.10f %.2f s" % (n, k + 1, m, rep["energy"], dt),
+                  file=sys.stderr, flush=True)
+        mps.free()
+        out["regions_%d" % n] = {"seconds": round(t_all, 2), "energy": rows[-1]["energy"], "sweeps": rows}
+    t1 = out["regions_%d" % regions[0]]["seconds"]
+    out["speedup"] = {str(n): round(t1 / out["regions_%d" % n]["seconds"], 3) for n in regions}
+    e1 = out["regions_%d" % regions[0]]["energy"]
+    out["max_rel_energy_diff"] = max(abs(out["regions_%d" % n]["energy"] - e1) / abs(e1) for n in regions)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -614,6 +650,9 @@ def main():
     ap.add_argument("--no-large", action="store_true", help="skip the matvec rates of the m >= 2000 bonds")
     ap.add_argument("--no-steps", action="store_true", help="skip the per-step timings")
     ap.add_argument("--only-sweep", action="store_true", help="run only the sweep-seconds leg (for profiling)")
+    ap.add_argument("--fig1", action="store_true",
+                    help="run only the region-parallel timing of the 24x8 cylinder (m up to 2000, 1/2/4/8 "
+                         "regions on this GPU; minutes) and print its JSON")
     ap.add_argument("--fig3", action="store_true",
                     help="run only the prediction-fidelity study at the paper's size (200-site chains, m up to "
                          "600; minutes) and print its JSON")
@@ -641,6 +680,10 @@ def main():
         pl.autotune_import(args.tune_db)
     if args.only_sweep:
         print(json.dumps({"sweep": sweep_leg(ctx, pl, synth, torch, concurrent=not args.sequential_regions)}))
+        ctx.close()
+        return
+    if args.fig1:
+        print(json.dumps({"region_speedup_fig1": fig1_run(ctx, pl, synth, torch)}))
         ctx.close()
         return
     if args.fig3:
