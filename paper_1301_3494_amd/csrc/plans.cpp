@@ -83,8 +83,11 @@ double GemmList::padded_flops(TileShape t) const {
 void GemmList::pick_tile() {
     // Relative throughput per padded flop of each shape, from timings of the
     // H_eff GEMMs of the 8 x 4 cylinder (m = 1024) on MI355X: shorter K steps
-    // (more resident workgroups) win on these short, ragged K loops.
-    static const double kRate[kNumShapes] = {1.0, 1.0, 0.8, 0.75, 1.1, 1.15, 1.05, 1.2, 1.25, 1.2, 0.9};
+    // (more resident workgroups) win on these short, ragged K loops, and the
+    // LDS-DMA shapes (FP32) ran 1.4-1.9x faster than their full-depth base
+    // shapes (stage 1: 64x64 51.6 -> 36.4 us, 128x32 56.8 -> 38.5 us,
+    // 32x128 70.6 -> 37.6 us).
+    static const double kRate[kNumShapes] = {1.0, 1.0, 0.8, 0.75, 1.1, 1.15, 1.05, 1.2, 1.45, 1.45, 1.2};
     double best = 0.0;
     bool have = false;
     for (int t = 0; t < kNumShapes; ++t) {
