@@ -126,8 +126,9 @@ int pdmrg_ctx_set_timing(pdmrg_ctx *ctx, int enable);
  *      bond sectors and MPO widths, so later operators of the same shape are
  *      not re-timed (sweep() uses cached plans but never times candidates);
  *   2  as 1, with one line per tuned signature on stderr.
- * Results are identical for every shape in FP64; in FP32 / BF16x3 they can
- * differ in the last bits (the split-K partition follows the tile count).
+ * Every shape computes the same product; the summation order follows the
+ * tile shape and the K split, so results can differ in the last bits (FP64:
+ * about 1e-15 relative).  A given plan is bitwise reproducible.
  * Returns PDMRG_EINVAL for another level. */
 int pdmrg_ctx_set_autotune(pdmrg_ctx *ctx, int level);
 /* Debugging aid, process-wide: on != 0 fills every device buffer the library
@@ -214,9 +215,11 @@ int heff_info(const pdmrg_heff *op, double *flops_Lpsi, double *flops_W, double 
               int64_t *n_psi, int64_t *n_L, int64_t *n_R, int64_t *n_T1, int64_t *n_T2);
 /* Plan of an operator: tile shape of the stage-1 and stage-3 grouped GEMMs
  * (0: 64x64, 1: 128x32, 2: 32x128, 3: 128x128; 4: 64x64 and 5: 128x32 with
- * half-depth, 6: 64x64 and 7: 128x32 with quarter-depth K steps), their tile
- * counts, and the
- * number of K parts stage 3 is split into (outputs optional). */
+ * half-depth, 6: 64x64 and 7: 128x32 with quarter-depth K steps; 8: 128x32,
+ * 9: 64x64, 10: 32x128 with K steps of 16 staged by direct-to-LDS loads, FP32
+ * and FP64 only), their tile counts (without the idle padding of the launch
+ * order), and the number of K parts of the longest stage-3 item (the other
+ * items are cut into ranges of about the same length).  Outputs optional. */
 int heff_plan_info(const pdmrg_heff *op, int32_t *shape_Lpsi, int32_t *shape_R, int32_t *tiles_Lpsi,
                    int32_t *tiles_R, int32_t *splitk_parts);
 /* diag(H_eff) into diag_dev (TWO_SITE layout, FP64). */
