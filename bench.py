@@ -623,7 +623,7 @@ def fig1_run(ctx, pl, synth, torch, regions=(1, 2, 4, 8), sched=(100, 200, 400, 
         for k, m in enumerate(sched):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            rep = mps.sweep(mpo, m, 1 if k == 0 else n, dav=dav, dav_shared=davs)
+            rep = mps.sweep(mpo, m, 1 if k == 0 else n, dav=dav, dav_shared=davs, concurrent=True)
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
             t_all += dt

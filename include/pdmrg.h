@@ -281,7 +281,11 @@ int davidson_step(pdmrg_ctx *ctx, pdmrg_heff *op, pdmrg_heff *op64, double *psi_
  * mode 0 = ABSORB_RIGHT (A kept, centre Lambda B), 1 = ABSORB_LEFT (B kept,
  * centre A Lambda), 2 = SPLIT (A Lambda and Lambda B, plus V = 1/Lambda
  * floored at 1/(1e-12 lambda_max); Eqs. eqn:inverse, eqn:isvd).
- * Returns a result handle; read the new bond with svd_result_bond, then copy
+ * Returns a result handle (status PDMRG_WARN_NOT_CONVERGED if a block's
+ * Jacobi iteration met its tolerance in none of 60 sweeps: the result is then
+ * an exact rotation of the block with absolute, not relative, accuracy; else
+ * PDMRG_WARN_V_FLOORED if SPLIT floored a V entry); read the new bond with
+ * svd_result_bond, then copy
  * tensors into caller buffers with svd_result_copy (SITE layouts on
  * (bl, new) and (new, br); lam / V in bond order). */
 #define PDMRG_ABSORB_RIGHT 0
@@ -347,6 +351,9 @@ typedef struct {
     double max_infidelity;            /* largest 1 - |<Psi'|Psi>| over the merges:
                                          Psi' = psi_L V psi_R (Eq. eqn:merge), Psi the
                                          shared-bond eigenvector (Fig. 3); 0 without merges */
+    int32_t n_svd_unconverged;        /* SVD blocks whose Jacobi iteration ran out of
+                                         sweeps (kept with absolute accuracy)   */
+    int32_t pad_;
 } pdmrg_sweep_report;
 int mps_alloc(pdmrg_ctx *ctx, int nsites, const pdmrg_phys *phys, int32_t q_target,
               const pdmrg_bond *bonds, pdmrg_mps **out);
@@ -424,7 +431,7 @@ int mps_expect_pairs(pdmrg_ctx *ctx, pdmrg_mps *mps, int nterms, const double *c
  *     M_z = <S^z> averaged over the sites (xc, y) of sublattice
  *     (x - y) mod 3 = 0 (the one mpo_build pins), xc = (Lx - 1)/2 zero-based;
  *     needs Ly % 3 == 0.
- * The pair values come from mps_expect_pairs (concurrent streams), the site
+ * The pair values come from mps_expect_pairs (pairs one after the other), the site
  * values from mps_expect_site.  PDMRG_EINVAL on a gauge, size or kind
  * mismatch. */
 int mps_order_parameter(pdmrg_ctx *ctx, pdmrg_mps *mps, int kind, int Lx, int Ly, double *value);

@@ -46,7 +46,8 @@ class CSweepParams(Structure):
 class CSweepReport(Structure):
     _fields_ = [("energy", c_double), ("max_trunc", c_double), ("seconds", c_double),
                 ("seconds_heff", c_double), ("n_matvec", c_int64), ("n_floored", c_int32),
-                ("max_bond", c_int32), ("max_infidelity", c_double)]
+                ("max_bond", c_int32), ("max_infidelity", c_double),
+                ("n_svd_unconverged", c_int32), ("pad_", c_int32)]
 
 
 class PdmrgError(RuntimeError):
@@ -458,7 +459,7 @@ class Mps:
             check(lib().mps_set_site(h, i, flat.ctypes.data_as(POINTER(c_double)), n))
 
     def sweep(self, mpo, max_m, n_regions=1, prec=F64, refine=True, dav=None, dav_shared=None,
-              cutoff=1e-12, eps=1e-4, concurrent=True):
+              cutoff=1e-12, eps=1e-4, concurrent=False):
         p = CSweepParams(int(max_m), int(n_regions), int(prec), int(bool(refine)),
                          dav or dav_params(4, 8, 1e-8), dav_shared or dav_params(40, 8, 1e-10),
                          float(cutoff), float(eps), int(bool(concurrent)), 0)
@@ -524,7 +525,7 @@ class Mps:
                                     out.ctypes.data_as(POINTER(c_double))))
         return out
 
-    def expect_pairs(self, terms, pairs, concurrent=True):
+    def expect_pairs(self, terms, pairs, concurrent=False):
         """mps_expect_pairs: sum_t c_t <A_t(i) B_t(k)> for each (i, k) in pairs;
         terms = [(c, A, B), ...] with d x d operators."""
         c = np.ascontiguousarray([t[0] for t in terms], dtype=np.float64)

@@ -49,6 +49,7 @@ int pdmrg_ctx_create(int device, void *stream, pdmrg_ctx **out) {
 int pdmrg_ctx_destroy(pdmrg_ctx *ctx) {
     API_BEGIN
     if (!ctx) return PDMRG_OK;
+    ctx->pool.reset();   // joins the idle worker threads
     (void)hipStreamSynchronize(ctx->stream);
     for (pdmrg_ctx *c : ctx->sub) {
         (void)hipStreamSynchronize(c->stream);
@@ -412,7 +413,13 @@ int svd_truncate(pdmrg_ctx *ctx, const pdmrg_bond *bl, const pdmrg_bond *br, con
     auto r = std::make_unique<pdmrg_svd>();
     svd_truncate_run(ctx, Bond::from(bl), Bond::from(br), Phys::from(phys), psi_dev, max_m, cutoff, eps, mode, r->r);
     const bool floored = mode == PDMRG_SPLIT && r->r.n_floored > 0;
+    const int unconv = r->r.n_unconverged;
     *out = r.release();
+    if (unconv > 0) {
+        pdmrg::set_last_error("svd_truncate: " + std::to_string(unconv) +
+                              " block(s) of the Jacobi SVD ran out of sweeps (absolute accuracy only)");
+        return PDMRG_WARN_NOT_CONVERGED;
+    }
     if (floored) {
         pdmrg::set_last_error("svd_truncate: some V entries were floored");
         return PDMRG_WARN_V_FLOORED;

@@ -5,12 +5,16 @@
 
 #include <algorithm>
 #include <atomic>
+#include <condition_variable>
 #include <cstdint>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <stdexcept>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/pdmrg.h"
@@ -95,6 +99,8 @@ struct MpoSite {
 };
 
 // ---------------------------------------------------------------- device memory
+// Bytes the caching allocator reserves for a request of n bytes.
+size_t size_class(size_t n);
 // pdmrg_set_alloc_poison: fill buffers with NaN bytes as they are handed out
 extern std::atomic<bool> g_alloc_poison;
 
@@ -123,6 +129,34 @@ void upload(DevBuf &buf, const std::vector<T> &v, hipStream_t s) {
     if (!v.empty()) HIP_OK(hipMemcpyAsync(buf.ptr, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
 }
 
+// Host worker threads for independent jobs of one context (the regions of a
+// half-sweep, the merges of one merge phase, groups of correlators).  Threads
+// are created on first use and live as long as the context, so a sweep does
+// not create and tear down threads per phase; each one selects the context's
+// device before every job.
+class WorkerPool {
+public:
+    explicit WorkerPool(int device) : device_(device) {}
+    ~WorkerPool();
+    WorkerPool(const WorkerPool &) = delete;
+    WorkerPool &operator=(const WorkerPool &) = delete;
+    // fn(k) for k = 0 .. n-1, job k on worker k; returns once every job has
+    // returned.  fn must not throw (jobs report errors through their own
+    // records).
+    void run(int n, const std::function<void(int)> &fn);
+
+private:
+    void loop(int k);
+    int device_;
+    std::mutex mu_;
+    std::condition_variable cv_work_, cv_done_;
+    std::vector<std::thread> threads_;
+    std::vector<const std::function<void(int)> *> job_;
+    std::vector<char> ready_;
+    int pending_ = 0;
+    bool quit_ = false;
+};
+
 }  // namespace pdmrg
 
 // Events per timed heff_apply: before stage 1, the W stage, the stage-3 GEMM,
@@ -146,8 +180,10 @@ struct pdmrg_ctx {
     // cached per block signature, 2 = 1 plus a log line per tuned plan.
     int autotune = 0;
     // Per-region contexts of concurrent sweeps (own stream and work space),
-    // created on first use and destroyed with this context.
+    // created on first use and destroyed with this context; their host
+    // threads come from `pool`.
     std::vector<pdmrg_ctx *> sub;
+    std::unique_ptr<pdmrg::WorkerPool> pool;
     bool owns_stream = false;
     // heff_apply through captured graphs (replayed on `stream`); the capture
     // happens on cap_stream, created on first use.

@@ -15,7 +15,6 @@
 #include <chrono>
 #include <cmath>
 #include <functional>
-#include <thread>
 
 using namespace pdmrg;
 
@@ -25,8 +24,18 @@ struct pdmrg_mps {
     std::vector<Bond> bonds;                 // N + 1
     std::vector<DevBuf> sites;               // SITE layouts, FP64
     std::vector<DevBuf> L, R;                // environments on bonds 0..N
-    std::map<int, std::vector<double>> V;    // shared bond -> V (bond order)
-    std::map<int, DevBuf> Vd;
+    // V = Lambda^{-1} per bond (bond order; host and device copies) where
+    // hasV[b] is set.  Sized N + 1 once, so the concurrent jobs of a sweep
+    // only assign the slots of their own bonds and never change the
+    // containers themselves.
+    std::vector<std::vector<double>> V;
+    std::vector<DevBuf> Vd;
+    std::vector<char> hasV;
+    void clear_v() {
+        for (auto &v : V) v.clear();
+        for (auto &d : Vd) d = DevBuf();
+        std::fill(hasV.begin(), hasV.end(), 0);
+    }
     bool ready = false;                      // canonical form + environments
     int n_regions = 1;
     bool split = false;
@@ -120,17 +129,14 @@ struct Driver {
             env_R(i + 1);
             m->sites[i] = take(r.left, na);
             m->sites[i + 1] = take(r.right, nb);
-            // keys of the shared bonds exist before any concurrent merge runs
-            auto vit = m->V.find(i + 1);
-            if (vit == m->V.end()) vit = m->V.emplace(i + 1, std::vector<double>()).first;
-            vit->second = r.V;
-            auto dit = m->Vd.find(i + 1);
-            if (dit == m->Vd.end()) dit = m->Vd.emplace(i + 1, DevBuf()).first;
-            dit->second = DevBuf();
-            upload(dit->second, r.V, s());
+            m->V[i + 1] = r.V;
+            m->Vd[i + 1] = DevBuf();
+            upload(m->Vd[i + 1], r.V, s());
+            m->hasV[i + 1] = 1;
             rep.n_floored += r.n_floored;
         }
         HIP_OK(hipStreamSynchronize(s()));
+        rep.n_svd_unconverged += r.n_unconverged;
         rep.max_trunc = std::max(rep.max_trunc, r.discarded);
         rep.max_bond = std::max(rep.max_bond, r.bnew.total);
     }
@@ -184,7 +190,8 @@ struct Driver {
     }
 
     void merge_shared(int j) {
-        DevBuf psi = contract(j, m->Vd.at(j + 1).as<double>());
+        PD_REQUIRE(m->hasV[j + 1], PDMRG_EINVAL, "merge: no V on the shared bond");
+        DevBuf psi = contract(j, m->Vd[j + 1].as<double>());
         // prediction fidelity of the merged state (Fig. 3): psi_L V psi_R
         // against the state the shared-bond eigensolver converges to
         const int64_t n = two_site_layout(m->bonds[j], m->bonds[j + 2], m->p).size;
@@ -243,48 +250,53 @@ struct Driver {
     }
 
     // Runs independent jobs (disjoint sites, bonds and environments): with
-    // prm.concurrent, one host thread and one stream per job; else one after
-    // the other here.  Reports are merged; the first error is rethrown.
+    // prm.concurrent, each on a worker thread of the context's pool with its
+    // own stream and work space; else one after the other here.  Reports are
+    // merged; the first error is rethrown.  Jobs only read the MPS containers
+    // and assign the slots (sites, bonds, environments, V) of their own sites
+    // and bonds.
     void run_jobs(const std::vector<std::function<void(Driver &)>> &jobs) {
         if (!prm.concurrent || jobs.size() <= 1) {
             for (auto &j : jobs) j(*this);
             return;
         }
         HIP_OK(hipStreamSynchronize(s()));
+        const int n = (int)jobs.size();
         std::vector<Driver> ds;
-        for (size_t k = 0; k < jobs.size(); ++k) {
-            Driver d{sub_ctx((int)k), m, mpo};
+        for (int k = 0; k < n; ++k) {
+            Driver d{sub_ctx(k), m, mpo};
             d.prm = prm;
+            d.envs = envs;
             ds.push_back(d);
         }
-        std::vector<int> codes(jobs.size(), 0);
-        std::vector<std::string> msgs(jobs.size());
-        std::vector<std::thread> th;
-        for (size_t k = 0; k < jobs.size(); ++k)
-            th.emplace_back([&, k] {
-                try {
-                    HIP_OK(hipSetDevice(ctx->device));
-                    jobs[k](ds[k]);
-                    HIP_OK(hipStreamSynchronize(ds[k].s()));
-                } catch (const Error &e) {
-                    codes[k] = e.code;
-                    msgs[k] = e.what();
-                } catch (const std::exception &e) {
-                    codes[k] = PDMRG_EINVAL;
-                    msgs[k] = e.what();
-                }
-            });
-        for (auto &t : th) t.join();
-        for (size_t k = 0; k < jobs.size(); ++k) {
+        if (!ctx->pool) ctx->pool.reset(new WorkerPool(ctx->device));
+        std::vector<int> codes(n, 0);
+        std::vector<std::string> msgs(n);
+        const std::function<void(int)> body = [&](int k) {
+            try {
+                HIP_OK(hipSetDevice(ctx->device));
+                jobs[k](ds[k]);
+                HIP_OK(hipStreamSynchronize(ds[k].s()));
+            } catch (const Error &e) {
+                codes[k] = e.code;
+                msgs[k] = e.what();
+            } catch (const std::exception &e) {
+                codes[k] = PDMRG_EINVAL;
+                msgs[k] = e.what();
+            }
+        };
+        ctx->pool->run(n, body);
+        for (int k = 0; k < n; ++k) {
             const pdmrg_sweep_report &r = ds[k].rep;
             rep.n_matvec += r.n_matvec;
             rep.n_floored += r.n_floored;
             rep.max_trunc = std::max(rep.max_trunc, r.max_trunc);
             rep.max_bond = std::max(rep.max_bond, r.max_bond);
             rep.max_infidelity = std::max(rep.max_infidelity, r.max_infidelity);
+            rep.n_svd_unconverged += r.n_svd_unconverged;
             t_heff += ds[k].t_heff;
         }
-        for (size_t k = 0; k < jobs.size(); ++k)
+        for (int k = 0; k < n; ++k)
             if (codes[k] != 0) throw Error(codes[k], msgs[k]);
     }
 
@@ -358,8 +370,7 @@ struct Driver {
             ctx->ws_env.ensure((size_t)(std::max<int64_t>(ep.nU1, 1) + std::max<int64_t>(ep.nU2, 1)) * sizeof(double));
             double *U1 = ctx->ws_env.as<double>();
             ep.run(GemmPrec::F64, E.ptr, m->sites[i].ptr, out.ptr, U1, U1 + std::max<int64_t>(ep.nU1, 1), s());
-            auto it = m->Vd.find(i + 1);
-            if (it != m->Vd.end() && m->split) scale_env_v(out, ep.Eout, m->bonds[i + 1], Wi.dr, it->second.as<double>());
+            if (m->split && m->hasV[i + 1]) scale_env_v(out, ep.Eout, m->bonds[i + 1], Wi.dr, m->Vd[i + 1].as<double>());
             HIP_OK(hipStreamSynchronize(s()));
             E = std::move(out);
         }
@@ -376,9 +387,10 @@ struct Driver {
     // below 1e-14 of the largest).
     void unsplit() {
         if (!m->split) return;
-        for (auto &kv : m->Vd) {
-            const int j = kv.first - 1;
-            DevBuf psi = contract(j, kv.second.as<double>());
+        for (int b = 1; b < m->N; ++b) {
+            if (!m->hasV[b]) continue;
+            const int j = b - 1;
+            DevBuf psi = contract(j, m->Vd[b].as<double>());
             SvdOut r;
             svd_truncate_run(ctx, m->bonds[j], m->bonds[j + 2], m->p, psi.as<double>(), 1 << 30, 1e-14, prm.eps,
                              PDMRG_ABSORB_LEFT, r);
@@ -387,8 +399,7 @@ struct Driver {
             m->sites[j + 1] = take(r.B, site_layout(r.bnew, m->bonds[j + 2], m->p).size);
         }
         HIP_OK(hipStreamSynchronize(s()));
-        m->V.clear();
-        m->Vd.clear();
+        m->clear_v();
         m->split = false;
         m->icanon = false;
         m->regions.clear();
@@ -415,9 +426,9 @@ struct Driver {
             m->sites[i] = take(r.left, site_layout(m->bonds[i], r.bnew, m->p).size);
             m->sites[i + 1] = take(r.right, site_layout(r.bnew, m->bonds[i + 2], m->p).size);
             m->V[i + 1] = r.V;
-            DevBuf vd;
-            upload(vd, r.V, s());
-            m->Vd[i + 1] = std::move(vd);
+            m->Vd[i + 1] = DevBuf();
+            upload(m->Vd[i + 1], r.V, s());
+            m->hasV[i + 1] = 1;
             nfl += r.n_floored;
             HIP_OK(hipStreamSynchronize(s()));
         }
@@ -510,7 +521,10 @@ struct Driver {
             ctx->ws_env.ensure((size_t)(std::max<int64_t>(ep.nU1, 1) + std::max<int64_t>(ep.nU2, 1)) * sizeof(double));
             double *U1 = ctx->ws_env.as<double>();
             ep.run(GemmPrec::F64, E.ptr, m->sites[j].ptr, out.ptr, U1, U1 + std::max<int64_t>(ep.nU1, 1), s());
-            if (j < k) scale_env_v(out, ep.Eout, m->bonds[j + 1], W.dr, m->Vd.at(j + 1).as<double>());
+            if (j < k) {
+                PD_REQUIRE(m->hasV[j + 1], PDMRG_EINVAL, "correlator: no V on an inner bond");
+                scale_env_v(out, ep.Eout, m->bonds[j + 1], W.dr, m->Vd[j + 1].as<double>());
+            }
             HIP_OK(hipStreamSynchronize(s()));
             E = std::move(out);
             last = ep.Eout;
@@ -615,6 +629,9 @@ int mps_alloc(pdmrg_ctx *ctx, int nsites, const pdmrg_phys *phys, int32_t q_targ
     PD_REQUIRE(m->bonds[nsites].q == std::vector<int>{q_target} && m->bonds[nsites].dim == std::vector<int>{1},
                PDMRG_ESHAPE, "mps_alloc: last bond must be {q=target, dim=1}");
     m->sites.resize(nsites);
+    m->V.resize(nsites + 1);
+    m->Vd.resize(nsites + 1);
+    m->hasV.assign(nsites + 1, 0);
     for (int i = 0; i < nsites; ++i) {
         const int64_t n = site_layout(m->bonds[i], m->bonds[i + 1], m->p).size;
         PD_REQUIRE(n > 0, PDMRG_ESHAPE, "mps_alloc: site " + std::to_string(i) + " has no allowed block");
@@ -635,8 +652,7 @@ int mps_set_site(pdmrg_mps *m, int site, const double *host_data, int64_t n) {
     m->ready = false;
     m->split = false;
     m->icanon = false;
-    m->V.clear();
-    m->Vd.clear();
+    m->clear_v();
     API_CATCH
 }
 
@@ -736,10 +752,10 @@ int mps_inverse_canonical(pdmrg_ctx *ctx, pdmrg_mps *m, double cutoff, double ep
 int mps_get_v(const pdmrg_mps *m, int bond, double *V, int64_t cap) {
     API_TRY
     PD_REQUIRE(m && V && bond >= 0 && bond <= m->N, PDMRG_EINVAL, "mps_get_v: bad arguments");
-    auto it = m->V.find(bond);
-    PD_REQUIRE(it != m->V.end() && m->split, PDMRG_EINVAL, "mps_get_v: no V on this bond");
-    PD_REQUIRE(cap >= (int64_t)it->second.size(), PDMRG_EINVAL, "mps_get_v: capacity too small");
-    std::copy(it->second.begin(), it->second.end(), V);
+    PD_REQUIRE(m->hasV[bond] && m->split, PDMRG_EINVAL, "mps_get_v: no V on this bond");
+    const std::vector<double> &v = m->V[bond];
+    PD_REQUIRE(cap >= (int64_t)v.size(), PDMRG_EINVAL, "mps_get_v: capacity too small");
+    std::copy(v.begin(), v.end(), V);
     API_CATCH
 }
 
@@ -836,7 +852,7 @@ int mps_order_parameter(pdmrg_ctx *ctx, pdmrg_mps *m, int kind, int Lx, int Ly, 
             A[8 + e] = sm[e], B[8 + e] = sp[e];
         }
         std::vector<double> v(si.size());
-        const int rc = mps_expect_pairs(ctx, m, 3, coef, A, B, (int)si.size(), si.data(), sk.data(), 1, v.data());
+        const int rc = mps_expect_pairs(ctx, m, 3, coef, A, B, (int)si.size(), si.data(), sk.data(), 0, v.data());
         if (rc != PDMRG_OK) return rc;
         double acc = 0.0;
         for (int y = 0; y < Ly; ++y) acc += v[Ly + y] - 0.5 * v[y] - 0.5 * v[2 * Ly + y];

@@ -62,6 +62,7 @@ struct SvdOut {
     std::vector<double> lam, V;    // in new-bond order
     double discarded = 0;
     int n_floored = 0;
+    int n_unconverged = 0;         // Jacobi blocks that ran out of sweeps
 };
 // Process-wide tuning cache to / from a text file (one line per signature).
 // Cylinder geometry of the Sec. III lattices: site (x, y) in the snake order

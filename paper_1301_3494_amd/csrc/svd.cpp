@@ -22,8 +22,12 @@ namespace pdmrg {
 namespace {
 
 constexpr int kJacBlock = 8;
-constexpr int kMaxSweeps = 40;
+constexpr int kMaxSweeps = 60;
 constexpr int kMaxDepth = 8;
+// Relative size (to a block's largest singular value) below which singular
+// values are rounding noise of the FP64 block: the Appendix recursion does not
+// descend into a trailing set that lies wholly below it.
+constexpr double kNoise = 64.0 * 2.220446049250313e-16;
 
 struct Arena {
     std::shared_ptr<DevBuf> buf = std::make_shared<DevBuf>();
@@ -67,8 +71,12 @@ void run_copies(const std::vector<CopyTask> &tasks, hipStream_t s) {
 }
 
 // One-sided block Jacobi on every matrix; returns sorted factors in `arena`.
+// floor (one per matrix, used from depth 1 on): values below it are rounding
+// noise of the block at depth 0, where the recursion stops.  n_unconv is
+// incremented by the number of blocks (at any depth) whose Jacobi iteration
+// did not meet its tolerance within kMaxSweeps sweeps.
 void svd_batch(pdmrg_ctx *ctx, const std::vector<Mat> &mats, std::vector<SvdRes> &out, double eps, int depth,
-               std::vector<Arena> &keep) {
+               std::vector<Arena> &keep, const std::vector<double> &floor, int &n_unconv) {
     hipStream_t s = ctx->stream;
     const int nm = (int)mats.size();
     out.assign(nm, SvdRes());
@@ -164,6 +172,9 @@ void svd_batch(pdmrg_ctx *ctx, const std::vector<Mat> &mats, std::vector<SvdRes>
         }
         if (!any) break;
     }
+    // blocks whose rows were not orthogonal to tol after kMaxSweeps sweeps:
+    // still an exact rotation of the block (absolute accuracy), reported
+    for (int i = 0; i < nm; ++i) n_unconv += active[i] ? 1 : 0;
 
     // singular values = row norms
     std::vector<RowRef> refs;
@@ -228,8 +239,9 @@ void svd_batch(pdmrg_ctx *ctx, const std::vector<Mat> &mats, std::vector<SvdRes>
     run_copies(gt, s);
 
     // Appendix recursion on the trailing singular values
-    if (depth < kMaxDepth) {
+    {
         std::vector<int> who, pstart;
+        std::vector<double> subfloor;
         for (int i = 0; i < nm; ++i) {
             const auto &l = out[i].lam;
             if (l.empty() || !(l[0] > 0.0)) continue;
@@ -237,10 +249,18 @@ void svd_batch(pdmrg_ctx *ctx, const std::vector<Mat> &mats, std::vector<SvdRes>
             for (int j = 0; j < (int)l.size(); ++j)
                 if (l[j] < eps * l[0]) { p = j; break; }
             if (p < 0) continue;
+            // trailing values all below the noise floor of the original block
+            // (kNoise of its largest value) carry no information to recover
+            const double fl = depth == 0 ? kNoise * l[0] : floor[i];
+            if (!(l[p] >= fl)) continue;
             who.push_back(i);
             pstart.push_back(p);
+            subfloor.push_back(fl);
         }
         if (!who.empty()) {
+            PD_REQUIRE(depth < kMaxDepth, PDMRG_ENUMERIC,
+                       "svd: Appendix recursion still finds values below eps after " + std::to_string(kMaxDepth) +
+                           " levels");
             Arena sub;
             size_t need2 = 64;
             for (size_t w = 0; w < who.size(); ++w) {
@@ -280,7 +300,7 @@ void svd_batch(pdmrg_ctx *ctx, const std::vector<Mat> &mats, std::vector<SvdRes>
             gx.launch(GemmPrec::F64, true, sl, s);
             HIP_OK(hipStreamSynchronize(s));
             std::vector<SvdRes> so;
-            svd_batch(ctx, subs, so, eps, depth + 1, keep);
+            svd_batch(ctx, subs, so, eps, depth + 1, keep, subfloor, n_unconv);
             // Ut[p:] <- Ut~ Ut[p:] ; Vt[p:] <- Vt~ Vt[p:]  (via T, then copy back)
             const double *SB = so[0].Ut;
             for (auto &r : so) SB = std::min<const double *>(SB, std::min(r.Ut, r.Vt));
@@ -418,7 +438,9 @@ void svd_truncate_run(pdmrg_ctx *ctx, const Bond &bl, const Bond &br, const Phys
     run_copies(gather, s);
     std::vector<SvdRes> res;
     std::vector<Arena> keep;
-    svd_batch(ctx, mats, res, eps, 0, keep);
+    int n_unconv = 0;
+    svd_batch(ctx, mats, res, eps, 0, keep, {}, n_unconv);
+    out.n_unconverged = n_unconv;
 
     // global truncation
     struct Cand { double l; int q, idx, sec; };

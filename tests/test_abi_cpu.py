@@ -141,6 +141,25 @@ def test_mpo_bulk_dimension_of_benchmark_lattices():
     assert D4.max() == 23                       # 3 (Ly + 1) + 2
 
 
+def test_jq2_mpo_of_the_16x8_cylinder_against_operator_schmidt_ranks():
+    """The library's J-Q2 MPO on the 16 x 8 cylinder (the m = 4000 workload):
+    D is never below the operator-Schmidt rank of the Hamiltonian across any
+    cut and equals it, 98 = 2 + 3 Ly + 9 Ly, at every bulk column cut (the
+    largest rank of the lattice); inside a column the prefix machine keeps
+    110 channels where the rank is 80."""
+    from test_oracle_pins import product_basis_rank
+    Lx, Ly = 16, 8
+    N = Lx * Ly
+    _, D = _lib_mpo(3, Lx, Ly, (1.0, 0.7))
+    terms = models.jq2_terms(Lx, Ly, 1.0, 0.7)
+    ranks = [product_basis_rank(terms, c) for c in range(1, N)]
+    assert all(D[c] >= ranks[c - 1] for c in range(1, N))
+    for x in range(2, Lx - 1):
+        assert D[x * Ly] == ranks[x * Ly - 1] == 2 + 12 * Ly
+    assert max(ranks) == 98 and D.max() == 110
+    assert ranks[Ly * Lx // 2 + 2] == 80
+
+
 def test_errors_are_reported_not_raised():
     L = _lib()
     h = c_void_p()

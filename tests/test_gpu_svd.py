@@ -7,6 +7,7 @@ import pytest
 
 from helpers import pl, synth, blocks_to_flat, flat_to_blocks, dev, host, say
 from oracle import dmrg
+from test_oracle_pins import tie_psi, TIE_CASES
 from oracle.blocks import Bond, two_site_keys, two_site_shape, flatten
 
 pytestmark = pytest.mark.gpu
@@ -126,3 +127,67 @@ def test_split_then_merge_round_trip(ctx):
     err = np.linalg.norm(host(out) - host(x))
     say("  split/merge round trip", err)
     assert err <= 1e-12
+
+
+def _middle_blocks(psi, bl, br):
+    """The middle-charge blocks of Psi as dense matrices (rows (s1, a), columns
+    (s2, b)), keyed by charge."""
+    Bl, Br = Bond(bl), Bond(br)
+    out = {}
+    for qm in sorted({q + s for q in Bl.qs for s in PQ}):
+        rows = [(s1, qm - PQ[s1]) for s1 in range(2) if Bl.has(qm - PQ[s1])]
+        cols = [(s2, qm + PQ[s2]) for s2 in range(2) if Br.has(qm + PQ[s2])]
+        if rows and cols:
+            out[qm] = np.block([[psi[(qa, s1, s2)] for (s2, qb) in cols] for (s1, qa) in rows])
+    return out
+
+
+def _mp_singular_values(M, dps=40):
+    import mpmath
+    mpmath.mp.dps = dps
+    s = mpmath.svd_r(mpmath.matrix(M.tolist()), compute_uv=False)
+    return np.array(sorted((float(v) for v in s), reverse=True))
+
+
+@pytest.mark.parametrize("mode", [pl.ABSORB_RIGHT, pl.ABSORB_LEFT, pl.SPLIT])
+def test_svd_small_values_relative_accuracy(ctx, mode):
+    """Appendix accuracy on the GPU: graded blocks (24 x 28, 48 x 56, 24 x 28,
+    singular values from 1 down to 1e-12 with random orthogonal factors)
+    against 40-digit singular values of the same FP64 blocks (mpmath): every
+    lambda, and V = 1/lambda where it is not floored, to 1e-5 relative down to
+    1e-12 lambda_1, in all three modes."""
+    bl, br = {-1: 24, 1: 24}, {-1: 28, 1: 28}
+    psi = _graded_psi(bl, br, 11, 1e-12)
+    ref = np.concatenate([_mp_singular_values(M_) for q, M_ in sorted(_middle_blocks(psi, bl, br).items())])
+    ref = ref / np.sqrt(np.sum(ref ** 2))
+    B1, B2, P = pl.Bond(bl), pl.Bond(br), pl.Phys(PQ)
+    tx, nx = pl.layout(pl.TWO_SITE, B1, B2, P)
+    x = dev(blocks_to_flat(psi, tx, nx, pl.TWO_SITE))
+    res = pl.SvdResult(ctx, B1, B2, P, x, 10 ** 6, cutoff=0.0, eps=1e-4, mode=mode)
+    assert res.lam.size == ref.size
+    lmax = ref.max()
+    ok = ref >= 1e-12 * lmax
+    rel = np.abs(res.lam - ref) / ref
+    say("  mode", mode, "smallest lambda/lambda_1 %.2e" % (ref.min() / lmax),
+        "max rel err %.2e" % rel[ok].max())
+    assert rel[ok].max() <= 1e-5
+    if mode == pl.SPLIT:
+        lam_max = res.lam.max()
+        unfl = res.lam >= 1e-12 * lam_max
+        assert np.abs(res.V[unfl] * ref[unfl] - 1.0).max() <= 1e-5
+        assert np.allclose(res.V[~unfl], 1.0 / (1e-12 * lam_max), rtol=1e-15)
+
+
+@pytest.mark.parametrize("max_m", sorted(TIE_CASES))
+def test_svd_truncation_tie_break(ctx, max_m):
+    """Exactly degenerate singular values in the q = -2 and q = +2 sectors with
+    max_m cutting the multiplet (R1): the GPU keeps the smaller charge, and its
+    bond table equals the oracle's bit for bit."""
+    bl, br, psi = tie_psi()
+    B1, B2, P = pl.Bond(bl), pl.Bond(br), pl.Phys(PQ)
+    tx, nx = pl.layout(pl.TWO_SITE, B1, B2, P)
+    x = dev(blocks_to_flat(psi, tx, nx, pl.TWO_SITE))
+    ref = dmrg.svd_truncate(psi, Bond(bl), Bond(br), PQ, max_m, "right", cutoff=0.0)
+    for mode in (pl.ABSORB_RIGHT, pl.ABSORB_LEFT, pl.SPLIT):
+        res = pl.SvdResult(ctx, B1, B2, P, x, max_m, cutoff=0.0, mode=mode)
+        assert res.bond == dict(zip(ref.bond.qs, ref.bond.dims)) == TIE_CASES[max_m]

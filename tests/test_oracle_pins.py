@@ -56,6 +56,74 @@ def test_mpo_bond_dimension_is_operator_schmidt_rank_in_bulk():
             assert mpo.D(cut) == r, cut
 
 
+def product_basis_rank(terms, cut):
+    """Operator-Schmidt rank of sum_t c_t prod_s op_{t,s} across the cut
+    (sites < cut on the left) for terms over the Hilbert-Schmidt orthogonal
+    local basis {I, Sz, S+, S-}: every distinct product is an orthogonal basis
+    element, so the rank is that of the coefficient matrix C[left product,
+    right product] after equal products are merged.  Rows whose only entry is
+    in the identity column (terms wholly on the left) span one direction and
+    are merged into one row.  Works at any lattice size."""
+    from collections import defaultdict
+    acc = defaultdict(float)
+    for coef, f in terms:
+        assert all(o in ("I", "Sz", "Sp", "Sm") for _, o in f)
+        left = tuple((s, o) for s, o in f if s < cut and o != "I")
+        right = tuple((s, o) for s, o in f if s >= cut and o != "I")
+        acc[(left, right)] += coef
+    rows = defaultdict(dict)
+    for (left, right), c in acc.items():
+        if c != 0.0:
+            rows[left][right] = c
+    keep = [d for d in rows.values() if set(d) != {()}]
+    if any(set(d) == {()} for d in rows.values()):
+        keep.append({(): 1.0})
+    cols = {r: k for k, r in enumerate(sorted({r for d in keep for r in d}))}
+    A = np.zeros((len(keep), len(cols)))
+    for i, d in enumerate(keep):
+        for r, c in d.items():
+            A[i, cols[r]] = c
+    return int(np.linalg.matrix_rank(A, tol=1e-12 * np.abs(A).max()))
+
+
+def _sparse_dense_hamiltonian(terms, N):
+    """Kronecker sum of the terms through sparse products (independent of the
+    MPO and of the oracle's dense builder)."""
+    import scipy.sparse as sp
+    H = sp.csr_matrix((2 ** N, 2 ** N))
+    eye = sp.identity(2, format="csr")
+    for coef, f in terms:
+        ops = dict(f)
+        M_ = sp.identity(1, format="csr")
+        for s in range(N):
+            M_ = sp.kron(M_, sp.csr_matrix(OPS[ops[s]]) if s in ops else eye, format="csr")
+        H = H + coef * M_
+    return H.toarray()
+
+
+def test_jq2_operator_schmidt_rank_pins_the_mpo():
+    """J-Q2 cylinder (Eq. eqn:q2 plus the J term), 4 x 3: the product-basis rank
+    equals the rank of the brute-force H reshaped across each cut; the MPO's
+    D is never below it, equals it at the bulk column cut (2 + 3 Ly + 9 Ly:
+    start, done, three channels per open site and nine per plaquette crossing
+    the cut), and inside a column the prefix machine keeps more channels than
+    the rank (50 against 20 at Ly = 3)."""
+    Lx, Ly = 4, 3
+    N = Lx * Ly
+    terms = models.jq2_terms(Lx, Ly, 1.0, 0.7)
+    mpo = M.build_mpo(terms, N, OPS, PQ)
+    H = _sparse_dense_hamiltonian(terms, N)
+    for cut in (3, 4, 6):
+        assert product_basis_rank(terms, cut) == M.operator_schmidt_rank(H, N, 2, cut), cut
+    ranks = [product_basis_rank(terms, c) for c in range(N + 1)]
+    assert all(mpo.D(c) >= ranks[c] for c in range(1, N))
+    assert ranks[6] == mpo.D(6) == 2 + 12 * Ly
+    assert ranks[4] == ranks[5] == 20 and mpo.D(4) == mpo.D(5) == 50
+    # the first and last column cuts: the Hamiltonian of a single column lies in
+    # the span of its two-site channels, one less than the bulk count
+    assert ranks[3] == ranks[9] == 2 + 12 * Ly - 1
+
+
 def test_mpo_bulk_dimensions():
     chain = M.build_mpo(models.heisenberg_terms(models.chain_bonds(10)), 10, OPS, PQ)
     assert max(chain.D(b) for b in range(11)) == 5
@@ -299,6 +367,50 @@ def test_svd_truncate_eckart_young_and_gauge():
     # untruncated: A Lambda B rebuilds psi exactly
     back = dmrg.contract_two(full.A, full.center, PQ)
     assert max(np.abs(back[k] - psi[k]).max() for k in psi) < 1e-13
+
+
+def tie_psi():
+    """Two-site blocks on bonds {-1: 2, 1: 2} -> {-1: 2, 1: 2} whose
+    middle-charge blocks are diagonal: q = -2 and q = +2 both diag(1/2, 1/4),
+    q = 0 diag(1, 1/8, 1/8, 1/32).  Their singular values are exact powers of
+    two, so the q = -2 and q = +2 values tie exactly (and so do two q = 0
+    values)."""
+    bl = {-1: 2, 1: 2}
+    br = {-1: 2, 1: 2}
+    diag = {-2: [0.5, 0.25], 0: [1.0, 0.125, 0.125, 0.03125], 2: [0.5, 0.25]}
+    Bl, Br = Bond(bl), Bond(br)
+    psi = {}
+    for qm, vals in diag.items():
+        rows = [(s1, qm - PQ[s1]) for s1 in range(2) if Bl.has(qm - PQ[s1])]
+        cols = [(s2, qm + PQ[s2]) for s2 in range(2) if Br.has(qm + PQ[s2])]
+        nr = sum(Bl.dim(q) for _, q in rows)
+        nc = sum(Br.dim(q) for _, q in cols)
+        Mq = np.zeros((nr, nc))
+        Mq[np.arange(len(vals)), np.arange(len(vals))] = vals
+        r0 = 0
+        for s1, qa in rows:
+            c0 = 0
+            for s2, qb in cols:
+                psi[(qa, s1, s2)] = Mq[r0:r0 + Bl.dim(qa), c0:c0 + Br.dim(qb)].copy()
+                c0 += Br.dim(qb)
+            r0 += Bl.dim(qa)
+    return bl, br, psi
+
+
+# max_m -> kept sectors (R1: lambda descending, then charge ascending, then index)
+TIE_CASES = {1: {0: 1}, 2: {-2: 1, 0: 1}, 3: {-2: 1, 0: 1, 2: 1}, 4: {-2: 2, 0: 1, 2: 1},
+             6: {-2: 2, 0: 2, 2: 2}, 7: {-2: 2, 0: 3, 2: 2}}
+
+
+@pytest.mark.parametrize("max_m", sorted(TIE_CASES))
+def test_truncation_tie_break_keeps_smaller_charge(max_m):
+    """Exactly degenerate singular values in two sectors with max_m cutting the
+    multiplet: the oracle keeps the smaller charge (q = -2 before q = +2), and
+    inside a sector the count is what the bond records."""
+    bl, br, psi = tie_psi()
+    for step1 in (dmrg.svd_gesvd, dmrg.svd_rho):
+        res = dmrg.svd_truncate(psi, Bond(bl), Bond(br), PQ, max_m, "right", cutoff=0.0, step1=step1)
+        assert dict(zip(res.bond.qs, res.bond.dims)) == TIE_CASES[max_m]
 
 
 def test_split_merge_round_trip():
