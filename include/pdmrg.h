@@ -254,6 +254,21 @@ int env_update_info(int dir, const pdmrg_bond *bl, const pdmrg_bond *br, const p
 int env_update(pdmrg_ctx *ctx, int dir, const pdmrg_bond *bl, const pdmrg_bond *br,
                const pdmrg_phys *phys, const pdmrg_mpo_site *W, const double *env_in_dev,
                const double *site_dev, double *env_out_dev, int prec);
+/* env_update_noalloc: the same update for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation).  It calls no hipMalloc / hipFree: the two intermediates
+ * and the device copies of the work lists live in a file-scope device array
+ * of 64 MiB per GPU, set up when a context is created on that GPU and held
+ * until the process ends.  Arguments, layouts and results are those of
+ * env_update (same kernels, same bits).  An update whose intermediates and
+ * lists need more than 64 MiB is rejected with PDMRG_EINVAL before anything
+ * is launched.  Every call on a GPU shares that GPU's array (each call
+ * overwrites what the last one left; nothing needs to start at zero), so
+ * calls that overlap on one GPU, from several threads or streams, race.
+ * Synchronises the context stream. */
+int env_update_noalloc(pdmrg_ctx *ctx, int dir, const pdmrg_bond *bl, const pdmrg_bond *br,
+                       const pdmrg_phys *phys, const pdmrg_mpo_site *W, const double *env_in_dev,
+                       const double *site_dev, double *env_out_dev, int prec);
 
 /* ---------------------------------------------------------------- Davidson
  * Lowest eigenpair of H_eff by Davidson (Rayleigh-Ritz on an orthonormal

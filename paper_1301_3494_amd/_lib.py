@@ -75,7 +75,7 @@ EXPORTS = [
     "pdmrg_last_error", "pdmrg_version", "pdmrg_ctx_create", "pdmrg_ctx_destroy", "pdmrg_ctx_set_timing",
     "pdmrg_ctx_timing", "pdmrg_ctx_set_autotune", "pdmrg_set_alloc_poison", "pdmrg_ctx_set_graphs", "pdmrg_autotune_export", "pdmrg_autotune_import", "pdmrg_layout_size", "pdmrg_layout_blocks", "mpo_build", "mpo_from_sites",
     "mpo_info", "mpo_get_site", "mpo_free", "heff_create", "heff_apply", "heff_info", "heff_plan_info", "heff_diag",
-    "heff_free", "env_update", "env_update_info", "davidson_step", "svd_truncate", "svd_result_bond", "svd_result_copy",
+    "heff_free", "env_update", "env_update_noalloc", "env_update_info", "davidson_step", "svd_truncate", "svd_result_bond", "svd_result_copy",
     "svd_free", "merge_regions", "mps_alloc", "mps_set_site", "mps_bond", "mps_get_site", "sweep",
     "mps_energy", "mps_free", "grad_site", "grad_mpo", "mps_inverse_canonical", "mps_get_v", "mps_expect_site",
     "mps_expect_pairs", "mps_order_parameter",
@@ -112,6 +112,7 @@ def _declare(L):
         "heff_plan_info": (c_int, [P, pi32, pi32, pi32, pi32, pi32]),
         "heff_free": (None, [P]),
         "env_update": (c_int, [P, c_int, pb, pb, pp, pm, P, P, P, c_int]),
+        "env_update_noalloc": (c_int, [P, c_int, pb, pb, pp, pm, P, P, P, c_int]),
         "env_update_info": (c_int, [c_int, pb, pb, pp, pm, pd, pi64]),
         "davidson_step": (c_int, [P, P, P, P, POINTER(CDavParams), pd, pd, pi32]),
         "svd_truncate": (c_int, [P, pb, pb, pp, P, c_int32, c_double, c_double, c_int, POINTER(P)]),
@@ -290,6 +291,12 @@ class Heff:
 def env_update(ctx, direction, bl, br, phys, W, env_in, site, env_out, prec=F64):
     check(lib().env_update(ctx.h, int(direction), bl.ref, br.ref, phys.ref, W.ref, ptr(env_in), ptr(site),
                            ptr(env_out), int(prec)))
+
+
+def env_update_noalloc(ctx, direction, bl, br, phys, W, env_in, site, env_out, prec=F64):
+    """env_update through the entry point that allocates no device memory."""
+    check(lib().env_update_noalloc(ctx.h, int(direction), bl.ref, br.ref, phys.ref, W.ref, ptr(env_in), ptr(site),
+                                   ptr(env_out), int(prec)))
 
 
 def env_update_info(direction, bl, br, phys, W):

@@ -39,6 +39,7 @@ int pdmrg_ctx_create(int device, void *stream, pdmrg_ctx **out) {
     HIP_OK(hipGetDeviceCount(&n));
     PD_REQUIRE(device >= 0 && device < n, PDMRG_EINVAL, "ctx_create: no such device");
     HIP_OK(hipSetDevice(device));
+    pdmrg::noalloc_init(device);
     auto *c = new pdmrg_ctx();
     c->device = device;
     c->stream = static_cast<hipStream_t>(stream);

@@ -71,6 +71,10 @@ struct SvdOut {
 inline int lattice_snake(int x, int y, int Ly) { return x * Ly + ((x % 2 == 0) ? y : Ly - 1 - y); }
 inline int tri_sublattice(int x, int y) { return ((x - y) % 3 + 3) % 3; }
 
+// Resolves the device address of env_update_noalloc's scratch array on the
+// current device (noalloc.hip); called when a context is created.
+void noalloc_init(int device);
+
 int tune_export(const char *path);
 int tune_import(const char *path);
 void grad_site_run(pdmrg_ctx *ctx, const GradPlan &plan, const double *L, const double *psi, const double *R,

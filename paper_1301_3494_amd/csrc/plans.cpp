@@ -177,6 +177,17 @@ static std::vector<GemmTile> place_tiles(const std::vector<GemmItem> &items, con
 }
 
 void GemmList::finish(hipStream_t s) {
+    build_tiles();
+    upload(d_items, items, s);
+    upload(d_segs, segs, s);
+    upload(d_tiles, tiles, s);
+    if (ftiles.empty()) d_ftiles.release();
+    else upload(d_ftiles, ftiles, s);
+    if (rowoff.empty()) d_rowoff.release();
+    else upload(d_rowoff, rowoff, s);
+}
+
+void GemmList::build_tiles() {
     if (!(shapes_allowed & (1u << (int)shape))) shape = TileShape::T64x64;
     const int bm = tile_bm(shape), bn = tile_bn(shape);
     std::vector<int64_t> kof(items.size());
@@ -219,13 +230,6 @@ void GemmList::finish(hipStream_t s) {
             ftiles.push_back(f);
         }
     }
-    upload(d_items, items, s);
-    upload(d_segs, segs, s);
-    upload(d_tiles, tiles, s);
-    if (ftiles.empty()) d_ftiles.release();
-    else upload(d_ftiles, ftiles, s);
-    if (rowoff.empty()) d_rowoff.release();
-    else upload(d_rowoff, rowoff, s);
 }
 
 static void check_span(const std::vector<int64_t> &slot_elems, int slot, int64_t off, int rows, int cols,
@@ -370,12 +374,17 @@ int64_t GemmList::split_k(int parts, int pslot, LcList &reduce, bool all) {
 }
 
 void GemmList::launch(GemmPrec prec, bool c_is_f64, const Slots &sl, hipStream_t s) const {
+    GemmDev dv{d_items.as<GemmItem>(), d_segs.as<GemmSeg>(), d_tiles.as<GemmTile>(), d_ftiles.as<FlatTile>(),
+               d_rowoff.as<int64_t>()};
+    launch(prec, c_is_f64, sl, dv, s);
+}
+
+void GemmList::launch(GemmPrec prec, bool c_is_f64, const Slots &sl, const GemmDev &dv, hipStream_t s) const {
     if ((prec == GemmPrec::F32 || prec == GemmPrec::F64) && !ftiles.empty()) {
-        launch_gemm_flat(prec, shape, c_is_f64, sl, d_ftiles.as<FlatTile>(), d_rowoff.as<int64_t>(), (int)ftiles.size(), s);
+        launch_gemm_flat(prec, shape, c_is_f64, sl, dv.ftiles, dv.rowoff, (int)ftiles.size(), s);
         return;
     }
-    launch_gemm(prec, shape, ta, tb, c_is_f64, sl, d_items.as<GemmItem>(), d_segs.as<GemmSeg>(),
-                d_tiles.as<GemmTile>(), d_rowoff.as<int64_t>(), (int)tiles.size(), s);
+    launch_gemm(prec, shape, ta, tb, c_is_f64, sl, dv.items, dv.segs, dv.tiles, dv.rowoff, (int)tiles.size(), s);
 }
 
 int LcList::add_task(int dst_slot, int64_t dst_off, int rows, int cols, int ld) {
@@ -405,13 +414,17 @@ void LcList::add_src(int slot, int64_t off, int ld, double coef) {
     elems_in += (int64_t)t.rows * t.cols;
 }
 
-void LcList::finish(hipStream_t s) {
+void LcList::build_tiles() {
     tiles.clear();
     for (size_t i = 0; i < tasks.size(); ++i) {
         const LcTask &t = tasks[i];
         const int64_t n = (int64_t)t.rows * t.cols;
         for (int64_t c = 0; c * chunk < n; ++c) tiles.push_back(LcTile{(int32_t)i, (int32_t)c, chunk, 0});
     }
+}
+
+void LcList::finish(hipStream_t s) {
+    build_tiles();
     upload(d_tasks, tasks, s);
     upload(d_srcs, srcs, s);
     upload(d_tiles, tiles, s);
@@ -423,8 +436,11 @@ void LcList::launch_f32_to_f64(const Slots &sl, hipStream_t s) const {
 }
 
 void LcList::launch(bool f64, const Slots &sl, hipStream_t s) const {
-    launch_lincomb(f64, chunk, sl, d_tasks.as<LcTask>(), d_srcs.as<LcSrc>(), d_tiles.as<LcTile>(), (int)tiles.size(),
-                   s);
+    launch(f64, sl, LcDev{d_tasks.as<LcTask>(), d_srcs.as<LcSrc>(), d_tiles.as<LcTile>()}, s);
+}
+
+void LcList::launch(bool f64, const Slots &sl, const LcDev &dv, hipStream_t s) const {
+    launch_lincomb(f64, chunk, sl, dv.tasks, dv.srcs, dv.tiles, (int)tiles.size(), s);
 }
 
 std::vector<double> two_site_mpo(const MpoSite &W1, const MpoSite &W2) {
@@ -808,6 +824,20 @@ void EnvPlan::build(int dir_, const Bond &bl_, const Bond &br_, const Phys &p_, 
     g1.finish(s);
     w.finish(s);
     g3.finish(s);
+}
+
+void EnvPlan::run(GemmPrec prec, const void *env_in, const void *site, void *env_out, void *U1, void *U2,
+                  const GemmDev &d1, const LcDev &dw, const GemmDev &d3, hipStream_t s) const {
+    Slots sl{};
+    sl.p[0] = env_in;
+    sl.p[1] = site;
+    sl.p[2] = env_out;
+    sl.p[3] = U1;
+    sl.p[4] = U2;
+    const bool f64 = prec == GemmPrec::F64;
+    g1.launch(prec, f64, sl, d1, s);
+    w.launch(f64, sl, dw, s);
+    g3.launch(prec, f64, sl, d3, s);
 }
 
 void EnvPlan::run(GemmPrec prec, const void *env_in, const void *site, void *env_out, void *U1, void *U2,

@@ -14,6 +14,20 @@ struct RowBlock {
     int32_t r0, rows, ldc;
 };
 
+// Device copies of a list's records (tiles in launch order).
+struct GemmDev {
+    const GemmItem *items;
+    const GemmSeg *segs;
+    const GemmTile *tiles;
+    const FlatTile *ftiles;
+    const int64_t *rowoff;
+};
+struct LcDev {
+    const LcTask *tasks;
+    const LcSrc *srcs;
+    const LcTile *tiles;
+};
+
 struct GemmList {
     bool ta = false, tb = false;
     TileShape shape = TileShape::T64x64;   // set by pick_tile()
@@ -43,7 +57,11 @@ struct GemmList {
     double padded_flops(TileShape t) const;
     // Build the tiles and place them for the launch (see place_tiles), upload.
     void finish(hipStream_t s);
+    // The host part of finish: tiles (and flat tiles) in launch order.
+    void build_tiles();
     void launch(GemmPrec prec, bool c_is_f64, const Slots &sl, hipStream_t s) const;
+    // Same with the records at caller-provided device addresses.
+    void launch(GemmPrec prec, bool c_is_f64, const Slots &sl, const GemmDev &dv, hipStream_t s) const;
     // Copy of the host-side lists (no device buffers).
     GemmList host_copy() const;
     // Throws unless every element an item touches lies inside its slot's
@@ -73,7 +91,9 @@ struct LcList {
     int add_task(int dst_slot, int64_t dst_off, int rows, int cols, int ld);
     void add_src(int slot, int64_t off, int ld, double coef);
     void finish(hipStream_t s);
+    void build_tiles();   // the host part of finish
     void launch(bool f64, const Slots &sl, hipStream_t s) const;
+    void launch(bool f64, const Slots &sl, const LcDev &dv, hipStream_t s) const;
     void launch_f32_to_f64(const Slots &sl, hipStream_t s) const;
     void validate(const std::vector<int64_t> &slot_elems) const;
 };
@@ -123,6 +143,10 @@ struct EnvPlan {
     // slots: 0 env_in, 1 site, 2 env_out, 3 U1, 4 U2
     void run(GemmPrec prec, const void *env_in, const void *site, void *env_out, void *U1, void *U2,
              hipStream_t s) const;
+    // Same with the work-list records at caller-provided device addresses
+    // (plan built with upload = false and the lists' build_tiles() called).
+    void run(GemmPrec prec, const void *env_in, const void *site, void *env_out, void *U1, void *U2,
+             const GemmDev &d1, const LcDev &dw, const GemmDev &d3, hipStream_t s) const;
 };
 
 // Psi' = psiL V psiR (Eq. eqn:merge).
