@@ -419,6 +419,78 @@ def sweep_leg(ctx, pl, synth, torch, m=1024, regions=4, timed=2, concurrent=True
     }
 
 
+def sweep_c3_leg(ctx, pl, synth, torch, regions=4, seed=3, concurrent=True):
+    """The metric's sweep half on its own configuration: Heisenberg 24 x 8
+    cylinder (D = 26), two serial warm-up sweeps at m = 200, then parallel
+    sweeps with 4 regions at m = 650, 650, 1100, 1100, 1550, 1550 (FP64), and
+    the last two sweeps of the schedule, at m = 2000, timed in the FP64 path
+    and in the mixed path (FP32 MFMA H_eff, FP64 Davidson refinement), both
+    from a device copy of the same state.  Davidson 4 matvecs / 1e-8 at
+    interior bonds, 40 / 1e-10 at shared bonds."""
+    Lx, Ly = 24, 8
+    mpo = pl.Mpo("square", Lx, Ly, (1.0, 1.0))
+    bonds, sites = synth.random_mps(Lx * Ly, 16, seed)
+    dav, dav_shared = pl.dav_params(4, 8, 1e-8), pl.dav_params(40, 8, 1e-10)
+    mps = pl.Mps(ctx, bonds, sites)
+    ramp = []
+    t_all = time.perf_counter()
+    for k, m in enumerate((200, 200, 650, 650, 1100, 1100, 1550, 1550)):
+        n = 1 if k < 2 else regions
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rep = mps.sweep(mpo, m, n, dav=dav, dav_shared=dav_shared, concurrent=concurrent)
+        torch.cuda.synchronize()
+        ramp.append({"m": m, "regions": n, "seconds": round(time.perf_counter() - t0, 3), "energy": rep["energy"]})
+        print("bench: c3 ramp sweep %d m %d regions %d %.2f s E=%.12f" % (k + 1, m, n, ramp[-1]["seconds"],
+                                                                          rep["energy"]), file=sys.stderr, flush=True)
+    res = {}
+    for name, prec in (("f64", pl.F64), ("mixed", pl.F32)):
+        st = mps.copy()
+        secs, reps = [], []
+        for k in range(2):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rep = st.sweep(mpo, 2000, regions, prec=prec, dav=dav, dav_shared=dav_shared, concurrent=concurrent)
+            torch.cuda.synchronize()
+            secs.append(time.perf_counter() - t0)
+            reps.append(rep)
+            print("bench: c3 %s sweep at m 2000: %.2f s E=%.15f" % (name, secs[-1], rep["energy"]),
+                  file=sys.stderr, flush=True)
+        st.free()
+        res[name] = dict(seconds=sum(secs) / len(secs), energy=reps[-1]["energy"],
+                         energies=[r["energy"] for r in reps], n_matvec=sum(r["n_matvec"] for r in reps) // 2,
+                         seconds_heff=sum(r["seconds_heff"] for r in reps) / 2,
+                         seconds_svd=sum(r["seconds_svd"] for r in reps) / 2,
+                         seconds_env=sum(r["seconds_env"] for r in reps) / 2,
+                         max_trunc=max(r["max_trunc"] for r in reps), max_bond=max(r["max_bond"] for r in reps),
+                         n_svd_unconverged=sum(r["n_svd_unconverged"] for r in reps))
+    mps.free()
+    e64, emx = res["f64"]["energy"], res["mixed"]["energy"]
+    rel = abs(emx - e64) / abs(e64)
+    return {
+        "workload": "heisenberg_cyl24x8_m2000_4regions_sweep",
+        "schedule": "2 serial sweeps at m=200, parallel (%d regions, %s) at m=650,650,1100,1100,1550,1550 in "
+                    "FP64, then the 2 sweeps at m=2000 timed per precision from copies of the same state; "
+                    "Davidson 4 matvecs / 1e-8 interior, 40 / 1e-10 shared bonds" % (
+                        regions, "concurrent" if concurrent else "one after the other"),
+        "seconds_per_sweep_f64": round(res["f64"]["seconds"], 4),
+        "seconds_per_sweep_mixed": round(res["mixed"]["seconds"], 4),
+        "speedup_mixed_vs_f64": round(res["f64"]["seconds"] / res["mixed"]["seconds"], 4),
+        "seconds_heff_f64": round(res["f64"]["seconds_heff"], 4),
+        "seconds_heff_mixed": round(res["mixed"]["seconds_heff"], 4),
+        "step_seconds_summed_over_regions": {k: {"davidson": round(v["seconds_heff"], 3),
+                                                 "svd": round(v["seconds_svd"], 3),
+                                                 "env_update": round(v["seconds_env"], 3)} for k, v in res.items()},
+        "n_matvec_per_sweep": {k: v["n_matvec"] for k, v in res.items()},
+        "energy_f64": e64, "energy_mixed": emx, "rel_energy_diff": rel, "meets_1e-9": rel <= 1e-9,
+        "energies_f64": res["f64"]["energies"], "energies_mixed": res["mixed"]["energies"],
+        "max_bond": res["f64"]["max_bond"], "max_trunc_f64": res["f64"]["max_trunc"],
+        "n_svd_unconverged": {k: v["n_svd_unconverged"] for k, v in res.items()},
+        "ramp_seconds": round(sum(r["seconds"] for r in ramp), 2), "ramp": ramp,
+        "seconds_total": round(time.perf_counter() - t_all, 2),
+    }
+
+
 SPIN_OPS = {
     "Sz": [[-0.5, 0.0], [0.0, 0.5]],
     "Sp": [[0.0, 0.0], [1.0, 0.0]],   # |up><down| (local basis: down, up)
@@ -649,7 +721,10 @@ def main():
     ap.add_argument("--no-sweep", action="store_true", help="skip the sweep-seconds leg")
     ap.add_argument("--no-large", action="store_true", help="skip the matvec rates of the m >= 2000 bonds")
     ap.add_argument("--no-steps", action="store_true", help="skip the per-step timings")
-    ap.add_argument("--only-sweep", action="store_true", help="run only the sweep-seconds leg (for profiling)")
+    ap.add_argument("--only-sweep", action="store_true",
+                    help="run only the 8x4 m=1024 sweep-seconds leg (for profiling)")
+    ap.add_argument("--only-c3", action="store_true",
+                    help="run only the 24x8 m=2000 sweep-seconds leg (the metric's sweep half; for profiling)")
     ap.add_argument("--fig1", action="store_true",
                     help="run only the region-parallel timing of the 24x8 cylinder (m up to 2000, 1/2/4/8 "
                          "regions on this GPU; minutes) and print its JSON")
@@ -680,6 +755,10 @@ def main():
         pl.autotune_import(args.tune_db)
     if args.only_sweep:
         print(json.dumps({"sweep": sweep_leg(ctx, pl, synth, torch, concurrent=not args.sequential_regions)}))
+        ctx.close()
+        return
+    if args.only_c3:
+        print(json.dumps({"sweep": sweep_c3_leg(ctx, pl, synth, torch, concurrent=not args.sequential_regions)}))
         ctx.close()
         return
     if args.fig1:
@@ -764,7 +843,8 @@ def main():
         out["large_bonds"] = large_bond_rates(ctx, pl, synth, np, torch)
     if not args.no_sweep:
         state = {}
-        out["sweep"] = sweep_leg(ctx, pl, synth, torch, concurrent=not args.sequential_regions, keep=state)
+        out["sweep"] = sweep_c3_leg(ctx, pl, synth, torch, concurrent=not args.sequential_regions)
+        out["sweep_8x4_m1024"] = sweep_leg(ctx, pl, synth, torch, concurrent=not args.sequential_regions, keep=state)
         out["measure"] = measure_leg(ctx, pl, np, torch, state)
         out["order_parameters"] = order_leg(ctx, pl, synth, torch)
         out["prediction_fidelity"] = fidelity_leg(ctx, pl, synth, torch)

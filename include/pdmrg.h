@@ -359,7 +359,9 @@ typedef struct {
     double energy;                    /* full <H> after the sweep             */
     double max_trunc;                 /* largest discarded weight             */
     double seconds;                   /* wall time of the sweep               */
-    double seconds_heff;              /* time inside H_eff matvecs            */
+    double seconds_heff;              /* time inside Davidson (H_eff matvecs and the
+                                         eigensolver's vector work); these three
+                                         times add up over concurrent regions   */
     int64_t n_matvec;
     int32_t n_floored;
     int32_t max_bond;
@@ -369,6 +371,8 @@ typedef struct {
     int32_t n_svd_unconverged;        /* SVD blocks whose Jacobi iteration ran out of
                                          sweeps (kept with absolute accuracy)   */
     int32_t pad_;
+    double seconds_svd;               /* time inside truncated SVDs           */
+    double seconds_env;               /* time inside environment updates      */
 } pdmrg_sweep_report;
 int mps_alloc(pdmrg_ctx *ctx, int nsites, const pdmrg_phys *phys, int32_t q_target,
               const pdmrg_bond *bonds, pdmrg_mps **out);
@@ -378,6 +382,10 @@ int mps_get_site(pdmrg_mps *mps, int site, double *host_data, int64_t cap);
 int sweep(pdmrg_ctx *ctx, pdmrg_mps *mps, const pdmrg_mpo *mpo, const pdmrg_sweep_params *p,
           pdmrg_sweep_report *rep);
 int mps_energy(pdmrg_ctx *ctx, pdmrg_mps *mps, const pdmrg_mpo *mpo, double *energy);
+/* Deep copy on the device (site tensors, environments, V of every bond, the
+ * region split): the copy sweeps on exactly as the source would.  Owned by
+ * the caller (mps_free). */
+int mps_copy(pdmrg_ctx *ctx, const pdmrg_mps *src, pdmrg_mps **out);
 /* Measurement sweep for dE/dW of E = <Psi|H|Psi>/<Psi|Psi> at fixed Psi:
  * G_dev (device, n_G doubles) receives G_0, ..., G_{N-1} concatenated, G_i
  * of shape [Dl_i][d][d][Dr_i] (mpo_get_site sizes), each the grad_site value

@@ -47,7 +47,8 @@ class CSweepReport(Structure):
     _fields_ = [("energy", c_double), ("max_trunc", c_double), ("seconds", c_double),
                 ("seconds_heff", c_double), ("n_matvec", c_int64), ("n_floored", c_int32),
                 ("max_bond", c_int32), ("max_infidelity", c_double),
-                ("n_svd_unconverged", c_int32), ("pad_", c_int32)]
+                ("n_svd_unconverged", c_int32), ("pad_", c_int32), ("seconds_svd", c_double),
+                ("seconds_env", c_double)]
 
 
 class PdmrgError(RuntimeError):
@@ -77,7 +78,7 @@ EXPORTS = [
     "mpo_info", "mpo_get_site", "mpo_free", "heff_create", "heff_apply", "heff_info", "heff_plan_info", "heff_diag",
     "heff_free", "env_update", "env_update_noalloc", "env_update_info", "davidson_step", "svd_truncate", "svd_result_bond", "svd_result_copy",
     "svd_free", "merge_regions", "mps_alloc", "mps_set_site", "mps_bond", "mps_get_site", "sweep",
-    "mps_energy", "mps_free", "grad_site", "grad_mpo", "mps_inverse_canonical", "mps_get_v", "mps_expect_site",
+    "mps_energy", "mps_copy", "mps_free", "grad_site", "grad_mpo", "mps_inverse_canonical", "mps_get_v", "mps_expect_site",
     "mps_expect_pairs", "mps_order_parameter",
 ]
 
@@ -125,6 +126,7 @@ def _declare(L):
         "mps_bond": (c_int, [P, c_int, pi32, pi32, pi32, c_int32]),
         "mps_get_site": (c_int, [P, c_int, pd, c_int64]),
         "sweep": (c_int, [P, P, P, POINTER(CSweepParams), POINTER(CSweepReport)]),
+        "mps_copy": (c_int, [P, P, POINTER(c_void_p)]),
         "mps_energy": (c_int, [P, P, P, pd]),
         "mps_free": (None, [P]),
         "grad_site": (c_int, [P, pb, pb, pp, pm, P, P, P, P]),
@@ -464,6 +466,15 @@ class Mps:
                 for r in range(rows):
                     flat[off + r * ld: off + r * ld + cols] = b[r]
             check(lib().mps_set_site(h, i, flat.ctypes.data_as(POINTER(c_double)), n))
+
+    def copy(self):
+        """Deep device copy (mps_copy)."""
+        other = Mps.__new__(Mps)
+        other.ctx, other.phys, other.B, other.N = self.ctx, self.phys, list(self.B), self.N
+        h = c_void_p()
+        check(lib().mps_copy(self.ctx.h, self.h, byref(h)))
+        other.h = h
+        return other
 
     def sweep(self, mpo, max_m, n_regions=1, prec=F64, refine=True, dav=None, dav_shared=None,
               cutoff=1e-12, eps=1e-4, concurrent=False):

@@ -51,7 +51,7 @@ struct Driver {
     const pdmrg_mpo *mpo;
     pdmrg_sweep_params prm{};
     pdmrg_sweep_report rep{};
-    double t_heff = 0.0;
+    double t_heff = 0.0, t_svd = 0.0, t_env = 0.0;   // wall seconds per step kind
     bool envs = true;   // gauge moves update environments (off: no MPO needed)
 
     hipStream_t s() const { return ctx->stream; }
@@ -81,6 +81,7 @@ struct Driver {
     }
 
     void env_L(int i) {   // L[i+1] from L[i] and site i
+        const auto t0 = std::chrono::steady_clock::now();
         EnvPlan ep;
         ep.build(1, m->bonds[i], m->bonds[i + 1], m->p, W(i), s());
         DevBuf out(std::max<int64_t>(ep.Eout.size, 1) * sizeof(double));
@@ -89,9 +90,11 @@ struct Driver {
         ep.run(GemmPrec::F64, m->L[i].ptr, m->sites[i].ptr, out.ptr, U1, U1 + std::max<int64_t>(ep.nU1, 1), s());
         HIP_OK(hipStreamSynchronize(s()));
         m->L[i + 1] = std::move(out);
+        t_env += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     }
 
     void env_R(int i) {   // R[i] from R[i+1] and site i
+        const auto t0 = std::chrono::steady_clock::now();
         EnvPlan ep;
         ep.build(-1, m->bonds[i], m->bonds[i + 1], m->p, W(i), s());
         DevBuf out(std::max<int64_t>(ep.Eout.size, 1) * sizeof(double));
@@ -100,6 +103,7 @@ struct Driver {
         ep.run(GemmPrec::F64, m->R[i + 1].ptr, m->sites[i].ptr, out.ptr, U1, U1 + std::max<int64_t>(ep.nU1, 1), s());
         HIP_OK(hipStreamSynchronize(s()));
         m->R[i] = std::move(out);
+        t_env += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     }
 
     DevBuf take(const DevBuf &src, int64_t n) {
@@ -157,19 +161,24 @@ struct Driver {
         return r.energy;
     }
 
+    void svd_timed(int i, const DevBuf &psi, int max_m, double cutoff, int mode, SvdOut &r) {
+        const auto t0 = std::chrono::steady_clock::now();
+        svd_truncate_run(ctx, m->bonds[i], m->bonds[i + 2], m->p, psi.as<double>(), max_m, cutoff, prm.eps, mode, r);
+        t_svd += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+
     void optimize(int i, int mode, const pdmrg_dav_params &dav) {
         DevBuf psi = contract(i, nullptr);
         solve(i, psi, dav);
         SvdOut r;
-        svd_truncate_run(ctx, m->bonds[i], m->bonds[i + 2], m->p, psi.as<double>(), prm.max_m, prm.cutoff, prm.eps,
-                         mode, r);
+        svd_timed(i, psi, prm.max_m, prm.cutoff, mode, r);
         store(i, r, mode);
     }
 
     void gauge_move(int i, int mode, int max_m, double cutoff) {
         DevBuf psi = contract(i, nullptr);
         SvdOut r;
-        svd_truncate_run(ctx, m->bonds[i], m->bonds[i + 2], m->p, psi.as<double>(), max_m, cutoff, prm.eps, mode, r);
+        svd_timed(i, psi, max_m, cutoff, mode, r);
         store(i, r, mode);
     }
 
@@ -199,8 +208,7 @@ struct Driver {
         solve(j, psi, prm.dav_shared);   // Davidson normalises its start vector
         rep.max_infidelity = std::max(rep.max_infidelity, infidelity(pred.as<double>(), psi.as<double>(), n));
         SvdOut r;
-        svd_truncate_run(ctx, m->bonds[j], m->bonds[j + 2], m->p, psi.as<double>(), prm.max_m, prm.cutoff, prm.eps,
-                         PDMRG_SPLIT, r);
+        svd_timed(j, psi, prm.max_m, prm.cutoff, PDMRG_SPLIT, r);
         store(j, r, PDMRG_SPLIT);
     }
 
@@ -295,6 +303,8 @@ struct Driver {
             rep.max_infidelity = std::max(rep.max_infidelity, r.max_infidelity);
             rep.n_svd_unconverged += r.n_svd_unconverged;
             t_heff += ds[k].t_heff;
+            t_svd += ds[k].t_svd;
+            t_env += ds[k].t_env;
         }
         for (int k = 0; k < n; ++k)
             if (codes[k] != 0) throw Error(codes[k], msgs[k]);
@@ -707,6 +717,8 @@ int sweep(pdmrg_ctx *ctx, pdmrg_mps *m, const pdmrg_mpo *mpo, const pdmrg_sweep_
         rep->energy = E;
         rep->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         rep->seconds_heff = dr.t_heff;
+        rep->seconds_svd = dr.t_svd;
+        rep->seconds_env = dr.t_env;
     }
     API_CATCH
 }
@@ -875,6 +887,38 @@ int mps_order_parameter(pdmrg_ctx *ctx, pdmrg_mps *m, int kind, int Lx, int Ly, 
     } else {
         throw Error(PDMRG_EINVAL, "mps_order_parameter: kind must be 0 (D_x) or 1 (M_z)");
     }
+    API_CATCH
+}
+
+int mps_copy(pdmrg_ctx *ctx, const pdmrg_mps *src, pdmrg_mps **out) {
+    API_TRY
+    PD_REQUIRE(ctx && src && out, PDMRG_EINVAL, "mps_copy: null argument");
+    auto m = std::make_unique<pdmrg_mps>();
+    m->N = src->N;
+    m->q_target = src->q_target;
+    m->p = src->p;
+    m->bonds = src->bonds;
+    m->V = src->V;
+    m->hasV = src->hasV;
+    m->ready = src->ready;
+    m->n_regions = src->n_regions;
+    m->split = src->split;
+    m->icanon = src->icanon;
+    m->regions = src->regions;
+    auto dup = [&](const DevBuf &b) {
+        DevBuf d;
+        if (b.ptr) {
+            d.alloc(b.bytes);
+            HIP_OK(hipMemcpyAsync(d.ptr, b.ptr, b.bytes, hipMemcpyDeviceToDevice, ctx->stream));
+        }
+        return d;
+    };
+    for (const auto &b : src->sites) m->sites.push_back(dup(b));
+    for (const auto &b : src->L) m->L.push_back(dup(b));
+    for (const auto &b : src->R) m->R.push_back(dup(b));
+    for (const auto &b : src->Vd) m->Vd.push_back(dup(b));
+    HIP_OK(hipStreamSynchronize(ctx->stream));
+    *out = m.release();
     API_CATCH
 }
 

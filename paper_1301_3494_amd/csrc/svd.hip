@@ -38,6 +38,7 @@ constexpr int M = J2 - 1;        // circle schedule modulus
 constexpr int JT = 256;          // 4 waves; one 16 x 16 entry per thread
 constexpr int CH = 512;          // columns staged in LDS at a time
 constexpr int U = J2 * CH / JT;  // staged elements per thread and chunk
+static_assert(J2 * CH % JT == 0 && CH % 16 == 0, "chunk must split evenly over the threads and 16-column steps");
 constexpr unsigned kOut = 0x80000000u;   // buffer offset past every record
 
 __device__ __forceinline__ d4 mfma_f64(double a, double b, d4 c) {
@@ -140,18 +141,23 @@ __global__ __launch_bounds__(JT) void jac_pair_kernel(const JacItem *__restrict_
     const __amdgpu_buffer_rsrc_t rW = rows_rsrc(it.W, (int64_t)it.nv * it.len);
     const __amdgpu_buffer_rsrc_t rZ = rows_rsrc(it.Z, (int64_t)it.nv * it.nv);
 
-    // Element u of this thread in a chunk: row u / 2, column tid + 256 (u % 2).
+    // Element u of this thread in a chunk: flat index e = u JT + tid of the
+    // J2 x CH chunk, row e / CH, column e % CH (consecutive threads take
+    // consecutive columns of one row).
     auto load_chunk = [&](__amdgpu_buffer_rsrc_t rs, int len, int c0, double (&v)[U]) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int r = u >> 1, c = c0 + tid + JT * (u & 1);
+            const int e = u * JT + tid, r = e / CH, c = c0 + e % CH;
             const unsigned off = (r < n && c < len) ? (unsigned)(((int64_t)grow(r) * len + c) * 8) : kOut;
             v[u] = bload(rs, off);
         }
     };
     auto store_chunk = [&](double (*dst)[CH + 1], const double (&v)[U]) {
 #pragma unroll
-        for (int u = 0; u < U; ++u) dst[u >> 1][tid + JT * (u & 1)] = v[u];
+        for (int u = 0; u < U; ++u) {
+            const int e = u * JT + tid;
+            dst[e / CH][e % CH] = v[u];
+        }
     };
     {
         double v[U], z[U];
