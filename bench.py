@@ -220,16 +220,29 @@ def oracle_steps(wl, svd_bond):
 def large_bond_rates(ctx, pl, synth, np, torch, steps=10):
     """Matvec rate at the centre bonds of the larger lattices (the m >= 2000
     contractions): 24 x 8 Heisenberg cylinder m = 2000 (D = 26), triangular
-    12 x 6 m = 3000 (D = 23) and J-Q2 16 x 8 m = 4000 (D = 110); synthetic
-    seeded environments, FP32 and FP64, plans as for the headline bond."""
+    12 x 6 m = 3000 (D = 23) and J-Q2 16 x 8 m = 4000 (the exact MPO: 110
+    channels on the environments' bonds inside the columns, 98 at the centre
+    column cut); synthetic seeded environments, FP32 and FP64, plans as for
+    the headline bond.  jq2_16x8_m4000_D40: the same bond with the MPO cut
+    down to its first 40 channels on each of the three bonds (a synthetic
+    D = 40 operator of the J-Q2 structure, the size the configuration
+    states)."""
     PQ = (-1, 1)
     out = {}
     for name, lattice, Lx, Ly, m in (("cyl24x8_m2000", "square", 24, 8, 2000),
                                      ("tri12x6_m3000", "triangular", 12, 6, 3000),
-                                     ("jq2_16x8_m4000", "jq2", 16, 8, 4000)):
+                                     ("jq2_16x8_m4000", "jq2", 16, 8, 4000),
+                                     ("jq2_16x8_m4000_D40", "jq2", 16, 8, 4000)):
         N = Lx * Ly
         c = N // 2 - 1
         mpo = pl.Mpo(lattice, Lx, Ly, (1.0, 1.0))
+        W1, W2 = mpo.site(c), mpo.site(c + 1)
+        dL, dR = mpo.deltas[c], mpo.deltas[c + 2]
+        if name.endswith("_D40"):
+            k = 40
+            W1 = pl.MpoSite(mpo.W[c][:k, :, :, :k], mpo.deltas[c][:k], mpo.deltas[c + 1][:k])
+            W2 = pl.MpoSite(mpo.W[c + 1][:k, :, :, :k], mpo.deltas[c + 1][:k], mpo.deltas[c + 2][:k])
+            dL, dR = mpo.deltas[c][:k], mpo.deltas[c + 2][:k]
         bonds = synth.binomial_bonds(N, m)
         rng = np.random.default_rng(3)
         B1, B2, P = pl.Bond(bonds[c]), pl.Bond(bonds[c + 2]), pl.Phys(PQ)
@@ -243,14 +256,14 @@ def large_bond_rates(ctx, pl, synth, np, torch, steps=10):
                 v[off: off + rows * ld].reshape(rows, ld)[:, :cols] = b
             return torch.from_numpy(v).cuda()
 
-        L = flat(pl.ENV_L, B1, mpo.deltas[c], synth.random_env_blocks(bonds[c], mpo.deltas[c], rng))
-        R = flat(pl.ENV_R, B2, mpo.deltas[c + 2], synth.random_env_blocks(bonds[c + 2], mpo.deltas[c + 2], rng))
+        L = flat(pl.ENV_L, B1, dL, synth.random_env_blocks(bonds[c], dL, rng))
+        R = flat(pl.ENV_R, B2, dR, synth.random_env_blocks(bonds[c + 2], dR, rng))
         _, nx = pl.layout(pl.TWO_SITE, B1, B2, P)
         x = torch.from_numpy(rng.standard_normal(nx)).cuda()
         y = torch.empty_like(x)
-        rec = {"D": int(mpo.W[c].shape[3]), "psi_elems": nx}
+        rec = {"D": int(W1.W.shape[3]), "D_env": [int(W1.W.shape[0]), int(W2.W.shape[3])], "psi_elems": nx}
         for pname, prec in (("f32", pl.F32), ("f64", pl.F64)):
-            op = pl.Heff(ctx, B1, B2, P, mpo.site(c), mpo.site(c + 1), L, R, prec)
+            op = pl.Heff(ctx, B1, B2, P, W1, W2, L, R, prec)
             info = op.info()
             wall, ms = time_matvecs(ctx, pl, torch, op, x, y, steps, 2)
             t = wall / steps
@@ -367,8 +380,21 @@ def cpu_baseline(wl, flops, budget_s=12.0):
     except Exception:
         threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": round(flops / dt / 1e12, 6), "unit": "TFLOP/s", "cores": threads, "kind": "oracle",
+            "cpu_model": host_cpu_model(), "host_logical_cpus": os.cpu_count(),
             "sample": "%d oracle H_eff matvecs (numpy/BLAS FP64) on the same 8x4 m=1024 block shapes, "
                       "%.3f s each" % (n, dt)}
+
+
+def host_cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def sweep_leg(ctx, pl, synth, torch, m=1024, regions=4, timed=2, concurrent=True, keep=None):

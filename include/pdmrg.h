@@ -397,6 +397,19 @@ int mps_copy(pdmrg_ctx *ctx, const pdmrg_mps *src, pdmrg_mps **out);
  * and re-splits it.  *energy (optional) receives E
  * before the gauge changes.  PDMRG_ESHAPE if n_G is not the total size. */
 int grad_mpo(pdmrg_ctx *ctx, pdmrg_mps *mps, const pdmrg_mpo *mpo, double *G_dev, int64_t n_G, double *energy);
+/* dE/dtheta_k for the couplings theta given to mpo_build (e.g. J and Delta,
+ * J and Q, J and h; the same order and count): the measurement sweep of
+ * grad_mpo (same effect on the MPS) followed, on the device, by
+ * dE/dtheta_k = sum_i <G_i, dW_i/dtheta_k> with dW_i/dtheta_k taken from
+ * tables mpo_build keeps for every coupling (each coefficient of its models
+ * is affine in each coupling when the others are fixed).  Hellmann-Feynman
+ * derivative at fixed state: the derivative of the ground-state energy when
+ * the state is converged.  dE: host, ncouplings doubles; energy (optional)
+ * receives E.  PDMRG_EINVAL if the MPO was not made by mpo_build, ncouplings
+ * differs from the build's count, or the MPO's channel structure depends on
+ * a coupling (no table for it). */
+int grad_couplings(pdmrg_ctx *ctx, pdmrg_mps *mps, const pdmrg_mpo *mpo, double *dE, int32_t ncouplings,
+                   double *energy);
 
 /* ---------------------------------------------------------------------------
  * Inverse canonical gauge and local measurements (Sec. IV, Figs. imps_step

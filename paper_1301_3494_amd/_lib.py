@@ -78,7 +78,7 @@ EXPORTS = [
     "mpo_info", "mpo_get_site", "mpo_free", "heff_create", "heff_apply", "heff_info", "heff_plan_info", "heff_diag",
     "heff_free", "env_update", "env_update_noalloc", "env_update_info", "davidson_step", "svd_truncate", "svd_result_bond", "svd_result_copy",
     "svd_free", "merge_regions", "mps_alloc", "mps_set_site", "mps_bond", "mps_get_site", "sweep",
-    "mps_energy", "mps_copy", "mps_free", "grad_site", "grad_mpo", "mps_inverse_canonical", "mps_get_v", "mps_expect_site",
+    "mps_energy", "mps_copy", "mps_free", "grad_site", "grad_mpo", "grad_couplings", "mps_inverse_canonical", "mps_get_v", "mps_expect_site",
     "mps_expect_pairs", "mps_order_parameter",
 ]
 
@@ -131,6 +131,7 @@ def _declare(L):
         "mps_free": (None, [P]),
         "grad_site": (c_int, [P, pb, pb, pp, pm, P, P, P, P]),
         "grad_mpo": (c_int, [P, P, P, P, c_int64, pd]),
+        "grad_couplings": (c_int, [P, P, P, pd, c_int32, pd]),
         "mps_inverse_canonical": (c_int, [P, P, c_double, c_double, pi32]),
         "mps_get_v": (c_int, [P, c_int, pd, c_int64]),
         "mps_expect_site": (c_int, [P, P, pd, pd]),
@@ -374,6 +375,7 @@ class Mpo:
         else:
             cc = (c_double * len(couplings))(*couplings)
             check(L.mpo_build(LATTICES.get(lattice, lattice), int(Lx), int(Ly), cc, len(couplings), byref(h)))
+        self.ncouplings = 0 if sites is not None else len(couplings)
         self.h = h
         n, d = c_int32(), c_int32()
         check(L.mpo_info(h, byref(n), byref(d), None, None))
@@ -625,26 +627,12 @@ def mpo_energy(mps, deltas, W):
     return _energy_function().apply(mps, deltas, *W)
 
 
-def coupling_derivatives(lattice, Lx, Ly, couplings):
-    """dW_i/dtheta_k for each coupling k, exact for the built-in models (every
-    coefficient is affine in each coupling): W(theta + e_k) - W(theta)."""
-    base = Mpo(lattice, Lx, Ly, couplings)
-    out = []
-    for k in range(len(couplings)):
-        c = list(couplings)
-        c[k] += 1.0
-        up = Mpo(lattice, Lx, Ly, c)
-        if any(a.shape != b.shape for a, b in zip(up.W, base.W)):
-            raise ValueError("MPO structure changes with coupling %d; derivative undefined here" % k)
-        out.append([a - b for a, b in zip(up.W, base.W)])
-        up.free()
-    base.free()
-    return out
-
-
-def dE_dcouplings(mps, mpo, lattice, Lx, Ly, couplings):
-    """(E, [dE/dtheta_k]) by one grad_mpo measurement sweep."""
-    E, G = mps.gradients(mpo)
-    Gh = [g.cpu().numpy() for g in G]
-    return E, [float(sum(np.sum(g * dw) for g, dw in zip(Gh, dW)))
-               for dW in coupling_derivatives(lattice, Lx, Ly, couplings)]
+def dE_dcouplings(mps, mpo):
+    """(E, [dE/dtheta_k]) for the couplings mpo_build was given: grad_couplings
+    (one measurement sweep and the device contraction with the MPO's
+    coefficient-derivative tables)."""
+    n = mpo.ncouplings
+    dE = np.zeros(max(n, 1))
+    E = c_double()
+    check(lib().grad_couplings(mps.ctx.h, mps.h, mpo.h, dE.ctypes.data_as(POINTER(c_double)), n, byref(E)))
+    return E.value, [float(v) for v in dE[:n]]

@@ -565,21 +565,21 @@ struct Driver {
             gp.build(m->bonds[i], m->bonds[i + 1], m->p, W(i), s());
             grad_site_run(ctx, gp, m->L[i].as<double>(), m->sites[i].as<double>(), m->R[i + 1].as<double>(),
                           G + goff[i]);
-            // norm^2 of the centre
+            // G_i / <Psi|Psi>, the squared norm of the centre: a fixed-order
+            // device reduction, then G scaled twice by 1/sqrt(norm^2)
             const int64_t n = site_layout(m->bonds[i], m->bonds[i + 1], m->p).size;
-            std::vector<double> h(n);
-            HIP_OK(hipMemcpyAsync(h.data(), m->sites[i].ptr, n * sizeof(double), hipMemcpyDeviceToHost, s()));
-            HIP_OK(hipStreamSynchronize(s()));
-            double nrm2 = 0.0;
-            for (double v : h) nrm2 += v * v;
-            PD_REQUIRE(nrm2 > 0.0, PDMRG_ENUMERIC, "grad_mpo: zero state");
+            constexpr int kBlocks = 240;
+            DevBuf part((size_t)kBlocks * sizeof(double)), nrm(sizeof(double));
+            launch_multidot(m->sites[i].as<double>(), n, 1, m->sites[i].as<double>(), n, part.as<double>(), kBlocks,
+                            s());
+            launch_reduce_partials(part.as<double>(), kBlocks, 1, nrm.as<double>(), 1, s());
             const int64_t gn = goff[i + 1] - goff[i];
-            std::vector<double> g(gn);
-            HIP_OK(hipMemcpyAsync(g.data(), G + goff[i], gn * sizeof(double), hipMemcpyDeviceToHost, s()));
+            launch_scale_by_inv_sqrt(G + goff[i], nrm.as<double>(), G + goff[i], gn, s());
+            launch_scale_by_inv_sqrt(G + goff[i], nrm.as<double>(), G + goff[i], gn, s());
+            double nrm2 = 0.0;
+            HIP_OK(hipMemcpyAsync(&nrm2, nrm.ptr, sizeof(double), hipMemcpyDeviceToHost, s()));
             HIP_OK(hipStreamSynchronize(s()));
-            for (double &v : g) v /= nrm2;
-            HIP_OK(hipMemcpyAsync(G + goff[i], g.data(), gn * sizeof(double), hipMemcpyHostToDevice, s()));
-            HIP_OK(hipStreamSynchronize(s()));
+            PD_REQUIRE(nrm2 > 0.0 && std::isfinite(nrm2), PDMRG_ENUMERIC, "grad_mpo: zero or non-finite state");
             if (i + 1 < m->N) gauge_move(i, PDMRG_ABSORB_RIGHT, 1 << 30, 1e-14);
         }
         m->ready = false;   // centre now on the last site: the next sweep re-canonicalises
@@ -746,6 +746,62 @@ int grad_mpo(pdmrg_ctx *ctx, pdmrg_mps *m, const pdmrg_mpo *mpo, double *G_dev, 
     dr.prm.eps = 1e-4;
     if (energy) *energy = dr.energy();
     dr.gradients(G_dev, goff);
+    API_CATCH
+}
+
+int grad_couplings(pdmrg_ctx *ctx, pdmrg_mps *m, const pdmrg_mpo *mpo, double *dE, int32_t ncouplings,
+                   double *energy) {
+    API_TRY
+    PD_REQUIRE(ctx && m && mpo && dE && ncouplings >= 1, PDMRG_EINVAL, "grad_couplings: bad arguments");
+    check_mpo(m, mpo);
+    PD_REQUIRE((int)mpo->dW.size() == ncouplings, PDMRG_EINVAL,
+               "grad_couplings: the MPO carries " + std::to_string(mpo->dW.size()) +
+                   " coupling derivative tables (mpo_build MPOs only)");
+    std::vector<int64_t> goff(m->N + 1, 0);
+    for (int i = 0; i < m->N; ++i) {
+        const MpoSite &w = mpo->W[i];
+        goff[i + 1] = goff[i] + (int64_t)w.Dl * w.d * w.d * w.Dr;
+    }
+    const int64_t nG = goff[m->N];
+    for (int k = 0; k < ncouplings; ++k)
+        PD_REQUIRE((int64_t)mpo->dW[k].size() == nG, PDMRG_EINVAL,
+                   "grad_couplings: the MPO's structure depends on coupling " + std::to_string(k));
+    hipStream_t s = ctx->stream;
+    DevBuf G((size_t)nG * sizeof(double));
+    Driver dr{ctx, m, mpo};
+    dr.prm.eps = 1e-4;
+    if (energy) *energy = dr.energy();
+    dr.gradients(G.as<double>(), goff);
+    // dE/dtheta_k = sum_i <G_i, dW_i/dtheta_k>: fixed-order tiled dot products
+    std::vector<double> dWall;
+    dWall.reserve((size_t)ncouplings * nG);
+    for (int k = 0; k < ncouplings; ++k) dWall.insert(dWall.end(), mpo->dW[k].begin(), mpo->dW[k].end());
+    std::vector<DotTask> tasks;
+    std::vector<DotTile> tiles;
+    std::vector<int32_t> t0, g_of;
+    for (int k = 0; k < ncouplings; ++k) {
+        tasks.push_back(DotTask{0, (int64_t)k * nG, (int32_t)nG, k});
+        t0.push_back((int32_t)tiles.size());
+        g_of.push_back(k);
+        for (int64_t c = 0; c * kDotChunk < nG; ++c) tiles.push_back(DotTile{k, (int32_t)c});
+    }
+    t0.push_back((int32_t)tiles.size());
+    PD_REQUIRE(nG < (int64_t(1) << 31), PDMRG_EINVAL, "grad_couplings: gradient too large");
+    DevBuf d_dw, d_tasks, d_tiles, d_t0, d_g, partial, out;
+    upload(d_dw, dWall, s);
+    upload(d_tasks, tasks, s);
+    upload(d_tiles, tiles, s);
+    upload(d_t0, t0, s);
+    upload(d_g, g_of, s);
+    partial.ensure(std::max<size_t>(tiles.size(), 1) * sizeof(double));
+    out.ensure((size_t)ncouplings * sizeof(double));
+    Slots sl{};
+    sl.p[0] = G.ptr;
+    sl.p[1] = d_dw.ptr;
+    launch_dot_partials(sl, 0, 1, d_tasks.as<DotTask>(), d_tiles.as<DotTile>(), (int)tiles.size(), partial.as<double>(), s);
+    launch_dot_reduce(partial.as<double>(), d_t0.as<int32_t>(), d_g.as<int32_t>(), ncouplings, out.as<double>(), s);
+    HIP_OK(hipMemcpyAsync(dE, out.ptr, (size_t)ncouplings * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
     API_CATCH
 }
 

@@ -32,6 +32,10 @@ struct pdmrg_mpo {
     int N = 0, d = 0;
     std::vector<int> phys_q;
     std::vector<pdmrg::MpoSite> W;   // W[i]: Dl = D(i), Dr = D(i+1)
+    // mpo_build only: per coupling k, dW_i/dtheta_k of every site
+    // concatenated in site order (the grad_mpo layout); empty where the
+    // channel structure depends on that coupling
+    std::vector<std::vector<double>> dW;
 };
 
 namespace pdmrg {

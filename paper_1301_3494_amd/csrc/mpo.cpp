@@ -87,9 +87,13 @@ void add_xxz(std::vector<Term> &t, const std::vector<std::pair<int, int>> &bonds
 
 }  // namespace
 
-extern "C" int mpo_build(int lattice, int Lx, int Ly, const double *couplings, int ncouplings, pdmrg_mpo **out) {
-    try {
-        PD_REQUIRE(out && couplings && ncouplings >= 2 && Lx >= 1, PDMRG_EINVAL, "mpo_build: bad arguments");
+namespace {
+// The MPO of a lattice model at the given couplings (throws on bad input).
+std::unique_ptr<pdmrg_mpo> build_model(int lattice, int Lx, int Ly, const std::vector<double> &cpl) {
+    {
+        const double *couplings = cpl.data();
+        const int ncouplings = (int)cpl.size();
+        PD_REQUIRE(ncouplings >= 2 && Lx >= 1, PDMRG_EINVAL, "mpo_build: bad arguments");
         const double c0 = couplings[0], c1 = couplings[1];
         std::vector<Term> terms;
         int N = 0;
@@ -292,6 +296,38 @@ extern "C" int mpo_build(int lattice, int Lx, int Ly, const double *couplings, i
                     put(i, idx_pre(i, prefix(before - 1)), idx_pre(i + 1, prefix(before - 1)), I, 1.0, false);
                 }
             }
+        }
+        return m;
+    }
+}
+
+bool same_structure(const pdmrg_mpo &a, const pdmrg_mpo &b) {
+    if (a.N != b.N || a.d != b.d) return false;
+    for (int i = 0; i < a.N; ++i)
+        if (a.W[i].Dl != b.W[i].Dl || a.W[i].Dr != b.W[i].Dr || a.W[i].dl != b.W[i].dl || a.W[i].dr != b.W[i].dr)
+            return false;
+    return true;
+}
+}  // namespace
+
+extern "C" int mpo_build(int lattice, int Lx, int Ly, const double *couplings, int ncouplings, pdmrg_mpo **out) {
+    try {
+        PD_REQUIRE(out && couplings && ncouplings >= 2, PDMRG_EINVAL, "mpo_build: bad arguments");
+        const std::vector<double> c(couplings, couplings + ncouplings);
+        auto m = build_model(lattice, Lx, Ly, c);
+        // coefficient derivatives dW/dtheta_k: every coefficient of these
+        // models is affine in each coupling with the others held fixed, so
+        // W(theta + e_k) - W(theta) is the derivative (not kept if the
+        // channel structure changed)
+        m->dW.assign(ncouplings, std::vector<double>());
+        for (int k = 0; k < ncouplings; ++k) {
+            std::vector<double> ck = c;
+            ck[k] += 1.0;
+            auto up = build_model(lattice, Lx, Ly, ck);
+            if (!same_structure(*m, *up)) continue;
+            std::vector<double> &d = m->dW[k];
+            for (int i = 0; i < m->N; ++i)
+                for (size_t e = 0; e < m->W[i].W.size(); ++e) d.push_back(up->W[i].W[e] - m->W[i].W[e]);
         }
         *out = m.release();
         return PDMRG_OK;

@@ -207,3 +207,66 @@ def test_davidson_matches_oracle(ctx, prec):
     assert abs(E - Eo) <= 1e-9 * abs(Eo)
     xg = flatten(flat_to_blocks(host(x), t["x"][0], pl.TWO_SITE), keys, shapes)
     assert abs(abs(xg @ xo) - 1.0) <= 1e-6
+
+
+def test_davidson_mixed_vs_f64_at_m2000_bond(ctx):
+    """One bond at the sweep workload's scale: width-8 Heisenberg cylinder
+    (6 x 8, D = 26, the 24 x 8 workload's MPO width) at m = 2000, environments
+    built by both sides from the same seeded isometric MPS.  Davidson to a
+    residual of 1e-8 (stalls near 2e-8 in FP64 and 1e-7 mixed after 300
+    products: energy error ~ residual^2 / gap) in FP64 and in the
+    mixed mode (FP32 products, FP64 refinement) against the oracle's Davidson
+    on its own environments: both within 1e-9 relative, and the mixed energy
+    is not the FP64 one bit for bit (the check sees the FP32 products)."""
+    Lx, Ly, m, seed = 6, 8, 2000, 12
+    N = Lx * Ly
+    c = N // 2 - 1
+    mpo = M.build_mpo(models.heisenberg_terms(models.square_cylinder_bonds(Lx, Ly)), N, models.OPS, PQ)
+    bonds, sites = synth.random_mps(N, m, seed)
+    sites = synth.isometric_scale(sites, bonds, PQ, c)
+    Ph = pl.Phys(PQ)
+    Lo, Ro = dmrg.left_boundary(), dmrg.right_boundary(0)
+    Lg, Rg = dev(np.ones(1)), dev(np.ones(1))
+    for i in range(c):
+        Lo = dmrg.update_L(Lo, sites[i], mpo.W[i], PQ, mpo.deltas[i], mpo.deltas[i + 1])
+        tA, nA = _site_tables(bonds[i], bonds[i + 1])
+        _, nout = pl.layout(pl.ENV_L, pl.Bond(bonds[i + 1]), deltas=mpo.deltas[i + 1])
+        out = dev(np.zeros(nout))
+        pl.env_update(ctx, 1, pl.Bond(bonds[i]), pl.Bond(bonds[i + 1]), Ph, mpo_site(mpo, i), Lg,
+                      dev(blocks_to_flat(sites[i], tA, nA, pl.SITE)), out)
+        Lg = out
+    for i in range(N - 1, c + 1, -1):
+        Ro = dmrg.update_R(Ro, sites[i], mpo.W[i], PQ, mpo.deltas[i], mpo.deltas[i + 1])
+        tA, nA = _site_tables(bonds[i], bonds[i + 1])
+        _, nout = pl.layout(pl.ENV_R, pl.Bond(bonds[i]), deltas=mpo.deltas[i])
+        out = dev(np.zeros(nout))
+        pl.env_update(ctx, -1, pl.Bond(bonds[i]), pl.Bond(bonds[i + 1]), Ph, mpo_site(mpo, i), Rg,
+                      dev(blocks_to_flat(sites[i], tA, nA, pl.SITE)), out)
+        Rg = out
+    psi = synth.random_two_site_blocks(bonds[c], bonds[c + 2], PQ, np.random.default_rng(seed + 7))
+    bl, br = Bond(bonds[c]), Bond(bonds[c + 2])
+    keys = two_site_keys(bl, br, PQ)
+    shapes = [two_site_shape(k, bl, br, PQ) for k in keys]
+    mv = lambda v: flatten(dmrg.heff_apply(Lo, Ro, mpo.W[c], mpo.W[c + 1], unflatten(v, keys, shapes),
+                                           bl, br, PQ, mpo.deltas[c], mpo.deltas[c + 2]), keys, shapes)
+    diag = flatten(dmrg.heff_diag(Lo, Ro, mpo.W[c], mpo.W[c + 1], bl, br, PQ, mpo.deltas[c], mpo.deltas[c + 2]),
+                   keys, shapes)
+    Eo, _, rno, nmvo = dmrg.davidson(mv, flatten(psi, keys, shapes), diag, dmrg.DavidsonParams(300, 1e-8, 8))
+    t, (B1, B2, P) = tables(bonds[c], bonds[c + 2], PQ, mpo.deltas[c], mpo.deltas[c + 2])
+    W1, W2 = mpo_site(mpo, c), mpo_site(mpo, c + 1)
+    x0 = blocks_to_flat(psi, t["x"][0], t["x"][1], pl.TWO_SITE)
+    E = {}
+    for name, prec in (("f64", pl.F64), ("mixed", pl.F32)):
+        op = pl.Heff(ctx, B1, B2, P, W1, W2, Lg, Rg, prec)
+        op64 = pl.Heff(ctx, B1, B2, P, W1, W2, Lg, Rg, pl.F64) if prec != pl.F64 else None
+        x = dev(x0)
+        E[name], rn, nmv, code = pl.davidson_step(ctx, op, x, max_matvec=300, max_sub=8, tol=1e-8, op64=op64)
+        say("  m=2000 bond", name, "E", E[name], "resid", rn, "nmv", nmv)
+        assert rn <= 5e-7, name
+        op.free()
+        if op64 is not None:
+            op64.free()
+    say("  oracle E", Eo, "resid", rno, "nmv", nmvo, "n_psi", t["x"][1], "mixed - f64", E["mixed"] - E["f64"])
+    for name in E:
+        assert abs(E[name] - Eo) <= 1e-9 * abs(Eo), name
+    assert E["mixed"] != E["f64"]
