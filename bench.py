@@ -517,6 +517,51 @@ def sweep_c3_leg(ctx, pl, synth, torch, regions=4, seed=3, concurrent=True):
     }
 
 
+def c5_run(ctx, pl, synth, torch, m=4000, regions=8, stride=4, sweeps=1):
+    """The J-Q2 configuration at its size: 16 x 8 cylinder (J = 1, Q = 1),
+    exact MPO (98 channels at the column cuts, 110 inside the columns),
+    m = 4000 on the binomial bonds of a seeded random MPS, 8 regions of 16
+    sites run one after another (one region's operators at this size hold
+    tens of GB; each region is one device's share of the staggered sweep,
+    and its GEMMs fill the device alone), mixed precision (FP32 H_eff, FP64 Davidson
+    refinement), environments recomputed with stride `stride`.  Reports the
+    canonicalisation, the sweep(s), dE/dJ and dE/dQ from grad_couplings with
+    the homogeneity check J dE/dJ + Q dE/dQ = E (exact at fixed state), and the
+    allocator's peak of device memory in use."""
+    Lx, Ly, J, Q = 16, 8, 1.0, 1.0
+    N = Lx * Ly
+    mpo = pl.Mpo("jq2", Lx, Ly, (J, Q))
+    bonds, sites = synth.random_mps(N, m, 6)
+    pl.set_env_stride(ctx, stride)
+    pl.set_verbose(ctx, 1)   # a pass at this size runs for minutes: one line per bond
+    pl.memory_stats(reset_peak=True)
+    mps = pl.Mps(ctx, bonds, sites)
+    dav, dav_shared = pl.dav_params(4, 8, 1e-8), pl.dav_params(12, 8, 1e-10)
+    out = {"workload": "jq2_cyl16x8_m%d_%dregions" % (m, regions), "D_max": int(max(mpo.D)),
+           "env_stride": stride, "sweeps": []}
+    for k in range(sweeps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rep = mps.sweep(mpo, m, regions, prec=pl.F32, dav=dav, dav_shared=dav_shared, concurrent=False)
+        torch.cuda.synchronize()
+        row = {"seconds": round(time.perf_counter() - t0, 2), "energy": rep["energy"], "max_bond": rep["max_bond"],
+               "n_matvec": rep["n_matvec"], "seconds_davidson": round(rep["seconds_heff"], 2),
+               "seconds_svd": round(rep["seconds_svd"], 2), "seconds_env": round(rep["seconds_env"], 2)}
+        out["sweeps"].append(row)
+        print("bench: c5 sweep %d %s" % (k + 1, row), file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    E, (gJ, gQ) = pl.dE_dcouplings(mps, mpo)
+    out["grad"] = {"seconds": round(time.perf_counter() - t0, 2), "energy": E, "dE_dJ": gJ, "dE_dQ": gQ,
+                   "homogeneity_rel": abs(J * gJ + Q * gQ - E) / abs(E)}
+    in_use, peak, cached = pl.memory_stats()
+    out["peak_device_gb"] = round(peak / 1e9, 2)
+    print("bench: c5 grad %s peak %.1f GB" % (out["grad"], peak / 1e9), file=sys.stderr, flush=True)
+    mps.free()
+    pl.set_env_stride(ctx, 0)
+    pl.set_verbose(ctx, 0)
+    return out
+
+
 SPIN_OPS = {
     "Sz": [[-0.5, 0.0], [0.0, 0.5]],
     "Sp": [[0.0, 0.0], [1.0, 0.0]],   # |up><down| (local basis: down, up)
@@ -749,6 +794,9 @@ def main():
     ap.add_argument("--no-steps", action="store_true", help="skip the per-step timings")
     ap.add_argument("--only-sweep", action="store_true",
                     help="run only the 8x4 m=1024 sweep-seconds leg (for profiling)")
+    ap.add_argument("--c5", action="store_true",
+                    help="run only the J-Q2 16x8 m=4000 8-region sweep with environment recompute, dE/dJ and dE/dQ "
+                         "and the peak device memory (minutes) and print its JSON")
     ap.add_argument("--only-c3", action="store_true",
                     help="run only the 24x8 m=2000 sweep-seconds leg (the metric's sweep half; for profiling)")
     ap.add_argument("--fig1", action="store_true",
@@ -781,6 +829,10 @@ def main():
         pl.autotune_import(args.tune_db)
     if args.only_sweep:
         print(json.dumps({"sweep": sweep_leg(ctx, pl, synth, torch, concurrent=not args.sequential_regions)}))
+        ctx.close()
+        return
+    if args.c5:
+        print(json.dumps({"jq2_c5": c5_run(ctx, pl, synth, torch)}))
         ctx.close()
         return
     if args.only_c3:

@@ -131,6 +131,27 @@ int pdmrg_ctx_set_timing(pdmrg_ctx *ctx, int enable);
  * about 1e-15 relative).  A given plan is bitwise reproducible.
  * Returns PDMRG_EINVAL for another level. */
 int pdmrg_ctx_set_autotune(pdmrg_ctx *ctx, int level);
+/* Environment recompute (memory for time) for sweep, grad_mpo and
+ * grad_couplings on this context: with stride k >= 2, a pass keeps the
+ * environments of every k-th bond and of the region boundaries and drops the
+ * others once it has moved past them; a pass that needs a dropped one
+ * rebuilds it (and the ones between) from the nearest kept environment with
+ * env_update steps on the current site tensors, so results are the same bits
+ * as with every environment kept.  Memory: about N/k + k environments per
+ * region instead of N + 1; cost: about one extra environment update per bond.
+ * k <= 1 (the default 0): every environment is kept. */
+int pdmrg_ctx_set_env_stride(pdmrg_ctx *ctx, int stride);
+/* Progress log of sweep, grad_mpo and grad_couplings on this context: with
+ * level 1 every optimised bond (bond, kept m, energy, Davidson and SVD
+ * seconds) and every gauge move prints one line on stderr; 0 (the default):
+ * silent.  PDMRG_EINVAL for a negative level. */
+int pdmrg_ctx_set_verbose(pdmrg_ctx *ctx, int level);
+/* Device memory of the library's caching allocator (all contexts of the
+ * process, bytes): in_use = handed out and not released, peak = largest
+ * in_use since the last reset, cached = released blocks held for reuse.
+ * reset_peak != 0 sets peak to the current in_use afterwards.  Outputs
+ * optional. */
+int pdmrg_memory_stats(int64_t *in_use, int64_t *peak, int64_t *cached, int reset_peak);
 /* Debugging aid, process-wide: on != 0 fills every device buffer the library
  * allocates or takes from its cache (workspaces, plans, MPS storage) with
  * 0xFF bytes, a NaN in FP64 and FP32, before first use, so that a kernel

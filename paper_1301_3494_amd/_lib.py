@@ -74,7 +74,9 @@ def lib():
 
 EXPORTS = [
     "pdmrg_last_error", "pdmrg_version", "pdmrg_ctx_create", "pdmrg_ctx_destroy", "pdmrg_ctx_set_timing",
-    "pdmrg_ctx_timing", "pdmrg_ctx_set_autotune", "pdmrg_set_alloc_poison", "pdmrg_ctx_set_graphs", "pdmrg_autotune_export", "pdmrg_autotune_import", "pdmrg_layout_size", "pdmrg_layout_blocks", "mpo_build", "mpo_from_sites",
+    "pdmrg_ctx_timing", "pdmrg_ctx_set_autotune", "pdmrg_set_alloc_poison", "pdmrg_ctx_set_env_stride",
+    "pdmrg_ctx_set_verbose",
+    "pdmrg_memory_stats", "pdmrg_ctx_set_graphs", "pdmrg_autotune_export", "pdmrg_autotune_import", "pdmrg_layout_size", "pdmrg_layout_blocks", "mpo_build", "mpo_from_sites",
     "mpo_info", "mpo_get_site", "mpo_free", "heff_create", "heff_apply", "heff_info", "heff_plan_info", "heff_diag",
     "heff_free", "env_update", "env_update_noalloc", "env_update_info", "davidson_step", "svd_truncate", "svd_result_bond", "svd_result_copy",
     "svd_free", "merge_regions", "mps_alloc", "mps_set_site", "mps_bond", "mps_get_site", "sweep",
@@ -98,6 +100,9 @@ def _declare(L):
         "pdmrg_ctx_set_graphs": (c_int, [P, c_int]),
         "pdmrg_autotune_export": (c_int, [c_char_p, pi32]),
         "pdmrg_set_alloc_poison": (c_int, [c_int]),
+        "pdmrg_ctx_set_env_stride": (c_int, [P, c_int]),
+        "pdmrg_ctx_set_verbose": (c_int, [P, c_int]),
+        "pdmrg_memory_stats": (c_int, [pi64, pi64, pi64, c_int]),
         "pdmrg_autotune_import": (c_int, [c_char_p, pi32]),
         "pdmrg_layout_size": (c_int, [c_int, pb, pb, pp, pi32, c_int32, pi64, pi32]),
         "pdmrg_layout_blocks": (c_int, [c_int, pb, pb, pp, pi32, c_int32, pi32, pi64, pi32, pi32, pi32]),
@@ -625,6 +630,23 @@ def mpo_energy(mps, deltas, W):
     """Differentiable E(W) at fixed state (torch.autograd); W: list of
     [Dl, d, d, Dr] tensors, deltas: channel charges of bonds 0..N."""
     return _energy_function().apply(mps, deltas, *W)
+
+
+def set_env_stride(ctx, stride):
+    """Environment recompute stride of sweeps / measurement sweeps on ctx."""
+    check(lib().pdmrg_ctx_set_env_stride(ctx.h, int(stride)))
+
+
+def set_verbose(ctx, level):
+    """Progress lines (one per optimised bond / gauge move) on stderr."""
+    check(lib().pdmrg_ctx_set_verbose(ctx.h, int(level)))
+
+
+def memory_stats(reset_peak=False):
+    """(in_use, peak, cached) device bytes of the library's allocator."""
+    a, b, c = c_int64(), c_int64(), c_int64()
+    check(lib().pdmrg_memory_stats(byref(a), byref(b), byref(c), int(bool(reset_peak))))
+    return a.value, b.value, c.value
 
 
 def dE_dcouplings(mps, mpo):

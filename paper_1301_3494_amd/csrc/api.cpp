@@ -88,6 +88,27 @@ int pdmrg_ctx_set_autotune(pdmrg_ctx *ctx, int level) {
     API_END
 }
 
+int pdmrg_ctx_set_env_stride(pdmrg_ctx *ctx, int stride) {
+    API_BEGIN
+    PD_REQUIRE(ctx && stride >= 0, PDMRG_EINVAL, "set_env_stride: bad arguments");
+    ctx->env_stride = stride;
+    API_END
+}
+
+int pdmrg_ctx_set_verbose(pdmrg_ctx *ctx, int level) {
+    API_BEGIN
+    PD_REQUIRE(ctx && level >= 0, PDMRG_EINVAL, "set_verbose: bad arguments");
+    ctx->verbose = level;
+    API_END
+}
+
+int pdmrg_memory_stats(int64_t *in_use, int64_t *peak, int64_t *cached, int reset_peak) {
+    API_BEGIN
+    pdmrg::alloc_stats(in_use, peak, cached);
+    if (reset_peak) pdmrg::alloc_reset_peak();
+    API_END
+}
+
 int pdmrg_set_alloc_poison(int on) {
     API_BEGIN
     pdmrg::g_alloc_poison.store(on != 0);

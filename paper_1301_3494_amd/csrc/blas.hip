@@ -5,6 +5,8 @@
 // atomics), so results are bitwise reproducible.
 #include "kernels.hpp"
 
+#include <algorithm>
+
 namespace pdmrg {
 
 // ------------------------------------------------------------ W stage
@@ -72,6 +74,7 @@ __global__ __launch_bounds__(256) void lincomb_kernel(Slots slots, const LcTask 
 void launch_lincomb(bool f64, int chunk, const Slots &slots, const LcTask *tasks, const LcSrc *srcs,
                     const LcTile *tiles, int ntiles, hipStream_t s) {
     if (ntiles <= 0) return;
+    check_grid(ntiles, 256, "W stage");
     const dim3 g(ntiles), b(256);
     if (chunk == kLcChunkSmall) {
         if (f64) hipLaunchKernelGGL((lincomb_kernel<double, double, kLcChunkSmall>), g, b, 0, s, slots, tasks, srcs, tiles);
@@ -85,6 +88,7 @@ void launch_lincomb(bool f64, int chunk, const Slots &slots, const LcTask *tasks
 void launch_lincomb_f32_f64(int chunk, const Slots &slots, const LcTask *tasks, const LcSrc *srcs,
                             const LcTile *tiles, int ntiles, hipStream_t s) {
     if (ntiles <= 0) return;
+    check_grid(ntiles, 256, "W stage");
     const dim3 g(ntiles), b(256);
     if (chunk == kLcChunkSmall)
         hipLaunchKernelGGL((lincomb_kernel<float, double, kLcChunkSmall>), g, b, 0, s, slots, tasks, srcs, tiles);
@@ -93,34 +97,39 @@ void launch_lincomb_f32_f64(int chunk, const Slots &slots, const LcTask *tasks, 
 }
 
 // ------------------------------------------------------------ block dot products
+// Workgroup b takes tiles b, b + gridDim.x, ... (grid stride: tile lists can
+// outgrow one launch's grid); partial[t] is tile t's sum.
 __global__ __launch_bounds__(256) void dot_partial_kernel(Slots slots, int a_slot, int b_slot,
                                                           const DotTask *__restrict__ tasks,
-                                                          const DotTile *__restrict__ tiles,
+                                                          const DotTile *__restrict__ tiles, int ntiles,
                                                           double *__restrict__ partial) {
     constexpr int U = kDotChunk / 256;
     __shared__ double red[256];
-    const DotTile tl = tiles[blockIdx.x];
-    const DotTask tk = tasks[tl.task];
-    const double *a = static_cast<const double *>(slots.p[a_slot]) + tk.a_off;
-    const double *b = static_cast<const double *>(slots.p[b_slot]) + tk.b_off;
-    const int e0 = tl.chunk * kDotChunk + (int)threadIdx.x;
-    double va[U], vb[U];
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const DotTile tl = tiles[t];
+        const DotTask tk = tasks[tl.task];
+        const double *a = static_cast<const double *>(slots.p[a_slot]) + tk.a_off;
+        const double *b = static_cast<const double *>(slots.p[b_slot]) + tk.b_off;
+        const int e0 = tl.chunk * kDotChunk + (int)threadIdx.x;
+        double va[U], vb[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-        const int e = e0 + 256 * u;
-        va[u] = e < tk.n ? a[e] : 0.0;
-        vb[u] = e < tk.n ? b[e] : 0.0;
-    }
-    double acc = 0.0;
+        for (int u = 0; u < U; ++u) {
+            const int e = e0 + 256 * u;
+            va[u] = e < tk.n ? a[e] : 0.0;
+            vb[u] = e < tk.n ? b[e] : 0.0;
+        }
+        double acc = 0.0;
 #pragma unroll
-    for (int u = 0; u < U; ++u) acc += va[u] * vb[u];
-    red[threadIdx.x] = acc;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        for (int u = 0; u < U; ++u) acc += va[u] * vb[u];
+        red[threadIdx.x] = acc;
         __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) partial[t] = red[0];
+        __syncthreads();   // red is rewritten by the next tile
     }
-    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 
 __global__ void dot_reduce_kernel(const double *__restrict__ partial, const int32_t *__restrict__ t0,
@@ -135,7 +144,8 @@ __global__ void dot_reduce_kernel(const double *__restrict__ partial, const int3
 void launch_dot_partials(const Slots &slots, int a_slot, int b_slot, const DotTask *tasks, const DotTile *tiles,
                          int ntiles, double *partial, hipStream_t s) {
     if (ntiles <= 0) return;
-    hipLaunchKernelGGL(dot_partial_kernel, dim3(ntiles), dim3(256), 0, s, slots, a_slot, b_slot, tasks, tiles,
+    const unsigned g = (unsigned)std::min<int64_t>(ntiles, kMaxGrid);
+    hipLaunchKernelGGL(dot_partial_kernel, dim3(g), dim3(256), 0, s, slots, a_slot, b_slot, tasks, tiles, ntiles,
                        partial);
 }
 
@@ -435,31 +445,37 @@ void launch_small_eig(const double *G, int k, int ld, double *theta_out, double 
 }
 
 // ------------------------------------------------------------ local measurements
+// Grid stride over the tiles, as dot_partial_kernel.
 __global__ __launch_bounds__(256) void seg_dot_kernel(const SegDot *__restrict__ tasks,
-                                                      const SegTile *__restrict__ tiles,
+                                                      const SegTile *__restrict__ tiles, int ntiles,
                                                       double *__restrict__ partial) {
     __shared__ double red[256];
-    const SegTile tl = tiles[blockIdx.x];
-    const SegDot tk = tasks[tl.task];
-    const int nr = min(kSegRows, tk.rows - tl.r0);
-    const int n = nr * tk.width;
-    double acc = 0.0;
-    for (int e = threadIdx.x; e < n; e += 256) {
-        const int r = tl.r0 + e / tk.width, c = e % tk.width;
-        const double *row = tk.x + (int64_t)r * tk.ld;
-        acc += row[tk.ca + c] * row[tk.cb + c];
-    }
-    red[threadIdx.x] = acc;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const SegTile tl = tiles[t];
+        const SegDot tk = tasks[tl.task];
+        const int nr = min(kSegRows, tk.rows - tl.r0);
+        const int n = nr * tk.width;
+        double acc = 0.0;
+        for (int e = threadIdx.x; e < n; e += 256) {
+            const int r = tl.r0 + e / tk.width, c = e % tk.width;
+            const double *row = tk.x + (int64_t)r * tk.ld;
+            acc += row[tk.ca + c] * row[tk.cb + c];
+        }
+        red[threadIdx.x] = acc;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) partial[t] = red[0];
         __syncthreads();
     }
-    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 
 void launch_seg_dot_partials(const SegDot *tasks, const SegTile *tiles, int ntiles, double *partial, hipStream_t s) {
-    if (ntiles > 0) hipLaunchKernelGGL(seg_dot_kernel, dim3(ntiles), dim3(256), 0, s, tasks, tiles, partial);
+    if (ntiles <= 0) return;
+    const unsigned g = (unsigned)std::min<int64_t>(ntiles, kMaxGrid);
+    hipLaunchKernelGGL(seg_dot_kernel, dim3(g), dim3(256), 0, s, tasks, tiles, ntiles, partial);
 }
 
 __global__ void set_identity_kernel(const SqBlock *__restrict__ blocks) {

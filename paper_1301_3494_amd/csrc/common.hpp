@@ -101,6 +101,10 @@ struct MpoSite {
 // ---------------------------------------------------------------- device memory
 // Bytes the caching allocator reserves for a request of n bytes.
 size_t size_class(size_t n);
+// Device bytes handed out by the allocator and not yet released (current and
+// peak since the last reset), and bytes held in its cache.
+void alloc_stats(int64_t *in_use, int64_t *peak, int64_t *cached);
+void alloc_reset_peak();
 // pdmrg_set_alloc_poison: fill buffers with NaN bytes as they are handed out
 extern std::atomic<bool> g_alloc_poison;
 
@@ -185,6 +189,10 @@ struct pdmrg_ctx {
     std::vector<pdmrg_ctx *> sub;
     std::unique_ptr<pdmrg::WorkerPool> pool;
     bool owns_stream = false;
+    // Environment recompute stride of sweeps and measurement sweeps on this
+    // context (pdmrg_ctx_set_env_stride; <= 1: keep every environment).
+    int env_stride = 0;
+    int verbose = 0;   // progress lines on stderr
     // heff_apply through captured graphs (replayed on `stream`); the capture
     // happens on cap_stream, created on first use.
     bool graphs = false;

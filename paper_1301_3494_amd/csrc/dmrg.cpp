@@ -14,6 +14,7 @@
 
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <functional>
 
 using namespace pdmrg;
@@ -53,6 +54,11 @@ struct Driver {
     pdmrg_sweep_report rep{};
     double t_heff = 0.0, t_svd = 0.0, t_env = 0.0;   // wall seconds per step kind
     bool envs = true;   // gauge moves update environments (off: no MPO needed)
+    // Environment recompute stride k (>= 2: between passes only every k-th
+    // bond's environments and the region boundaries are kept; the others are
+    // rebuilt from the nearest kept one when a pass needs them; <= 1: every
+    // environment is kept).
+    int stride = 0;
 
     hipStream_t s() const { return ctx->stream; }
     const MpoSite &W(int i) const { return mpo->W[i]; }
@@ -80,7 +86,53 @@ struct Driver {
         return out;
     }
 
+    // Region boundaries: their environments are always kept (a region never
+    // reaches past them for a recompute).
+    bool boundary_L(int j) const {
+        if (j == 0) return true;
+        for (auto &r : m->regions) if (r.first == j) return true;
+        return false;
+    }
+    bool boundary_R(int j) const {
+        if (j == m->N) return true;
+        for (auto &r : m->regions) if (r.second + 1 == j) return true;
+        return false;
+    }
+    bool keep_L(int j) const { return stride <= 1 || j % stride == 0 || boundary_L(j); }
+    bool keep_R(int j) const { return stride <= 1 || j % stride == 0 || boundary_R(j); }
+    // Frees an environment the current pass leaves behind: `ckpt` keeps the
+    // stride checkpoints (still valid for the next pass), otherwise only the
+    // region boundaries stay.
+    void drop_L(int j, bool ckpt) {
+        if (stride <= 1 || j < 0 || j > m->N) return;
+        if (ckpt ? keep_L(j) : boundary_L(j)) return;
+        m->L[j] = DevBuf();
+    }
+    void drop_R(int j, bool ckpt) {
+        if (stride <= 1 || j < 0 || j > m->N) return;
+        if (ckpt ? keep_R(j) : boundary_R(j)) return;
+        m->R[j] = DevBuf();
+    }
+    // L[i] / R[i] present: rebuilt from the nearest kept one towards the
+    // outside of the pass (every environment on the way is kept until the
+    // pass drops it).
+    void ensure_L(int i) {
+        if (m->L[i].ptr) return;
+        int j = i - 1;
+        while (j > 0 && !m->L[j].ptr) --j;
+        PD_REQUIRE(m->L[j].ptr != nullptr, PDMRG_EINVAL, "sweep: no stored left environment to rebuild from");
+        for (int t = j; t < i; ++t) env_L(t);
+    }
+    void ensure_R(int i) {
+        if (m->R[i].ptr) return;
+        int j = i + 1;
+        while (j < m->N && !m->R[j].ptr) ++j;
+        PD_REQUIRE(m->R[j].ptr != nullptr, PDMRG_EINVAL, "sweep: no stored right environment to rebuild from");
+        for (int t = j - 1; t >= i; --t) env_R(t);
+    }
+
     void env_L(int i) {   // L[i+1] from L[i] and site i
+        ensure_L(i);
         const auto t0 = std::chrono::steady_clock::now();
         EnvPlan ep;
         ep.build(1, m->bonds[i], m->bonds[i + 1], m->p, W(i), s());
@@ -94,6 +146,7 @@ struct Driver {
     }
 
     void env_R(int i) {   // R[i] from R[i+1] and site i
+        ensure_R(i + 1);
         const auto t0 = std::chrono::steady_clock::now();
         EnvPlan ep;
         ep.build(-1, m->bonds[i], m->bonds[i + 1], m->p, W(i), s());
@@ -147,13 +200,17 @@ struct Driver {
 
     double solve(int i, DevBuf &psi, const pdmrg_dav_params &dav) {
         const Bond &bl = m->bonds[i], &br = m->bonds[i + 2];
+        ensure_L(i);
+        ensure_R(i + 2);
         const double *Ld = m->L[i].as<double>(), *Rd = m->R[i + 2].as<double>();
         pdmrg_heff op, op64;
         // bond shapes change from bond to bond and sweep to sweep: take tuned
         // plans from the cache, never time candidates here
-        heff_build(ctx, &op, bl, br, m->p, W(i), W(i + 1), Ld, Rd, prm.prec, false);
+        // FP64 operators read the environments in place; the low-precision
+        // operator reuses the FP64 one's intermediates (the two alternate)
         const bool refine = prm.prec != PDMRG_F64 && prm.refine;
-        if (refine) heff_build(ctx, &op64, bl, br, m->p, W(i), W(i + 1), Ld, Rd, PDMRG_F64, false);
+        if (refine) heff_build(ctx, &op64, bl, br, m->p, W(i), W(i + 1), Ld, Rd, PDMRG_F64, false, true);
+        heff_build(ctx, &op, bl, br, m->p, W(i), W(i + 1), Ld, Rd, prm.prec, false, true, refine ? &op64 : nullptr);
         const auto t0 = std::chrono::steady_clock::now();
         DavResult r = davidson_run(ctx, &op, refine ? &op64 : nullptr, psi.as<double>(), dav);
         t_heff += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -169,17 +226,26 @@ struct Driver {
 
     void optimize(int i, int mode, const pdmrg_dav_params &dav) {
         DevBuf psi = contract(i, nullptr);
-        solve(i, psi, dav);
+        const double h0 = t_heff, s0 = t_svd;
+        const double e = solve(i, psi, dav);
         SvdOut r;
         svd_timed(i, psi, prm.max_m, prm.cutoff, mode, r);
         store(i, r, mode);
+        if (ctx->verbose)
+            std::fprintf(stderr, "pdmrg: bond %d|%d m=%d E=%.12f davidson %.2fs svd %.2fs\n", i, i + 1,
+                         m->bonds[i + 1].total, e, t_heff - h0, t_svd - s0),
+                std::fflush(stderr);
     }
 
     void gauge_move(int i, int mode, int max_m, double cutoff) {
         DevBuf psi = contract(i, nullptr);
+        const double s0 = t_svd;
         SvdOut r;
         svd_timed(i, psi, max_m, cutoff, mode, r);
         store(i, r, mode);
+        if (ctx->verbose)
+            std::fprintf(stderr, "pdmrg: gauge %d|%d m=%d svd %.2fs\n", i, i + 1, m->bonds[i + 1].total, t_svd - s0),
+                std::fflush(stderr);
     }
 
     // 1 - |<a|b>| / (|a| |b|) of two device vectors (fixed-order reductions)
@@ -223,7 +289,10 @@ struct Driver {
         upload(m->R[N], one, s());
         // right-canonical form with the centre on site 0, by two-site SVDs
         // from the right keeping every nonzero singular value
-        for (int i = N - 2; i >= 0; --i) gauge_move(i, PDMRG_ABSORB_LEFT, 1 << 30, 1e-14);
+        for (int i = N - 2; i >= 0; --i) {
+            gauge_move(i, PDMRG_ABSORB_LEFT, 1 << 30, 1e-14);
+            drop_R(i + 2, true);
+        }
         m->ready = true;
     }
 
@@ -275,6 +344,7 @@ struct Driver {
             Driver d{sub_ctx(k), m, mpo};
             d.prm = prm;
             d.envs = envs;
+            d.stride = stride;
             ds.push_back(d);
         }
         if (!ctx->pool) ctx->pool.reset(new WorkerPool(ctx->device));
@@ -320,9 +390,17 @@ struct Driver {
                 const bool right = (r % 2 == 0) == (half == 0);
                 jobs.push_back([lo, hi, right](Driver &d) {
                     if (right)
-                        for (int i = lo; i < hi; ++i) d.optimize(i, PDMRG_ABSORB_RIGHT, d.prm.dav);
+                        for (int i = lo; i < hi; ++i) {
+                            d.optimize(i, PDMRG_ABSORB_RIGHT, d.prm.dav);
+                            d.drop_L(i, true);
+                            d.drop_R(i + 2, false);
+                        }
                     else
-                        for (int i = hi - 1; i >= lo; --i) d.optimize(i, PDMRG_ABSORB_LEFT, d.prm.dav);
+                        for (int i = hi - 1; i >= lo; --i) {
+                            d.optimize(i, PDMRG_ABSORB_LEFT, d.prm.dav);
+                            d.drop_R(i + 2, true);
+                            d.drop_L(i, false);
+                        }
                 });
             }
             run_jobs(jobs);
@@ -563,6 +641,8 @@ struct Driver {
         for (int i = 0; i < m->N; ++i) {
             GradPlan gp;
             gp.build(m->bonds[i], m->bonds[i + 1], m->p, W(i), s());
+            ensure_L(i);
+            ensure_R(i + 1);
             grad_site_run(ctx, gp, m->L[i].as<double>(), m->sites[i].as<double>(), m->R[i + 1].as<double>(),
                           G + goff[i]);
             // G_i / <Psi|Psi>, the squared norm of the centre: a fixed-order
@@ -581,6 +661,8 @@ struct Driver {
             HIP_OK(hipStreamSynchronize(s()));
             PD_REQUIRE(nrm2 > 0.0 && std::isfinite(nrm2), PDMRG_ENUMERIC, "grad_mpo: zero or non-finite state");
             if (i + 1 < m->N) gauge_move(i, PDMRG_ABSORB_RIGHT, 1 << 30, 1e-14);
+            drop_L(i, false);
+            drop_R(i + 1, false);
         }
         m->ready = false;   // centre now on the last site: the next sweep re-canonicalises
     }
@@ -697,6 +779,7 @@ int sweep(pdmrg_ctx *ctx, pdmrg_mps *m, const pdmrg_mpo *mpo, const pdmrg_sweep_
     PD_REQUIRE(p->max_m >= 1 && p->n_regions >= 1, PDMRG_EINVAL, "sweep: bad parameters");
     const auto t0 = std::chrono::steady_clock::now();
     Driver dr{ctx, m, mpo};
+    dr.stride = ctx->env_stride;
     dr.prm = *p;
     if (m->icanon) dr.unsplit();   // fold V back before re-canonicalising
     if (!m->ready) dr.init();
@@ -728,6 +811,7 @@ int mps_energy(pdmrg_ctx *ctx, pdmrg_mps *m, const pdmrg_mpo *mpo, double *energ
     PD_REQUIRE(ctx && m && mpo && energy, PDMRG_EINVAL, "mps_energy: null argument");
     check_mpo(m, mpo);
     Driver dr{ctx, m, mpo};
+    dr.stride = ctx->env_stride;
     *energy = dr.energy();
     API_CATCH
 }
@@ -743,6 +827,7 @@ int grad_mpo(pdmrg_ctx *ctx, pdmrg_mps *m, const pdmrg_mpo *mpo, double *G_dev, 
     }
     PD_REQUIRE(n_G == goff[m->N], PDMRG_ESHAPE, "grad_mpo: expected " + std::to_string(goff[m->N]) + " elements");
     Driver dr{ctx, m, mpo};
+    dr.stride = ctx->env_stride;
     dr.prm.eps = 1e-4;
     if (energy) *energy = dr.energy();
     dr.gradients(G_dev, goff);
@@ -769,6 +854,7 @@ int grad_couplings(pdmrg_ctx *ctx, pdmrg_mps *m, const pdmrg_mpo *mpo, double *d
     hipStream_t s = ctx->stream;
     DevBuf G((size_t)nG * sizeof(double));
     Driver dr{ctx, m, mpo};
+    dr.stride = ctx->env_stride;
     dr.prm.eps = 1e-4;
     if (energy) *energy = dr.energy();
     dr.gradients(G.as<double>(), goff);

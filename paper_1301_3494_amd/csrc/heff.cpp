@@ -70,10 +70,10 @@ void tune_heff(pdmrg_ctx *ctx, pdmrg_heff *op, const std::string &key) {
     Slots sl{};
     sl.p[0] = xin.ptr;
     sl.p[1] = yout.ptr;
-    sl.p[2] = op->L.ptr;
-    sl.p[3] = op->R.ptr;
-    sl.p[4] = op->T1.ptr;
-    sl.p[5] = op->T2.ptr;
+    sl.p[2] = op->lp;
+    sl.p[3] = op->rp;
+    sl.p[4] = op->t1;
+    sl.p[5] = op->t2;
     const int reps = 3;
     int best1 = (int)pl.g1.shape, best3 = (int)pl.g3.shape;
     double t1best = 1e30, t3best = 1e30;
@@ -97,7 +97,8 @@ void tune_heff(pdmrg_ctx *ctx, pdmrg_heff *op, const std::string &key) {
         for (int parts : cand) {
             pl.set_g3_shape((TileShape)t, s, parts);
             op->P.ensure(std::max<int64_t>(pl.nP, 1) * pes);
-            sl.p[6] = op->P.ptr;
+            op->pp = op->P.ptr;
+            sl.p[6] = op->pp;
             const double ms = time_ms(s, reps, [&] {
                 pl.g3.launch(gp, f64, sl, s);
                 if (f64) pl.r3.launch(true, sl, s);
@@ -119,6 +120,14 @@ void tune_heff(pdmrg_ctx *ctx, pdmrg_heff *op, const std::string &key) {
 }
 }  // namespace
 
+// Bytes behind an operator's intermediate (1 T1, 2 T2, 3 split-K partials).
+static size_t ws_bytes(const pdmrg_heff *o, int which) {
+    const size_t es = o->prec == PDMRG_F64 ? sizeof(double) : sizeof(float);
+    const HeffPlan &pl = o->plan;
+    const int64_t n = which == 1 ? pl.nT1 : which == 2 ? pl.nT2 : pl.nP;
+    return (size_t)std::max<int64_t>(n, 1) * es;
+}
+
 GemmPrec gemm_prec(int prec) {
     switch (prec) {
         case PDMRG_F64: return GemmPrec::F64;
@@ -129,7 +138,8 @@ GemmPrec gemm_prec(int prec) {
 }
 
 void heff_build(pdmrg_ctx *ctx, pdmrg_heff *op, const Bond &bl, const Bond &br, const Phys &p,
-                const MpoSite &W1, const MpoSite &W2, const double *L, const double *R, int prec, bool may_time) {
+                const MpoSite &W1, const MpoSite &W2, const double *L, const double *R, int prec, bool may_time,
+                bool borrow_env, const pdmrg_heff *ws_from) {
     hipStream_t s = ctx->stream;
     (void)gemm_prec(prec);
     op->prec = prec;
@@ -151,18 +161,32 @@ void heff_build(pdmrg_ctx *ctx, pdmrg_heff *op, const Bond &bl, const Bond &br, 
                           (int)pl.diag_groups.size() - 1, pl.diag_max_rows, s);
     }
     const size_t es = prec == PDMRG_F64 ? sizeof(double) : sizeof(float);
-    op->L.ensure(std::max<int64_t>(op->nL, 1) * es);
-    op->R.ensure(std::max<int64_t>(op->nR, 1) * es);
-    if (prec == PDMRG_F64) {
-        if (op->nL) HIP_OK(hipMemcpyAsync(op->L.ptr, L, op->nL * es, hipMemcpyDeviceToDevice, s));
-        if (op->nR) HIP_OK(hipMemcpyAsync(op->R.ptr, R, op->nR * es, hipMemcpyDeviceToDevice, s));
+    if (prec == PDMRG_F64 && borrow_env) {
+        op->lp = L;
+        op->rp = R;
     } else {
-        launch_convert_f64_f32(L, op->L.as<float>(), op->nL, s);
-        launch_convert_f64_f32(R, op->R.as<float>(), op->nR, s);
-        op->xs.ensure(std::max<int64_t>(op->nX, 1) * sizeof(float));
+        op->L.ensure(std::max<int64_t>(op->nL, 1) * es);
+        op->R.ensure(std::max<int64_t>(op->nR, 1) * es);
+        if (prec == PDMRG_F64) {
+            if (op->nL) HIP_OK(hipMemcpyAsync(op->L.ptr, L, op->nL * es, hipMemcpyDeviceToDevice, s));
+            if (op->nR) HIP_OK(hipMemcpyAsync(op->R.ptr, R, op->nR * es, hipMemcpyDeviceToDevice, s));
+        } else {
+            launch_convert_f64_f32(L, op->L.as<float>(), op->nL, s);
+            launch_convert_f64_f32(R, op->R.as<float>(), op->nR, s);
+        }
+        op->lp = op->L.ptr;
+        op->rp = op->R.ptr;
     }
-    op->T1.ensure(std::max<int64_t>(pl.nT1, 1) * es);
-    op->T2.ensure(std::max<int64_t>(pl.nT2, 1) * es);
+    if (prec != PDMRG_F64) op->xs.ensure(std::max<int64_t>(op->nX, 1) * sizeof(float));
+    // intermediates: another operator's where they are large enough
+    auto pick = [&](DevBuf &own, void *other, size_t other_bytes, size_t need) -> void * {
+        if (other && other_bytes >= need) return other;
+        own.ensure(need);
+        return own.ptr;
+    };
+    const size_t n1 = std::max<int64_t>(pl.nT1, 1) * es, n2 = std::max<int64_t>(pl.nT2, 1) * es;
+    op->t1 = pick(op->T1, ws_from ? ws_from->t1 : nullptr, ws_from ? ws_bytes(ws_from, 1) : 0, n1);
+    op->t2 = pick(op->T2, ws_from ? ws_from->t2 : nullptr, ws_from ? ws_bytes(ws_from, 2) : 0, n2);
     if (ctx->autotune > 0) {
         const std::string key = tune_key(ctx->device, prec, bl, br, W1, W2);
         Tuned hit;
@@ -179,7 +203,8 @@ void heff_build(pdmrg_ctx *ctx, pdmrg_heff *op, const Bond &bl, const Bond &br, 
             tune_heff(ctx, op, key);
         }
     }
-    op->P.ensure(std::max<int64_t>(pl.nP, 1) * (prec == PDMRG_F64 ? sizeof(double) : sizeof(float)));
+    op->pp = pick(op->P, ws_from ? ws_from->pp : nullptr, ws_from ? ws_bytes(ws_from, 3) : 0,
+                  std::max<int64_t>(pl.nP, 1) * (prec == PDMRG_F64 ? sizeof(double) : sizeof(float)));
 }
 
 int tune_export(const char *path) {
@@ -250,11 +275,11 @@ static void heff_launch(pdmrg_heff *op, const double *x, double *y, hipStream_t 
         sl.p[0] = op->xs.ptr;
     }
     sl.p[1] = y;
-    sl.p[2] = op->L.ptr;
-    sl.p[3] = op->R.ptr;
-    sl.p[4] = op->T1.ptr;
-    sl.p[5] = op->T2.ptr;
-    sl.p[6] = op->P.ptr;
+    sl.p[2] = op->lp;
+    sl.p[3] = op->rp;
+    sl.p[4] = op->t1;
+    sl.p[5] = op->t2;
+    sl.p[6] = op->pp;
     pl.g1.launch(gp, f64, sl, s);
     if (ev) HIP_OK(hipEventRecord(ev[1], s));
     pl.w.launch(f64, sl, s);

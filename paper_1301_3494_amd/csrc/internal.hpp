@@ -10,6 +10,10 @@ struct pdmrg_heff {
     pdmrg::DevBuf P;               // split-K partials of stage 3 (FP64)
     pdmrg::DevBuf diag;            // diag(H_eff), FP64
     pdmrg::DevBuf diag_terms, diag_groups;
+    // buffers the launches use: the owned ones above, or the caller's FP64
+    // environments (borrowed) and another operator's intermediates (shared)
+    const void *lp = nullptr, *rp = nullptr;
+    void *t1 = nullptr, *t2 = nullptr, *pp = nullptr;
     int64_t nX = 0, nL = 0, nR = 0;
     // captured kernel sequences of heff_apply, one per (x, y) pair
     struct Graph {
@@ -44,9 +48,14 @@ GemmPrec gemm_prec(int prec);
 // may_time: with ctx->autotune >= 1, time the candidate plans on a cache
 // miss (false: a miss takes the cost model, as inside sweeps where bond
 // shapes rarely repeat).
+// borrow_env (FP64 only): the operator reads L and R in place (the caller
+// keeps them alive and unchanged while it is used) instead of copying them.
+// ws_from: an operator of the same bond whose intermediates (T1, T2, split-K
+// partials) this one reuses where they are large enough; the two must not be
+// applied at the same time.
 void heff_build(pdmrg_ctx *ctx, pdmrg_heff *op, const Bond &bl, const Bond &br, const Phys &p,
                 const MpoSite &W1, const MpoSite &W2, const double *L, const double *R, int prec,
-                bool may_time = true);
+                bool may_time = true, bool borrow_env = false, const pdmrg_heff *ws_from = nullptr);
 void heff_run(pdmrg_ctx *ctx, pdmrg_heff *op, const double *x, double *y);
 
 struct DavResult {

@@ -77,6 +77,15 @@ struct DiagTerm {
     double coef;
 };
 
+// A launch's grid size in work-items is a 32-bit count of the dispatch
+// packet: blocks x threads must stay below 2^32.  Kernels over work lists
+// that can be longer than that (the dot launches of a measurement at large
+// bond dimension) take at most kMaxGrid workgroups and walk their tiles with
+// a grid stride; check_grid throws PDMRG_ESHAPE for any launch past the limit
+// (instead of a launch that fails without running).
+constexpr int64_t kMaxGrid = int64_t(1) << 20;
+void check_grid(int64_t blocks, int threads, const char *what);
+
 // Frobenius product of two packed blocks of n elements: slot a at a_off and
 // slot b at b_off; its value is added into output entry g.
 struct DotTask {

@@ -156,6 +156,7 @@ using BlockMap = std::map<std::pair<int, size_t>, std::vector<void *>>;
 struct DeviceCache {
     BlockMap free_, pending_;
     size_t pending_bytes = 0;
+    int64_t in_use = 0, peak = 0, cached = 0;   // bytes (size classes)
 };
 DeviceCache &cache() {
     static DeviceCache *c = new DeviceCache();   // never destroyed: no hipFree after runtime teardown
@@ -241,7 +242,28 @@ void DevBuf::alloc(size_t n) {
     }
     ptr = p;
     bytes = cls;
+    {
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        c.in_use += (int64_t)cls;
+        c.peak = std::max(c.peak, c.in_use);
+    }
     poison(ptr, cls);
+}
+
+void alloc_stats(int64_t *in_use, int64_t *peak, int64_t *cached) {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    DeviceCache &c = cache();
+    int64_t held = 0;
+    for (auto *m : {&c.free_, &c.pending_})
+        for (auto &kv : *m) held += (int64_t)kv.first.second * (int64_t)kv.second.size();
+    if (in_use) *in_use = c.in_use;
+    if (peak) *peak = c.peak;
+    if (cached) *cached = held;
+}
+
+void alloc_reset_peak() {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    cache().peak = cache().in_use;
 }
 
 void DevBuf::release() {
@@ -252,10 +274,16 @@ void DevBuf::release() {
             DeviceCache &c = cache();
             c.pending_[std::make_pair(dev, bytes)].push_back(ptr);
             c.pending_bytes += bytes;
+            c.in_use -= (int64_t)bytes;
         }
     }
     ptr = nullptr;
     bytes = 0;
+}
+
+void check_grid(int64_t blocks, int threads, const char *what) {
+    PD_REQUIRE(blocks >= 0 && blocks * (int64_t)threads < (int64_t(1) << 32), PDMRG_ESHAPE,
+               std::string(what) + ": launch grid beyond 2^32 work-items");
 }
 
 // ---------------------------------------------------------------- worker pool

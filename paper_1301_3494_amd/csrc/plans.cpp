@@ -113,6 +113,7 @@ GemmList GemmList::host_copy() const {
     GemmList g;
     g.ta = ta;
     g.tb = tb;
+    g.elem_bytes = elem_bytes;
     g.shape = shape;
     g.shapes_allowed = shapes_allowed;
     g.items = items;
@@ -198,6 +199,7 @@ void GemmList::build_tiles() {
             ntiles_real += ((items[i].M + bm - 1) / bm) * ((items[i].N + bn - 1) / bn);
     }
     tiles = place_tiles(items, kof, bm, bn);
+    check_grid((int64_t)tiles.size(), 256, "gemm");
     PD_REQUIRE(std::count_if(tiles.begin(), tiles.end(), [](const GemmTile &t) { return t.item >= 0; }) ==
                    ntiles_real, PDMRG_ESHAPE, "gemm: tile placement lost tiles");
     ftiles.clear();
@@ -256,7 +258,8 @@ void GemmList::validate(const std::vector<int64_t> &slot_elems) const {
             const GemmSeg &sg = segs[it.seg0 + k];
             const int64_t span_a = ta ? (int64_t)sg.K * sg.lda : (int64_t)it.M * sg.lda;
             const int64_t span_b = tb ? (int64_t)it.N * sg.ldb : (int64_t)sg.K * sg.ldb;
-            PD_REQUIRE(span_a * 8 < ((int64_t)1 << 31) && span_b * 8 < ((int64_t)1 << 31), PDMRG_ESHAPE,
+            PD_REQUIRE(span_a * elem_bytes < ((int64_t)1 << 31) && span_b * elem_bytes < ((int64_t)1 << 31),
+                       PDMRG_ESHAPE,
                        "gemm: operand block exceeds 2 GiB");
         }
         for (int k = 0; k < it.nseg; ++k) {
@@ -488,6 +491,7 @@ void HeffPlan::build(const Bond &bl_, const Bond &br_, const Phys &p_, const Mpo
     std::vector<int64_t> t1base(nl, -1);
     nT1 = 0;
     g1 = GemmList();
+    g1.elem_bytes = prec == PDMRG_F64 ? 8 : 4;
     for (int j = 0; j < nl; ++j) {
         const int M = Lt.rows[j], N = X.cols[j], K = bl.dim[j];
         if (M == 0 || N == 0) continue;
@@ -548,15 +552,31 @@ void HeffPlan::build(const Bond &bl_, const Bond &br_, const Phys &p_, const Mpo
         }
 
     // stage 3: y[i, s1 s2] = T2[i, s1 s2] x Rbra[k], one stacked item per k
+    // (cut into several where the stacked T2 operand would span 2 GiB or
+    // more, the reach of the kernels' 32-bit buffer offsets)
     g3 = GemmList();
+    const int64_t es3 = prec == PDMRG_F64 ? 8 : 4;
+    g3.elem_bytes = (int)es3;
     for (int k = 0; k < br.nsec(); ++k) {
         if (by_k[k].empty()) continue;
-        std::vector<RowBlock> blks;
-        for (auto [i, sg] : by_k[k])
-            blks.push_back(RowBlock{X.base[i] + X.colo[(size_t)i * d2 + sg], 0, bl.dim[i], X.cols[i]});
-        g3.add_stacked_item(1, br.dim[k], blks);
-        const auto [i0, sg0] = by_k[k][0];
-        if (Rt.rows[k] > 0) g3.add_seg(5, t2base[(size_t)i0 * d2 + sg0], Rt.rows[k], 3, Rt.base[k], br.dim[k], Rt.rows[k]);
+        const int64_t ld = std::max(Rt.rows[k], 1);
+        size_t b0 = 0;
+        while (b0 < by_k[k].size()) {
+            std::vector<RowBlock> blks;
+            int64_t rows = 0;
+            size_t b1 = b0;
+            for (; b1 < by_k[k].size(); ++b1) {
+                const auto [i, sg] = by_k[k][b1];
+                if (!blks.empty() && (rows + bl.dim[i]) * ld * es3 >= (int64_t(1) << 31)) break;
+                blks.push_back(RowBlock{X.base[i] + X.colo[(size_t)i * d2 + sg], 0, bl.dim[i], X.cols[i]});
+                rows += bl.dim[i];
+            }
+            g3.add_stacked_item(1, br.dim[k], blks);
+            const auto [i0, sg0] = by_k[k][b0];
+            if (Rt.rows[k] > 0)
+                g3.add_seg(5, t2base[(size_t)i0 * d2 + sg0], Rt.rows[k], 3, Rt.base[k], br.dim[k], Rt.rows[k]);
+            b0 = b1;
+        }
     }
 
     // diag(H_eff): sum over channels with delta = 0 of L[a,w,a] W12 R[b,w2,b]

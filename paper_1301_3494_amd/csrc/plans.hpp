@@ -30,6 +30,7 @@ struct LcDev {
 
 struct GemmList {
     bool ta = false, tb = false;
+    int elem_bytes = 8;                    // operand element size (4 in the FP32 / BF16x3 modes)
     TileShape shape = TileShape::T64x64;   // set by pick_tile()
     unsigned shapes_allowed = ((1u << kNumShapes) - 1) & ~kDmaShapes;   // H_eff plans add kDmaShapes
     std::vector<GemmItem> items;

@@ -212,3 +212,23 @@ def test_grad_couplings_rejects_mpo_without_tables(ctx):
     raw.ncouplings = 2
     with pytest.raises(pl.PdmrgError):
         pl.dE_dcouplings(mps, raw)
+
+
+def test_grad_per_site_identity_past_one_grid(ctx):
+    """J-Q2 16 x 8 at m = 1200 (binomial bonds, seeded random state, D = 110):
+    at the bonds next to the edges the measurement's block dot products take
+    more tiles than one launch's grid (about 1.3e6 > 2^20), so the dot kernel
+    walks them with a grid stride.  E is linear in every W_i, so each
+    <G_i, W_i> equals E; a dropped or stale tile breaks it at that site."""
+    Lx, Ly, m = 16, 8, 1200
+    N = Lx * Ly
+    mpo = pl.Mpo("jq2", Lx, Ly, (1.0, 1.0))
+    bonds, sites = synth.random_mps(N, m, 6)
+    mps = pl.Mps(ctx, bonds, sites)
+    _, G = mps.gradients(mpo)
+    E = mps.energy(mpo)   # of the re-gauged state (the random one's norm can overflow)
+    gw = np.array([float(np.sum(G[i].cpu().numpy() * mpo.W[i])) for i in range(N)])
+    bad = np.nonzero(np.abs(gw - E) > 1e-8 * abs(E))[0]
+    say("E", E, "worst <G_i,W_i> rel", np.max(np.abs(gw - E)) / abs(E), "bad sites", bad[:8])
+    assert len(bad) == 0
+    mps.free()

@@ -130,3 +130,29 @@ def test_concurrent_regions_bitwise_equal_to_sequential(ctx):
     for a, b in zip(out[False][1], out[True][1]):
         assert np.array_equal(a, b)
     assert abs(out[True][0][-1] - E_ED_CHAIN16) <= 1e-6 * abs(E_ED_CHAIN16)
+
+
+@pytest.mark.parametrize("n_regions,concurrent", [(1, False), (2, False), (4, True)])
+def test_env_recompute_stride_same_bits_less_memory(ctx, n_regions, concurrent):
+    """Environment recompute (stride 3): the sweeps give the same bits as
+    with every environment kept, the measurement sweep the same gradient,
+    and the allocator's peak of device memory in use is lower."""
+    N, m = 24, 48
+    mpo = pl.Mpo("chain", N, 1, (1.0, 1.0))
+    bonds, sites = synth.random_mps(N, 16, 11)
+    out = {}
+    for stride in (0, 3):
+        pl.set_env_stride(ctx, stride)
+        mps = pl.Mps(ctx, bonds, sites)
+        pl.memory_stats(reset_peak=True)
+        in0 = pl.memory_stats()[0]
+        E = [mps.sweep(mpo, m, 1 if k == 0 else n_regions, concurrent=concurrent)["energy"] for k in range(3)]
+        peak = pl.memory_stats()[1] - in0
+        _, G = mps.gradients(mpo)
+        out[stride] = (E, [g.cpu().numpy() for g in G], peak)
+        mps.free()
+    pl.set_env_stride(ctx, 0)
+    say("stride energies", out[0][0], out[3][0], "peak bytes", out[0][2], out[3][2])
+    assert out[0][0] == out[3][0]
+    assert all(np.array_equal(a, b) for a, b in zip(out[0][1], out[3][1]))
+    assert out[3][2] < out[0][2]
