@@ -813,11 +813,22 @@ def main():
     ap.add_argument("--tune-save", default=None, help="write the tuning cache to this file at the end")
     ap.add_argument("--autotune", type=int, default=1, choices=[0, 1, 2],
                     help="tile-shape selection: 0 cost model, 1 timed at operator creation, 2 = 1 + log")
+    ap.add_argument("--hw-queues", type=int, default=8,
+                    help="hardware queues of this process (GPU_MAX_HW_QUEUES, 1..32; 0 keeps the environment's)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: measures one GPU (the regions of one sweep share a device); "
               "--gpus %d is not supported" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    # The concurrent regions of a sweep (and the merges, up to 8 regions) run on
+    # their own streams; HIP maps streams onto GPU_MAX_HW_QUEUES hardware
+    # queues (4 by default), and streams that share a queue serialise.  Set
+    # before the HIP runtime starts (the first device call below).
+    if args.hw_queues:
+        if not 1 <= args.hw_queues <= 32:
+            print("bench.py: --hw-queues must be in 1..32", file=sys.stderr)
+            sys.exit(2)
+        os.environ["GPU_MAX_HW_QUEUES"] = str(args.hw_queues)
 
     import numpy as np
     import torch
@@ -898,6 +909,7 @@ def main():
         "data": "synthetic (seeded random MPS, environments built on the GPU)",
         "config": {"workload": "heisenberg_cyl8x4_m1024_centre_heff", "lattice": "8x4 cylinder, snake order",
                    "autotune": args.autotune, "tune_db": os.path.basename(args.tune_db) if args.tune_db else None,
+                   "hw_queues": int(os.environ.get("GPU_MAX_HW_QUEUES", "4")),
                    "m": wl["m"], "mpo_D": int(W1.W.shape[0]), "psi_elems": info["n_psi"],
                    "flops_per_matvec": info["flops"], "dense_equiv_flops": 4.0 * 14 * 4 * 1024 ** 3},
         "roofline": {"bound": "mfma", "kernel": "%s stage %d (%s), %s tiles" % (
