@@ -6,6 +6,7 @@
 #include "kernels.hpp"
 
 #include <algorithm>
+#include <stdexcept>
 
 namespace pdmrg {
 
@@ -332,6 +333,179 @@ __global__ void scale_inv_sqrt_kernel(const double *x, const double *nrm2, doubl
 }
 void launch_scale_by_inv_sqrt(const double *x, const double *nrm2, double *y, int64_t n, hipStream_t s) {
     hipLaunchKernelGGL(scale_inv_sqrt_kernel, grid_for(n), dim3(256), 0, s, x, nrm2, y, n);
+}
+
+// ------------------------------------------------------------ fused Davidson passes
+// Block b owns the contiguous element range [b chunk, (b + 1) chunk); every
+// thread keeps one running sum per output, then the sums of a block are
+// reduced in a fixed order (lanes by xor-shuffle, the 4 waves in LDS).
+template <int NO>
+__device__ __forceinline__ void block_store_sums(double (&acc)[NO], int nout, double *row) {
+    __shared__ double sh[4][NO];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int v = 0; v < NO; ++v) {
+        if (v < nout) {   // uniform over the block
+            double x = acc[v];
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+            if (lane == 0) sh[wave][v] = x;
+        }
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < nout) {
+        const int v = threadIdx.x;
+        row[v] = ((sh[0][v] + sh[1][v]) + sh[2][v]) + sh[3][v];
+    }
+}
+
+__device__ __forceinline__ void block_range(int64_t n, int64_t &i0, int64_t &i1) {
+    const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
+    i0 = blockIdx.x * chunk;
+    i1 = min(n, i0 + chunk);
+}
+
+template <int KM>
+__global__ __launch_bounds__(256) void dav_ritz_kernel(const double *__restrict__ V, const double *__restrict__ HV,
+                                                       int64_t ldv, int k, const double *__restrict__ c,
+                                                       const double *__restrict__ theta,
+                                                       const double *__restrict__ diag, double *__restrict__ X,
+                                                       double *__restrict__ HX, double *__restrict__ R,
+                                                       double *__restrict__ T, int64_t n, double *partial) {
+    const double th = *theta;
+    double cc[KM], acc[KM + 1];
+#pragma unroll
+    for (int v = 0; v < KM; ++v) cc[v] = v < k ? c[v] : 0.0;
+#pragma unroll
+    for (int v = 0; v <= KM; ++v) acc[v] = 0.0;
+    int64_t i0, i1;
+    block_range(n, i0, i1);
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += 256) {
+        double vv[KM], x = 0.0, hx = 0.0;
+#pragma unroll
+        for (int v = 0; v < KM; ++v)
+            if (v < k) {
+                vv[v] = V[v * ldv + i];
+                x += cc[v] * vv[v];
+            }
+#pragma unroll
+        for (int v = 0; v < KM; ++v)
+            if (v < k) hx += cc[v] * HV[v * ldv + i];
+        const double r = hx - th * x;
+        double den = diag[i] - th;
+        if (fabs(den) < 1e-8) den = copysign(1e-8, den);
+        const double t = r / den;
+        X[i] = x;
+        HX[i] = hx;
+        R[i] = r;
+        T[i] = t;
+        acc[0] += r * r;
+#pragma unroll
+        for (int v = 0; v < KM; ++v)
+            if (v < k) acc[v + 1] += vv[v] * t;
+    }
+    block_store_sums<KM + 1>(acc, k + 1, partial + (int64_t)blockIdx.x * (k + 1));
+}
+
+template <int KM>
+__global__ __launch_bounds__(256) void dav_sub_dot_kernel(const double *__restrict__ V, int64_t ldv, int k,
+                                                          const double *__restrict__ d, double *__restrict__ T,
+                                                          int64_t n, int with_dots, double *partial) {
+    double dd[KM], acc[KM];
+#pragma unroll
+    for (int v = 0; v < KM; ++v) {
+        dd[v] = v < k ? d[v] : 0.0;
+        acc[v] = 0.0;
+    }
+    int64_t i0, i1;
+    block_range(n, i0, i1);
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += 256) {
+        double vv[KM], a = 0.0;
+#pragma unroll
+        for (int v = 0; v < KM; ++v)
+            if (v < k) {
+                vv[v] = V[v * ldv + i];
+                a += dd[v] * vv[v];
+            }
+        const double t = T[i] - a;
+        T[i] = t;
+        if (with_dots) {
+#pragma unroll
+            for (int v = 0; v < KM; ++v)
+                if (v < k) acc[v] += vv[v] * t;
+        } else {
+            acc[0] += t * t;
+        }
+    }
+    const int nout = with_dots ? k : 1;
+    block_store_sums<KM>(acc, nout, partial + (int64_t)blockIdx.x * nout);
+}
+
+template <int KM>
+__global__ __launch_bounds__(256) void dav_ext_gram_kernel(const double *__restrict__ V,
+                                                           const double *__restrict__ HV, int64_t ldv, int k,
+                                                           int64_t n, double *partial) {
+    double acc[2 * KM + 1];
+#pragma unroll
+    for (int v = 0; v <= 2 * KM; ++v) acc[v] = 0.0;
+    int64_t i0, i1;
+    block_range(n, i0, i1);
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += 256) {
+        const double vk = V[k * ldv + i], hk = HV[k * ldv + i];
+#pragma unroll
+        for (int v = 0; v < KM; ++v)
+            if (v < k) {
+                acc[v] += V[v * ldv + i] * hk;
+                acc[KM + 1 + v] += HV[v * ldv + i] * vk;
+            }
+        acc[KM] += vk * hk;
+    }
+    // row of 2 KM + 1 sums: [V_v.HV_k (v < k) ..., V_k.HV_k at KM, HV_v.V_k at KM + 1 + v]
+    block_store_sums<2 * KM + 1>(acc, 2 * KM + 1, partial + (int64_t)blockIdx.x * (2 * KM + 1));
+}
+
+__global__ void dav_g_scatter_kernel(double *G, int ld, int k, int km, const double *dots, int exact_row) {
+    const int v = threadIdx.x;
+    if (v < k) G[(int64_t)v * ld + k] = dots[v];
+    if (v == k) G[(int64_t)k * ld + k] = dots[km];
+    if (v < k) G[(int64_t)k * ld + v] = dots[km + 1 + v];
+    __syncthreads();
+    if (exact_row && k > 0 && v == 0) G[k] = G[(int64_t)k * ld];
+}
+
+void launch_dav_ritz(const double *V, const double *HV, int64_t ldv, int k, const double *c, const double *theta,
+                     const double *diag, double *x, double *hx, double *r, double *t, int64_t n, double *partial,
+                     int nblk, hipStream_t s) {
+    if (k < 1 || k > kDavFused) throw std::invalid_argument("dav_ritz: k out of range");
+    if (k <= 8)
+        hipLaunchKernelGGL(dav_ritz_kernel<8>, dim3(nblk), dim3(256), 0, s, V, HV, ldv, k, c, theta, diag, x, hx,
+                           r, t, n, partial);
+    else
+        hipLaunchKernelGGL(dav_ritz_kernel<kDavFused>, dim3(nblk), dim3(256), 0, s, V, HV, ldv, k, c, theta, diag,
+                           x, hx, r, t, n, partial);
+}
+void launch_dav_sub_dot(const double *V, int64_t ldv, int k, const double *d, double *t, int64_t n,
+                        bool with_dots, double *partial, int nblk, hipStream_t s) {
+    if (k < 1 || k > kDavFused) throw std::invalid_argument("dav_sub_dot: k out of range");
+    if (k <= 8)
+        hipLaunchKernelGGL(dav_sub_dot_kernel<8>, dim3(nblk), dim3(256), 0, s, V, ldv, k, d, t, n, (int)with_dots,
+                           partial);
+    else
+        hipLaunchKernelGGL(dav_sub_dot_kernel<kDavFused>, dim3(nblk), dim3(256), 0, s, V, ldv, k, d, t, n,
+                           (int)with_dots, partial);
+}
+int dav_ext_gram_width(int k) { return k < 8 ? 8 : kDavFused; }
+void launch_dav_ext_gram(const double *V, const double *HV, int64_t ldv, int k, int64_t n, double *partial,
+                         int nblk, hipStream_t s) {
+    if (k < 0 || k >= kDavFused) throw std::invalid_argument("dav_ext_gram: k out of range");
+    if (k < 8)
+        hipLaunchKernelGGL(dav_ext_gram_kernel<8>, dim3(nblk), dim3(256), 0, s, V, HV, ldv, k, n, partial);
+    else
+        hipLaunchKernelGGL(dav_ext_gram_kernel<kDavFused>, dim3(nblk), dim3(256), 0, s, V, HV, ldv, k, n, partial);
+}
+void launch_dav_g_scatter(double *G, int ld, int k, const double *dots, bool exact_row, hipStream_t s) {
+    hipLaunchKernelGGL(dav_g_scatter_kernel, dim3(1), dim3(64), 0, s, G, ld, k, dav_ext_gram_width(k), dots,
+                       (int)exact_row);
 }
 
 // ------------------------------------------------------------ projected eigenproblem

@@ -27,10 +27,12 @@ struct DavWs {
     double *G;        // [ks][ks]
     double *c;        // [ks]
     double *dots;     // [ks]
-    double *scal;     // [8]: 0 theta, 1 rr, 2 tn2, 3 nrm2
+    double *scal;     // [kScal]: 0 theta, 1 rr, 2 tn2, 3 nrm2; the fused
+                      // passes reduce [rr, V_0.t, ..] into 1 .. k + 1
     double *partial;  // [nblk][ks]
 };
-constexpr int kBlk = 240;
+constexpr int kBlk = 1024;   // blocks of the reduction passes (4 per CU: memory parallelism)
+constexpr int kScal = 8 + kDavFused + 2;
 }  // namespace
 
 DavResult davidson_run(pdmrg_ctx *ctx, pdmrg_heff *op, pdmrg_heff *op64, double *psi,
@@ -46,7 +48,8 @@ DavResult davidson_run(pdmrg_ctx *ctx, pdmrg_heff *op, pdmrg_heff *op64, double 
     // workspace (owned by the context, grown on demand)
     DevBuf &ws = ctx->ws_dav;
     const size_t nvec = (size_t)2 * ks + 4;
-    const size_t small = (size_t)ks * ks + 2 * ks + 8 + (size_t)kBlk * ks;
+    const size_t ndots = std::max(ks, 2 * kDavFused + 2);
+    const size_t small = (size_t)ks * ks + ks + ndots + kScal + (size_t)kBlk * (2 * std::max(ks, kDavFused) + 2);
     ws.ensure((nvec * n + small) * sizeof(double));
     DavWs w;
     double *b = ws.as<double>();
@@ -58,9 +61,12 @@ DavResult davidson_run(pdmrg_ctx *ctx, pdmrg_heff *op, pdmrg_heff *op64, double 
     w.t = b; b += n;
     w.G = b; b += (size_t)ks * ks;
     w.c = b; b += ks;
-    w.dots = b; b += ks;
-    w.scal = b; b += 8;
+    w.dots = b; b += ndots;
+    w.scal = b; b += kScal;
     w.partial = b;
+    // subspaces of up to kDavFused vectors take the fused passes (one read of
+    // each vector per pass, fewer launches); larger ones the separate kernels
+    const bool fused = ks <= kDavFused;
 
     auto dot_into = [&](const double *U, int nv, const double *x, double *out, int stride = 1) {
         launch_multidot(U, n, nv, x, n, w.partial, kBlk, s);
@@ -80,6 +86,12 @@ DavResult davidson_run(pdmrg_ctx *ctx, pdmrg_heff *op, pdmrg_heff *op64, double 
     };
     // G column/row for vector k: G[i][k] = V_i . HV_k, G[k][i] = V_k . HV_i
     auto extend_G = [&](int k) {
+        if (fused) {
+            launch_dav_ext_gram(w.V, w.HV, n, k, n, w.partial, kBlk, s);
+            launch_reduce_partials(w.partial, kBlk, 2 * dav_ext_gram_width(k) + 1, w.dots, 1, s);
+            launch_dav_g_scatter(w.G, ks, k, w.dots, refine, s);
+            return;
+        }
         dot_into(w.V, k + 1, w.HV + (size_t)k * n, w.G + k, ks);          // column k
         if (k > 0) dot_into(w.HV, k, w.V + (size_t)k * n, w.G + (size_t)k * ks);   // row k
         // Mixed precision: G[0][k] = x . H~ t_k carries the low-precision error
@@ -87,6 +99,29 @@ DavResult davidson_run(pdmrg_ctx *ctx, pdmrg_heff *op, pdmrg_heff *op64, double 
         // uses the exact FP64 product; take the exact one for both.
         if (refine && k > 0)
             HIP_OK(hipMemcpyAsync(w.G + k, w.G + (size_t)k * ks, sizeof(double), hipMemcpyDeviceToDevice, s));
+    };
+
+    // Ritz pair of the k-vector basis, residual r (|r|^2 -> scal[1]),
+    // preconditioned correction t orthogonalised twice against V
+    // (|t|^2 -> scal[2]); theta -> scal[0], x, hx
+    auto ritz_step = [&](int k) {
+        launch_small_eig(w.G, k, ks, w.scal + 0, w.c, s);
+        if (fused) {
+            launch_dav_ritz(w.V, w.HV, n, k, w.c, w.scal + 0, diag, w.X, w.HX, w.r, w.t, n, w.partial, kBlk, s);
+            launch_reduce_partials(w.partial, kBlk, k + 1, w.scal + 1, 1, s);   // rr, first projections
+            launch_dav_sub_dot(w.V, n, k, w.scal + 2, w.t, n, true, w.partial, kBlk, s);
+            launch_reduce_partials(w.partial, kBlk, k, w.dots, 1, s);           // second projections
+            launch_dav_sub_dot(w.V, n, k, w.dots, w.t, n, false, w.partial, kBlk, s);
+            launch_reduce_partials(w.partial, kBlk, 1, w.scal + 2, 1, s);       // |t|^2
+            return;
+        }
+        launch_combine(w.V, n, k, w.c, w.X, n, 0.0, s);
+        launch_combine(w.HV, n, k, w.c, w.HX, n, 0.0, s);
+        launch_residual(w.HX, w.X, w.scal + 0, w.r, n, s);
+        dot_into(w.r, 1, w.r, w.scal + 1);
+        launch_precond(w.r, diag, w.scal + 0, w.t, n, s);
+        cgs2(k, w.t);
+        dot_into(w.t, 1, w.t, w.scal + 2);
     };
 
     // V0 = psi / |psi|
@@ -100,14 +135,7 @@ DavResult davidson_run(pdmrg_ctx *ctx, pdmrg_heff *op, pdmrg_heff *op64, double 
     double theta = 0, rn = 0;
     bool converged = false;
     while (true) {
-        launch_small_eig(w.G, k, ks, w.scal + 0, w.c, s);
-        launch_combine(w.V, n, k, w.c, w.X, n, 0.0, s);
-        launch_combine(w.HV, n, k, w.c, w.HX, n, 0.0, s);
-        launch_residual(w.HX, w.X, w.scal + 0, w.r, n, s);
-        dot_into(w.r, 1, w.r, w.scal + 1);
-        launch_precond(w.r, diag, w.scal + 0, w.t, n, s);
-        cgs2(k, w.t);
-        dot_into(w.t, 1, w.t, w.scal + 2);
+        ritz_step(k);
         HIP_OK(hipMemcpyAsync(host, w.scal, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
         HIP_OK(hipStreamSynchronize(s));
         theta = host[0];
@@ -135,12 +163,7 @@ DavResult davidson_run(pdmrg_ctx *ctx, pdmrg_heff *op, pdmrg_heff *op64, double 
                 matvec(op64, w.V, w.HV);
                 k = 1;
                 extend_G(0);
-                launch_small_eig(w.G, 1, ks, w.scal + 0, w.c, s);
-                launch_residual(w.HV, w.V, w.scal + 0, w.r, n, s);
-                dot_into(w.r, 1, w.r, w.scal + 1);
-                launch_precond(w.r, diag, w.scal + 0, w.t, n, s);
-                cgs2(1, w.t);
-                dot_into(w.t, 1, w.t, w.scal + 2);
+                ritz_step(1);   // x = V0 (c = 1), hx = HV0
                 HIP_OK(hipMemcpyAsync(host, w.scal, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
                 HIP_OK(hipStreamSynchronize(s));
                 theta = host[0];

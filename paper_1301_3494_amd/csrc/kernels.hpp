@@ -194,6 +194,28 @@ void launch_precond(const double *r, const double *diag, const double *theta, do
                     hipStream_t s);
 // y = x / sqrt(*nrm2)
 void launch_scale_by_inv_sqrt(const double *x, const double *nrm2, double *y, int64_t n, hipStream_t s);
+// Fused Davidson passes for subspaces of at most kDavFused vectors (one read
+// of every vector per pass; partial sums per block in a fixed order, reduced
+// by launch_reduce_partials):
+//   ritz:       x = V c, hx = HV c, r = hx - theta x, t = r / (diag - theta)
+//               (|den| >= 1e-8); partial row [r.r, V_0.t, ..., V_{k-1}.t]
+//   sub_dot:    t -= sum_v d[v] V[v]; partial row [V_0.t, ..., V_{k-1}.t]
+//               (with_dots) or [t.t]
+//   ext_gram:   partial row of w = 2 km + 1 sums (km = dav_ext_gram_width(k)):
+//               V_v.HV_k at v < k, V_k.HV_k at km, HV_v.V_k at km + 1 + v
+//   g_scatter:  G[v][k] and G[k][v] from that reduced row; with exact_row
+//               G[0][k] = G[k][0] (the mixed-precision rule)
+// Partial rows are nvec = row length apart, one per block (nblk blocks).
+constexpr int kDavFused = 16;
+void launch_dav_ritz(const double *V, const double *HV, int64_t ldv, int k, const double *c, const double *theta,
+                     const double *diag, double *x, double *hx, double *r, double *t, int64_t n, double *partial,
+                     int nblk, hipStream_t s);
+void launch_dav_sub_dot(const double *V, int64_t ldv, int k, const double *d, double *t, int64_t n,
+                        bool with_dots, double *partial, int nblk, hipStream_t s);
+int dav_ext_gram_width(int k);
+void launch_dav_ext_gram(const double *V, const double *HV, int64_t ldv, int k, int64_t n, double *partial,
+                         int nblk, hipStream_t s);
+void launch_dav_g_scatter(double *G, int ld, int k, const double *dots, bool exact_row, hipStream_t s);
 // Lowest eigenpair of the k x k symmetric matrix G (row-major, ld) by cyclic
 // Jacobi in one workgroup: theta_out[0] = eigenvalue, c_out[0..k) eigenvector
 // with c[0] >= 0.

@@ -213,11 +213,13 @@ def test_davidson_mixed_vs_f64_at_m2000_bond(ctx):
     """One bond at the sweep workload's scale: width-8 Heisenberg cylinder
     (6 x 8, D = 26, the 24 x 8 workload's MPO width) at m = 2000, environments
     built by both sides from the same seeded isometric MPS.  Davidson to a
-    residual of 1e-8 (stalls near 2e-8 in FP64 and 1e-7 mixed after 300
-    products: energy error ~ residual^2 / gap) in FP64 and in the
+    residual of 1e-8 (energy error ~ residual^2 / gap) in FP64 and in the
     mixed mode (FP32 products, FP64 refinement) against the oracle's Davidson
     on its own environments: both within 1e-9 relative, and the mixed energy
-    is not the FP64 one bit for bit (the check sees the FP32 products)."""
+    is not the FP64 one bit for bit (the check sees the FP32 products).
+    From the random start the first 70-90 products (the number varies with
+    rounding) find the ground state; then the residual falls by about 0.6 per
+    restart cycle of 8 products, so 500 products leave a margin."""
     Lx, Ly, m, seed = 6, 8, 2000, 12
     N = Lx * Ly
     c = N // 2 - 1
@@ -260,7 +262,7 @@ def test_davidson_mixed_vs_f64_at_m2000_bond(ctx):
         op = pl.Heff(ctx, B1, B2, P, W1, W2, Lg, Rg, prec)
         op64 = pl.Heff(ctx, B1, B2, P, W1, W2, Lg, Rg, pl.F64) if prec != pl.F64 else None
         x = dev(x0)
-        E[name], rn, nmv, code = pl.davidson_step(ctx, op, x, max_matvec=300, max_sub=8, tol=1e-8, op64=op64)
+        E[name], rn, nmv, code = pl.davidson_step(ctx, op, x, max_matvec=500, max_sub=8, tol=1e-8, op64=op64)
         say("  m=2000 bond", name, "E", E[name], "resid", rn, "nmv", nmv)
         assert rn <= 5e-7, name
         op.free()
