@@ -323,6 +323,7 @@ struct Driver {
         }
         ctx->sub[r]->autotune = ctx->autotune;
         ctx->sub[r]->graphs = ctx->graphs;
+        ctx->sub[r]->verbose = ctx->verbose;
         return ctx->sub[r];
     }
 

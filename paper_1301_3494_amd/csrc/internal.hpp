@@ -94,6 +94,19 @@ void grad_site_run(pdmrg_ctx *ctx, const GradPlan &plan, const double *L, const 
                    double *G);
 void svd_truncate_run(pdmrg_ctx *ctx, const Bond &bl, const Bond &br, const Phys &p, const double *psi,
                       int max_m, double cutoff, double eps, int mode, SvdOut &out);
+// Several truncated SVDs in one batch: the sector blocks of all problems
+// share the Jacobi launches (each block on its own tolerance); each problem
+// is truncated on its own.  The results equal separate svd_truncate_run calls.
+struct SvdProblem {
+    const Bond *bl, *br;
+    const Phys *p;
+    const double *psi;
+    int max_m;
+    double cutoff;
+    int mode;
+};
+void svd_truncate_multi(pdmrg_ctx *ctx, const std::vector<SvdProblem> &probs, double eps,
+                        std::vector<SvdOut> &outs);
 
 }  // namespace pdmrg
 

@@ -98,6 +98,9 @@ void svd_batch(pdmrg_ctx *ctx, const std::vector<Mat> &mats, std::vector<SvdRes>
         PD_REQUIRE((int64_t)nv * len * 8 < (int64_t(1) << 31), PDMRG_EINVAL, "svd: block too large");
         items[i].nv = nv;
         items[i].len = len;
+        // each matrix on its own tolerance, so a matrix's rotations do not
+        // depend on which others share its launches
+        items[i].tol = std::max(1e-14, 8.0 * 2.220446049250313e-16 * std::sqrt((double)len));
         items[i].W = ar.take((size_t)nv * len);
         items[i].Z = ar.take((size_t)nv * nv);
         out[i].nr = m.nr;
@@ -153,21 +156,19 @@ void svd_batch(pdmrg_ctx *ctx, const std::vector<Mat> &mats, std::vector<SvdRes>
     upload(d_pairs, flat, s);
     std::vector<int32_t> active(nm, 1);
     d_off.ensure(std::max(nm, 1) * sizeof(unsigned long long));
-    std::vector<double> tol(nm);
-    for (int i = 0; i < nm; ++i) tol[i] = std::max(1e-14, 8.0 * 2.220446049250313e-16 * std::sqrt((double)items[i].len));
-    double tol_all = *std::max_element(tol.begin(), tol.end());
+
     for (int sweep = 0; sweep < kMaxSweeps; ++sweep) {
         upload(d_active, active, s);
         launch_fill(d_off.as<double>(), 0.0, nm, s);
         for (int r = 0; r < rmax; ++r)
             launch_jac_round(d_items.as<JacItem>(), d_pairs.as<JacPair>() + roff[r], roff[r + 1] - roff[r],
-                             d_active.as<int32_t>(), d_off.as<unsigned long long>(), tol_all, s);
+                             d_active.as<int32_t>(), d_off.as<unsigned long long>(), s);
         std::vector<double> off(nm);
         HIP_OK(hipMemcpyAsync(off.data(), d_off.ptr, nm * sizeof(double), hipMemcpyDeviceToHost, s));
         HIP_OK(hipStreamSynchronize(s));
         bool any = false;
         for (int i = 0; i < nm; ++i) {
-            if (active[i] && off[i] <= tol_all) active[i] = 0;
+            if (active[i] && off[i] <= items[i].tol) active[i] = 0;
             any = any || active[i];
         }
         if (!any) break;
@@ -371,25 +372,23 @@ void svd_batch(pdmrg_ctx *ctx, const std::vector<Mat> &mats, std::vector<SvdRes>
 
 }  // namespace
 
-void svd_truncate_run(pdmrg_ctx *ctx, const Bond &bl, const Bond &br, const Phys &p, const double *psi, int max_m,
-                      double cutoff, double eps, int mode, SvdOut &out) {
-    hipStream_t s = ctx->stream;
-    PD_REQUIRE(mode >= 0 && mode <= 2, PDMRG_EINVAL, "svd_truncate: bad mode");
-    PD_REQUIRE(max_m >= 1, PDMRG_EINVAL, "svd_truncate: max_m must be >= 1");
+namespace {
+// Middle-charge sector block of one problem: rows (s1, i), columns (s2, k),
+// gathered densely at M.
+struct Sec {
+    int qm, nr = 0, nc = 0;
+    std::vector<std::pair<int, int>> rows;   // (s1, i)
+    std::vector<std::pair<int, int>> cols;   // (s2, k)
+    const double *M = nullptr;
+};
+
+std::vector<Sec> middle_sectors(const Bond &bl, const Bond &br, const Phys &p) {
     const int d = p.d();
-    const SiteLayout X = two_site_layout(bl, br, p);
-    // middle-charge blocks
     std::vector<int> mids;
     for (int i = 0; i < bl.nsec(); ++i)
         for (int s1 = 0; s1 < d; ++s1) mids.push_back(bl.q[i] + p.q[s1]);
     std::sort(mids.begin(), mids.end());
     mids.erase(std::unique(mids.begin(), mids.end()), mids.end());
-    struct Sec {
-        int qm, nr = 0, nc = 0;
-        std::vector<std::pair<int, int>> rows;   // (s1, i)
-        std::vector<std::pair<int, int>> cols;   // (s2, k)
-        const double *M = nullptr;
-    };
     std::vector<Sec> secs;
     for (int qm : mids) {
         Sec sc;
@@ -404,44 +403,19 @@ void svd_truncate_run(pdmrg_ctx *ctx, const Bond &bl, const Bond &br, const Phys
         }
         if (sc.nr > 0 && sc.nc > 0) secs.push_back(sc);
     }
-    size_t need = 64;
-    for (auto &sc : secs) need += round32((size_t)sc.nr * sc.nc);
-    ctx->ws_svd.ensure(need * sizeof(double));
-    double *mbase = ctx->ws_svd.as<double>();
-    size_t off = 0;
-    std::vector<CopyTask> gather;
-    std::vector<Mat> mats;
-    for (auto &sc : secs) {
-        double *M = mbase + off;
-        off += round32((size_t)sc.nr * sc.nc);
-        sc.M = M;
-        int r0 = 0;
-        for (auto [s1, i] : sc.rows) {
-            int col0 = -1;
-            for (auto [s2, k] : sc.cols) {
-                const int co = X.colo[(size_t)i * d * d + s1 * d + s2];
-                PD_REQUIRE(co >= 0, PDMRG_ESHAPE, "svd_truncate: missing block");
-                if (col0 < 0) col0 = co;
-            }
-            CopyTask t{};
-            t.src = psi + X.base[i] + col0;
-            t.dst = M + (size_t)r0 * sc.nc;
-            t.rows = bl.dim[i];
-            t.cols = sc.nc;
-            t.sld = X.cols[i];
-            t.dld = sc.nc;
-            gather.push_back(t);
-            r0 += bl.dim[i];
-        }
-        mats.push_back(Mat{M, sc.nr, sc.nc});
-    }
-    run_copies(gather, s);
-    std::vector<SvdRes> res;
-    std::vector<Arena> keep;
-    int n_unconv = 0;
-    svd_batch(ctx, mats, res, eps, 0, keep, {}, n_unconv);
-    out.n_unconverged = n_unconv;
+    return secs;
+}
 
+// Global truncation of one problem from its blocks' factors, and its output
+// tensors (Eq. eqn:svd; modes as in svd_truncate).
+void finish_problem(pdmrg_ctx *ctx, const SvdProblem &pb, const std::vector<Sec> &secs, const SvdRes *res,
+                    SvdOut &out) {
+    hipStream_t s = ctx->stream;
+    const Bond &bl = *pb.bl, &br = *pb.br;
+    const Phys &p = *pb.p;
+    const int d = p.d();
+    const int max_m = pb.max_m, mode = pb.mode;
+    const double cutoff = pb.cutoff;
     // global truncation
     struct Cand { double l; int q, idx, sec; };
     std::vector<Cand> cand;
@@ -534,6 +508,83 @@ void svd_truncate_run(pdmrg_ctx *ctx, const Bond &bl, const Bond &br, const Phys
         }
     }
     run_copies(ct, s);
+}
+
+}  // namespace
+
+void svd_truncate_multi(pdmrg_ctx *ctx, const std::vector<SvdProblem> &probs, double eps,
+                        std::vector<SvdOut> &outs) {
+    hipStream_t s = ctx->stream;
+    const int np = (int)probs.size();
+    outs.clear();
+    outs.resize(np);
+    if (np == 0) return;
+    std::vector<std::vector<Sec>> secs(np);
+    size_t need = 64;
+    for (int t = 0; t < np; ++t) {
+        const SvdProblem &pb = probs[t];
+        PD_REQUIRE(pb.mode >= 0 && pb.mode <= 2, PDMRG_EINVAL, "svd_truncate: bad mode");
+        PD_REQUIRE(pb.max_m >= 1, PDMRG_EINVAL, "svd_truncate: max_m must be >= 1");
+        secs[t] = middle_sectors(*pb.bl, *pb.br, *pb.p);
+        for (auto &sc : secs[t]) need += round32((size_t)sc.nr * sc.nc);
+    }
+    ctx->ws_svd.ensure(need * sizeof(double));
+    double *mbase = ctx->ws_svd.as<double>();
+    size_t off = 0;
+    std::vector<CopyTask> gather;
+    std::vector<Mat> mats;
+    std::vector<int> first(np + 1, 0);
+    for (int t = 0; t < np; ++t) {
+        const SvdProblem &pb = probs[t];
+        const Bond &bl = *pb.bl;
+        const int d = pb.p->d();
+        const SiteLayout X = two_site_layout(*pb.bl, *pb.br, *pb.p);
+        first[t] = (int)mats.size();
+        for (auto &sc : secs[t]) {
+            double *M = mbase + off;
+            off += round32((size_t)sc.nr * sc.nc);
+            sc.M = M;
+            int r0 = 0;
+            for (auto [s1, i] : sc.rows) {
+                int col0 = -1;
+                for (auto [s2, k] : sc.cols) {
+                    const int co = X.colo[(size_t)i * d * d + s1 * d + s2];
+                    PD_REQUIRE(co >= 0, PDMRG_ESHAPE, "svd_truncate: missing block");
+                    if (col0 < 0) col0 = co;
+                }
+                CopyTask c{};
+                c.src = pb.psi + X.base[i] + col0;
+                c.dst = M + (size_t)r0 * sc.nc;
+                c.rows = bl.dim[i];
+                c.cols = sc.nc;
+                c.sld = X.cols[i];
+                c.dld = sc.nc;
+                gather.push_back(c);
+                r0 += bl.dim[i];
+            }
+            mats.push_back(Mat{M, sc.nr, sc.nc});
+        }
+    }
+    first[np] = (int)mats.size();
+    run_copies(gather, s);
+    // every block of every problem in one batch: one launch per Jacobi round
+    // for all of them (each block keeps its own tolerance, so its factors are
+    // those of a batch of its own)
+    std::vector<SvdRes> res;
+    std::vector<Arena> keep;
+    int n_unconv = 0;
+    svd_batch(ctx, mats, res, eps, 0, keep, {}, n_unconv);
+    for (int t = 0; t < np; ++t) {
+        finish_problem(ctx, probs[t], secs[t], res.data() + first[t], outs[t]);
+        outs[t].n_unconverged = t == 0 ? n_unconv : 0;   // the batch's count, reported once
+    }
+}
+
+void svd_truncate_run(pdmrg_ctx *ctx, const Bond &bl, const Bond &br, const Phys &p, const double *psi, int max_m,
+                      double cutoff, double eps, int mode, SvdOut &out) {
+    std::vector<SvdOut> outs;
+    svd_truncate_multi(ctx, {SvdProblem{&bl, &br, &p, psi, max_m, cutoff, mode}}, eps, outs);
+    out = std::move(outs[0]);
 }
 
 }  // namespace pdmrg

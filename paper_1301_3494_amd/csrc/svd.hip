@@ -119,7 +119,7 @@ __device__ __forceinline__ void jacobi_angle(double app, double apq, double aqq,
 __global__ __launch_bounds__(JT) void jac_pair_kernel(const JacItem *__restrict__ items,
                                                       const JacPair *__restrict__ pairs,
                                                       const int32_t *__restrict__ active,
-                                                      unsigned long long *__restrict__ offmax, double tol) {
+                                                      unsigned long long *__restrict__ offmax) {
     const JacPair pr = pairs[blockIdx.x];
     const JacItem it = items[pr.item];
     if (!active[pr.item]) return;
@@ -212,7 +212,7 @@ __global__ __launch_bounds__(JT) void jac_pair_kernel(const JacItem *__restrict_
     __syncthreads();
     const double poff = fmax(fmax(wred[0], wred[1]), fmax(wred[2], wred[3]));
     if (tid == 0) atomicMax(&offmax[pr.item], (unsigned long long)__double_as_longlong(poff));
-    if (poff <= tol) return;
+    if (poff <= it.tol) return;
     // rows absent from the matrix: isolated with eigenvalue -1 (never rotated)
     A[0][ei][ej] = (ei >= n || ej >= n) ? (ei == ej ? -1.0 : 0.0) : gij;
     Q[0][ei][ej] = ei == ej ? 1.0 : 0.0;
@@ -305,9 +305,9 @@ __global__ __launch_bounds__(JT) void jac_pair_kernel(const JacItem *__restrict_
 }
 
 void launch_jac_round(const JacItem *items, const JacPair *pairs, int npairs, const int32_t *active,
-                      unsigned long long *offmax, double tol, hipStream_t s) {
+                      unsigned long long *offmax, hipStream_t s) {
     if (npairs <= 0) return;
-    hipLaunchKernelGGL(jac_pair_kernel, dim3(npairs), dim3(JT), 0, s, items, pairs, active, offmax, tol);
+    hipLaunchKernelGGL(jac_pair_kernel, dim3(npairs), dim3(JT), 0, s, items, pairs, active, offmax);
 }
 
 __global__ void identity_kernel(const JacItem *items) {

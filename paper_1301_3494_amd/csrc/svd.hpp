@@ -4,9 +4,11 @@
 
 namespace pdmrg {
 
-// One matrix: nv rows of length len (W), rotation accumulator Z (nv x nv).
+// One matrix: nv rows of length len (W), rotation accumulator Z (nv x nv);
+// a pair needs a rotation while its relative off-diagonal exceeds tol.
 struct JacItem {
     double *W, *Z;
+    double tol;
     int32_t nv, len;
 };
 
@@ -30,7 +32,7 @@ struct CopyTask {
 };
 
 void launch_jac_round(const JacItem *items, const JacPair *pairs, int npairs, const int32_t *active,
-                      unsigned long long *offmax, double tol, hipStream_t s);
+                      unsigned long long *offmax, hipStream_t s);
 void launch_identity(const JacItem *items, int nitems, int max_nv, hipStream_t s);
 void launch_row_norms(const RowRef *rows, int nrows, double *out, hipStream_t s);
 void launch_copies(const CopyTask *tasks, int ntasks, int64_t max_elems, hipStream_t s);
