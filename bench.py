@@ -222,7 +222,7 @@ def large_bond_rates(ctx, pl, synth, np, torch, steps=10):
     contractions): 24 x 8 Heisenberg cylinder m = 2000 (D = 26), triangular
     12 x 6 m = 3000 (D = 23) and J-Q2 16 x 8 m = 4000 (the exact MPO: 110
     channels on the environments' bonds inside the columns, 98 at the centre
-    column cut); synthetic seeded environments, FP32 and FP64, plans as for
+    column cut); synthetic seeded environments, FP32, BF16x3 and FP64, plans as for
     the headline bond.  jq2_16x8_m4000_D40: the same bond with the MPO cut
     down to its first 40 channels on each of the three bonds (a synthetic
     D = 40 operator of the J-Q2 structure, the size the configuration
@@ -262,20 +262,24 @@ def large_bond_rates(ctx, pl, synth, np, torch, steps=10):
         x = torch.from_numpy(rng.standard_normal(nx)).cuda()
         y = torch.empty_like(x)
         rec = {"D": int(W1.W.shape[3]), "D_env": [int(W1.W.shape[0]), int(W2.W.shape[3])], "psi_elems": nx}
-        for pname, prec in (("f32", pl.F32), ("f64", pl.F64)):
+        for pname, prec in (("f32", pl.F32), ("bf16x3", pl.BF16X3), ("f64", pl.F64)):
             op = pl.Heff(ctx, B1, B2, P, W1, W2, L, R, prec)
             info = op.info()
             wall, ms = time_matvecs(ctx, pl, torch, op, x, y, steps, 2)
             t = wall / steps
+            issued = 3.0 if pname == "bf16x3" else 1.0   # MFMA flops issued per useful flop
             rec[pname] = {"ms_per_matvec": round(t * 1e3, 4), "tflops": round(info["flops"] / t / 1e12, 3),
-                          "pct_peak": round(100 * info["flops"] / t / 1e12 / PEAK_TFLOPS[pname], 2),
-                          "gemm_pct_peak": [round(100 * info["flops_Lpsi"] / (ms[0] * 1e-3) / 1e12 / PEAK_TFLOPS[pname], 2),
-                                            round(100 * info["flops_R"] / (ms[2] * 1e-3) / 1e12 / PEAK_TFLOPS[pname], 2)],
+                          "pct_peak": round(100 * issued * info["flops"] / t / 1e12 / PEAK_TFLOPS[pname], 2),
+                          "gemm_pct_peak": [round(100 * issued * info["flops_Lpsi"] / (ms[0] * 1e-3) / 1e12 /
+                                                  PEAK_TFLOPS[pname], 2),
+                                            round(100 * issued * info["flops_R"] / (ms[2] * 1e-3) / 1e12 /
+                                                  PEAK_TFLOPS[pname], 2)],
                           "plan": [info["shape_Lpsi"], info["shape_R"], info["splitk_parts"]]}
             rec["flops_per_matvec"] = info["flops"]
             op.free()
-        print("bench: large bond %s f32 %.2f TFLOP/s, f64 %.2f TFLOP/s" % (name, rec["f32"]["tflops"],
-              rec["f64"]["tflops"]), file=sys.stderr, flush=True)
+        rec["bf16x3_over_f32"] = round(rec["bf16x3"]["tflops"] / rec["f32"]["tflops"], 3)
+        print("bench: large bond %s f32 %.2f, bf16x3 %.2f, f64 %.2f TFLOP/s" % (
+              name, rec["f32"]["tflops"], rec["bf16x3"]["tflops"], rec["f64"]["tflops"]), file=sys.stderr, flush=True)
         out[name] = rec
         mpo.free()
         del L, R, x, y

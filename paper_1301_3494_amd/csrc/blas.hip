@@ -7,8 +7,20 @@
 
 #include <algorithm>
 #include <stdexcept>
+#include <type_traits>
 
 namespace pdmrg {
+
+// A value split for BF16x3: its FP32 rounding f = hi + lo with hi and lo
+// bf16 (both rounded to nearest even), packed as one word, hi in the low half.
+typedef float pf2 __attribute__((ext_vector_type(2)));
+typedef __bf16 pb2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t pack_split(float f) {
+    const pf2 x{f, 0.0f};
+    const pb2 h = __builtin_convertvector(x, pb2);
+    const pb2 l = __builtin_convertvector(x - __builtin_convertvector(h, pf2), pb2);
+    return (__builtin_bit_cast(uint32_t, h) & 0xffffu) | (__builtin_bit_cast(uint32_t, l) << 16);
+}
 
 // ------------------------------------------------------------ W stage
 // One workgroup per tile = a run of kLcChunk consecutive elements of a task's
@@ -69,7 +81,10 @@ __global__ __launch_bounds__(256) void lincomb_kernel(Slots slots, const LcTask 
     TD *dst = static_cast<TD *>(const_cast<void *>(slots.p[tk.dst_slot])) + tk.dst_off;
 #pragma unroll
     for (int u = 0; u < U; ++u)
-        if (ok[u]) dst[rr[u] * (unsigned)tk.ld + cc[u]] = (TD)acc[u];
+        if (ok[u]) {
+            if constexpr (std::is_same<TD, uint32_t>::value) dst[rr[u] * (unsigned)tk.ld + cc[u]] = pack_split(acc[u]);
+            else dst[rr[u] * (unsigned)tk.ld + cc[u]] = (TD)acc[u];
+        }
 }
 
 void launch_lincomb(bool f64, int chunk, const Slots &slots, const LcTask *tasks, const LcSrc *srcs,
@@ -84,6 +99,17 @@ void launch_lincomb(bool f64, int chunk, const Slots &slots, const LcTask *tasks
         if (f64) hipLaunchKernelGGL((lincomb_kernel<double, double, kLcChunk>), g, b, 0, s, slots, tasks, srcs, tiles);
         else hipLaunchKernelGGL((lincomb_kernel<float, float, kLcChunk>), g, b, 0, s, slots, tasks, srcs, tiles);
     }
+}
+
+void launch_lincomb_split(int chunk, const Slots &slots, const LcTask *tasks, const LcSrc *srcs,
+                          const LcTile *tiles, int ntiles, hipStream_t s) {
+    if (ntiles <= 0) return;
+    check_grid(ntiles, 256, "W stage");
+    const dim3 g(ntiles), b(256);
+    if (chunk == kLcChunkSmall)
+        hipLaunchKernelGGL((lincomb_kernel<float, uint32_t, kLcChunkSmall>), g, b, 0, s, slots, tasks, srcs, tiles);
+    else
+        hipLaunchKernelGGL((lincomb_kernel<float, uint32_t, kLcChunk>), g, b, 0, s, slots, tasks, srcs, tiles);
 }
 
 void launch_lincomb_f32_f64(int chunk, const Slots &slots, const LcTask *tasks, const LcSrc *srcs,
@@ -190,6 +216,10 @@ __global__ void cvt_d2f(const double *x, float *y, int64_t n) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         y[i] = (float)x[i];
 }
+__global__ void cvt_d2split(const double *x, uint32_t *y, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = pack_split((float)x[i]);
+}
 __global__ void cvt_f2d(const float *x, double *y, int64_t n) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         y[i] = (double)x[i];
@@ -208,6 +238,9 @@ static dim3 grid_for(int64_t n) {
 
 void launch_convert_f64_f32(const double *x, float *y, int64_t n, hipStream_t s) {
     if (n > 0) hipLaunchKernelGGL(cvt_d2f, grid_for(n), dim3(256), 0, s, x, y, n);
+}
+void launch_convert_f64_split(const double *x, uint32_t *y, int64_t n, hipStream_t s) {
+    if (n > 0) hipLaunchKernelGGL(cvt_d2split, grid_for(n), dim3(256), 0, s, x, y, n);
 }
 void launch_convert_f32_f64(const float *x, double *y, int64_t n, hipStream_t s) {
     if (n > 0) hipLaunchKernelGGL(cvt_f2d, grid_for(n), dim3(256), 0, s, x, y, n);

@@ -10,11 +10,10 @@
 //
 // Workgroup: 256 threads = 4 wave64.  FP64 / FP32 tiles are BM x BN with the
 // waves on a WGM x WGN grid, each wave owning an (BM/WGM) x (BN/WGN) sub-tile
-// of 16 x 16 MFMA blocks (v_mfma_f64_16x16x4 / v_mfma_f32_16x16x4).  The
-// BF16x3 kernel (64 x 64 tiles) splits FP32 operands on the fly into bf16
-// hi + lo halves (x = hi + lo, both rounded to nearest even) in K-contiguous
-// LDS tiles and accumulates hi*hi' + hi*lo' + lo*hi' with
-// v_mfma_f32_16x16x32_bf16 in FP32.
+// of 16 x 16 MFMA blocks (v_mfma_f64_16x16x4 / v_mfma_f32_16x16x4).  BF16x3
+// takes operands split once in memory (each 4-byte word a bf16 pair x = hi +
+// lo, both rounded to nearest even) through the FP32 LDS-DMA pipeline and
+// accumulates lo*hi' + hi*lo' + hi*hi' with v_mfma_f32_16x16x16_bf16 in FP32.
 //
 // Operands are read with buffer loads: the descriptor of each segment spans
 // its operand and an offset outside it returns zero, so ragged tile edges need
@@ -274,7 +273,27 @@ template <int N> __device__ __forceinline__ void wait_vm() {
     asm volatile("s_waitcnt vmcnt(%0)" :: "n"(N) : "memory");
 }
 
-template <typename T, typename TC, int BM, int BN, int WGM, int NS>
+// SPLIT (BF16x3): every 4-byte operand word holds a value as two bf16, the
+// high part in its low half and the low part in its high half (x = hi + lo);
+// the staging is the FP32 kernel's, and each K step of 16 issues three
+// v_mfma_f32_16x16x16_bf16 (lo * hi', hi * lo', hi * hi', small terms first)
+// in place of four v_mfma_f32_16x16x4_f32.
+typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
+typedef short s4v __attribute__((ext_vector_type(4)));
+typedef unsigned u2v __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ s4v split_hi(float w0, float w1, float w2, float w3) {
+    const unsigned a = __builtin_bit_cast(unsigned, w0), b = __builtin_bit_cast(unsigned, w1);
+    const unsigned c = __builtin_bit_cast(unsigned, w2), d = __builtin_bit_cast(unsigned, w3);
+    return __builtin_bit_cast(s4v, u2v{(a & 0xffffu) | (b << 16), (c & 0xffffu) | (d << 16)});
+}
+__device__ __forceinline__ s4v split_lo(float w0, float w1, float w2, float w3) {
+    const unsigned a = __builtin_bit_cast(unsigned, w0), b = __builtin_bit_cast(unsigned, w1);
+    const unsigned c = __builtin_bit_cast(unsigned, w2), d = __builtin_bit_cast(unsigned, w3);
+    return __builtin_bit_cast(s4v, u2v{(a >> 16) | (b & 0xffff0000u), (c >> 16) | (d & 0xffff0000u)});
+}
+
+template <typename T, typename TC, int BM, int BN, int WGM, int NS, bool SPLIT = false>
 __global__ __launch_bounds__(NT) void gemm_dma(Slots slots, const FlatTile *__restrict__ tiles,
                                                const int64_t *__restrict__ rowoff, int ntiles) {
     constexpr int BK = 16;
@@ -397,16 +416,41 @@ __global__ __launch_bounds__(NT) void gemm_dma(Slots slots, const FlatTile *__re
         for (int j = 0; j < WBN; ++j)
 #pragma unroll
             for (int q = 0; q < 4; ++q) b[j][q] = *reinterpret_cast<const T *>(st + boff[j][q]);
+        if constexpr (SPLIT) {
+            // a lane's four words are k = 4 g .. 4 g + 3 of its row (column):
+            // exactly the four bf16 of one v_mfma_f32_16x16x16_bf16 operand
+            s4v ah[WBM], al[WBM], bh[WBN], bl[WBN];
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
+            for (int i = 0; i < WBM; ++i) {
+                ah[i] = split_hi(a[i][0], a[i][1], a[i][2], a[i][3]);
+                al[i] = split_lo(a[i][0], a[i][1], a[i][2], a[i][3]);
+            }
+#pragma unroll
+            for (int j = 0; j < WBN; ++j) {
+                bh[j] = split_hi(b[j][0], b[j][1], b[j][2], b[j][3]);
+                bl[j] = split_lo(b[j][0], b[j][1], b[j][2], b[j][3]);
+            }
 #pragma unroll
             for (int i = 0; i < WBM; ++i)
 #pragma unroll
-                for (int j = 0; j < WBN; ++j) acc[i][j] = mfma16(a[i][q], b[j][q], acc[i][j]);
+                for (int j = 0; j < WBN; ++j) {
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al[i], bh[j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[i], bl[j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[i], bh[j], acc[i][j], 0, 0, 0);
+                }
+        } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int i = 0; i < WBM; ++i)
+#pragma unroll
+                    for (int j = 0; j < WBN; ++j) acc[i][j] = mfma16(a[i][q], b[j][q], acc[i][j]);
+        }
     }
 
     // result rows held by (lane, register r): v_mfma_f64_16x16x4 returns row
-    // 4 r + lane/16, v_mfma_f32_16x16x4 row 4 (lane/16) + r; column lane % 16
+    // 4 r + lane/16, v_mfma_f32_16x16x4 and v_mfma_f32_16x16x16_bf16 row
+    // 4 (lane/16) + r; column lane % 16
     TC *C = static_cast<TC *>(const_cast<void *>(slots.p[ft.c_slot])) + ft.c_off;
 #pragma unroll
     for (int i = 0; i < WBM; ++i)
@@ -424,187 +468,6 @@ __global__ __launch_bounds__(NT) void gemm_dma(Slots slots, const FlatTile *__re
         }
 }
 
-// ---------------------------------------------------------------- BF16 x3
-// Same tiles, buffer loads, double-buffered LDS and single barrier per K-step
-// as the FP32 kernel; each thread stages pairs of consecutive k of one row
-// (column) of A (B), splits them in registers into bf16 hi and lo halves
-// (x = hi + lo, both rounded to nearest even by the hardware's packed
-// convert) and stores each half with one 4-byte LDS write.  The K-contiguous
-// LDS rows feed v_mfma_f32_16x16x16_bf16 with 8-byte reads; per 16 x 16 block
-// and K-step the products lo*hi', hi*lo', hi*hi' accumulate in FP32, the
-// small terms first.  K steps of 16 keep the LDS at 2 x (BM + BN) x 80 bytes,
-// so several workgroups share a CU and hide each other's load latency (the
-// short K loops of these contractions are latency-bound, not MFMA-bound).
-typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
-typedef short s4v __attribute__((ext_vector_type(4)));
-
-template <typename TC, bool TA, bool TB, int BM, int BN, int WGM>
-__global__ __launch_bounds__(NT) void gemm_bf16x3(Slots slots, const GemmItem *__restrict__ items,
-                                                  const GemmSeg *__restrict__ segs,
-                                                  const GemmTile *__restrict__ tiles,
-                                                  const int64_t *__restrict__ rowoff, int ntiles) {
-    constexpr int WGN = 4 / WGM;
-    constexpr int BK = 16, LDK = BK + 4;          // 40-byte LDS rows: 8-byte aligned reads
-    constexpr int KG = BK / 2;                    // k pairs per row
-    constexpr int NGA = BM * KG / NT, NGB = BN * KG / NT;   // groups per thread and step
-    constexpr int SM = BM / WGM, SN = BN / WGN;
-    constexpr int WBM = SM / 16, WBN = SN / 16;
-    static_assert(NGA >= 1 && NGB >= 1 && WBM >= 1 && WBN >= 1, "tile shape");
-    static_assert((BM * KG) % NT == 0 && (BN * KG) % NT == 0, "tile shape");
-    // the host has placed the tiles in launch order (idle tiles: item < 0)
-    if ((int)blockIdx.x >= ntiles) return;
-    const GemmTile tile = tiles[blockIdx.x];
-    if (tile.item < 0) return;
-    const GemmItem it = items[tile.item];
-    __shared__ __attribute__((aligned(16))) unsigned short Ah[2][BM][LDK], Al[2][BM][LDK];
-    __shared__ __attribute__((aligned(16))) unsigned short Bh[2][BN][LDK], Bl[2][BN][LDK];
-    const int tid = threadIdx.x, lane = tid & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int wm = (wave / WGN) * SM, wn = (wave % WGN) * SN;
-    const int m0 = tile.m0, n0 = tile.n0;
-    f4 acc[WBM][WBN];
-#pragma unroll
-    for (int i = 0; i < WBM; ++i)
-#pragma unroll
-        for (int j = 0; j < WBN; ++j) acc[i][j] = f4{0, 0, 0, 0};
-
-    // group g of this thread: row (column) index and first k.  K-contiguous
-    // operands: 8 consecutive threads cover the 16 k of one row; otherwise
-    // consecutive threads take consecutive rows (coalesced per k).
-    auto a_grp = [&](int g, int &m, int &k) {
-        if (TA) { m = tid % BM; k = 2 * (tid / BM + g * (NT / BM)); }
-        else    { k = 2 * (tid % KG); m = tid / KG + g * (NT / KG); }
-    };
-    auto b_grp = [&](int g, int &n, int &k) {
-        if (TB) { k = 2 * (tid % KG); n = tid / KG + g * (NT / KG); }
-        else    { n = tid % BN; k = 2 * (tid / BN + g * (NT / BN)); }
-    };
-    float ra[NGA][2], rb[NGB][2];
-    int K = 0, lda = 0, ldb = 0;
-    __amdgpu_buffer_rsrc_t rA, rB;
-    auto set_seg = [&](const GemmSeg &sg) {
-        K = __builtin_amdgcn_readfirstlane(sg.K);
-        lda = __builtin_amdgcn_readfirstlane(sg.lda);
-        ldb = __builtin_amdgcn_readfirstlane(sg.ldb);
-        rA = operand_rsrc(static_cast<const float *>(slots.p[sg.a_slot]) + sg.a_off);
-        rB = operand_rsrc(static_cast<const float *>(slots.p[sg.b_slot]) + sg.b_off);
-    };
-    auto load = [&](int k0) {
-#pragma unroll
-        for (int g = 0; g < NGA; ++g) {
-            int m, k;
-            a_grp(g, m, k);
-            const int gm = m0 + m;
-#pragma unroll
-            for (int u = 0; u < 2; ++u) {
-                const int gk = k0 + k + u;
-                const unsigned off = TA ? (unsigned)(gk * lda + gm) : (unsigned)(gm * lda + gk);
-                ra[g][u] = buf_load(rA, (gm < it.M && gk < K) ? off * 4u : kOutOfRange, float());
-            }
-        }
-#pragma unroll
-        for (int g = 0; g < NGB; ++g) {
-            int n, k;
-            b_grp(g, n, k);
-            const int gn = n0 + n;
-#pragma unroll
-            for (int u = 0; u < 2; ++u) {
-                const int gk = k0 + k + u;
-                const unsigned off = TB ? (unsigned)(gn * ldb + gk) : (unsigned)(gk * ldb + gn);
-                rb[g][u] = buf_load(rB, (gn < it.N && gk < K) ? off * 4u : kOutOfRange, float());
-            }
-        }
-    };
-    // split 2 floats into packed hi and lo halves (one 32-bit word each)
-    auto split2 = [](const float (&x)[2], unsigned &hi, unsigned &lo) {
-        const f2v x0 = {x[0], x[1]};
-        const bf2 h = __builtin_convertvector(x0, bf2);
-        const bf2 l = __builtin_convertvector(x0 - __builtin_convertvector(h, f2v), bf2);
-        hi = __builtin_bit_cast(unsigned, h);
-        lo = __builtin_bit_cast(unsigned, l);
-    };
-    auto store = [&](int buf) {
-#pragma unroll
-        for (int g = 0; g < NGA; ++g) {
-            int m, k;
-            a_grp(g, m, k);
-            unsigned hi, lo;
-            split2(ra[g], hi, lo);
-            *reinterpret_cast<unsigned *>(&Ah[buf][m][k]) = hi;
-            *reinterpret_cast<unsigned *>(&Al[buf][m][k]) = lo;
-        }
-#pragma unroll
-        for (int g = 0; g < NGB; ++g) {
-            int n, k;
-            b_grp(g, n, k);
-            unsigned hi, lo;
-            split2(rb[g], hi, lo);
-            *reinterpret_cast<unsigned *>(&Bh[buf][n][k]) = hi;
-            *reinterpret_cast<unsigned *>(&Bl[buf][n][k]) = lo;
-        }
-    };
-
-    int sidx = 0, k0 = 0;
-    while (sidx < it.nseg && segs[it.seg0 + sidx].K <= 0) ++sidx;
-    int buf = 0;
-    if (sidx < it.nseg) {
-        set_seg(segs[it.seg0 + sidx]);
-        load(0);
-        store(0);
-    }
-    __syncthreads();
-    const int r16 = lane & 15, kq = (lane >> 4) * 4;
-    while (sidx < it.nseg) {
-        k0 += BK;
-        if (k0 >= K) {
-            k0 = 0;
-            ++sidx;
-            while (sidx < it.nseg && segs[it.seg0 + sidx].K <= 0) ++sidx;
-            if (sidx < it.nseg) set_seg(segs[it.seg0 + sidx]);
-        }
-        const bool more = sidx < it.nseg;
-        if (more) load(k0);
-        s4v ah[WBM], al[WBM], bh[WBN], bl[WBN];
-#pragma unroll
-        for (int i = 0; i < WBM; ++i) {
-            ah[i] = *reinterpret_cast<const s4v *>(&Ah[buf][wm + i * 16 + r16][kq]);
-            al[i] = *reinterpret_cast<const s4v *>(&Al[buf][wm + i * 16 + r16][kq]);
-        }
-#pragma unroll
-        for (int j = 0; j < WBN; ++j) {
-            bh[j] = *reinterpret_cast<const s4v *>(&Bh[buf][wn + j * 16 + r16][kq]);
-            bl[j] = *reinterpret_cast<const s4v *>(&Bl[buf][wn + j * 16 + r16][kq]);
-        }
-#pragma unroll
-        for (int i = 0; i < WBM; ++i)
-#pragma unroll
-            for (int j = 0; j < WBN; ++j) {
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al[i], bh[j], acc[i][j], 0, 0, 0);
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[i], bl[j], acc[i][j], 0, 0, 0);
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[i], bh[j], acc[i][j], 0, 0, 0);
-            }
-        if (more) store(buf ^ 1);
-        __syncthreads();
-        buf ^= 1;
-    }
-    // v_mfma_f32_16x16x16_bf16 result: register r of lane l is row 4 (l / 16) + r, column l % 16
-    TC *C = static_cast<TC *>(const_cast<void *>(slots.p[it.c_slot])) + it.c_off;
-#pragma unroll
-    for (int i = 0; i < WBM; ++i)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int gm = m0 + wm + i * 16 + (lane >> 4) * 4 + r;
-            if (gm >= it.M) continue;
-            TC *Cr = C + c_row(it, rowoff, gm);
-#pragma unroll
-            for (int j = 0; j < WBN; ++j) {
-                const int gn = n0 + wn + j * 16 + r16;
-                if (gn < it.N) Cr[gn] = (TC)acc[i][j][r];
-            }
-        }
-}
-
-// ---------------------------------------------------------------- launcher
 struct GemmArgs {
     Slots sl;
     const GemmItem *it;
@@ -630,17 +493,17 @@ static void dispatch_shape(bool ta, bool tb, dim3 g, hipStream_t s, const GemmAr
 // keep 8 FP32 workgroups of 64 x 64 resident per CU, which measured faster on
 // the H_eff GEMMs than three or four stages at lower occupancy.
 constexpr int kDmaStages = 2;
-template <typename T, typename TC, int BM, int BN, int WGM>
+template <typename T, typename TC, int BM, int BN, int WGM, bool SPLIT>
 static void dispatch_dma(dim3 g, hipStream_t s, const Slots &sl, const FlatTile *t, const int64_t *ro, int n) {
-    hipLaunchKernelGGL((gemm_dma<T, TC, BM, BN, WGM, kDmaStages>), g, dim3(NT), 0, s, sl, t, ro, n);
+    hipLaunchKernelGGL((gemm_dma<T, TC, BM, BN, WGM, kDmaStages, SPLIT>), g, dim3(NT), 0, s, sl, t, ro, n);
 }
-template <typename T, typename TC>
+template <typename T, typename TC, bool SPLIT = false>
 static void dispatch_dma_shape(TileShape shape, dim3 g, hipStream_t s, const Slots &sl, const FlatTile *t,
                                const int64_t *ro, int n) {
     switch (shape) {
-        case TileShape::T128x32_D: dispatch_dma<T, TC, 128, 32, 4>(g, s, sl, t, ro, n); break;
-        case TileShape::T64x64_D: dispatch_dma<T, TC, 64, 64, 2>(g, s, sl, t, ro, n); break;
-        case TileShape::T32x128_D: dispatch_dma<T, TC, 32, 128, 1>(g, s, sl, t, ro, n); break;
+        case TileShape::T128x32_D: dispatch_dma<T, TC, 128, 32, 4, SPLIT>(g, s, sl, t, ro, n); break;
+        case TileShape::T64x64_D: dispatch_dma<T, TC, 64, 64, 2, SPLIT>(g, s, sl, t, ro, n); break;
+        case TileShape::T32x128_D: dispatch_dma<T, TC, 32, 128, 1, SPLIT>(g, s, sl, t, ro, n); break;
         default: break;
     }
 }
@@ -669,32 +532,14 @@ static void dispatch_kmajor(TileShape shape, bool ta, bool tb, dim3 g, hipStream
     }
 }
 
-template <typename TC, int BM, int BN, int WGM>
-static void dispatch_bf16_shape(bool ta, bool tb, dim3 g, hipStream_t s, const GemmArgs &a) {
-    if (!ta && !tb) hipLaunchKernelGGL((gemm_bf16x3<TC, false, false, BM, BN, WGM>), g, dim3(NT), 0, s, a.sl, a.it, a.sg, a.tl, a.ro, a.n);
-    else if (ta && !tb) hipLaunchKernelGGL((gemm_bf16x3<TC, true, false, BM, BN, WGM>), g, dim3(NT), 0, s, a.sl, a.it, a.sg, a.tl, a.ro, a.n);
-    else if (!ta && tb) hipLaunchKernelGGL((gemm_bf16x3<TC, false, true, BM, BN, WGM>), g, dim3(NT), 0, s, a.sl, a.it, a.sg, a.tl, a.ro, a.n);
-    else hipLaunchKernelGGL((gemm_bf16x3<TC, true, true, BM, BN, WGM>), g, dim3(NT), 0, s, a.sl, a.it, a.sg, a.tl, a.ro, a.n);
-}
-
-// BF16x3 runs the four base tile shapes; the half / quarter-depth variants
-// map to their base shape (its K step is fixed at 16).
-template <typename TC>
-static void dispatch_bf16(TileShape shape, bool ta, bool tb, dim3 g, hipStream_t s, const GemmArgs &a) {
-    switch (shape) {
-        case TileShape::T128x32: case TileShape::T128x32_K16: case TileShape::T128x32_K8:
-            dispatch_bf16_shape<TC, 128, 32, 4>(ta, tb, g, s, a); break;
-        case TileShape::T32x128: dispatch_bf16_shape<TC, 32, 128, 1>(ta, tb, g, s, a); break;
-        case TileShape::T128x128: dispatch_bf16_shape<TC, 128, 128, 2>(ta, tb, g, s, a); break;
-        default: dispatch_bf16_shape<TC, 64, 64, 2>(ta, tb, g, s, a); break;
-    }
-}
-
 void launch_gemm_flat(GemmPrec prec, TileShape shape, bool c_is_f64, const Slots &slots, const FlatTile *tiles,
                       const int64_t *rowoff, int ntiles, hipStream_t s) {
     if (ntiles <= 0) return;
     const dim3 g(ntiles);
     if (prec == GemmPrec::F64) dispatch_dma_shape<double, double>(shape, g, s, slots, tiles, rowoff, ntiles);
+    else if (prec == GemmPrec::BF16X3 && c_is_f64)
+        dispatch_dma_shape<float, double, true>(shape, g, s, slots, tiles, rowoff, ntiles);
+    else if (prec == GemmPrec::BF16X3) dispatch_dma_shape<float, float, true>(shape, g, s, slots, tiles, rowoff, ntiles);
     else if (c_is_f64) dispatch_dma_shape<float, double>(shape, g, s, slots, tiles, rowoff, ntiles);
     else dispatch_dma_shape<float, float>(shape, g, s, slots, tiles, rowoff, ntiles);
 }
@@ -713,9 +558,7 @@ void launch_gemm(GemmPrec prec, TileShape shape, bool ta, bool tb, bool c_is_f64
             if (c_is_f64) dispatch_kmajor<float, double>(shape, ta, tb, grid, s, a);
             else dispatch_kmajor<float, float>(shape, ta, tb, grid, s, a);
             break;
-        case GemmPrec::BF16X3:
-            if (c_is_f64) dispatch_bf16<double>(shape, ta, tb, grid, s, a);
-            else dispatch_bf16<float>(shape, ta, tb, grid, s, a);
+        case GemmPrec::BF16X3:   // split operands: LDS-DMA lists only (launch_gemm_flat)
             break;
     }
 }

@@ -170,6 +170,9 @@ void heff_build(pdmrg_ctx *ctx, pdmrg_heff *op, const Bond &bl, const Bond &br, 
         if (prec == PDMRG_F64) {
             if (op->nL) HIP_OK(hipMemcpyAsync(op->L.ptr, L, op->nL * es, hipMemcpyDeviceToDevice, s));
             if (op->nR) HIP_OK(hipMemcpyAsync(op->R.ptr, R, op->nR * es, hipMemcpyDeviceToDevice, s));
+        } else if (prec == PDMRG_BF16X3) {   // split once per operator
+            launch_convert_f64_split(L, op->L.as<uint32_t>(), op->nL, s);
+            launch_convert_f64_split(R, op->R.as<uint32_t>(), op->nR, s);
         } else {
             launch_convert_f64_f32(L, op->L.as<float>(), op->nL, s);
             launch_convert_f64_f32(R, op->R.as<float>(), op->nR, s);
@@ -271,7 +274,8 @@ static void heff_launch(pdmrg_heff *op, const double *x, double *y, hipStream_t 
     if (f64) {
         sl.p[0] = x;
     } else {
-        launch_convert_f64_f32(x, op->xs.as<float>(), op->nX, s);
+        if (op->prec == PDMRG_BF16X3) launch_convert_f64_split(x, op->xs.as<uint32_t>(), op->nX, s);
+        else launch_convert_f64_f32(x, op->xs.as<float>(), op->nX, s);
         sl.p[0] = op->xs.ptr;
     }
     sl.p[1] = y;
@@ -282,7 +286,8 @@ static void heff_launch(pdmrg_heff *op, const double *x, double *y, hipStream_t 
     sl.p[6] = op->pp;
     pl.g1.launch(gp, f64, sl, s);
     if (ev) HIP_OK(hipEventRecord(ev[1], s));
-    pl.w.launch(f64, sl, s);
+    if (op->prec == PDMRG_BF16X3) pl.w.launch_split(sl, s);   // T2 is stage 3's split A operand
+    else pl.w.launch(f64, sl, s);
     if (ev) HIP_OK(hipEventRecord(ev[2], s));
     pl.g3.launch(gp, f64, sl, s);
     if (ev) HIP_OK(hipEventRecord(ev[3], s));

@@ -151,6 +151,10 @@ void launch_gemm_flat(GemmPrec prec, TileShape shape, bool c_is_f64, const Slots
 void launch_lincomb(bool f64, int chunk, const Slots &slots, const LcTask *tasks, const LcSrc *srcs,
                     const LcTile *tiles, int ntiles, hipStream_t s);
 // Same with FP32 sources summed in FP32 and an FP64 destination.
+// FP32 sums stored split for BF16x3 (each word a bf16 pair hi + lo, hi in the
+// low half)
+void launch_lincomb_split(int chunk, const Slots &slots, const LcTask *tasks, const LcSrc *srcs,
+                          const LcTile *tiles, int ntiles, hipStream_t s);
 void launch_lincomb_f32_f64(int chunk, const Slots &slots, const LcTask *tasks, const LcSrc *srcs,
                             const LcTile *tiles, int ntiles, hipStream_t s);
 // groups[g]..groups[g+1]: the terms of output block g (all share out_off, rows,
@@ -165,6 +169,8 @@ void launch_dot_partials(const Slots &slots, int a_slot, int b_slot, const DotTa
 void launch_dot_reduce(const double *partial, const int32_t *t0, const int32_t *g_of, int ngroups, double *out,
                        hipStream_t s);
 void launch_convert_f64_f32(const double *x, float *y, int64_t n, hipStream_t s);
+// y[i] = FP32 rounding of x[i] split into a bf16 pair (BF16x3 operands)
+void launch_convert_f64_split(const double *x, uint32_t *y, int64_t n, hipStream_t s);
 void launch_convert_f32_f64(const float *x, double *y, int64_t n, hipStream_t s);
 void launch_fill(double *x, double v, int64_t n, hipStream_t s);
 // Row scaling of row-major blocks: block k (base[k], rows[k] x cols[k]) gets

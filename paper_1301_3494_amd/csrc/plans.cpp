@@ -189,7 +189,8 @@ void GemmList::finish(hipStream_t s) {
 }
 
 void GemmList::build_tiles() {
-    if (!(shapes_allowed & (1u << (int)shape))) shape = TileShape::T64x64;
+    if (!(shapes_allowed & (1u << (int)shape)))
+        shape = (shapes_allowed & (1u << (int)TileShape::T64x64)) ? TileShape::T64x64 : TileShape::T64x64_D;
     const int bm = tile_bm(shape), bn = tile_bn(shape);
     std::vector<int64_t> kof(items.size());
     ntiles_real = 0;
@@ -383,7 +384,9 @@ void GemmList::launch(GemmPrec prec, bool c_is_f64, const Slots &sl, hipStream_t
 }
 
 void GemmList::launch(GemmPrec prec, bool c_is_f64, const Slots &sl, const GemmDev &dv, hipStream_t s) const {
-    if ((prec == GemmPrec::F32 || prec == GemmPrec::F64) && !ftiles.empty()) {
+    PD_REQUIRE(prec != GemmPrec::BF16X3 || !ftiles.empty() || tiles.empty(), PDMRG_EINVAL,
+               "gemm: BF16x3 needs an LDS-DMA plan (split operands)");
+    if (!ftiles.empty()) {
         launch_gemm_flat(prec, shape, c_is_f64, sl, dv.ftiles, dv.rowoff, (int)ftiles.size(), s);
         return;
     }
@@ -436,6 +439,11 @@ void LcList::finish(hipStream_t s) {
 void LcList::launch_f32_to_f64(const Slots &sl, hipStream_t s) const {
     launch_lincomb_f32_f64(chunk, sl, d_tasks.as<LcTask>(), d_srcs.as<LcSrc>(), d_tiles.as<LcTile>(),
                            (int)tiles.size(), s);
+}
+
+void LcList::launch_split(const Slots &sl, hipStream_t s) const {
+    launch_lincomb_split(chunk, sl, d_tasks.as<LcTask>(), d_srcs.as<LcSrc>(), d_tiles.as<LcTile>(), (int)tiles.size(),
+                         s);
 }
 
 void LcList::launch(bool f64, const Slots &sl, hipStream_t s) const {
@@ -627,11 +635,11 @@ void HeffPlan::build(const Bond &bl_, const Bond &br_, const Phys &p_, const Mpo
             diag_groups.push_back((int32_t)diag_terms.size());
         }
 
-    // tile shapes (the BF16x3 kernel runs the four base shapes, K step 32)
-    if (prec == PDMRG_BF16X3)
-        g1.shapes_allowed = g3.shapes_allowed = (1u << (int)TileShape::T64x64) | (1u << (int)TileShape::T128x32) |
-                                                (1u << (int)TileShape::T32x128) | (1u << (int)TileShape::T128x128);
-    if (prec != PDMRG_BF16X3) {   // both lists are non-transposed
+    // tile shapes: both lists are non-transposed with one segment per item,
+    // so the LDS-DMA shapes apply; BF16x3 (split operands) runs only those
+    if (prec == PDMRG_BF16X3) {
+        g1.shapes_allowed = g3.shapes_allowed = kDmaShapes;
+    } else {
         g1.shapes_allowed |= kDmaShapes;
         g3.shapes_allowed |= kDmaShapes;
     }

@@ -96,6 +96,8 @@ struct LcList {
     void launch(bool f64, const Slots &sl, hipStream_t s) const;
     void launch(bool f64, const Slots &sl, const LcDev &dv, hipStream_t s) const;
     void launch_f32_to_f64(const Slots &sl, hipStream_t s) const;
+    // FP32 sums written as split bf16 pairs (BF16x3 operands)
+    void launch_split(const Slots &sl, hipStream_t s) const;
     void validate(const std::vector<int64_t> &slot_elems) const;
 };
 

@@ -56,10 +56,11 @@ def test_autotuned_heff_matches_model_plan(case, prec):
     assert np.linalg.norm(y1 - y0) <= tol * np.linalg.norm(y0)
 
 
-@pytest.mark.parametrize("shape", [0, 1, 2, 3])
+@pytest.mark.parametrize("shape", [8, 9, 10])
 def test_bf16x3_every_tile_shape(case, shape, tmp_path):
-    """Each tile shape of the BF16x3 kernel (64x64, 128x32, 32x128, 128x128),
-    forced through an imported tuning entry, against the FP64 product."""
+    """Each tile shape of the BF16x3 path (the LDS-DMA shapes 128x32, 64x64,
+    32x128 on split operands), forced through an imported tuning entry, against
+    the FP64 product."""
     import torch
     from paper_1301_3494_amd import _lib as pl
     B1, B2, P, W1, W2, L, R, x = case
@@ -76,7 +77,7 @@ def test_bf16x3_every_tile_shape(case, shape, tmp_path):
     pl.autotune_import(str(f))
     op = pl.Heff(ctx, B1, B2, P, W1, W2, L, R, pl.BF16X3)
     info = op.info()
-    names = ["64x64", "128x32", "32x128", "128x128"]
+    names = SHAPES
     say(f"bf16x3 forced shape {names[shape]}: plan {info['shape_Lpsi']} / {info['shape_R']}, parts {info['splitk_parts']}")
     assert info["shape_Lpsi"] == names[shape] and info["shape_R"] == names[shape]
     y = torch.empty_like(x)

@@ -44,8 +44,6 @@ def _force_shape(ctx, make_op, prec, shape, parts, tmp_path):
 @pytest.mark.parametrize("where", ["left", "right", "next_to_left"])
 @pytest.mark.parametrize("shape", [None, 9])
 def test_heff_at_chain_edges(ctx, prec, tol, where, shape, tmp_path):
-    if shape is not None and prec == pl.BF16X3:
-        pytest.skip("the LDS-DMA shapes take FP32 and FP64 operands")
     N, m, seed = 10, 16, 3
     mpo = M.build_mpo(models.heisenberg_terms(models.chain_bonds(N)), N, models.OPS, PQ)
     bonds = synth.binomial_bonds(N, m)
