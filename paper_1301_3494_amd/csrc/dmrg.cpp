@@ -271,11 +271,16 @@ struct Driver {
         // against the state the shared-bond eigensolver converges to
         const int64_t n = two_site_layout(m->bonds[j], m->bonds[j + 2], m->p).size;
         DevBuf pred = take(psi, n);
-        solve(j, psi, prm.dav_shared);   // Davidson normalises its start vector
-        rep.max_infidelity = std::max(rep.max_infidelity, infidelity(pred.as<double>(), psi.as<double>(), n));
+        const double e = solve(j, psi, prm.dav_shared);   // Davidson normalises its start vector
+        const double inf = infidelity(pred.as<double>(), psi.as<double>(), n);
+        rep.max_infidelity = std::max(rep.max_infidelity, inf);
         SvdOut r;
         svd_timed(j, psi, prm.max_m, prm.cutoff, PDMRG_SPLIT, r);
         store(j, r, PDMRG_SPLIT);
+        if (ctx->verbose)
+            std::fprintf(stderr, "pdmrg: merge %d|%d m=%d E=%.12f infidelity %.3e\n", j, j + 1, m->bonds[j + 1].total,
+                         e, inf),
+                std::fflush(stderr);
     }
 
     void init() {

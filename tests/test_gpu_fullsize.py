@@ -147,7 +147,7 @@ def test_large_config_heff_sampled_rows(name):
         ref[k] = (rows, dmrg.heff_apply_rows(L, R, omp.W[c], omp.W[c + 1], psi, bl, br, PQ, omp.deltas[c],
                                              omp.deltas[c + 2], k, rows))
     ctx = pl.Context(0)
-    for prec, tol in ((pl.F64, 1e-12), (pl.F32, 1e-5)):
+    for prec, tol in ((pl.F64, 1e-12), (pl.F32, 1e-5), (pl.BF16X3, 1e-4)):
         op = pl.Heff(ctx, B1, B2, P, mpo_site(omp, c), mpo_site(omp, c + 1), Ld, Rd, prec)
         y = torch.full_like(x, float("nan"))
         op.apply(x, y)

@@ -156,3 +156,44 @@ def test_env_recompute_stride_same_bits_less_memory(ctx, n_regions, concurrent):
     assert out[0][0] == out[3][0]
     assert all(np.array_equal(a, b) for a, b in zip(out[0][1], out[3][1]))
     assert out[3][2] < out[0][2]
+
+
+def test_sweep_schedule_is_fig4(ctx):
+    """The library's region-parallel sweep follows Fig. 4 (reading R5) step by
+    step: with the progress log on and the regions one after the other, a
+    12-site chain in 3 regions optimises bonds 0, 1, 2 (region 1 right),
+    6, 5, 4 (region 2 left), 8, 9, 10 (region 3 right), merges at sites 3|4,
+    then moves every region back and merges at 7|8 -- the order the oracle's
+    schedule pin fixes."""
+    import os
+    import sys
+    import tempfile
+    N, m = 12, 8
+    mpo = pl.Mpo("chain", N, 1, (1.0, 1.0))
+    bonds, sites = synth.random_mps(N, m, 5)
+    mps = pl.Mps(ctx, bonds, sites)
+    mps.sweep(mpo, m, 3)   # canonical form, split, one parallel sweep
+    tmp = tempfile.TemporaryFile(mode="w+b")
+    saved = os.dup(2)
+    pl.set_verbose(ctx, 1)
+    try:
+        sys.stderr.flush()
+        os.dup2(tmp.fileno(), 2)
+        mps.sweep(mpo, m, 3, concurrent=False)
+    finally:
+        os.dup2(saved, 2)
+        os.close(saved)
+        pl.set_verbose(ctx, 0)
+    tmp.seek(0)
+    got = []
+    for line in tmp.read().decode().splitlines():
+        f = line.split()
+        if len(f) > 2 and f[0] == "pdmrg:" and f[1] in ("bond", "merge"):
+            got.append((f[1], int(f[2].split("|")[0])))
+    half_a = [0, 1, 2, 6, 5, 4, 8, 9, 10]
+    half_b = [2, 1, 0, 4, 5, 6, 10, 9, 8]
+    want = [("bond", i) for i in half_a] + [("merge", 3)] + [("bond", i) for i in half_b] + [("merge", 7)]
+    say("schedule", got)
+    assert got == want
+    mps.free()
+    mpo.free()

@@ -457,6 +457,31 @@ def test_one_region_equals_serial_bitwise():
         assert a.keys() == b.keys() and all(np.array_equal(a[k], b[k]) for k in a)
 
 
+def test_parallel_sweep_schedule_is_fig4():
+    """Fig. 4's staggering (reading R5) on a 12-site chain in 3 regions of 4
+    sites: half-sweep A moves region 1 right (bonds 0, 1, 2), region 2 left
+    (6, 5, 4) and region 3 right (8, 9, 10), then merges at the shared bond
+    1|2 (sites 3, 4); half-sweep B moves every region back and merges at 2|3
+    (sites 7, 8).  Schedules that merge other bonds or move the regions the
+    other way still converge, so the order is pinned step by step."""
+    N, m = 12, 8
+    mpo = M.build_mpo(models.heisenberg_terms(models.chain_bonds(N)), N, OPS, PQ)
+    bonds, sites = synth.random_mps(N, m, 5)
+    p = dmrg.SweepParams(schedule=[m], n_regions=3)
+    st = dmrg.State(mpo, [Bond(b) for b in bonds], [dict(s) for s in sites], 0)
+    dmrg.canonicalize_right(st)
+    regions = dmrg.regions_of(N, 3)
+    assert regions == [(0, 3), (4, 7), (8, 11)]
+    dmrg.split_regions(st, regions, m, p)
+    st.log.clear()
+    dmrg.parallel_sweep(st, regions, m, p)
+    got = [(e["kind"], e["site"]) for e in st.log]
+    half_a = [0, 1, 2, 6, 5, 4, 8, 9, 10]
+    half_b = [2, 1, 0, 4, 5, 6, 10, 9, 8]
+    want = [("bond", i) for i in half_a] + [("merge", 3)] + [("bond", i) for i in half_b] + [("merge", 7)]
+    assert got == want
+
+
 def test_region_order_invariance_bitwise():
     """No information crosses regions between merges, so visiting them in a
     different order gives bit-identical results."""
