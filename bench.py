@@ -566,6 +566,47 @@ def c5_run(ctx, pl, synth, torch, m=4000, regions=8, stride=4, sweeps=1):
     return out
 
 
+def c4_run(ctx, pl, synth, torch, m=3000, sweeps=2):
+    """The triangular configuration at its size: 12 x 6 cylinder (XXZ at the
+    SU(2) point, J = Delta = 1, D = 23), m = 3000 on the binomial bonds of a
+    seeded random MPS, serial two-site sweeps (one region) in FP32 with FP64
+    refinement, then dE/dJ and dE/dDelta from grad_couplings at that state:
+    E is linear in J at fixed Delta, so J dE/dJ = E holds at any state, while
+    dE/dDelta = E / 3 (the S^z S^z third of the exchange energy) holds for
+    the SU(2)-symmetric ground state and measures how far the sweeps are from
+    it; peak device memory."""
+    Lx, Ly, J, Delta = 12, 6, 1.0, 1.0
+    N = Lx * Ly
+    mpo = pl.Mpo("triangular", Lx, Ly, (J, Delta))
+    bonds, sites = synth.random_mps(N, m, 7)
+    pl.set_verbose(ctx, 1)   # one line per bond: a pass at this size runs for minutes
+    pl.memory_stats(reset_peak=True)
+    mps = pl.Mps(ctx, bonds, sites)
+    dav = pl.dav_params(4, 8, 1e-8)
+    out = {"workload": "triangular_cyl12x6_m%d_serial" % m, "D_max": int(max(mpo.D)), "sweeps": []}
+    for k in range(sweeps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rep = mps.sweep(mpo, m, 1, prec=pl.F32, dav=dav)
+        torch.cuda.synchronize()
+        row = {"seconds": round(time.perf_counter() - t0, 2), "energy": rep["energy"], "max_bond": rep["max_bond"],
+               "n_matvec": rep["n_matvec"], "seconds_davidson": round(rep["seconds_heff"], 2),
+               "seconds_svd": round(rep["seconds_svd"], 2), "seconds_env": round(rep["seconds_env"], 2)}
+        out["sweeps"].append(row)
+        print("bench: c4 sweep %d %s" % (k + 1, row), file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    E, (gJ, gD) = pl.dE_dcouplings(mps, mpo)
+    out["grad"] = {"seconds": round(time.perf_counter() - t0, 2), "energy": E, "dE_dJ": gJ, "dE_dDelta": gD,
+                   "J_dE_dJ_minus_E_rel": abs(J * gJ - E) / abs(E), "dE_dDelta_over_E": gD / E}
+    in_use, peak, cached = pl.memory_stats()
+    out["peak_device_gb"] = round(peak / 1e9, 2)
+    print("bench: c4 grad %s peak %.1f GB" % (out["grad"], peak / 1e9), file=sys.stderr, flush=True)
+    mps.free()
+    mpo.free()
+    pl.set_verbose(ctx, 0)
+    return out
+
+
 SPIN_OPS = {
     "Sz": [[-0.5, 0.0], [0.0, 0.5]],
     "Sp": [[0.0, 0.0], [1.0, 0.0]],   # |up><down| (local basis: down, up)
@@ -798,6 +839,9 @@ def main():
     ap.add_argument("--no-steps", action="store_true", help="skip the per-step timings")
     ap.add_argument("--only-sweep", action="store_true",
                     help="run only the 8x4 m=1024 sweep-seconds leg (for profiling)")
+    ap.add_argument("--c4", action="store_true",
+                    help="run only the triangular 12x6 m=3000 serial sweeps with dE/dJ and dE/dDelta and the peak "
+                         "device memory (minutes) and print its JSON")
     ap.add_argument("--c5", action="store_true",
                     help="run only the J-Q2 16x8 m=4000 8-region sweep with environment recompute, dE/dJ and dE/dQ "
                          "and the peak device memory (minutes) and print its JSON")
@@ -848,6 +892,10 @@ def main():
         return
     if args.c5:
         print(json.dumps({"jq2_c5": c5_run(ctx, pl, synth, torch)}))
+        ctx.close()
+        return
+    if args.c4:
+        print(json.dumps({"triangular_c4": c4_run(ctx, pl, synth, torch)}))
         ctx.close()
         return
     if args.only_c3:
