@@ -146,6 +146,17 @@ int pdmrg_ctx_set_env_stride(pdmrg_ctx *ctx, int stride);
  * seconds) and every gauge move prints one line on stderr; 0 (the default):
  * silent.  PDMRG_EINVAL for a negative level. */
 int pdmrg_ctx_set_verbose(pdmrg_ctx *ctx, int level);
+/* Preconditioning of the truncation SVD (svd_truncate, and every SVD of
+ * sweep, split, gauge conversion and grad passes on this context; Eq. eqn:svd
+ * and the Appendix): with mode 1 (the default) each middle-charge block of at
+ * least 64 rows (of the smaller dimension) and at most 2048 columns is
+ * factored by Householder QR after ordering its rows by decreasing norm, and
+ * the one-sided Jacobi iteration runs on the triangular factor, which needs
+ * about half the sweeps on the graded blocks of a DMRG state; 2 does this for
+ * every block up to 2048 columns, 0 never.  The factors are those of the same
+ * block to rounding (not the same bits as mode 0); the Appendix recursion
+ * runs on top unchanged.  PDMRG_EINVAL for another mode. */
+int pdmrg_ctx_set_svd_precondition(pdmrg_ctx *ctx, int mode);
 /* Device memory of the library's caching allocator (all contexts of the
  * process, bytes): in_use = handed out and not released, peak = largest
  * in_use since the last reset, cached = released blocks held for reuse.

@@ -76,6 +76,7 @@ EXPORTS = [
     "pdmrg_last_error", "pdmrg_version", "pdmrg_ctx_create", "pdmrg_ctx_destroy", "pdmrg_ctx_set_timing",
     "pdmrg_ctx_timing", "pdmrg_ctx_set_autotune", "pdmrg_set_alloc_poison", "pdmrg_ctx_set_env_stride",
     "pdmrg_ctx_set_verbose",
+    "pdmrg_ctx_set_svd_precondition",
     "pdmrg_memory_stats", "pdmrg_ctx_set_graphs", "pdmrg_autotune_export", "pdmrg_autotune_import", "pdmrg_layout_size", "pdmrg_layout_blocks", "mpo_build", "mpo_from_sites",
     "mpo_info", "mpo_get_site", "mpo_free", "heff_create", "heff_apply", "heff_info", "heff_plan_info", "heff_diag",
     "heff_free", "env_update", "env_update_noalloc", "env_update_info", "davidson_step", "svd_truncate", "svd_result_bond", "svd_result_copy",
@@ -102,6 +103,7 @@ def _declare(L):
         "pdmrg_set_alloc_poison": (c_int, [c_int]),
         "pdmrg_ctx_set_env_stride": (c_int, [P, c_int]),
         "pdmrg_ctx_set_verbose": (c_int, [P, c_int]),
+        "pdmrg_ctx_set_svd_precondition": (c_int, [P, c_int]),
         "pdmrg_memory_stats": (c_int, [pi64, pi64, pi64, c_int]),
         "pdmrg_autotune_import": (c_int, [c_char_p, pi32]),
         "pdmrg_layout_size": (c_int, [c_int, pb, pb, pp, pi32, c_int32, pi64, pi32]),
@@ -640,6 +642,12 @@ def set_env_stride(ctx, stride):
 def set_verbose(ctx, level):
     """Progress lines (one per optimised bond / gauge move) on stderr."""
     check(lib().pdmrg_ctx_set_verbose(ctx.h, int(level)))
+
+
+def set_svd_precondition(ctx, mode):
+    """QR preconditioning of the truncation SVD: 0 off, 1 blocks of >= 64
+    rows (default), 2 every block."""
+    check(lib().pdmrg_ctx_set_svd_precondition(ctx.h, int(mode)))
 
 
 def memory_stats(reset_peak=False):

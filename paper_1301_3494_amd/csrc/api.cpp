@@ -102,6 +102,13 @@ int pdmrg_ctx_set_verbose(pdmrg_ctx *ctx, int level) {
     API_END
 }
 
+int pdmrg_ctx_set_svd_precondition(pdmrg_ctx *ctx, int mode) {
+    API_BEGIN
+    PD_REQUIRE(ctx && mode >= 0 && mode <= 2, PDMRG_EINVAL, "set_svd_precondition: bad arguments");
+    ctx->svd_precond = mode;
+    API_END
+}
+
 int pdmrg_memory_stats(int64_t *in_use, int64_t *peak, int64_t *cached, int reset_peak) {
     API_BEGIN
     pdmrg::alloc_stats(in_use, peak, cached);

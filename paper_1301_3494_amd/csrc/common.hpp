@@ -193,6 +193,10 @@ struct pdmrg_ctx {
     // context (pdmrg_ctx_set_env_stride; <= 1: keep every environment).
     int env_stride = 0;
     int verbose = 0;   // progress lines on stderr
+    // Householder QR preconditioning of the truncation SVD's Jacobi iteration
+    // (pdmrg_ctx_set_svd_precondition): 0 off, 1 blocks of at least 64 rows,
+    // 2 every block (up to rows of 2048).
+    int svd_precond = 1;
     // heff_apply through captured graphs (replayed on `stream`); the capture
     // happens on cap_stream, created on first use.
     bool graphs = false;

@@ -329,6 +329,7 @@ struct Driver {
         ctx->sub[r]->autotune = ctx->autotune;
         ctx->sub[r]->graphs = ctx->graphs;
         ctx->sub[r]->verbose = ctx->verbose;
+        ctx->sub[r]->svd_precond = ctx->svd_precond;
         return ctx->sub[r];
     }
 

@@ -24,6 +24,9 @@ namespace {
 constexpr int kJacBlock = 8;
 constexpr int kMaxSweeps = 60;
 constexpr int kMaxDepth = 8;
+// Smallest matrix (rows of W) that takes the QR preconditioning by default:
+// below it the factorisation's launches cost more than the sweeps it saves.
+constexpr int kQrMinRows = 64;
 // Relative size (to a block's largest singular value) below which singular
 // values are rounding noise of the FP64 block: the Appendix recursion does not
 // descend into a trailing set that lies wholly below it.
@@ -70,6 +73,135 @@ void run_copies(const std::vector<CopyTask> &tasks, hipStream_t s) {
     HIP_OK(hipStreamSynchronize(s));   // d is freed on return
 }
 
+// Householder QR preconditioning of the Jacobi iteration (depth 0).  The rows
+// of a matrix's W (nv x len) are put in order of decreasing norm (P), the
+// len x nv matrix X = (P W)^T is factored X = Q R, and the Jacobi iteration
+// runs on the rows of R: Z R = D with orthogonal rows, so
+// P W = R^T Q^T = D^T (Z Q^T).  R of a graded matrix is graded and its rows
+// are close to orthogonal, so the iteration needs about half the sweeps.
+// The factors: rows of D (length nv, norms = singular values) taken back
+// through P, and Y = Z Q^T = [Z, 0] H_{nv-1} ... H_0 (length len), formed by
+// applying the reflectors to [Z, 0] panel by panel, last panel first.
+struct QrState {
+    std::vector<int> len, inv_off;   // per matrix: row length of W; offset of P^-1 in d_idx
+    std::vector<int32_t> idx;        // P then P^-1 per preconditioned matrix
+    DevBuf d_idx, d_items, d_panels, d_trail, d_back;
+    std::vector<QrItem> qitems;
+    std::vector<QrPanel> panels;
+    std::vector<QrApply> trail, back;
+    std::vector<int> panel_off, trail_off, back_off, panel_span;
+    int max_nv = 0;
+    int64_t max_elems = 0;
+};
+
+void qr_factor(const std::vector<Mat> &mats, std::vector<JacItem> &items, const std::vector<char> &pre,
+               const std::vector<double *> &qa, const std::vector<double *> &qm, const std::vector<double *> &qt,
+               QrState &qs, hipStream_t s) {
+    const int nm = (int)items.size();
+    qs.len.assign(nm, 0);
+    qs.inv_off.assign(nm, -1);
+    // row norms of W, on the host: the order P (decreasing norm, then index)
+    std::vector<RowRef> refs;
+    std::vector<int> first(nm, 0);
+    for (int i = 0; i < nm; ++i) {
+        qs.len[i] = std::max(mats[i].nr, mats[i].nc);
+        first[i] = (int)refs.size();
+        if (!pre[i]) continue;
+        for (int r = 0; r < items[i].nv; ++r) refs.push_back(RowRef{qm[i] + (size_t)r * qs.len[i], qs.len[i], 0});
+    }
+    DevBuf d_refs, d_norm;
+    upload(d_refs, refs, s);
+    d_norm.ensure(std::max<size_t>(refs.size(), 1) * sizeof(double));
+    launch_row_norms(d_refs.as<RowRef>(), (int)refs.size(), d_norm.as<double>(), s);
+    std::vector<double> norms(refs.size());
+    HIP_OK(hipMemcpyAsync(norms.data(), d_norm.ptr, refs.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    std::vector<int> perm_off(nm, -1);
+    for (int i = 0; i < nm; ++i) {
+        if (!pre[i]) continue;
+        const int nv = items[i].nv;
+        std::vector<int> perm(nv);
+        std::iota(perm.begin(), perm.end(), 0);
+        std::stable_sort(perm.begin(), perm.end(),
+                         [&](int a, int b) { return norms[first[i] + a] > norms[first[i] + b]; });
+        perm_off[i] = (int)qs.idx.size();
+        qs.idx.insert(qs.idx.end(), perm.begin(), perm.end());
+        qs.inv_off[i] = (int)qs.idx.size();
+        qs.idx.resize(qs.idx.size() + nv);
+        for (int r = 0; r < nv; ++r) qs.idx[qs.inv_off[i] + perm[r]] = r;
+    }
+    upload(qs.d_idx, qs.idx, s);
+    // A = P W
+    std::vector<CopyTask> cp;
+    int64_t mx = 0;
+    for (int i = 0; i < nm; ++i) {
+        if (!pre[i]) continue;
+        CopyTask t{};
+        t.src = qm[i];
+        t.dst = qa[i];
+        t.rows = items[i].nv;
+        t.cols = t.sld = t.dld = qs.len[i];
+        t.ridx = qs.d_idx.as<int32_t>() + perm_off[i];
+        cp.push_back(t);
+        mx = std::max<int64_t>(mx, (int64_t)items[i].nv * qs.len[i]);
+    }
+    DevBuf d_cp;
+    upload(d_cp, cp, s);
+    launch_copies(d_cp.as<CopyTask>(), (int)cp.size(), mx, s);
+    // panel task lists: factor, trailing update (Q^T), and later Y (from the right)
+    int npan = 0;
+    for (int i = 0; i < nm; ++i)
+        if (pre[i]) {
+            npan = std::max(npan, (items[i].nv + kQrPanel - 1) / kQrPanel);
+            qs.max_nv = std::max(qs.max_nv, items[i].nv);
+            qs.max_elems = std::max<int64_t>(qs.max_elems, (int64_t)items[i].nv * qs.len[i]);
+            qs.qitems.push_back(QrItem{qa[i], items[i].Z, items[i].W, qm[i], items[i].nv, qs.len[i]});
+        }
+    for (int pn = 0; pn < npan; ++pn) {
+        const int j0 = pn * kQrPanel;
+        qs.panel_off.push_back((int)qs.panels.size());
+        qs.trail_off.push_back((int)qs.trail.size());
+        qs.back_off.push_back((int)qs.back.size());
+        int span = 0;
+        for (int i = 0; i < nm; ++i) {
+            const int nv = items[i].nv, len = qs.len[i];
+            if (!pre[i] || nv <= j0) continue;
+            const int nb = std::min(kQrPanel, nv - j0);
+            double *T = qt[i] + (size_t)pn * kQrPanel * kQrPanel;
+            qs.panels.push_back(QrPanel{qa[i], T, nv, len, j0, 0});
+            span = std::max(span, len - j0);
+            for (int g0 = j0 + nb; g0 < nv; g0 += kQrPanel)
+                qs.trail.push_back(QrApply{qa[i] + (size_t)j0 * len, T, qa[i] + (size_t)g0 * len, nb,
+                                           std::min(kQrPanel, nv - g0), len, j0, 1, 0});
+            for (int g0 = 0; g0 < nv; g0 += kQrPanel)
+                qs.back.push_back(QrApply{qa[i] + (size_t)j0 * len, T, qm[i] + (size_t)g0 * len, nb,
+                                          std::min(kQrPanel, nv - g0), len, j0, 0, 0});
+        }
+        qs.panel_span.push_back(span);
+    }
+    qs.panel_off.push_back((int)qs.panels.size());
+    qs.trail_off.push_back((int)qs.trail.size());
+    qs.back_off.push_back((int)qs.back.size());
+    upload(qs.d_items, qs.qitems, s);
+    upload(qs.d_panels, qs.panels, s);
+    upload(qs.d_trail, qs.trail, s);
+    upload(qs.d_back, qs.back, s);
+    for (int pn = 0; pn < npan; ++pn) {
+        launch_qr_panels(qs.d_panels.as<QrPanel>() + qs.panel_off[pn], qs.panel_off[pn + 1] - qs.panel_off[pn],
+                         qs.panel_span[pn], s);
+        launch_qr_apply(qs.d_trail.as<QrApply>() + qs.trail_off[pn], qs.trail_off[pn + 1] - qs.trail_off[pn], s);
+    }
+    // the Jacobi iteration's rows: R
+    launch_qr_extract_r(qs.d_items.as<QrItem>(), (int)qs.qitems.size(), qs.max_nv, s);
+    HIP_OK(hipStreamSynchronize(s));   // d_refs, d_norm, d_cp are freed on return
+}
+
+void qr_right_factor(QrState &qs, hipStream_t s) {
+    launch_qr_embed_z(qs.d_items.as<QrItem>(), (int)qs.qitems.size(), qs.max_elems, s);
+    for (int pn = (int)qs.panel_span.size() - 1; pn >= 0; --pn)
+        launch_qr_apply(qs.d_back.as<QrApply>() + qs.back_off[pn], qs.back_off[pn + 1] - qs.back_off[pn], s);
+}
+
 // One-sided block Jacobi on every matrix; returns sorted factors in `arena`.
 // floor (one per matrix, used from depth 1 on): values below it are rounding
 // noise of the block at depth 0, where the recursion stops.  n_unconv is
@@ -81,15 +213,28 @@ void svd_batch(pdmrg_ctx *ctx, const std::vector<Mat> &mats, std::vector<SvdRes>
     const int nm = (int)mats.size();
     out.assign(nm, SvdRes());
     if (nm == 0) return;
+    // QR preconditioning (depth 0): which matrices take it
+    std::vector<char> pre(nm, 0);
+    bool any_pre = false;
+    for (int i = 0; i < nm; ++i) {
+        const int nv = std::min(mats[i].nr, mats[i].nc), len = std::max(mats[i].nr, mats[i].nc);
+        pre[i] = depth == 0 && ctx->svd_precond > 0 && nv >= (ctx->svd_precond >= 2 ? 2 : kQrMinRows) &&
+                 len <= kQrMaxLen;
+        any_pre = any_pre || pre[i];
+    }
     Arena ar;
     size_t need = 64;
-    for (const Mat &m : mats) {
+    for (int i = 0; i < nm; ++i) {
+        const Mat &m = mats[i];
         const size_t nv = std::min(m.nr, m.nc), len = std::max(m.nr, m.nc);
         need += round32(nv * len) + round32(nv * nv) + round32(nv * m.nr) + round32(nv * m.nc) + round32(nv) + 96;
+        if (pre[i]) need += round32(nv * len) + round32(nv * nv) + round32((nv + kQrPanel - 1) / kQrPanel * 256) + 96;
     }
     ar.reserve(need);
     std::vector<JacItem> items(nm);
     std::vector<CopyTask> cp;
+    // per preconditioned matrix: A (QR storage), the copy of M (later Y), R, T
+    std::vector<double *> qa(nm, nullptr), qm(nm, nullptr), qt(nm, nullptr);
     for (int i = 0; i < nm; ++i) {
         const Mat &m = mats[i];
         const bool wide = m.nr <= m.nc;
@@ -97,11 +242,19 @@ void svd_batch(pdmrg_ctx *ctx, const std::vector<Mat> &mats, std::vector<SvdRes>
         // the Jacobi kernel addresses W and Z with 32-bit byte offsets
         PD_REQUIRE((int64_t)nv * len * 8 < (int64_t(1) << 31), PDMRG_EINVAL, "svd: block too large");
         items[i].nv = nv;
-        items[i].len = len;
+        items[i].len = pre[i] ? nv : len;
         // each matrix on its own tolerance, so a matrix's rotations do not
         // depend on which others share its launches
-        items[i].tol = std::max(1e-14, 8.0 * 2.220446049250313e-16 * std::sqrt((double)len));
-        items[i].W = ar.take((size_t)nv * len);
+        items[i].tol = std::max(1e-14, 8.0 * 2.220446049250313e-16 * std::sqrt((double)items[i].len));
+        double *wm = ar.take((size_t)nv * len);
+        if (pre[i]) {
+            qm[i] = wm;
+            qa[i] = ar.take((size_t)nv * len);
+            qt[i] = ar.take((size_t)(nv + kQrPanel - 1) / kQrPanel * 256);
+            items[i].W = ar.take((size_t)nv * nv);   // rows of R
+        } else {
+            items[i].W = wm;
+        }
         items[i].Z = ar.take((size_t)nv * nv);
         out[i].nr = m.nr;
         out[i].nc = m.nc;
@@ -110,7 +263,7 @@ void svd_batch(pdmrg_ctx *ctx, const std::vector<Mat> &mats, std::vector<SvdRes>
         out[i].Vt = ar.take((size_t)nv * m.nc);
         CopyTask t{};
         t.src = m.M;
-        t.dst = items[i].W;
+        t.dst = wm;
         t.rows = nv;
         t.cols = len;
         t.sld = m.nc;
@@ -119,6 +272,8 @@ void svd_batch(pdmrg_ctx *ctx, const std::vector<Mat> &mats, std::vector<SvdRes>
         cp.push_back(t);
     }
     run_copies(cp, s);
+    QrState qs;
+    if (any_pre) qr_factor(mats, items, pre, qa, qm, qt, qs, s);
     DevBuf d_items;
     upload(d_items, items, s);
     int max_nv = 0;
@@ -176,6 +331,7 @@ void svd_batch(pdmrg_ctx *ctx, const std::vector<Mat> &mats, std::vector<SvdRes>
     // blocks whose rows were not orthogonal to tol after kMaxSweeps sweeps:
     // still an exact rotation of the block (absolute accuracy), reported
     for (int i = 0; i < nm; ++i) n_unconv += active[i] ? 1 : 0;
+    if (any_pre) qr_right_factor(qs, s);
 
     // singular values = row norms
     std::vector<RowRef> refs;
@@ -198,6 +354,7 @@ void svd_batch(pdmrg_ctx *ctx, const std::vector<Mat> &mats, std::vector<SvdRes>
     std::vector<double> scales;
     std::vector<CopyTask> gt;
     std::vector<std::tuple<const double *, double *, int, int>> rowjobs;   // src, dst, len, scale index
+    std::vector<int> gidx;   // per row job: offset of its column gather map in qs.d_idx, or -1
     for (int i = 0; i < nm; ++i) {
         const int nv = items[i].nv;
         std::vector<int> perm(nv);
@@ -211,7 +368,20 @@ void svd_batch(pdmrg_ctx *ctx, const std::vector<Mat> &mats, std::vector<SvdRes>
             const double *wrow = items[i].W + (size_t)perm[j] * items[i].len;
             const double *zrow = items[i].Z + (size_t)perm[j] * nv;
             const double inv = l > 0.0 ? 1.0 / l : 0.0;
-            if (wide) {
+            if (pre[i]) {
+                // X P = Q R with R = Z^T D: the D row (W side) scattered back
+                // through the row order P, scaled by 1 / lambda, and Y = Z Q^T
+                const int len = std::max(mats[i].nr, mats[i].nc);
+                const double *yrow = qm[i] + (size_t)perm[j] * len;
+                double *dside = wide ? out[i].Ut + (size_t)j * mats[i].nr : out[i].Vt + (size_t)j * mats[i].nc;
+                double *yside = wide ? out[i].Vt + (size_t)j * mats[i].nc : out[i].Ut + (size_t)j * mats[i].nr;
+                rowjobs.emplace_back(wrow, dside, nv, (int)scales.size());
+                scales.push_back(inv);
+                gidx.push_back(qs.inv_off[i]);
+                rowjobs.emplace_back(yrow, yside, len, (int)scales.size());
+                scales.push_back(1.0);
+                gidx.push_back(-1);
+            } else if (wide) {
                 rowjobs.emplace_back(zrow, out[i].Ut + (size_t)j * mats[i].nr, nv, (int)scales.size());
                 scales.push_back(1.0);
                 rowjobs.emplace_back(wrow, out[i].Vt + (size_t)j * mats[i].nc, items[i].len, (int)scales.size());
@@ -222,11 +392,16 @@ void svd_batch(pdmrg_ctx *ctx, const std::vector<Mat> &mats, std::vector<SvdRes>
                 rowjobs.emplace_back(zrow, out[i].Vt + (size_t)j * mats[i].nc, nv, (int)scales.size());
                 scales.push_back(1.0);
             }
+            if (!pre[i]) {
+                gidx.push_back(-1);
+                gidx.push_back(-1);
+            }
         }
     }
     DevBuf d_scales;
     upload(d_scales, scales, s);
-    for (auto &[src, dst, len, si] : rowjobs) {
+    for (size_t r = 0; r < rowjobs.size(); ++r) {
+        auto &[src, dst, len, si] = rowjobs[r];
         CopyTask t{};
         t.src = src;
         t.dst = dst;
@@ -235,6 +410,7 @@ void svd_batch(pdmrg_ctx *ctx, const std::vector<Mat> &mats, std::vector<SvdRes>
         t.sld = len;
         t.dld = len;
         t.rscale = d_scales.as<double>() + si;
+        if (gidx[r] >= 0) t.cidx = qs.d_idx.as<int32_t>() + gidx[r];
         gt.push_back(t);
     }
     run_copies(gt, s);

@@ -27,6 +27,9 @@
 // inner sweeps per meeting save fewer outer rounds than they cost.
 #include "svd.hpp"
 
+#include <algorithm>
+#include <stdexcept>
+
 namespace pdmrg {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
@@ -346,7 +349,8 @@ __global__ __launch_bounds__(256) void copy_kernel(const CopyTask *tasks) {
     const int64_t n = (int64_t)t.rows * t.cols;
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
         const int r = (int)(e / t.cols), c = (int)(e % t.cols);
-        double v = t.trans ? t.src[(int64_t)c * t.sld + r] : t.src[(int64_t)r * t.sld + c];
+        const int rs = t.ridx ? t.ridx[r] : r, cs = t.cidx ? t.cidx[c] : c;
+        double v = t.trans ? t.src[(int64_t)cs * t.sld + rs] : t.src[(int64_t)rs * t.sld + cs];
         if (t.rscale) v *= t.rscale[r];
         if (t.cscale) v *= t.cscale[c];
         t.dst[(int64_t)r * t.dld + c] = v;
@@ -357,6 +361,292 @@ void launch_copies(const CopyTask *tasks, int ntasks, int64_t max_elems, hipStre
     if (ntasks <= 0 || max_elems <= 0) return;
     const int g = (int)std::min<int64_t>(256, (max_elems + 255) / 256);
     hipLaunchKernelGGL(copy_kernel, dim3(g, ntasks), dim3(256), 0, s, tasks);
+}
+
+
+// ---------------------------------------------------------------------------
+// Householder QR preconditioning of the one-sided Jacobi iteration.
+//
+// Panel kernel: one workgroup of QT threads factors the 16 rows of a panel.
+// Thread t holds positions j0 + t + QT u (u < UQ) of all 16 rows in
+// registers; each reflector takes two block reductions (the column norm with
+// the pivot entry, then the dot products of the new reflector with the
+// panel's other rows, which give both the update of the later rows and the
+// new column of T).  Reductions are butterflies within a wave (every lane
+// ends with the same bits) followed by a fixed-order sum over the waves, so
+// every thread holds identical scalars and the result is reproducible.
+constexpr int QT = 512;
+constexpr int QW = QT / 64;
+
+template <int NV>
+__device__ __forceinline__ void qr_block_sum(double (&v)[NV], double (*red)[kQrPanel], int lane, int wave) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i)
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v[i] += __shfl_xor(v[i], o);
+    if (lane == 0)
+#pragma unroll
+        for (int i = 0; i < NV; ++i) red[wave][i] = v[i];
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        double a = red[0][i];
+#pragma unroll
+        for (int w = 1; w < QW; ++w) a += red[w][i];
+        v[i] = a;
+    }
+}
+
+template <int UQ>
+__global__ __launch_bounds__(QT) __attribute__((amdgpu_waves_per_eu(1, 2))) void qr_panel_kernel(const QrPanel *tasks) {
+    const QrPanel tk = tasks[blockIdx.x];
+    const int nb = min(kQrPanel, tk.nv - tk.j0);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    __shared__ double red[2][QW][kQrPanel];   // alternating, so one barrier per reduction suffices
+    __shared__ double Ts[kQrPanel][kQrPanel];
+    if (tid < kQrPanel * kQrPanel) Ts[tid / kQrPanel][tid % kQrPanel] = 0.0;
+    double x[kQrPanel][UQ];
+#pragma unroll
+    for (int r = 0; r < kQrPanel; ++r)
+#pragma unroll
+        for (int u = 0; u < UQ; ++u) {
+            const int q = tk.j0 + tid + QT * u;
+            x[r][u] = (r < nb && q < tk.len) ? tk.A[(int64_t)(tk.j0 + r) * tk.len + q] : 0.0;
+        }
+    int rb = 0;
+    // j runs as a loop; rows are picked and written back by selects, so every
+    // register index is a constant
+    for (int j = 0; j < nb; ++j) {   // nb is uniform over the workgroup
+        const int p = tk.j0 + j;
+        double xj[UQ];
+#pragma unroll
+        for (int u = 0; u < UQ; ++u) {
+            double t = x[0][u];
+#pragma unroll
+            for (int r = 1; r < kQrPanel; ++r) t = r == j ? x[r][u] : t;
+            xj[u] = t;
+        }
+        // sum of squares below the pivot, and the pivot itself (thread j, u = 0)
+        double a2[2] = {0.0, tid == j ? xj[0] : 0.0};
+#pragma unroll
+        for (int u = 0; u < UQ; ++u) {
+            const int q = tk.j0 + tid + QT * u;
+            a2[0] += q > p ? xj[u] * xj[u] : 0.0;
+        }
+        qr_block_sum<2>(a2, red[rb], lane, wave);
+        rb ^= 1;
+        const double sig = a2[0], alpha = a2[1];
+        double tau = 0.0, beta = alpha, inv = 0.0;
+        if (sig > 0.0) {
+            const double nrm = sqrt(fma(alpha, alpha, sig));
+            beta = alpha >= 0.0 ? -nrm : nrm;
+            tau = (beta - alpha) / beta;
+            inv = 1.0 / (alpha - beta);
+        }
+        // reflector v: 0 before p, 1 at p, x * inv after; row j keeps beta at p
+        double v[UQ];
+#pragma unroll
+        for (int u = 0; u < UQ; ++u) {
+            const int q = tk.j0 + tid + QT * u;
+            const double t = xj[u] * inv;
+            v[u] = q > p ? t : (q == p ? 1.0 : 0.0);
+            const double nx = q > p ? t : (q == p ? beta : xj[u]);
+#pragma unroll
+            for (int r = 0; r < kQrPanel; ++r) x[r][u] = r == j ? nx : x[r][u];
+        }
+        // dots of v with every other panel row (later rows: for their update;
+        // earlier rows hold their reflectors at positions >= p: for T)
+        double d[kQrPanel];
+#pragma unroll
+        for (int k = 0; k < kQrPanel; ++k) {
+            double t = 0.0;
+#pragma unroll
+            for (int u = 0; u < UQ; ++u) t = fma(v[u], x[k][u], t);
+            d[k] = (k != j && k < nb) ? t : 0.0;
+        }
+        qr_block_sum<kQrPanel>(d, red[rb], lane, wave);
+        rb ^= 1;
+#pragma unroll
+        for (int k = 0; k < kQrPanel; ++k) {
+            const double f = (k > j && k < nb) ? tau * d[k] : 0.0;
+#pragma unroll
+            for (int u = 0; u < UQ; ++u) x[k][u] = fma(-f, v[u], x[k][u]);
+        }
+        // T[0:j][j] = -tau T[0:j][0:j] (V[:, 0:j]^T v); T[j][j] = tau.  Column j
+        // is read by later steps only after their first reduction's barrier.
+        if (tid < j) {
+            double t = 0.0;
+#pragma unroll
+            for (int l = 0; l < kQrPanel; ++l)
+                if (l >= tid && l < j) t = fma(Ts[tid][l], d[l], t);
+            Ts[tid][j] = -tau * t;
+        }
+        if (tid == j) Ts[j][j] = tau;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kQrPanel; ++r)
+#pragma unroll
+        for (int u = 0; u < UQ; ++u) {
+            const int q = tk.j0 + tid + QT * u;
+            if (r < nb && q < tk.len) tk.A[(int64_t)(tk.j0 + r) * tk.len + q] = x[r][u];
+        }
+    if (tid < kQrPanel * kQrPanel) tk.T[tid] = Ts[tid / kQrPanel][tid % kQrPanel];
+}
+
+void launch_qr_panels(const QrPanel *tasks, int ntasks, int max_span, hipStream_t s) {
+    if (ntasks <= 0) return;
+    if (max_span <= QT)
+        hipLaunchKernelGGL(qr_panel_kernel<1>, dim3(ntasks), dim3(QT), 0, s, tasks);
+    else if (max_span <= 2 * QT)
+        hipLaunchKernelGGL(qr_panel_kernel<2>, dim3(ntasks), dim3(QT), 0, s, tasks);
+    else if (max_span <= 4 * QT)
+        hipLaunchKernelGGL(qr_panel_kernel<4>, dim3(ntasks), dim3(QT), 0, s, tasks);
+    else
+        throw std::invalid_argument("qr panel: rows longer than the panel kernel holds");
+}
+static_assert(4 * QT == kQrMaxLen, "panel kernel reach");
+
+// Apply kernel: one workgroup of 4 waves per (panel, group of 16 target rows).
+// D = V Y^T over positions j0.. (FP64 MFMA, reflector rows masked to their
+// support with the unit entry), C = T^T D or T D, then Y -= C^T V (FP64 MFMA),
+// both through the same 512-position chunks staged in LDS as the Jacobi
+// kernel uses.
+__global__ __launch_bounds__(JT) void qr_apply_kernel(const QrApply *tasks) {
+    const QrApply tk = tasks[blockIdx.x];
+    __shared__ double vrows[J2][CH + 1];
+    __shared__ double yrows[J2][CH + 1];
+    __shared__ double Dp[4][J2][J2 + 1];
+    __shared__ double Cs[J2][J2 + 1];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int r16 = lane & 15, g = lane >> 4;
+    const __amdgpu_buffer_rsrc_t rV = rows_rsrc(tk.V, (int64_t)tk.nb * tk.len);
+    const __amdgpu_buffer_rsrc_t rY = rows_rsrc(tk.Y, (int64_t)tk.ntgt * tk.len);
+    const int span = tk.len - tk.j0;
+    const int nch = (span + CH - 1) / CH;
+    auto stage = [&](int c0) {
+        double a[U], b[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = u * JT + tid, r = e / CH, q = tk.j0 + c0 + e % CH;
+            const bool in = q < tk.len;
+            const unsigned ov = (r < tk.nb && in && q > tk.j0 + r) ? (unsigned)(((int64_t)r * tk.len + q) * 8) : kOut;
+            const unsigned oy = (r < tk.ntgt && in) ? (unsigned)(((int64_t)r * tk.len + q) * 8) : kOut;
+            a[u] = (r < tk.nb && q == tk.j0 + r) ? 1.0 : bload(rV, ov);
+            b[u] = bload(rY, oy);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = u * JT + tid;
+            vrows[e / CH][e % CH] = a[u];
+            yrows[e / CH][e % CH] = b[u];
+        }
+        __syncthreads();
+    };
+    {
+        d4 acc = {0.0, 0.0, 0.0, 0.0};
+        for (int ch = 0; ch < nch; ++ch) {
+            const int c0 = ch * CH;
+            stage(c0);
+            const int w = min(CH, span - c0);
+            for (int kk = wave * 16; kk < w; kk += 64) {
+                double a[4], b[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    a[j] = vrows[r16][kk + 4 * g + j];
+                    b[j] = yrows[r16][kk + 4 * g + j];
+                }
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc = mfma_f64(a[j], b[j], acc);
+            }
+        }
+        // D[i][c] = v_i . y_c; register r of lane l: row 4 r + l / 16, column l % 16
+#pragma unroll
+        for (int r = 0; r < 4; ++r) Dp[wave][4 * r + g][r16] = acc[r];
+    }
+    __syncthreads();
+    {
+        const int ei = tid / J2, ej = tid % J2;
+        double c = 0.0;
+#pragma unroll
+        for (int i = 0; i < J2; ++i) {
+            const double t = tk.trans ? tk.T[i * J2 + ei] : tk.T[ei * J2 + i];
+            const double dij = ((Dp[0][i][ej] + Dp[1][i][ej]) + Dp[2][i][ej]) + Dp[3][i][ej];
+            c = fma(t, dij, c);
+        }
+        Cs[ei][ej] = c;   // coefficient of reflector ei in target row ej
+    }
+    __syncthreads();
+    double qa[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) qa[j] = Cs[4 * j + g][r16];
+    unsigned dbase[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int o = 4 * r + g;
+        dbase[r] = o < tk.ntgt ? (unsigned)((int64_t)o * tk.len) : kOut;
+    }
+    // the last chunk is still staged: go backwards
+    for (int i = 0; i < nch; ++i) {
+        const int ch = nch - 1 - i;
+        const int c0 = ch * CH;
+        if (i > 0) stage(c0);
+        const int w = min(CH, span - c0);
+        for (int n0 = wave * 16; n0 < w; n0 += 64) {
+            const int col = n0 + r16;
+            double b[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) b[j] = vrows[4 * j + g][col];
+            d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc = mfma_f64(qa[j], b[j], acc);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int o = 4 * r + g;
+                const unsigned offr =
+                    (dbase[r] != kOut && col < w) ? (dbase[r] + tk.j0 + c0 + col) * 8u : kOut;
+                bstore(rY, offr, yrows[o][col] - acc[r]);
+            }
+        }
+        __syncthreads();   // before the next chunk overwrites the staged rows
+    }
+}
+
+void launch_qr_apply(const QrApply *tasks, int ntasks, hipStream_t s) {
+    if (ntasks > 0) hipLaunchKernelGGL(qr_apply_kernel, dim3(ntasks), dim3(JT), 0, s, tasks);
+}
+
+// R[i][j] = A[j][i] for j >= i (the factor's upper triangle as rows), else 0.
+__global__ void qr_extract_r_kernel(const QrItem *items) {
+    const QrItem it = items[blockIdx.y];
+    const int64_t n = (int64_t)it.nv * it.nv;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        const int i = (int)(e / it.nv), j = (int)(e % it.nv);
+        it.R[e] = j >= i ? it.A[(int64_t)j * it.len + i] : 0.0;
+    }
+}
+
+void launch_qr_extract_r(const QrItem *items, int nitems, int max_nv, hipStream_t s) {
+    if (nitems <= 0 || max_nv <= 0) return;
+    const int g = std::min(1024, (max_nv * max_nv + 255) / 256);
+    hipLaunchKernelGGL(qr_extract_r_kernel, dim3(g, nitems), dim3(256), 0, s, items);
+}
+
+// Y[r][c] = Z[r][c] for c < nv, 0 after (Y: nv x len).
+__global__ void qr_embed_z_kernel(const QrItem *items) {
+    const QrItem it = items[blockIdx.y];
+    const int64_t n = (int64_t)it.nv * it.len;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        const int r = (int)(e / it.len), c = (int)(e % it.len);
+        it.Y[e] = c < it.nv ? it.Z[(int64_t)r * it.nv + c] : 0.0;
+    }
+}
+
+void launch_qr_embed_z(const QrItem *items, int nitems, int64_t max_elems, hipStream_t s) {
+    if (nitems <= 0 || max_elems <= 0) return;
+    const int g = (int)std::min<int64_t>(1024, (max_elems + 255) / 256);
+    hipLaunchKernelGGL(qr_embed_z_kernel, dim3(g, nitems), dim3(256), 0, s, items);
 }
 
 }  // namespace pdmrg

@@ -149,21 +149,32 @@ def _mp_singular_values(M, dps=40):
     return np.array(sorted((float(v) for v in s), reverse=True))
 
 
+@pytest.fixture(scope="module")
+def mp_ref():
+    bl, br = {-1: 24, 1: 24}, {-1: 28, 1: 28}
+    psi = _graded_psi(bl, br, 11, 1e-12)
+    ref = np.concatenate([_mp_singular_values(M_) for q, M_ in sorted(_middle_blocks(psi, bl, br).items())])
+    return bl, br, psi, ref / np.sqrt(np.sum(ref ** 2))
+
+
+@pytest.mark.parametrize("pre", [0, 2])
 @pytest.mark.parametrize("mode", [pl.ABSORB_RIGHT, pl.ABSORB_LEFT, pl.SPLIT])
-def test_svd_small_values_relative_accuracy(ctx, mode):
+def test_svd_small_values_relative_accuracy(ctx, mp_ref, mode, pre):
     """Appendix accuracy on the GPU: graded blocks (24 x 28, 48 x 56, 24 x 28,
     singular values from 1 down to 1e-12 with random orthogonal factors)
     against 40-digit singular values of the same FP64 blocks (mpmath): every
     lambda, and V = 1/lambda where it is not floored, to 1e-5 relative down to
-    1e-12 lambda_1, in all three modes."""
-    bl, br = {-1: 24, 1: 24}, {-1: 28, 1: 28}
-    psi = _graded_psi(bl, br, 11, 1e-12)
-    ref = np.concatenate([_mp_singular_values(M_) for q, M_ in sorted(_middle_blocks(psi, bl, br).items())])
-    ref = ref / np.sqrt(np.sum(ref ** 2))
+    1e-12 lambda_1, in all three modes, with the Jacobi iteration on the
+    blocks themselves (pre 0) and on their QR factors (pre 2)."""
+    bl, br, psi, ref = mp_ref
     B1, B2, P = pl.Bond(bl), pl.Bond(br), pl.Phys(PQ)
     tx, nx = pl.layout(pl.TWO_SITE, B1, B2, P)
     x = dev(blocks_to_flat(psi, tx, nx, pl.TWO_SITE))
-    res = pl.SvdResult(ctx, B1, B2, P, x, 10 ** 6, cutoff=0.0, eps=1e-4, mode=mode)
+    pl.set_svd_precondition(ctx, pre)
+    try:
+        res = pl.SvdResult(ctx, B1, B2, P, x, 10 ** 6, cutoff=0.0, eps=1e-4, mode=mode)
+    finally:
+        pl.set_svd_precondition(ctx, 1)
     assert res.lam.size == ref.size
     lmax = ref.max()
     ok = ref >= 1e-12 * lmax
@@ -191,3 +202,82 @@ def test_svd_truncation_tie_break(ctx, max_m):
     for mode in (pl.ABSORB_RIGHT, pl.ABSORB_LEFT, pl.SPLIT):
         res = pl.SvdResult(ctx, B1, B2, P, x, max_m, cutoff=0.0, mode=mode)
         assert res.bond == dict(zip(ref.bond.qs, ref.bond.dims)) == TIE_CASES[max_m]
+
+
+def _dmrg_graded_psi(bl, br, seed, rate):
+    """Two-site blocks graded the way a DMRG state's are: within each
+    (s, sector) segment of rows and of columns the weights fall like a Schmidt
+    spectrum, exp(-rate sqrt(k)), around a random Gaussian core."""
+    rng = np.random.default_rng(seed)
+    Bl, Br = Bond(bl), Bond(br)
+    psi = {}
+    for qa in Bl.qs:
+        for s1 in range(2):
+            for s2 in range(2):
+                qb = qa + PQ[s1] + PQ[s2]
+                if not Br.has(qb):
+                    continue
+                wr = np.exp(-rate * np.sqrt(np.arange(Bl.dim(qa)) + 0.3 * s1))
+                wc = np.exp(-rate * np.sqrt(np.arange(Br.dim(qb)) + 0.3 * s2))
+                psi[(qa, s1, s2)] = (wr[:, None] * rng.standard_normal((Bl.dim(qa), Br.dim(qb)))) * wc[None, :]
+    nrm = np.sqrt(sum(float(np.sum(v * v)) for v in psi.values()))
+    return {k: v / nrm for k, v in psi.items()}
+
+
+@pytest.mark.parametrize("shape", ["wide", "tall"])
+def test_svd_qr_preconditioned_large_blocks(ctx, shape):
+    """Middle-charge blocks of 300 x 500, 700 x 1100 and 400 x 600 (or their
+    transposes), graded like a DMRG state's: the QR-preconditioned Jacobi
+    iteration (several chunks and panels, the longest panel rows) gives the
+    singular values of LAPACK's SVD of the same blocks to 1e-13 lambda_1 and
+    those of the plain iteration to 1e-6 relative above 1e-8 lambda_1, and its
+    factors rebuild Psi and are orthonormal."""
+    import time
+    import torch
+    a, b = {-1: 300, 1: 400}, {-1: 500, 1: 600}
+    bl, br = (a, b) if shape == "wide" else (b, a)
+    psi = _dmrg_graded_psi(bl, br, 21, 0.9)
+    ref = np.sort(np.concatenate([np.linalg.svd(M_, compute_uv=False)
+                                  for M_ in _middle_blocks(psi, bl, br).values()]))[::-1]
+    B1, B2, P = pl.Bond(bl), pl.Bond(br), pl.Phys(PQ)
+    tx, nx = pl.layout(pl.TWO_SITE, B1, B2, P)
+    x = dev(blocks_to_flat(psi, tx, nx, pl.TWO_SITE))
+    out = {}
+    for pre in (0, 1):
+        pl.set_svd_precondition(ctx, pre)
+        try:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res = pl.SvdResult(ctx, B1, B2, P, x, 10 ** 6, cutoff=0.0, eps=1e-4, mode=pl.ABSORB_RIGHT)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+        finally:
+            pl.set_svd_precondition(ctx, 1)
+        assert res.code == 0, "Jacobi iteration did not converge"
+        out[pre] = res
+        lam = np.sort(res.lam)[::-1]
+        say("  pre", pre, "seconds %.4f" % dt, "max |lam - lapack| / lam_1 %.2e" % (np.abs(lam - ref).max() / ref[0]))
+        assert lam.size == ref.size
+        assert np.abs(lam - ref).max() <= 1e-13 * ref[0]
+    l0, l1 = np.sort(out[0].lam)[::-1], np.sort(out[1].lam)[::-1]
+    big = l0 > 1e-8 * l0[0]
+    assert (np.abs(l1[big] - l0[big]) / l0[big]).max() <= 1e-6
+    assert out[1].bond == out[0].bond
+    res = out[1]
+    Bn = pl.Bond(res.bond)
+    ta, na = pl.layout(pl.SITE, B1, Bn, P)
+    tb, nb = pl.layout(pl.SITE, Bn, B2, P)
+    A = flat_to_blocks(host(res.A)[:na], ta, pl.SITE)
+    R = flat_to_blocks(host(res.right)[:nb], tb, pl.SITE)
+    back = dmrg.contract_two(A, R, PQ)
+    keys = two_site_keys(Bond(bl), Bond(br), PQ)
+    shapes = [two_site_shape(k, Bond(bl), Bond(br), PQ) for k in keys]
+    err = np.linalg.norm(flatten(back, keys, shapes) - flatten(psi, keys, shapes))
+    say("  reconstruction", err)
+    assert err <= 1e-13
+    Bb = flat_to_blocks(host(res.B)[:nb], tb, pl.SITE)
+    for q, n in res.bond.items():
+        Ga = sum(A[(qa, s)].T @ A[(qa, s)] for (qa, s) in A if qa + PQ[s] == q)
+        Gb = sum(Bb[(q2, s)] @ Bb[(q2, s)].T for (q2, s) in Bb if q2 == q)
+        assert np.abs(Ga - np.eye(n)).max() <= 1e-12
+        assert np.abs(Gb - np.eye(n)).max() <= 1e-12
