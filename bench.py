@@ -853,6 +853,10 @@ def main():
     ap.add_argument("--fig3", action="store_true",
                     help="run only the prediction-fidelity study at the paper's size (200-site chains, m up to "
                          "600; minutes) and print its JSON")
+    ap.add_argument("--verbose", type=int, default=0, choices=[0, 1, 2],
+                    help="with --only-c3: progress lines per bond (1) and per SVD level (2) on stderr")
+    ap.add_argument("--svd-precondition", type=int, default=1, choices=[0, 1, 2],
+                    help="with --only-c3: QR preconditioning of the SVD's Jacobi iteration (0 off, 1 default, 2 all)")
     ap.add_argument("--sequential-regions", action="store_true",
                     help="sweep leg: regions one after the other on one stream instead of concurrently")
     ap.add_argument("--tune-db", default=os.path.join(ROOT, "paper_1301_3494_amd", "tuning", "mi355x.tsv"),
@@ -899,6 +903,8 @@ def main():
         ctx.close()
         return
     if args.only_c3:
+        pl.set_verbose(ctx, args.verbose)
+        pl.set_svd_precondition(ctx, args.svd_precondition)
         print(json.dumps({"sweep": sweep_c3_leg(ctx, pl, synth, torch, concurrent=not args.sequential_regions)}))
         ctx.close()
         return

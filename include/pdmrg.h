@@ -143,8 +143,10 @@ int pdmrg_ctx_set_autotune(pdmrg_ctx *ctx, int level);
 int pdmrg_ctx_set_env_stride(pdmrg_ctx *ctx, int stride);
 /* Progress log of sweep, grad_mpo and grad_couplings on this context: with
  * level 1 every optimised bond (bond, kept m, energy, Davidson and SVD
- * seconds) and every gauge move prints one line on stderr; 0 (the default):
- * silent.  PDMRG_EINVAL for a negative level. */
+ * seconds) and every gauge move prints one line on stderr; level 2 also one
+ * line per level of each truncation SVD (blocks, preconditioned blocks,
+ * largest block, Jacobi sweeps); 0 (the default): silent.  PDMRG_EINVAL for a
+ * negative level. */
 int pdmrg_ctx_set_verbose(pdmrg_ctx *ctx, int level);
 /* Preconditioning of the truncation SVD (svd_truncate, and every SVD of
  * sweep, split, gauge conversion and grad passes on this context; Eq. eqn:svd

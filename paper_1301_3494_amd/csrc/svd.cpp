@@ -14,6 +14,7 @@
 #include "svd.hpp"
 
 #include <cmath>
+#include <cstdio>
 #include <numeric>
 #include <tuple>
 
@@ -312,7 +313,9 @@ void svd_batch(pdmrg_ctx *ctx, const std::vector<Mat> &mats, std::vector<SvdRes>
     std::vector<int32_t> active(nm, 1);
     d_off.ensure(std::max(nm, 1) * sizeof(unsigned long long));
 
+    int sweeps_done = 0;
     for (int sweep = 0; sweep < kMaxSweeps; ++sweep) {
+        sweeps_done = sweep + 1;
         upload(d_active, active, s);
         launch_fill(d_off.as<double>(), 0.0, nm, s);
         for (int r = 0; r < rmax; ++r)
@@ -332,6 +335,15 @@ void svd_batch(pdmrg_ctx *ctx, const std::vector<Mat> &mats, std::vector<SvdRes>
     // still an exact rotation of the block (absolute accuracy), reported
     for (int i = 0; i < nm; ++i) n_unconv += active[i] ? 1 : 0;
     if (any_pre) qr_right_factor(qs, s);
+    if (ctx->verbose >= 2) {
+        int big = 0, npre = 0;
+        for (int i = 0; i < nm; ++i) {
+            big = std::max(big, items[i].nv);
+            npre += pre[i] ? 1 : 0;
+        }
+        std::fprintf(stderr, "pdmrg: svd level %d: %d blocks (%d preconditioned), largest %d rows, %d sweeps\n", depth,
+                     nm, npre, big, sweeps_done);
+    }
 
     // singular values = row norms
     std::vector<RowRef> refs;

@@ -367,42 +367,64 @@ void launch_copies(const CopyTask *tasks, int ntasks, int64_t max_elems, hipStre
 // ---------------------------------------------------------------------------
 // Householder QR preconditioning of the one-sided Jacobi iteration.
 //
-// Panel kernel: one workgroup of QT threads factors the 16 rows of a panel.
-// Thread t holds positions j0 + t + QT u (u < UQ) of all 16 rows in
-// registers; each reflector takes two block reductions (the column norm with
-// the pivot entry, then the dot products of the new reflector with the
-// panel's other rows, which give both the update of the later rows and the
-// new column of T).  Reductions are butterflies within a wave (every lane
-// ends with the same bits) followed by a fixed-order sum over the waves, so
-// every thread holds identical scalars and the result is reproducible.
-constexpr int QT = 512;
-constexpr int QW = QT / 64;
-
-template <int NV>
-__device__ __forceinline__ void qr_block_sum(double (&v)[NV], double (*red)[kQrPanel], int lane, int wave) {
+// Panel kernel: one workgroup of NT threads factors the 16 rows of a panel.
+// Thread t holds positions j0 + t + NT u (u < UQ) of all 16 rows in
+// registers.  Reflector j (pivot position p = j0 + j) needs one block
+// reduction of 16 sums C_k = sum_{q > p} x_j[q] x_k[q] (C_j is the squared
+// norm below the pivot) and the pivot-row entries E_k = x_k[p] (E_j is the
+// pivot), which thread j publishes.  With beta = -sign(E_j) sqrt(E_j^2 + C_j),
+// tau = (beta - E_j) / beta and v = x_j / (E_j - beta) below p (v_p = 1), the
+// dot of v with row k is E_k + C_k / (E_j - beta): for later rows it gives
+// their update, for earlier rows (which hold their reflectors there) the new
+// column of T.  The sums are a reduce-scatter butterfly within each wave and
+// a fixed-order sum over the waves, so every thread reads identical scalars
+// and the result is reproducible.
+template <int NT>
+__device__ __forceinline__ void qr_sum16(double (&v)[16], double (*red)[16], double *res, int tid) {
+    const int lane = tid & 63, wave = tid >> 6;
+    double h8[8], h4[4], h2[2];
 #pragma unroll
-    for (int i = 0; i < NV; ++i)
+    for (int i = 0; i < 8; ++i) {
+        const bool up = lane & 16;
+        h8[i] = (up ? v[8 + i] : v[i]) + __shfl_xor(up ? v[i] : v[8 + i], 16);
+    }
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) v[i] += __shfl_xor(v[i], o);
-    if (lane == 0)
+    for (int i = 0; i < 4; ++i) {
+        const bool up = lane & 8;
+        h4[i] = (up ? h8[4 + i] : h8[i]) + __shfl_xor(up ? h8[i] : h8[4 + i], 8);
+    }
 #pragma unroll
-        for (int i = 0; i < NV; ++i) red[wave][i] = v[i];
+    for (int i = 0; i < 2; ++i) {
+        const bool up = lane & 4;
+        h2[i] = (up ? h4[2 + i] : h4[i]) + __shfl_xor(up ? h4[i] : h4[2 + i], 4);
+    }
+    const bool up = lane & 2;
+    double one = (up ? h2[1] : h2[0]) + __shfl_xor(up ? h2[0] : h2[1], 2);
+    one += __shfl_xor(one, 1);
+    one += __shfl_xor(one, 32);
+    // lane bits 4..1 chose the halves: the lane holds value (lane >> 1) & 15
+    if ((lane & 33) == 0) red[wave][(lane >> 1) & 15] = one;
+    __syncthreads();
+    if (tid < 16) {
+        double a = red[0][tid];
+#pragma unroll
+        for (int w = 1; w < NT / 64; ++w) a += red[w][tid];
+        res[tid] = a;
+    }
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < NV; ++i) {
-        double a = red[0][i];
-#pragma unroll
-        for (int w = 1; w < QW; ++w) a += red[w][i];
-        v[i] = a;
-    }
+    for (int i = 0; i < 16; ++i) v[i] = res[i];
 }
 
-template <int UQ>
-__global__ __launch_bounds__(QT) __attribute__((amdgpu_waves_per_eu(1, 2))) void qr_panel_kernel(const QrPanel *tasks) {
+template <int NT, int UQ>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, 2))) void qr_panel_kernel(
+    const QrPanel *tasks) {
     const QrPanel tk = tasks[blockIdx.x];
     const int nb = min(kQrPanel, tk.nv - tk.j0);
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    __shared__ double red[2][QW][kQrPanel];   // alternating, so one barrier per reduction suffices
+    const int tid = threadIdx.x;
+    __shared__ double red[NT / 64][16];
+    __shared__ double res[16];
+    __shared__ double piv[2][kQrPanel];   // E of alternate steps: written before a step's first barrier
     __shared__ double Ts[kQrPanel][kQrPanel];
     if (tid < kQrPanel * kQrPanel) Ts[tid / kQrPanel][tid % kQrPanel] = 0.0;
     double x[kQrPanel][UQ];
@@ -410,10 +432,9 @@ __global__ __launch_bounds__(QT) __attribute__((amdgpu_waves_per_eu(1, 2))) void
     for (int r = 0; r < kQrPanel; ++r)
 #pragma unroll
         for (int u = 0; u < UQ; ++u) {
-            const int q = tk.j0 + tid + QT * u;
+            const int q = tk.j0 + tid + NT * u;
             x[r][u] = (r < nb && q < tk.len) ? tk.A[(int64_t)(tk.j0 + r) * tk.len + q] : 0.0;
         }
-    int rb = 0;
     // j runs as a loop; rows are picked and written back by selects, so every
     // register index is a constant
     for (int j = 0; j < nb; ++j) {   // nb is uniform over the workgroup
@@ -424,18 +445,28 @@ __global__ __launch_bounds__(QT) __attribute__((amdgpu_waves_per_eu(1, 2))) void
             double t = x[0][u];
 #pragma unroll
             for (int r = 1; r < kQrPanel; ++r) t = r == j ? x[r][u] : t;
-            xj[u] = t;
+            const int q = tk.j0 + tid + NT * u;
+            xj[u] = q > p ? t : 0.0;   // below the pivot only
         }
-        // sum of squares below the pivot, and the pivot itself (thread j, u = 0)
-        double a2[2] = {0.0, tid == j ? xj[0] : 0.0};
+        double cs[kQrPanel];
 #pragma unroll
-        for (int u = 0; u < UQ; ++u) {
-            const int q = tk.j0 + tid + QT * u;
-            a2[0] += q > p ? xj[u] * xj[u] : 0.0;
+        for (int k = 0; k < kQrPanel; ++k) {
+            double t = 0.0;
+#pragma unroll
+            for (int u = 0; u < UQ; ++u) t = fma(xj[u], x[k][u], t);
+            cs[k] = t;
         }
-        qr_block_sum<2>(a2, red[rb], lane, wave);
-        rb ^= 1;
-        const double sig = a2[0], alpha = a2[1];
+        double *E = piv[j & 1];
+        if (tid == j)   // position p is thread j's u = 0
+#pragma unroll
+            for (int k = 0; k < kQrPanel; ++k) E[k] = x[k][0];
+        qr_sum16<NT>(cs, red, res, tid);
+        double sig = cs[0], alpha = E[0];
+#pragma unroll
+        for (int k = 1; k < kQrPanel; ++k) {
+            sig = k == j ? cs[k] : sig;
+            alpha = k == j ? E[k] : alpha;
+        }
         double tau = 0.0, beta = alpha, inv = 0.0;
         if (sig > 0.0) {
             const double nrm = sqrt(fma(alpha, alpha, sig));
@@ -447,33 +478,24 @@ __global__ __launch_bounds__(QT) __attribute__((amdgpu_waves_per_eu(1, 2))) void
         double v[UQ];
 #pragma unroll
         for (int u = 0; u < UQ; ++u) {
-            const int q = tk.j0 + tid + QT * u;
-            const double t = xj[u] * inv;
-            v[u] = q > p ? t : (q == p ? 1.0 : 0.0);
-            const double nx = q > p ? t : (q == p ? beta : xj[u]);
+            const int q = tk.j0 + tid + NT * u;
+            v[u] = q > p ? xj[u] * inv : (q == p ? 1.0 : 0.0);
+            const bool keep = q < p;
 #pragma unroll
-            for (int r = 0; r < kQrPanel; ++r) x[r][u] = r == j ? nx : x[r][u];
+            for (int r = 0; r < kQrPanel; ++r) x[r][u] = (r == j && !keep) ? (q == p ? beta : v[u]) : x[r][u];
         }
-        // dots of v with every other panel row (later rows: for their update;
-        // earlier rows hold their reflectors at positions >= p: for T)
+        // d_k = v . x_k (row k after the earlier steps)
         double d[kQrPanel];
 #pragma unroll
-        for (int k = 0; k < kQrPanel; ++k) {
-            double t = 0.0;
-#pragma unroll
-            for (int u = 0; u < UQ; ++u) t = fma(v[u], x[k][u], t);
-            d[k] = (k != j && k < nb) ? t : 0.0;
-        }
-        qr_block_sum<kQrPanel>(d, red[rb], lane, wave);
-        rb ^= 1;
+        for (int k = 0; k < kQrPanel; ++k) d[k] = fma(cs[k], inv, E[k]);
 #pragma unroll
         for (int k = 0; k < kQrPanel; ++k) {
             const double f = (k > j && k < nb) ? tau * d[k] : 0.0;
 #pragma unroll
             for (int u = 0; u < UQ; ++u) x[k][u] = fma(-f, v[u], x[k][u]);
         }
-        // T[0:j][j] = -tau T[0:j][0:j] (V[:, 0:j]^T v); T[j][j] = tau.  Column j
-        // is read by later steps only after their first reduction's barrier.
+        // T[0:j][j] = -tau T[0:j][0:j] (V[:, 0:j]^T v); T[j][j] = tau.  Thread i
+        // only reads row i of T, which it wrote itself.
         if (tid < j) {
             double t = 0.0;
 #pragma unroll
@@ -488,7 +510,7 @@ __global__ __launch_bounds__(QT) __attribute__((amdgpu_waves_per_eu(1, 2))) void
     for (int r = 0; r < kQrPanel; ++r)
 #pragma unroll
         for (int u = 0; u < UQ; ++u) {
-            const int q = tk.j0 + tid + QT * u;
+            const int q = tk.j0 + tid + NT * u;
             if (r < nb && q < tk.len) tk.A[(int64_t)(tk.j0 + r) * tk.len + q] = x[r][u];
         }
     if (tid < kQrPanel * kQrPanel) tk.T[tid] = Ts[tid / kQrPanel][tid % kQrPanel];
@@ -496,16 +518,16 @@ __global__ __launch_bounds__(QT) __attribute__((amdgpu_waves_per_eu(1, 2))) void
 
 void launch_qr_panels(const QrPanel *tasks, int ntasks, int max_span, hipStream_t s) {
     if (ntasks <= 0) return;
-    if (max_span <= QT)
-        hipLaunchKernelGGL(qr_panel_kernel<1>, dim3(ntasks), dim3(QT), 0, s, tasks);
-    else if (max_span <= 2 * QT)
-        hipLaunchKernelGGL(qr_panel_kernel<2>, dim3(ntasks), dim3(QT), 0, s, tasks);
-    else if (max_span <= 4 * QT)
-        hipLaunchKernelGGL(qr_panel_kernel<4>, dim3(ntasks), dim3(QT), 0, s, tasks);
+    if (max_span <= 512)
+        hipLaunchKernelGGL((qr_panel_kernel<256, 2>), dim3(ntasks), dim3(256), 0, s, tasks);
+    else if (max_span <= 1024)
+        hipLaunchKernelGGL((qr_panel_kernel<256, 4>), dim3(ntasks), dim3(256), 0, s, tasks);
+    else if (max_span <= 2048)
+        hipLaunchKernelGGL((qr_panel_kernel<512, 4>), dim3(ntasks), dim3(512), 0, s, tasks);
     else
         throw std::invalid_argument("qr panel: rows longer than the panel kernel holds");
 }
-static_assert(4 * QT == kQrMaxLen, "panel kernel reach");
+static_assert(kQrMaxLen == 2048, "panel kernel reach");
 
 // Apply kernel: one workgroup of 4 waves per (panel, group of 16 target rows).
 // D = V Y^T over positions j0.. (FP64 MFMA, reflector rows masked to their
