@@ -502,7 +502,8 @@ def sweep_c3_leg(ctx, pl, synth, torch, regions=4, seed=3, concurrent=True):
         "schedule": "2 serial sweeps at m=200, parallel (%d regions, %s) at m=650,650,1100,1100,1550,1550 in "
                     "FP64, then the 2 sweeps at m=2000 timed per precision from copies of the same state; "
                     "Davidson 4 matvecs / 1e-8 interior, 40 / 1e-10 shared bonds" % (
-                        regions, "concurrent" if concurrent else "one after the other"),
+                        regions, "in lockstep, SVDs batched" if concurrent == 2 and not isinstance(concurrent, bool)
+                        else "concurrent" if concurrent else "one after the other"),
         "seconds_per_sweep_f64": round(res["f64"]["seconds"], 4),
         "seconds_per_sweep_mixed": round(res["mixed"]["seconds"], 4),
         "speedup_mixed_vs_f64": round(res["f64"]["seconds"] / res["mixed"]["seconds"], 4),
@@ -857,6 +858,8 @@ def main():
                     help="with --only-c3: progress lines per bond (1) and per SVD level (2) on stderr")
     ap.add_argument("--svd-precondition", type=int, default=1, choices=[0, 1, 2],
                     help="with --only-c3: QR preconditioning of the SVD's Jacobi iteration (0 off, 1 default, 2 all)")
+    ap.add_argument("--lockstep", action="store_true",
+                    help="with --only-c3: regions in lockstep with each step's SVDs in one batch (sweep concurrent = 2)")
     ap.add_argument("--sequential-regions", action="store_true",
                     help="sweep leg: regions one after the other on one stream instead of concurrently")
     ap.add_argument("--tune-db", default=os.path.join(ROOT, "paper_1301_3494_amd", "tuning", "mi355x.tsv"),
@@ -905,7 +908,8 @@ def main():
     if args.only_c3:
         pl.set_verbose(ctx, args.verbose)
         pl.set_svd_precondition(ctx, args.svd_precondition)
-        print(json.dumps({"sweep": sweep_c3_leg(ctx, pl, synth, torch, concurrent=not args.sequential_regions)}))
+        conc = 2 if args.lockstep else not args.sequential_regions
+        print(json.dumps({"sweep": sweep_c3_leg(ctx, pl, synth, torch, concurrent=conc)}))
         ctx.close()
         return
     if args.fig1:

@@ -375,8 +375,12 @@ int merge_regions(pdmrg_ctx *ctx, const pdmrg_bond *bl, const pdmrg_bond *bm,
  * one merge phase): with concurrent = 1 each region runs on its own HIP
  * stream, driven by its own host thread, with its own work space (the
  * paper's one process per region, on one device); with concurrent = 0 they
- * run one after the other on the context's stream.  The result is the same
- * bits either way.  energy: <Psi|H|Psi>/<Psi|Psi> of the whole MPS after the
+ * run one after the other on the context's stream; with concurrent = 2 the
+ * regions run in lockstep, one bond of every region per step (their
+ * eigensolvers as with 1, then the truncation SVDs of all the step's bonds
+ * as one batch whose sector blocks share the Jacobi launches, then their
+ * environment updates), and the merges of a phase form one step.  The
+ * result is the same bits in all three modes.  energy: <Psi|H|Psi>/<Psi|Psi> of the whole MPS after the
  * sweep (V applied on the shared bonds). */
 typedef struct {
     int32_t max_m;
@@ -386,7 +390,8 @@ typedef struct {
     pdmrg_dav_params dav;             /* interior bonds                       */
     pdmrg_dav_params dav_shared;      /* shared (merge) bonds                 */
     double cutoff, eps;
-    int32_t concurrent;               /* 1: regions on their own streams      */
+    int32_t concurrent;               /* 1: regions on their own streams;
+                                         2: in lockstep, SVDs batched        */
     int32_t pad_;
 } pdmrg_sweep_params;
 typedef struct {

@@ -489,7 +489,7 @@ class Mps:
               cutoff=1e-12, eps=1e-4, concurrent=False):
         p = CSweepParams(int(max_m), int(n_regions), int(prec), int(bool(refine)),
                          dav or dav_params(4, 8, 1e-8), dav_shared or dav_params(40, 8, 1e-10),
-                         float(cutoff), float(eps), int(bool(concurrent)), 0)
+                         float(cutoff), float(eps), _concurrency(concurrent), 0)
         rep = CSweepReport()
         check(lib().sweep(self.ctx.h, self.h, mpo.h, byref(p), byref(rep)))
         return {f: getattr(rep, f) for f, _ in CSweepReport._fields_}
@@ -642,6 +642,16 @@ def set_env_stride(ctx, stride):
 def set_verbose(ctx, level):
     """Progress lines (one per optimised bond / gauge move) on stderr."""
     check(lib().pdmrg_ctx_set_verbose(ctx.h, int(level)))
+
+
+def _concurrency(c):
+    """sweep's concurrent field: False / 0 one after the other, True / 1 own
+    streams, 2 lockstep with batched SVDs."""
+    if isinstance(c, bool) or c in (0, 1):
+        return int(bool(c))
+    if c == 2:
+        return 2
+    raise ValueError("concurrent must be False, True or 2")
 
 
 def set_svd_precondition(ctx, mode):

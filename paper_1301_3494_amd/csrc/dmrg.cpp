@@ -316,6 +316,76 @@ struct Driver {
         m->split = true;
     }
 
+    // One lockstep step over several bonds: one bond of every region, or the
+    // shared bonds of a merge phase (Fig. 4).  The bonds share no sites or
+    // environments.  The eigensolver runs per bond as independent jobs; the
+    // truncated SVDs of all bonds share one batch (their sector blocks go
+    // into the same Jacobi launches); then every bond stores its factors and
+    // updates its environments as a job again.  The results equal those of
+    // the bonds taken one at a time.
+    struct Step {
+        int i;         // bond between sites i and i + 1
+        int mode;      // PDMRG_ABSORB_RIGHT, PDMRG_ABSORB_LEFT or PDMRG_SPLIT
+        bool shared;   // merge at a shared bond: psi_L V psi_R, prediction fidelity
+        bool right;    // direction of an interior step (which environments to drop)
+    };
+    void lockstep(const std::vector<Step> &steps) {
+        const int n = (int)steps.size();
+        std::vector<DevBuf> psi(n);
+        std::vector<double> energy(n, 0.0), dav_s(n, 0.0);
+        std::vector<std::function<void(Driver &)>> solve_jobs, store_jobs;
+        for (int k = 0; k < n; ++k)
+            solve_jobs.push_back([&, k](Driver &d) {
+                const Step &st = steps[k];
+                const double h0 = d.t_heff;
+                if (st.shared) {
+                    PD_REQUIRE(d.m->hasV[st.i + 1], PDMRG_EINVAL, "merge: no V on the shared bond");
+                    psi[k] = d.contract(st.i, d.m->Vd[st.i + 1].as<double>());
+                    // prediction fidelity of the merged state (Fig. 3): psi_L V
+                    // psi_R against the state the shared-bond eigensolver reaches
+                    const int64_t nx = two_site_layout(d.m->bonds[st.i], d.m->bonds[st.i + 2], d.m->p).size;
+                    DevBuf pred = d.take(psi[k], nx);
+                    energy[k] = d.solve(st.i, psi[k], d.prm.dav_shared);   // Davidson normalises its start
+                    d.rep.max_infidelity =
+                        std::max(d.rep.max_infidelity, d.infidelity(pred.as<double>(), psi[k].as<double>(), nx));
+                } else {
+                    psi[k] = d.contract(st.i, nullptr);
+                    energy[k] = d.solve(st.i, psi[k], d.prm.dav);
+                }
+                dav_s[k] = d.t_heff - h0;
+            });
+        run_jobs(solve_jobs);
+        std::vector<SvdProblem> probs;
+        for (int k = 0; k < n; ++k)
+            probs.push_back(SvdProblem{&m->bonds[steps[k].i], &m->bonds[steps[k].i + 2], &m->p, psi[k].as<double>(),
+                                       prm.max_m, prm.cutoff, steps[k].mode});
+        std::vector<SvdOut> outs;
+        const auto t0 = std::chrono::steady_clock::now();
+        svd_truncate_multi(ctx, probs, prm.eps, outs);
+        const double svd_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        t_svd += svd_s;
+        for (int k = 0; k < n; ++k)
+            store_jobs.push_back([&, k](Driver &d) {
+                const Step &st = steps[k];
+                d.store(st.i, outs[k], st.mode);
+                if (!st.shared) {
+                    if (st.right) {
+                        d.drop_L(st.i, true);
+                        d.drop_R(st.i + 2, false);
+                    } else {
+                        d.drop_R(st.i + 2, true);
+                        d.drop_L(st.i, false);
+                    }
+                }
+                if (ctx->verbose)
+                    std::fprintf(stderr, "pdmrg: bond %d|%d m=%d E=%.12f davidson %.2fs svd %.2fs (batch of %d)%s\n",
+                                 st.i, st.i + 1, d.m->bonds[st.i + 1].total, energy[k], dav_s[k], svd_s, n,
+                                 st.shared ? " merge" : ""),
+                        std::fflush(stderr);
+            });
+        run_jobs(store_jobs);
+    }
+
     // Context of region r for concurrent work: own non-blocking stream (default
     // priority) and work space, same device and tuning level.
     pdmrg_ctx *sub_ctx(int r) {
@@ -390,6 +460,10 @@ struct Driver {
     void parallel_sweep() {
         const auto rg = m->regions;
         const int n = (int)rg.size();
+        if (prm.concurrent == 2) {
+            lockstep_sweep();
+            return;
+        }
         for (int half = 0; half < 2; ++half) {
             std::vector<std::function<void(Driver &)>> jobs;
             for (int r = 0; r < n; ++r) {
@@ -417,6 +491,33 @@ struct Driver {
                 merges.push_back([j](Driver &d) { d.merge_shared(j); });
             }
             run_jobs(merges);
+        }
+    }
+
+    // The staggered sweep of Fig. 4 with the regions in lockstep: step t
+    // optimises bond t of every region (in its direction) and the merges of a
+    // phase form one step, each step through lockstep().
+    void lockstep_sweep() {
+        const auto rg = m->regions;
+        const int n = (int)rg.size();
+        int len = 0;
+        for (auto &r : rg) len = std::max(len, r.second - r.first);
+        for (int half = 0; half < 2; ++half) {
+            for (int t = 0; t < len; ++t) {
+                std::vector<Step> steps;
+                for (int r = 0; r < n; ++r) {
+                    const int lo = rg[r].first, hi = rg[r].second;
+                    if (t >= hi - lo) continue;
+                    const bool right = (r % 2 == 0) == (half == 0);
+                    steps.push_back(Step{right ? lo + t : hi - 1 - t, right ? PDMRG_ABSORB_RIGHT : PDMRG_ABSORB_LEFT,
+                                         false, right});
+                }
+                lockstep(steps);
+            }
+            // merge phase: shared bonds 1|2, 3|4, ... then 2|3, 4|5, ...
+            std::vector<Step> merges;
+            for (int r = half; r < n - 1; r += 2) merges.push_back(Step{rg[r].second, PDMRG_SPLIT, true, false});
+            if (!merges.empty()) lockstep(merges);
         }
     }
 
@@ -783,7 +884,8 @@ int sweep(pdmrg_ctx *ctx, pdmrg_mps *m, const pdmrg_mpo *mpo, const pdmrg_sweep_
     API_TRY
     PD_REQUIRE(ctx && m && mpo && p, PDMRG_EINVAL, "sweep: null argument");
     check_mpo(m, mpo);
-    PD_REQUIRE(p->max_m >= 1 && p->n_regions >= 1, PDMRG_EINVAL, "sweep: bad parameters");
+    PD_REQUIRE(p->max_m >= 1 && p->n_regions >= 1 && p->concurrent >= 0 && p->concurrent <= 2, PDMRG_EINVAL,
+               "sweep: bad parameters");
     const auto t0 = std::chrono::steady_clock::now();
     Driver dr{ctx, m, mpo};
     dr.stride = ctx->env_stride;

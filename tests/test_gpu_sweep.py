@@ -103,13 +103,15 @@ def test_xx_chain_closed_form_two_regions(ctx):
 
 
 def test_concurrent_regions_bitwise_equal_to_sequential(ctx):
-    """Regions on their own streams and host threads give the same bits as
-    one after the other (no data crosses regions between merges)."""
+    """Regions on their own streams and host threads, and regions in lockstep
+    with the truncation SVDs of each step in one batch (concurrent = 2), give
+    the same bits as one after the other (no data crosses regions between
+    merges, and a block's Jacobi iteration does not depend on its batch)."""
     N = 16
     bonds, sites = synth.random_mps(N, 16, 5)
     mpo = pl.Mpo("chain", N, 1, (1.0, 1.0))
     out = {}
-    for conc in (False, True):
+    for conc in (False, True, 2):
         mps = pl.Mps(ctx, bonds, sites)
         es = []
         for k, m in enumerate([32, 48, 48, 64]):
@@ -125,10 +127,11 @@ def test_concurrent_regions_bitwise_equal_to_sequential(ctx):
             tens.append(buf)
         out[conc] = (es, tens)
         mps.free()
-    say("sequential", out[False][0], "concurrent", out[True][0])
-    assert out[False][0] == out[True][0]
-    for a, b in zip(out[False][1], out[True][1]):
-        assert np.array_equal(a, b)
+    say("sequential", out[False][0], "concurrent", out[True][0], "lockstep", out[2][0])
+    for conc in (True, 2):
+        assert out[False][0] == out[conc][0]
+        for a, b in zip(out[False][1], out[conc][1]):
+            assert np.array_equal(a, b)
     assert abs(out[True][0][-1] - E_ED_CHAIN16) <= 1e-6 * abs(E_ED_CHAIN16)
 
 
