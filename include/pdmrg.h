@@ -145,7 +145,7 @@ int pdmrg_ctx_set_env_stride(pdmrg_ctx *ctx, int stride);
  * level 1 every optimised bond (bond, kept m, energy, Davidson and SVD
  * seconds) and every gauge move prints one line on stderr; level 2 also one
  * line per level of each truncation SVD (blocks, preconditioned blocks,
- * largest block, Jacobi sweeps); 0 (the default): silent.  PDMRG_EINVAL for a
+ * largest block, Jacobi sweeps and launched rounds); 0 (the default): silent.  PDMRG_EINVAL for a
  * negative level. */
 int pdmrg_ctx_set_verbose(pdmrg_ctx *ctx, int level);
 /* Preconditioning of the truncation SVD (svd_truncate, and every SVD of

@@ -313,12 +313,18 @@ void svd_batch(pdmrg_ctx *ctx, const std::vector<Mat> &mats, std::vector<SvdRes>
     std::vector<int32_t> active(nm, 1);
     d_off.ensure(std::max(nm, 1) * sizeof(unsigned long long));
 
-    int sweeps_done = 0;
+    int sweeps_done = 0, nrounds = 0;
     for (int sweep = 0; sweep < kMaxSweeps; ++sweep) {
         sweeps_done = sweep + 1;
         upload(d_active, active, s);
         launch_fill(d_off.as<double>(), 0.0, nm, s);
-        for (int r = 0; r < rmax; ++r)
+        // rounds past every active matrix's last hold only pairs of converged
+        // matrices, which do nothing: not launched
+        int ract = 0;
+        for (int i = 0; i < nm; ++i)
+            if (active[i]) ract = std::max(ract, nblk[i] - 1);
+        nrounds += ract;
+        for (int r = 0; r < ract; ++r)
             launch_jac_round(d_items.as<JacItem>(), d_pairs.as<JacPair>() + roff[r], roff[r + 1] - roff[r],
                              d_active.as<int32_t>(), d_off.as<unsigned long long>(), s);
         std::vector<double> off(nm);
@@ -341,8 +347,9 @@ void svd_batch(pdmrg_ctx *ctx, const std::vector<Mat> &mats, std::vector<SvdRes>
             big = std::max(big, items[i].nv);
             npre += pre[i] ? 1 : 0;
         }
-        std::fprintf(stderr, "pdmrg: svd level %d: %d blocks (%d preconditioned), largest %d rows, %d sweeps\n", depth,
-                     nm, npre, big, sweeps_done);
+        std::fprintf(stderr,
+                     "pdmrg: svd level %d: %d blocks (%d preconditioned), largest %d rows, %d sweeps, %d rounds\n",
+                     depth, nm, npre, big, sweeps_done, nrounds);
     }
 
     // singular values = row norms
