@@ -192,3 +192,16 @@ def test_autotune_cache_file_round_trip(tmp_path):
         pl.autotune_import(bad)
     with pytest.raises(pl.PdmrgError):
         pl.autotune_import(tmp_path / "missing.txt")
+
+
+def test_sweep_concurrency_field_mapping():
+    """The binding passes the sweep's region mode as the C field expects:
+    False / 0 one after the other, True / 1 own streams, 2 lockstep with
+    batched SVDs; anything else is refused before reaching the library."""
+    assert pl._concurrency(False) == 0 and pl._concurrency(0) == 0
+    assert pl._concurrency(True) == 1 and pl._concurrency(1) == 1
+    assert pl._concurrency(np.bool_(True)) == 1
+    assert pl._concurrency(2) == 2
+    for bad in (3, -1, "2"):
+        with pytest.raises(ValueError):
+            pl._concurrency(bad)
