@@ -3,7 +3,10 @@
 //
 // Psi viewed as the (m d) x (d m) matrix is block-diagonal in the middle
 // charge; each block M (rows (s1, a), columns (s2, b)) is gathered densely and
-// decomposed M = U Lambda Vt by one-sided block Jacobi (svd.hip).  Appendix
+// decomposed M = U Lambda Vt by one-sided block Jacobi (svd.hip); at the top
+// level, blocks of at least 64 rows are first ordered by row norm and QR
+// factored, and the iteration runs on the triangular factor (qr_factor,
+// qr_right_factor: about half the sweeps on graded blocks).  Appendix
 // recursion: for the singular values of a block below eps * lambda_1 (indices
 // p..k-1), X = Ut[p:] M Vt[p:]^T is formed with FP64 GEMMs and decomposed the
 // same way (recursively), then Ut[p:] <- Ut~ Ut[p:], Vt[p:] <- Vt~ Vt[p:],

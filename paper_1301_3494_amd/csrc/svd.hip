@@ -24,7 +24,12 @@
 //
 // Measured alternatives: 16-row blocks (32 x 32 inner problem) halve the
 // rounds per sweep but cost more than twice as much per round; up to three
-// inner sweeps per meeting save fewer outer rounds than they cost.
+// inner sweeps per meeting save fewer outer rounds than they cost; 8 waves
+// (W and Z rotated by separate halves at once) and the inner sweep in one
+// wave without workgroup barriers are no faster.
+//
+// Also here: the Householder QR that preconditions the iteration (panel and
+// reflector-application kernels, below) and the copy / norm helpers.
 #include "svd.hpp"
 
 #include <algorithm>
